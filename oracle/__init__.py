@@ -1,0 +1,21 @@
+"""FP64 CPU oracle for generalized Nystrom (GN) low-rank approximation.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and its
+Python binding) may import, call or link anything in this package; only the
+tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py``
+use it.  It shares no code with the GPU path: the Philox counter-based generator,
+the SRHT construction and every GN step are written here from their definitions,
+independently of the HIP sources.
+
+Paper: Y. Nakatsukasa, "Fast and stable randomized low-rank matrix
+approximation" (arXiv:2009.11392).
+
+Modules
+  philox  -- Philox4x32-10 words, Box-Muller Gaussians, SRHT signs and samples.
+  gn      -- the GN / stabilized GN pipeline (Algorithm 2.1 and Section 5.1),
+             plus the comparison formulas used as pins (HMT, Tropp17, SVD
+             epsilon-pseudoinverse, Nystrom, CUR) and the theorem bounds.
+  exact   -- exact rational GN on tiny integer inputs (brute-force pin).
+
+Parity status of each function is stated in its module header.
+"""

@@ -1,0 +1,111 @@
+"""CPU pins for the oracle's random sketches (no GPU).
+
+The paper only requires i.i.d. zero-mean unit-variance Gaussian sketches
+(Section 3.1) or an SRHT (Section 1); these tests check exactly those properties
+of the oracle's generator, plus the closed form of the Sylvester-Hadamard matrix
+against scipy.linalg.hadamard and the bfloat16 rounding against torch.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.stats as st
+
+from oracle import philox
+
+
+def test_gaussian_moments_and_ks():
+    z = philox.gaussian(12345, philox.STREAM_Y, 1000, 1000).ravel()
+    n = z.size
+    assert abs(z.mean()) < 5 / np.sqrt(n)
+    assert abs(z.var() - 1.0) < 5 * np.sqrt(2.0 / n)
+    # third and fourth moments of N(0,1): 0 and 3
+    assert abs(np.mean(z ** 3)) < 5 * np.sqrt(15.0 / n)
+    assert abs(np.mean(z ** 4) - 3.0) < 5 * np.sqrt(96.0 / n)
+    assert st.kstest(z, "norm").pvalue > 1e-4
+
+
+def test_gaussian_pairs_and_neighbours_uncorrelated():
+    Z = philox.gaussian(7, philox.STREAM_X, 2000, 256)
+    n = Z[:, 0::2].size
+    for a, b in ((Z[:, 0::2], Z[:, 1::2]),          # z0 vs z1 of the same block
+                 (Z[:-1], Z[1:]),                      # adjacent rows
+                 (Z[:, :-2], Z[:, 2:])):               # adjacent blocks
+        c = np.corrcoef(a.ravel(), b.ravel())[0, 1]
+        assert abs(c) < 5 / np.sqrt(n)
+
+
+def test_streams_and_seeds_differ():
+    a = philox.gaussian(1, 1, 64, 64)
+    assert not np.array_equal(a, philox.gaussian(1, 2, 64, 64))
+    assert not np.array_equal(a, philox.gaussian(2, 1, 64, 64))
+    assert not np.array_equal(a, philox.gaussian(1 + (1 << 32), 1, 64, 64))
+
+
+def test_gaussian_prefix_stable_and_offsets():
+    big = philox.gaussian(99, philox.STREAM_Y, 300, 77)
+    assert np.array_equal(philox.gaussian(99, philox.STREAM_Y, 100, 50), big[:100, :50])
+    assert np.array_equal(philox.gaussian(99, philox.STREAM_Y, 40, 31, row0=17, col0=5),
+                          big[17:57, 5:36])
+
+
+def test_philox_avalanche_and_distinct():
+    c = np.arange(1 << 16, dtype=np.uint64)
+    w = np.stack(philox.philox4x32_10(c, 0, 0, 0, 42), -1)
+    flat = w.view(np.uint8).reshape(len(c), -1)
+    assert len(np.unique(flat, axis=0)) == len(c)
+    # flipping one counter bit changes about half of the 128 output bits
+    w2 = np.stack(philox.philox4x32_10(c ^ np.uint64(1 << 7), 0, 0, 0, 42), -1)
+    diff = np.unpackbits((w ^ w2).view(np.uint8)).reshape(len(c), -1).sum(1)
+    assert abs(diff.mean() - 64) < 1.0
+    bits = np.unpackbits(w.view(np.uint8))
+    assert abs(bits.mean() - 0.5) < 5 * 0.5 / np.sqrt(bits.size)
+
+
+def test_uniforms_in_range():
+    i = np.arange(4096, dtype=np.uint64)
+    w = philox.philox4x32_10(i, 3, 1, 0, 5)
+    z0, z1 = philox.box_muller(*w)
+    assert np.all(np.isfinite(z0)) and np.all(np.isfinite(z1))
+    # radius^2 = z0^2 + z1^2 is Exp(1/2)-distributed: mean 2
+    assert abs(np.mean(z0 ** 2 + z1 ** 2) - 2.0) < 0.2
+
+
+def test_bf16_rounding_ties_and_torch():
+    one = 1.0
+    ties = np.array([one + 2 ** -8, one + 3 * 2 ** -8, -(one + 2 ** -8), 3.0 + 2 ** -7])
+    expect = np.array([1.0, one + 2 ** -6, -1.0, 3.0])
+    assert np.array_equal(philox.round_bf16(ties), expect)
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    x32 = (rng.standard_normal(100000) * 10.0 ** rng.uniform(-8, 3, 100000)).astype(np.float32)
+    ref = torch.from_numpy(x32).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(philox.round_bf16_bits(x32.astype(np.float64)), ref)
+
+
+def test_srht_signs_balanced():
+    d = philox.srht_signs(3, 1 << 16)
+    assert set(np.unique(d)) == {-1, 1}
+    assert abs(d.astype(np.float64).mean()) < 5 / np.sqrt(d.size)
+    assert np.array_equal(philox.srht_signs(3, 1000), d[:1000])
+
+
+def test_srht_sample_distinct_sorted_prefix():
+    npad, r = 4096, 1000
+    idx = philox.srht_sample(11, npad, r)
+    assert len(np.unique(idx)) == r and idx.min() >= 0 and idx.max() < npad
+    keys = philox.srht_keys(11, npad)
+    assert np.all(np.diff(keys[idx].astype(np.float64)) >= 0)
+    assert np.all(keys[idx].max() <= np.delete(keys, idx).min())
+    assert np.array_equal(philox.srht_sample(11, npad, 300), idx[:300])
+
+
+def test_srht_matches_scipy_hadamard():
+    for n, r in ((64, 10), (100, 17), (512, 512)):
+        npad = philox.next_pow2(n)
+        H = sla.hadamard(npad).astype(np.float64)
+        d = philox.srht_signs(5, npad)[:n].astype(np.float64)
+        idx = philox.srht_sample(5, npad, r)
+        X = philox.srht_matrix(5, n, r)
+        assert np.array_equal(X, d[:, None] * H[:n, idx])
+    X = philox.srht_matrix(9, 256, 256)
+    assert np.array_equal(X.T @ X, 256.0 * np.eye(256))
