@@ -1,0 +1,220 @@
+/*
+ * gn.h -- C ABI of libgn, an MI355X (gfx950) library for generalized Nystrom
+ * (GN) low-rank approximation (Y. Nakatsukasa, "Fast and stable randomized
+ * low-rank matrix approximation", arXiv:2009.11392).
+ *
+ * GN approximates A (m x n) by  A_hat = AX (Y^T A X)_eps^+ Y^T A  with a sketch
+ * X (n x r) and an oversampled sketch Y (m x (r+l))  (Section 2, eqs. (3)-(4);
+ * Algorithm 2.1).  The library computes, on one GPU:
+ *   gn_generate_gaussian / gn_srht_generate  -- the random sketches,
+ *   gn_sketch     -- the single pass over A that forms AX and Y^T A,
+ *   gn_core       -- C = Y^T (AX), its Householder QR and the eps-truncation,
+ *   gn_factors / gn_apply -- the factored approximant and products with it,
+ *   gn_residual   -- ||A - F G||_F^2 formed tile by tile (error measurement),
+ *   gn_quantize_bf16_bs -- bfloat16 storage of A with power-of-two block scales.
+ *
+ * Conventions (every entry point):
+ *   * Pointers are device pointers unless marked (host).  All matrices are
+ *     row-major; "ld" arguments are row strides in elements.
+ *   * The caller owns every buffer, including the workspace `ws`; the library
+ *     never allocates or frees device memory and keeps no state between calls.
+ *   * Arguments are validated synchronously; on an error the call returns
+ *     before anything is enqueued.  Otherwise the work is enqueued on `stream`
+ *     and the call returns without synchronizing.  GN_ERR_HIP reports a failed
+ *     kernel launch.  Numeric conditions found on the device (a non-finite R
+ *     diagonal, kept rank 0) are reported through the device status word of
+ *     gn_core_out, never by aborting.
+ *   * Calls are reentrant; calls on different streams with disjoint buffers may
+ *     run concurrently.
+ */
+#ifndef GN_H_
+#define GN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* gn_stream_t; /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+  GN_OK = 0,
+  GN_ERR_ARG = 1,        /* null pointer, bad enum value, eps/nu not finite     */
+  GN_ERR_SHAPE = 2,      /* inconsistent m, n, r, l, ld                          */
+  GN_ERR_DTYPE = 3,      /* dtype not valid for this mode / entry point          */
+  GN_ERR_ALIGN = 4,      /* pointer not 16-byte aligned                          */
+  GN_ERR_WORKSPACE = 5,  /* ws too small (query gn_workspace_size)               */
+  GN_ERR_HIP = 6,        /* a HIP launch or runtime call failed                  */
+  GN_ERR_NUMERIC = 7,    /* (status word only) non-finite or rank-0 core         */
+  GN_ERR_UNSUPPORTED = 8 /* size beyond what this build handles                  */
+} gn_status;
+
+typedef enum { GN_SKETCH_GAUSSIAN = 0, GN_SKETCH_SRHT = 1, GN_SKETCH_USER = 2 } gn_sketch_kind;
+
+/* Storage / contraction precision of A, X, Y in the sketch pass.  The core
+ * (QR, truncation, triangular solves, products with the factors) is FP64 in
+ * every mode. */
+typedef enum {
+  GN_MODE_F64 = 0,     /* A, X, Y double; AX, Y^T A double (FP64 accumulation)      */
+  GN_MODE_F32 = 1,     /* A, X, Y float;  AX, Y^T A float  (FP32 accumulation)      */
+  GN_MODE_BF16_BS = 2  /* A bfloat16 with one float scale per 128x128 block,
+                          X, Y bfloat16; AX, Y^T A float (FP32 accumulation)        */
+} gn_mode;
+
+typedef enum { GN_DT_F64 = 0, GN_DT_F32 = 1, GN_DT_BF16 = 2 } gn_dtype;
+
+/* Problem statement (Algorithm 2.1 inputs: A's shape, r, l, eps, sketch type,
+ * seed).  l < 0 selects l = ceil(r/2) (Algorithm 2.1, step 1); l = 0 means no
+ * oversampling (the Nystrom and HMT special cases with USER sketches).  Requires
+ * 1 <= r <= min(m, n); r + l <= 4096 (core QR held on chip).  eps is absolute,
+ * in units of A (Section 2: eps = O(u ||A||)); the core keeps the leading k
+ * columns whose |R_ii| >= tau = eps * nu_x * nu_y, where nu_x, nu_y are the
+ * sketch norm scales (<= 0 selects sqrt(rows)+sqrt(cols) for a Gaussian and
+ * sqrt(n') for an SRHT; USER sketches should pass their own).  eps <= 0 means
+ * plain GN: no truncation unless a diagonal entry is zero or not finite. */
+typedef struct {
+  int64_t m, n, r, l;
+  int32_t kind_x;   /* gn_sketch_kind: GAUSSIAN, SRHT or USER             */
+  int32_t kind_y;   /* gn_sketch_kind: GAUSSIAN or USER                   */
+  uint64_t seed;    /* Philox4x32-10 key for X, Y and the SRHT            */
+  int32_t mode;     /* gn_mode                                            */
+  int32_t reserved; /* must be 0                                          */
+  double eps, nu_x, nu_y;
+} gn_problem;
+
+/* Output of gn_core.  k and status live in device memory so that nothing on
+ * the path synchronizes; read them back only when needed.
+ *   k      : kept rank, 0 <= k <= r (prefix of |R_ii| >= tau).
+ *   status : bit flags, 0 = fine.  1 = non-finite diagonal in R, 2 = k == 0
+ *            (both are GN_ERR_NUMERIC conditions), 4 = some |R_jj| >= tau after
+ *            the first diagonal below tau (diagnostic only: the QR was not
+ *            rank revealing there).
+ *   Q1     : (r+l) x r, ld r: Householder Q of C = Y^T (AX), columns scaled so
+ *            that R_ii >= 0.
+ *   R      : r x r, ld r: upper triangular R of C (strictly lower part zero).
+ *   Q2, R2 : r x r, ld r: when k < r, the QR factors of R[:k,:]^T
+ *            (Q2: first k columns; R2: upper k x k block, R2_ii >= 0), so that
+ *            the eps-pseudoinverse of C is Q2 R2^{-T} Q1[:, :k]^T
+ *            (Section 5.1.1; see the design notes for the transpose).  When
+ *            k == r they are left unchanged and unused. */
+typedef struct {
+  int32_t* k;
+  int32_t* status;
+  double* Q1;
+  double* R;
+  double* Q2;
+  double* R2;
+} gn_core_out;
+
+/* Operations for gn_workspace_size. */
+typedef enum {
+  GN_OP_SKETCH = 0,
+  GN_OP_CORE = 1,
+  GN_OP_FACTORS = 2,
+  GN_OP_APPLY = 3,     /* with kcols = the number of right-hand sides         */
+  GN_OP_RESIDUAL = 4,
+  GN_OP_SRHT = 5
+} gn_op;
+
+/* Bytes of device workspace the given operation needs for problem p.  For
+ * GN_OP_APPLY, kcols is the number of columns (side 0) or rows (side 1) of W;
+ * it is ignored otherwise. */
+gn_status gn_workspace_size(const gn_problem* p /*host*/, int32_t op, int64_t kcols,
+                            size_t* bytes /*host*/);
+
+/* Gaussian sketch block G[row0 + i, col0 + j] for 0 <= i < rows, 0 <= j < cols,
+ * i.i.d. N(0,1) (Section 3.1) from Philox4x32-10: element (i, j) of stream s
+ * takes the Box-Muller pair of the Philox block at counter (i, j >> 1, s, 0)
+ * with key (seed lo, seed hi), z0 for even j and z1 for odd j, computed in FP64
+ * and rounded to nearest-even into `dtype`.  layout 0 writes out[i*ld + j],
+ * layout 1 writes the transpose out[j*ld + i].  Streams: 1 = X, 2 = Y. */
+gn_status gn_generate_gaussian(uint64_t seed, int32_t stream, int64_t row0, int64_t col0,
+                               int64_t rows, int64_t cols, int32_t dtype, int32_t layout,
+                               void* out, int64_t ld, gn_stream_t stream_);
+
+/* SRHT sketch parameters (Section 1): X = the first n rows of D H S, with H the
+ * Sylvester-ordered Walsh-Hadamard matrix of order n' = next power of two >= n,
+ * D = diag(signs), S the r sampled columns.  signs (n' int8, +1/-1): the top bit
+ * of word (i & 3) of the Philox block at (i >> 2, 0, 3, 0).  idx (r int32): the
+ * columns with the r smallest 64-bit keys (key_j from words 2b, 2b+1, b = j & 1,
+ * of the block at (j >> 1, 0, 4, 0)), in ascending (key, j) order.  Needs
+ * gn_workspace_size(GN_OP_SRHT) bytes of ws.  n' <= 2^17, r <= n'. */
+gn_status gn_srht_generate(uint64_t seed, int64_t n, int64_t r, int8_t* signs, int32_t* idx,
+                           void* ws, size_t ws_bytes, gn_stream_t stream);
+
+/* The sketch pass (Algorithm 2.1, step 2): AX (m x r) and Y^T A ((r+l) x n)
+ * from A (m x n, row stride lda >= n).
+ *   A        : mode dtype (double, float, or bfloat16 bits for BF16_BS).
+ *   A_scales : BF16_BS only: float[ceil(m/128) * ceil(n/128)], row-major, the
+ *              scale of each 128 x 128 block (A = scale * stored value).
+ *   X_user   : kind_x == USER only: n x r in the mode's sketch dtype, ld ldx.
+ *   Y_user   : kind_y == USER only: m x (r+l) in the sketch dtype, ld ldy.
+ *   AX, YtA  : outputs in the accumulation dtype (double for F64, float else),
+ *              row strides ldax >= r and ldya >= n.
+ *   signs_out, idx_out : optional (may be NULL); SRHT parameters as in
+ *              gn_srht_generate.
+ * Generated sketches are drawn on the device from `seed` (streams 1 and 2).
+ * All pointers 16-byte aligned. */
+gn_status gn_sketch(const gn_problem* p, const void* A, int64_t lda, const float* A_scales,
+                    const void* X_user, int64_t ldx, const void* Y_user, int64_t ldy,
+                    void* AX, int64_t ldax, void* YtA, int64_t ldya, int8_t* signs_out,
+                    int32_t* idx_out, void* ws, size_t ws_bytes, gn_stream_t stream);
+
+/* The core (Algorithm 2.1 step 2 and Section 5.1.1): C = Y^T (AX) accumulated
+ * in FP64 (Y regenerated from the seed unless kind_y == USER), Householder QR
+ * C = Q R with R_ii >= 0, the kept rank k, and, when k < r, the QR of
+ * R[:k,:]^T.  AX as produced by gn_sketch (ld ldax). */
+gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void* Y_user,
+                  int64_t ldy, const gn_core_out* out /*host struct of device ptrs*/, void* ws,
+                  size_t ws_bytes, gn_stream_t stream);
+
+/* The factored approximant A_hat = F G in FP64 (Section 5.1, the stable order):
+ *   k == r : F = (AX) R^{-1} by triangular solves,  G = Q1^T (Y^T A)
+ *   k <  r : F = (AX Q2) R2^{-T},                   G = Q1[:, :k]^T (Y^T A)
+ * F is m x r (ld ldf), G is r x n (ld ldg); columns of F and rows of G beyond
+ * k are set to zero.  Forming F costs O(m r^2) (the paper advises it only for
+ * evaluation); use gn_apply for products. */
+gn_status gn_factors(const gn_problem* p, const void* AX, int64_t ldax, const void* YtA,
+                     int64_t ldya, const gn_core_out* core, double* F, int64_t ldf, double* G,
+                     int64_t ldg, void* ws, size_t ws_bytes, gn_stream_t stream);
+
+/* Products with the approximant in the order of Section 2 (after Alg. 2.1):
+ *   side 0: out (m x kcols, ld ldo) = A_hat W,  W n x kcols (ld ldw),
+ *           evaluated as AX (R^{-1} (Q^T (Y^T A W)));
+ *   side 1: out (kcols x n, ld ldo) = W A_hat,  W kcols x m (ld ldw),
+ *           evaluated as (((W AX) R^{-1}) Q^T) Y^T A.
+ * (with Q2 R2^{-T} in place of R^{-1} when k < r).  W and out are double. */
+gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ldax,
+                   const void* YtA, int64_t ldya, const gn_core_out* core, const double* W,
+                   int64_t ldw, int64_t kcols, double* out, int64_t ldo, void* ws,
+                   size_t ws_bytes, gn_stream_t stream);
+
+/* ||A - F G||_F^2 accumulated in FP64, tile by tile (no Gram-matrix shortcut),
+ * written to *out_sumsq (device double).  A is m x n in `a_dtype` (for
+ * GN_DT_BF16, A_scales as in gn_sketch, else NULL); F m x k (ld ldf), G k x n
+ * (ld ldg), both double.  The reduction order is fixed (deterministic). */
+gn_status gn_residual(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
+                      int32_t a_dtype, const float* A_scales, const double* F, int64_t ldf,
+                      const double* G, int64_t ldg, double* out_sumsq, void* ws,
+                      size_t ws_bytes, gn_stream_t stream);
+
+/* bfloat16 storage with power-of-two block scales: for each 128 x 128 block,
+ * s = 2^ceil(log2 max|a|) (1 for an all-zero block), out = RNE_bf16(a / s).
+ * A is m x n in a_dtype (GN_DT_F64 or GN_DT_F32); out is m x n bfloat16 bits
+ * (ld ldo); scales float[ceil(m/128) * ceil(n/128)]. */
+gn_status gn_quantize_bf16_bs(int64_t m, int64_t n, const void* A, int64_t lda, int32_t a_dtype,
+                              uint16_t* out, int64_t ldo, float* scales, gn_stream_t stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* gn_status_string(int32_t s);
+
+/* Library version, "major.minor.patch" (static storage). */
+const char* gn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GN_H_ */

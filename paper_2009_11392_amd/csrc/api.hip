@@ -1,0 +1,401 @@
+// libgn C ABI: argument validation, workspace layout and launch order.
+// Every entry point validates synchronously, then enqueues on the caller's
+// stream and returns without synchronizing.
+#include <math.h>
+
+#include "gn_internal.h"
+
+using namespace gn;
+
+namespace {
+
+constexpr int64_t kMaxCore = 4096;      // r + l: core QR held on chip
+constexpr int64_t kMaxSrhtPad = 1 << 17;  // n' for the SRHT column selection
+constexpr int64_t kMaxSrhtR = 2048;       // sampled columns per row in registers
+
+struct Plan {
+  int64_t m, n, r, l, rl, npad;
+  int32_t mode, kx, ky, sdt, adt;
+  double tau;
+};
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+gn_status make_plan(const gn_problem* p, Plan& P) {
+  if (!p) return GN_ERR_ARG;
+  if (p->reserved != 0) return GN_ERR_ARG;
+  if (p->mode < GN_MODE_F64 || p->mode > GN_MODE_BF16_BS) return GN_ERR_ARG;
+  if (p->kind_x < GN_SKETCH_GAUSSIAN || p->kind_x > GN_SKETCH_USER) return GN_ERR_ARG;
+  if (p->kind_y != GN_SKETCH_GAUSSIAN && p->kind_y != GN_SKETCH_USER) return GN_ERR_ARG;
+  if (!isfinite(p->eps) || !isfinite(p->nu_x) || !isfinite(p->nu_y)) return GN_ERR_ARG;
+  if (p->m < 1 || p->n < 1 || p->r < 1 || p->r > p->m || p->r > p->n) return GN_ERR_SHAPE;
+  if (p->m > INT32_MAX || p->n > INT32_MAX) return GN_ERR_UNSUPPORTED;
+  P.m = p->m;
+  P.n = p->n;
+  P.r = p->r;
+  P.l = (p->l < 0) ? (p->r + 1) / 2 : p->l;
+  P.rl = P.r + P.l;
+  if (P.rl > kMaxCore) return GN_ERR_UNSUPPORTED;
+  P.npad = next_pow2(P.n);
+  P.mode = p->mode;
+  P.kx = p->kind_x;
+  P.ky = p->kind_y;
+  P.sdt = sketch_dtype(p->mode);
+  P.adt = accum_dtype(p->mode);
+  if (P.kx == GN_SKETCH_SRHT && (P.npad > kMaxSrhtPad || P.r > kMaxSrhtR)) return GN_ERR_UNSUPPORTED;
+  double nux = p->nu_x, nuy = p->nu_y;
+  if (nux <= 0.0)
+    nux = (P.kx == GN_SKETCH_SRHT) ? sqrt((double)P.npad)
+          : (P.kx == GN_SKETCH_GAUSSIAN) ? sqrt((double)P.n) + sqrt((double)P.r)
+                                         : 1.0;
+  if (nuy <= 0.0)
+    nuy = (P.ky == GN_SKETCH_GAUSSIAN) ? sqrt((double)P.m) + sqrt((double)P.rl) : 1.0;
+  P.tau = (p->eps > 0.0) ? p->eps * nux * nuy : 0.0;
+  return GN_OK;
+}
+
+// ---- workspace layouts (offsets in bytes, each region 256-byte aligned)
+struct SketchWs {
+  size_t xt, yt, signs, idx, keys, total;
+};
+SketchWs sketch_ws(const Plan& P) {
+  SketchWs w{};
+  size_t off = 0;
+  const size_t es = dtype_size(P.sdt);
+  w.xt = off;
+  if (P.kx != GN_SKETCH_SRHT) off += align_up((size_t)P.r * P.n * es);
+  w.yt = off;
+  off += align_up((size_t)P.rl * P.m * es);
+  w.signs = off;
+  w.idx = off;
+  w.keys = off;
+  if (P.kx == GN_SKETCH_SRHT) {
+    w.signs = off;
+    off += align_up((size_t)P.npad);
+    w.idx = off;
+    off += align_up((size_t)P.r * 4);
+    w.keys = off;
+    off += srht_ws_bytes(P.npad);
+  }
+  w.total = off;
+  return w;
+}
+
+struct CoreWs {
+  size_t yt, c, qr, z, qr2, total;
+};
+CoreWs core_ws(const Plan& P) {
+  CoreWs w{};
+  size_t off = 0;
+  w.yt = off;
+  if (P.ky == GN_SKETCH_GAUSSIAN) off += align_up((size_t)P.rl * P.m * dtype_size(P.sdt));
+  w.c = off;
+  off += align_up((size_t)P.rl * P.r * 8);
+  w.qr = off;
+  off += qr_ws_bytes(P.rl, P.r);
+  w.z = off;
+  off += align_up((size_t)P.r * P.r * 8);
+  w.qr2 = off;
+  off += qr_ws_bytes(P.r, P.r);
+  w.total = off;
+  return w;
+}
+
+struct ApplyWs {
+  size_t t1, t2, t3, total;
+};
+ApplyWs apply_ws(const Plan& P, int64_t kc) {
+  ApplyWs w{};
+  const size_t blk = align_up((size_t)P.rl * (size_t)(kc > 0 ? kc : 1) * 8);
+  w.t1 = 0;
+  w.t2 = blk;
+  w.t3 = 2 * blk;
+  w.total = 3 * blk;
+  return w;
+}
+
+// copy (and widen) an m x r matrix of dtype dt into double, run only when the
+// gate says the core was not truncated.
+__global__ void __launch_bounds__(256) widen_gated(int64_t rows, int64_t cols, const void* src,
+                                                   int32_t dt, int64_t lds, double* dst,
+                                                   int64_t ldd, const int32_t* kdev, int64_t r) {
+  if (*kdev < r) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e / cols, j = e - i * cols;
+  double v;
+  if (dt == GN_DT_F64)
+    v = reinterpret_cast<const double*>(src)[i * lds + j];
+  else if (dt == GN_DT_F32)
+    v = (double)reinterpret_cast<const float*>(src)[i * lds + j];
+  else
+    v = (double)bf16_bits_to_f32(reinterpret_cast<const uint16_t*>(src)[i * lds + j]);
+  dst[i * ldd + j] = v;
+}
+
+gn_status widen(int64_t rows, int64_t cols, const void* src, int32_t dt, int64_t lds, double* dst,
+                int64_t ldd, const int32_t* kdev, int64_t r, hipStream_t s) {
+  widen_gated<<<dim3((unsigned)cdiv(rows * cols, 256)), dim3(256), 0, s>>>(rows, cols, src, dt, lds,
+                                                                           dst, ldd, kdev, r);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gn_version(void) { return "0.1.0"; }
+
+const char* gn_status_string(int32_t s) {
+  switch (s) {
+    case GN_OK: return "GN_OK";
+    case GN_ERR_ARG: return "GN_ERR_ARG: invalid argument";
+    case GN_ERR_SHAPE: return "GN_ERR_SHAPE: inconsistent shapes or leading dimensions";
+    case GN_ERR_DTYPE: return "GN_ERR_DTYPE: dtype not valid here";
+    case GN_ERR_ALIGN: return "GN_ERR_ALIGN: pointer not 16-byte aligned";
+    case GN_ERR_WORKSPACE: return "GN_ERR_WORKSPACE: workspace too small";
+    case GN_ERR_HIP: return "GN_ERR_HIP: HIP launch or runtime failure";
+    case GN_ERR_NUMERIC: return "GN_ERR_NUMERIC: non-finite or rank-0 core";
+    case GN_ERR_UNSUPPORTED: return "GN_ERR_UNSUPPORTED: size beyond this build's limits";
+    default: return "unknown gn_status";
+  }
+}
+
+gn_status gn_workspace_size(const gn_problem* p, int32_t op, int64_t kcols, size_t* bytes) {
+  if (!bytes) return GN_ERR_ARG;
+  Plan P;
+  GN_TRY(make_plan(p, P));
+  switch (op) {
+    case GN_OP_SKETCH: *bytes = sketch_ws(P).total; break;
+    case GN_OP_CORE: *bytes = core_ws(P).total; break;
+    case GN_OP_FACTORS: *bytes = 256; break;
+    case GN_OP_APPLY:
+      if (kcols < 1) return GN_ERR_SHAPE;
+      *bytes = apply_ws(P, kcols).total;
+      break;
+    case GN_OP_RESIDUAL: *bytes = residual_ws_bytes(P.m, P.n); break;
+    case GN_OP_SRHT: *bytes = srht_ws_bytes(P.npad); break;
+    default: return GN_ERR_ARG;
+  }
+  return GN_OK;
+}
+
+gn_status gn_generate_gaussian(uint64_t seed, int32_t stream, int64_t row0, int64_t col0,
+                               int64_t rows, int64_t cols, int32_t dtype, int32_t layout, void* out,
+                               int64_t ld, gn_stream_t stream_) {
+  if (!out) return GN_ERR_ARG;
+  if (dtype < GN_DT_F64 || dtype > GN_DT_BF16 || (layout != 0 && layout != 1)) return GN_ERR_ARG;
+  if (rows < 0 || cols < 0 || row0 < 0 || col0 < 0) return GN_ERR_SHAPE;
+  if (row0 + rows > ((int64_t)1 << 32) || ((col0 + cols) >> 1) > ((int64_t)1 << 32))
+    return GN_ERR_UNSUPPORTED;
+  if (layout == 0 ? (ld < cols) : (ld < rows)) return GN_ERR_SHAPE;
+  return launch_gaussian(seed, stream, row0, col0, rows, cols, dtype, layout, out, ld,
+                         (hipStream_t)stream_);
+}
+
+gn_status gn_srht_generate(uint64_t seed, int64_t n, int64_t r, int8_t* signs, int32_t* idx,
+                           void* ws, size_t ws_bytes, gn_stream_t stream) {
+  if (!signs || !idx || !ws) return GN_ERR_ARG;
+  if (n < 1 || r < 1) return GN_ERR_SHAPE;
+  const int64_t npad = next_pow2(n);
+  if (r > npad) return GN_ERR_SHAPE;
+  if (npad > kMaxSrhtPad) return GN_ERR_UNSUPPORTED;
+  if (ws_bytes < srht_ws_bytes(npad)) return GN_ERR_WORKSPACE;
+  if (((uintptr_t)ws & 7u) != 0) return GN_ERR_ALIGN;
+  return launch_srht(seed, npad, r, signs, idx, (uint64_t*)ws, (hipStream_t)stream);
+}
+
+gn_status gn_sketch(const gn_problem* p, const void* A, int64_t lda, const float* A_scales,
+                    const void* X_user, int64_t ldx, const void* Y_user, int64_t ldy, void* AX,
+                    int64_t ldax, void* YtA, int64_t ldya, int8_t* signs_out, int32_t* idx_out,
+                    void* ws, size_t ws_bytes, gn_stream_t stream_) {
+  Plan P;
+  GN_TRY(make_plan(p, P));
+  hipStream_t s = (hipStream_t)stream_;
+  if (!A || !AX || !YtA || !ws) return GN_ERR_ARG;
+  if (P.mode == GN_MODE_BF16_BS && !A_scales) return GN_ERR_ARG;
+  if (P.kx == GN_SKETCH_USER && !X_user) return GN_ERR_ARG;
+  if (P.ky == GN_SKETCH_USER && !Y_user) return GN_ERR_ARG;
+  if (lda < P.n || ldax < P.r || ldya < P.n) return GN_ERR_SHAPE;
+  if (P.kx == GN_SKETCH_USER && ldx < P.r) return GN_ERR_SHAPE;
+  if (P.ky == GN_SKETCH_USER && ldy < P.rl) return GN_ERR_SHAPE;
+  if (!aligned16(A) || !aligned16(AX) || !aligned16(YtA) || !aligned16(ws)) return GN_ERR_ALIGN;
+  const SketchWs W = sketch_ws(P);
+  if (ws_bytes < W.total) return GN_ERR_WORKSPACE;
+  char* base = (char*)ws;
+  void* Xt = base + W.xt;
+  void* Yt = base + W.yt;
+
+  // sketches (Algorithm 2.1, step 1)
+  if (P.ky == GN_SKETCH_GAUSSIAN)
+    GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, P.sdt, 1, Yt, P.m, s));
+  else
+    GN_TRY(launch_transpose(Y_user, P.m, P.rl, ldy, P.sdt, Yt, P.m, s));
+  if (P.kx == GN_SKETCH_GAUSSIAN)
+    GN_TRY(launch_gaussian(p->seed, 1, 0, 0, P.n, P.r, P.sdt, 1, Xt, P.n, s));
+  else if (P.kx == GN_SKETCH_USER)
+    GN_TRY(launch_transpose(X_user, P.n, P.r, ldx, P.sdt, Xt, P.n, s));
+
+  // the pass (Algorithm 2.1, step 2)
+  if (P.kx == GN_SKETCH_SRHT) {
+    int8_t* signs = (int8_t*)(base + W.signs);
+    int32_t* idx = (int32_t*)(base + W.idx);
+    GN_TRY(launch_srht(p->seed, P.npad, P.r, signs, idx, (uint64_t*)(base + W.keys), s));
+    GN_TRY(launch_pass_srht(P.mode, P.m, P.n, P.r, A, lda, A_scales, signs, idx, AX, ldax, s));
+    if (signs_out && hipMemcpyAsync(signs_out, signs, (size_t)P.npad, hipMemcpyDeviceToDevice, s) !=
+                         hipSuccess)
+      return GN_ERR_HIP;
+    if (idx_out && hipMemcpyAsync(idx_out, idx, (size_t)P.r * 4, hipMemcpyDeviceToDevice, s) !=
+                       hipSuccess)
+      return GN_ERR_HIP;
+  } else {
+    GN_TRY(launch_pass_ax(P.mode, P.m, P.n, P.r, A, lda, A_scales, Xt, P.n, AX, ldax, s));
+  }
+  GN_TRY(launch_pass_yta(P.mode, P.m, P.n, P.rl, A, lda, A_scales, Yt, P.m, YtA, ldya, s));
+  return GN_OK;
+}
+
+gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void* Y_user, int64_t ldy,
+                  const gn_core_out* out, void* ws, size_t ws_bytes, gn_stream_t stream_) {
+  Plan P;
+  GN_TRY(make_plan(p, P));
+  hipStream_t s = (hipStream_t)stream_;
+  if (!AX || !out || !ws || !out->k || !out->status || !out->Q1 || !out->R || !out->Q2 || !out->R2)
+    return GN_ERR_ARG;
+  if (P.ky == GN_SKETCH_USER && !Y_user) return GN_ERR_ARG;
+  if (ldax < P.r) return GN_ERR_SHAPE;
+  if (P.ky == GN_SKETCH_USER && ldy < P.rl) return GN_ERR_SHAPE;
+  if (!aligned16(AX) || !aligned16(ws)) return GN_ERR_ALIGN;
+  const CoreWs W = core_ws(P);
+  if (ws_bytes < W.total) return GN_ERR_WORKSPACE;
+  char* base = (char*)ws;
+  double* C = (double*)(base + W.c);
+  double* Z = (double*)(base + W.z);
+
+  // C = Y^T (AX) in FP64 (the order of the Section 5.1 evaluation)
+  MatRef yt;
+  if (P.ky == GN_SKETCH_GAUSSIAN) {
+    void* Yt = base + W.yt;
+    GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, P.sdt, 1, Yt, P.m, s));
+    yt = MatRef{Yt, P.sdt, P.m, 1};
+  } else {
+    yt = MatRef{Y_user, P.sdt, 1, ldy};  // Y^T(c, i) = Y[i*ldy + c]
+  }
+  MatRef ax{AX, P.adt, ldax, 1};
+  GN_TRY(launch_dgemm(P.rl, P.r, P.m, 1.0, yt, ax, 0.0, C, P.r, 1, nullptr, false, s));
+  // Householder QR, kept rank, and the second QR when truncated
+  GN_TRY(launch_qr(P.rl, P.r, C, P.r, out->Q1, P.r, out->R, P.r, (double*)(base + W.qr), nullptr, s));
+  GN_TRY(launch_truncate(P.r, out->R, P.r, P.tau, out->k, out->status, Z, P.r, s));
+  GN_TRY(launch_qr(P.r, P.r, Z, P.r, out->Q2, P.r, out->R2, P.r, (double*)(base + W.qr2), out->k, s));
+  return GN_OK;
+}
+
+gn_status gn_factors(const gn_problem* p, const void* AX, int64_t ldax, const void* YtA,
+                     int64_t ldya, const gn_core_out* core, double* F, int64_t ldf, double* G,
+                     int64_t ldg, void* ws, size_t ws_bytes, gn_stream_t stream_) {
+  Plan P;
+  GN_TRY(make_plan(p, P));
+  hipStream_t s = (hipStream_t)stream_;
+  (void)ws;
+  (void)ws_bytes;
+  if (!AX || !YtA || !core || !F || !G || !core->k || !core->Q1 || !core->R || !core->Q2 || !core->R2)
+    return GN_ERR_ARG;
+  if (ldax < P.r || ldya < P.n || ldf < P.r || ldg < P.n) return GN_ERR_SHAPE;
+  // F = AX R^{-1}  or  (AX Q2) R2^{-T}
+  GN_TRY(widen(P.m, P.r, AX, P.adt, ldax, F, ldf, core->k, P.r, s));
+  MatRef ax{AX, P.adt, ldax, 1};
+  MatRef q2{core->Q2, GN_DT_F64, P.r, 1};
+  GN_TRY(launch_dgemm(P.m, P.r, P.r, 1.0, ax, q2, 0.0, F, ldf, 1, nullptr, false, s, core->k, P.r,
+                      true));
+  GN_TRY(launch_trsm_core(P.m, P.r, core->R, core->R2, P.r, core->k, F, ldf, 1, false, true, s));
+  // G = Q1[:, :k]^T (Y^T A), rows >= k zero
+  MatRef q1t{core->Q1, GN_DT_F64, 1, P.r};
+  MatRef yta{YtA, P.adt, ldya, 1};
+  GN_TRY(launch_dgemm(P.r, P.n, P.rl, 1.0, q1t, yta, 0.0, G, ldg, 1, core->k, true, s));
+  return GN_OK;
+}
+
+gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ldax, const void* YtA,
+                   int64_t ldya, const gn_core_out* core, const double* W, int64_t ldw, int64_t kc,
+                   double* out, int64_t ldo, void* ws, size_t ws_bytes, gn_stream_t stream_) {
+  Plan P;
+  GN_TRY(make_plan(p, P));
+  hipStream_t s = (hipStream_t)stream_;
+  if (!AX || !YtA || !core || !W || !out || !ws || !core->k || !core->Q1 || !core->R || !core->Q2 ||
+      !core->R2)
+    return GN_ERR_ARG;
+  if (side != 0 && side != 1) return GN_ERR_ARG;
+  if (kc < 1) return GN_ERR_SHAPE;
+  if (ldax < P.r || ldya < P.n) return GN_ERR_SHAPE;
+  if (side == 0 && (ldw < kc || ldo < kc)) return GN_ERR_SHAPE;
+  if (side == 1 && (ldw < P.m || ldo < P.n)) return GN_ERR_SHAPE;
+  const ApplyWs Wl = apply_ws(P, kc);
+  if (ws_bytes < Wl.total) return GN_ERR_WORKSPACE;
+  char* base = (char*)ws;
+  double* t1 = (double*)(base + Wl.t1);
+  double* t2 = (double*)(base + Wl.t2);
+  double* t3 = (double*)(base + Wl.t3);
+  MatRef ax{AX, P.adt, ldax, 1};
+  MatRef yta{YtA, P.adt, ldya, 1};
+  if (side == 0) {
+    // t1 = (Y^T A) W : rl x kc
+    GN_TRY(launch_dgemm(P.rl, kc, P.n, 1.0, yta, MatRef{W, GN_DT_F64, ldw, 1}, 0.0, t1, kc, 1,
+                        nullptr, false, s));
+    // t2 = Q1[:, :k]^T t1 : r x kc (rows >= k zero)
+    GN_TRY(launch_dgemm(P.r, kc, P.rl, 1.0, MatRef{core->Q1, GN_DT_F64, 1, P.r},
+                        MatRef{t1, GN_DT_F64, kc, 1}, 0.0, t2, kc, 1, core->k, true, s));
+    // t2 <- R^{-1} t2  or  R2^{-T} t2   (left solve on the transposed view)
+    GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, 1, kc, true, true, s));
+    // t3 = t2 (k == r)  or  Q2 t2 (k < r)
+    GN_TRY(widen(P.r, kc, t2, GN_DT_F64, kc, t3, kc, core->k, P.r, s));
+    GN_TRY(launch_dgemm(P.r, kc, P.r, 1.0, MatRef{core->Q2, GN_DT_F64, P.r, 1},
+                        MatRef{t2, GN_DT_F64, kc, 1}, 0.0, t3, kc, 1, nullptr, false, s, core->k,
+                        P.r, true));
+    // out = AX t3 : m x kc
+    GN_TRY(launch_dgemm(P.m, kc, P.r, 1.0, ax, MatRef{t3, GN_DT_F64, kc, 1}, 0.0, out, ldo, 1,
+                        nullptr, false, s));
+  } else {
+    // t1 = W AX : kc x r
+    GN_TRY(launch_dgemm(kc, P.r, P.m, 1.0, MatRef{W, GN_DT_F64, ldw, 1}, ax, 0.0, t1, P.r, 1,
+                        nullptr, false, s));
+    // t2 = t1 (k == r)  or  t1 Q2 (k < r); then t2 <- t2 R^{-1}  or  t2 R2^{-T}
+    GN_TRY(widen(kc, P.r, t1, GN_DT_F64, P.r, t2, P.r, core->k, P.r, s));
+    GN_TRY(launch_dgemm(kc, P.r, P.r, 1.0, MatRef{t1, GN_DT_F64, P.r, 1},
+                        MatRef{core->Q2, GN_DT_F64, P.r, 1}, 0.0, t2, P.r, 1, nullptr, false, s,
+                        core->k, P.r, true));
+    GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, P.r, 1, false, true, s));
+    // t3 = t2 Q1^T : kc x rl   (columns of t2 beyond k are zero)
+    GN_TRY(launch_dgemm(kc, P.rl, P.r, 1.0, MatRef{t2, GN_DT_F64, P.r, 1},
+                        MatRef{core->Q1, GN_DT_F64, 1, P.r}, 0.0, t3, P.rl, 1, nullptr, false, s));
+    // out = t3 (Y^T A) : kc x n
+    GN_TRY(launch_dgemm(kc, P.n, P.rl, 1.0, MatRef{t3, GN_DT_F64, P.rl, 1}, yta, 0.0, out, ldo, 1,
+                        nullptr, false, s));
+  }
+  return GN_OK;
+}
+
+gn_status gn_residual(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, int32_t a_dtype,
+                      const float* A_scales, const double* F, int64_t ldf, const double* G,
+                      int64_t ldg, double* out_sumsq, void* ws, size_t ws_bytes,
+                      gn_stream_t stream_) {
+  if (!A || !F || !G || !out_sumsq || !ws) return GN_ERR_ARG;
+  if (a_dtype < GN_DT_F64 || a_dtype > GN_DT_BF16) return GN_ERR_ARG;
+  if (a_dtype == GN_DT_BF16 && !A_scales) return GN_ERR_ARG;
+  if (m < 1 || n < 1 || k < 0 || lda < n || ldf < k || ldg < n) return GN_ERR_SHAPE;
+  if (ws_bytes < residual_ws_bytes(m, n)) return GN_ERR_WORKSPACE;
+  if (((uintptr_t)ws & 7u) != 0) return GN_ERR_ALIGN;
+  return launch_residual(m, n, k, MatRef{A, a_dtype, lda, 1}, A_scales, MatRef{F, GN_DT_F64, ldf, 1},
+                         MatRef{G, GN_DT_F64, ldg, 1}, (double*)ws, out_sumsq,
+                         (hipStream_t)stream_);
+}
+
+gn_status gn_quantize_bf16_bs(int64_t m, int64_t n, const void* A, int64_t lda, int32_t a_dtype,
+                              uint16_t* out, int64_t ldo, float* scales, gn_stream_t stream) {
+  if (!A || !out || !scales) return GN_ERR_ARG;
+  if (a_dtype != GN_DT_F64 && a_dtype != GN_DT_F32) return GN_ERR_DTYPE;
+  if (m < 1 || n < 1 || lda < n || ldo < n) return GN_ERR_SHAPE;
+  return launch_quantize(m, n, A, lda, a_dtype, out, ldo, scales, (hipStream_t)stream);
+}
+
+}  // extern "C"

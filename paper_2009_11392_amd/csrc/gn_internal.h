@@ -1,0 +1,175 @@
+// Internal declarations shared by the libgn HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/gn.h"
+
+namespace gn {
+
+// ---------------------------------------------------------------------------- errors
+#define GN_LAUNCH_CHECK()                                 \
+  do {                                                    \
+    if (hipGetLastError() != hipSuccess) return GN_ERR_HIP; \
+  } while (0)
+
+#define GN_TRY(expr)                 \
+  do {                               \
+    gn_status s_ = (expr);           \
+    if (s_ != GN_OK) return s_;      \
+  } while (0)
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------- Philox4x32-10
+// Counter-based generator of Salmon et al. (SC'11): ten rounds of two 32x32->64
+// multiplies with Weyl-sequence key increments between rounds.
+struct U4 {
+  uint32_t a, b, c, d;
+};
+
+__device__ __forceinline__ U4 philox10(U4 ctr, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t lo0 = 0xD2511F53u * ctr.a;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, ctr.a);
+    const uint32_t lo1 = 0xCD9E8D57u * ctr.c;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, ctr.c);
+    ctr = U4{hi1 ^ ctr.b ^ k0, lo1, hi0 ^ ctr.d ^ k1, lo0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return ctr;
+}
+
+// Two standard normals from one Philox block: 53-bit uniforms u1 in (0,1],
+// u2 in [0,1) and the Box-Muller map, all in double precision.
+__device__ __forceinline__ void normal_pair(U4 w, double& z0, double& z1) {
+  const uint64_t ka = ((uint64_t)(w.a >> 5) << 26) | (uint64_t)(w.b >> 6);
+  const uint64_t kb = ((uint64_t)(w.c >> 5) << 26) | (uint64_t)(w.d >> 6);
+  const double u1 = 1.0 - (double)ka * 0x1.0p-53;
+  const double u2 = (double)kb * 0x1.0p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  const double theta = 6.283185307179586 * u2;
+  z0 = rad * cos(theta);
+  z1 = rad * sin(theta);
+}
+
+// ---------------------------------------------------------------------------- bfloat16
+// Round a double to bfloat16 (8 significant bits) to nearest, ties to even,
+// straight from the FP64 bit pattern.  Valid for zero and for magnitudes in the
+// bfloat16 normal range (all values this library rounds).
+__device__ __forceinline__ uint16_t f64_to_bf16_bits(double x) {
+  uint64_t u = (uint64_t)__double_as_longlong(x);
+  const uint64_t keep_lsb = (u >> 45) & 1ull;
+  u += (1ull << 44) - 1ull + keep_lsb;
+  u &= ~((1ull << 45) - 1ull);
+  const float f = (float)__longlong_as_double((long long)u);  // exact
+  return (uint16_t)(__float_as_uint(f) >> 16);
+}
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
+  return __uint_as_float((uint32_t)b << 16);
+}
+
+// ---------------------------------------------------------------------------- element traits
+template <typename T>
+__device__ __forceinline__ double to_f64(T v);
+template <>
+__device__ __forceinline__ double to_f64<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ double to_f64<float>(float v) { return (double)v; }
+template <>
+__device__ __forceinline__ double to_f64<uint16_t>(uint16_t v) { return (double)bf16_bits_to_f32(v); }
+
+inline size_t dtype_size(int32_t dt) { return dt == GN_DT_F64 ? 8 : (dt == GN_DT_F32 ? 4 : 2); }
+inline int32_t sketch_dtype(int32_t mode) {
+  return mode == GN_MODE_F64 ? GN_DT_F64 : (mode == GN_MODE_F32 ? GN_DT_F32 : GN_DT_BF16);
+}
+inline int32_t accum_dtype(int32_t mode) { return mode == GN_MODE_F64 ? GN_DT_F64 : GN_DT_F32; }
+
+inline int64_t next_pow2(int64_t n) {
+  int64_t p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// ---------------------------------------------------------------------------- launchers
+// sketch_gen.hip
+gn_status launch_gaussian(uint64_t seed, int32_t stream_id, int64_t row0, int64_t col0,
+                          int64_t rows, int64_t cols, int32_t dtype, int32_t layout, void* out,
+                          int64_t ld, hipStream_t s);
+gn_status launch_srht(uint64_t seed, int64_t npad, int64_t r, int8_t* signs, int32_t* idx,
+                      uint64_t* keys_ws, hipStream_t s);
+gn_status launch_transpose(const void* in, int64_t rows, int64_t cols, int64_t ldi, int32_t dtype,
+                           void* out, int64_t ldo, hipStream_t s);
+size_t srht_ws_bytes(int64_t npad);
+
+// pass.hip : sketch-pass contractions and the SRHT transform
+// AX (m x r) = A (m x n) * Xt^T, with Xt (r x n) the transposed sketch.
+gn_status launch_pass_ax(int32_t mode, int64_t m, int64_t n, int64_t r, const void* A, int64_t lda,
+                         const float* scales, const void* Xt, int64_t ldxt, void* AX, int64_t ldax,
+                         hipStream_t s);
+// YtA ((r+l) x n) = Yt ((r+l) x m) * A (m x n).
+gn_status launch_pass_yta(int32_t mode, int64_t m, int64_t n, int64_t rl, const void* A,
+                          int64_t lda, const float* scales, const void* Yt, int64_t ldyt, void* YtA,
+                          int64_t ldya, hipStream_t s);
+// AX = A * (D H S): FWHT of sign-flipped rows of A, then sampling.
+gn_status launch_pass_srht(int32_t mode, int64_t m, int64_t n, int64_t r, const void* A, int64_t lda,
+                           const float* scales, const int8_t* signs, const int32_t* idx, void* AX,
+                           int64_t ldax, hipStream_t s);
+
+// dgemm.hip : FP64 strided GEMM  D = alpha * op(A) op(B) + beta * D
+struct MatRef {
+  const void* p;
+  int32_t dtype;   // gn_dtype of the stored elements
+  int64_t rs, cs;  // element (i, j) at p[i*rs + j*cs]
+};
+// kmask: when non-null, rows (mask_rows) or columns (!mask_rows) of D with index
+// >= *kmask are written as zero (used to zero factors beyond the kept rank).
+// gate: when non-null the kernel does nothing unless (*gate < gate_n) == gate_trunc
+// (launches that only matter for a truncated / untruncated core).
+gn_status launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, MatRef A, MatRef B,
+                       double beta, double* D, int64_t rsd, int64_t csd, const int32_t* kmask,
+                       bool mask_rows, hipStream_t s, const int32_t* gate = nullptr,
+                       int64_t gate_n = 0, bool gate_trunc = true);
+// Per-tile sums of (Ref - A*B)^2 written to partial[], then reduced in fixed order.
+gn_status launch_residual(int64_t M, int64_t N, int64_t K, MatRef Ref, const float* ref_scales,
+                          MatRef A, MatRef B, double* partial, double* out, hipStream_t s);
+size_t residual_ws_bytes(int64_t M, int64_t N);
+
+// qr.hip : Householder QR of an M x N FP64 matrix (M >= N, M <= 4096), in place.
+// On exit the upper triangle holds R (R_ii >= 0 after the sign fix) and Q
+// (M x N, ld ldq) holds the explicit orthonormal factor.  When gate_k is
+// non-null, every kernel returns immediately unless *gate_k < N (used for the
+// second QR, which is only needed when the core is truncated).
+gn_status launch_qr(int64_t M, int64_t N, double* Aq, int64_t lda, double* Q, int64_t ldq,
+                    double* R, int64_t ldr, double* ws, const int32_t* gate_k, hipStream_t s);
+size_t qr_ws_bytes(int64_t M, int64_t N);
+// k = prefix count of |R_ii| >= tau; status flags; builds R[:k,:]^T (r x r,
+// zero beyond column k) in Z.
+gn_status launch_truncate(int64_t r, const double* R, int64_t ldr, double tau, int32_t* k,
+                          int32_t* status, double* Z, int64_t ldz, hipStream_t s);
+
+// trsm.hip : right-side triangular solves with the kept-rank factor.
+// Solves Xo * T = B for Xo (rows x r) where T = R (upper, when *k == r) or
+// T = R2^T (lower, when *k < r, only the leading k columns); columns >= k of
+// Xo are zero.  B and Xo may alias.  side handled by strides.
+// left = false: X T = B with T = R (k == r) or T = R2^T (k < r): X = B R^{-1} or
+//               B R2^{-T}  (right-side products with the core pseudoinverse).
+// left = true : X T = B with T = R^T (k == r) or T = R2 (k < r): the transpose
+//               of R^{-1} B^T or R2^{-T} B^T (left-side products), on a
+//               transposed view of the data.
+// Columns >= k of X are zeroed when k < r.  Solved in place on X (rows x r).
+gn_status launch_trsm_core(int64_t rows, int64_t r, const double* R, const double* R2, int64_t ldt,
+                           const int32_t* k, double* X, int64_t rsx, int64_t csx, bool left,
+                           bool maybe_trunc, hipStream_t s);
+
+// quant.hip
+gn_status launch_quantize(int64_t m, int64_t n, const void* A, int64_t lda, int32_t dtype,
+                          uint16_t* out, int64_t ldo, float* scales, hipStream_t s);
+
+}  // namespace gn

@@ -1,0 +1,175 @@
+// On-device sketch generators: Philox4x32-10 Gaussians and SRHT signs / column
+// sample (Section 1 and Section 3.1 of the paper: i.i.d. N(0,1) sketches, or the
+// subsampled randomized Hadamard transform).
+#include "gn_internal.h"
+
+namespace gn {
+namespace {
+
+template <int DT>
+__device__ __forceinline__ void store_elem(void* out, int64_t off, double z) {
+  if constexpr (DT == GN_DT_F64) {
+    reinterpret_cast<double*>(out)[off] = z;
+  } else if constexpr (DT == GN_DT_F32) {
+    reinterpret_cast<float*>(out)[off] = __double2float_rn(z);
+  } else {
+    reinterpret_cast<uint16_t*>(out)[off] = f64_to_bf16_bits(z);
+  }
+}
+
+// Row-major output: consecutive threads take consecutive column pairs.
+template <int DT>
+__global__ void __launch_bounds__(256) gaussian_rowmajor(uint32_t k0, uint32_t k1, uint32_t sid,
+                                                         int64_t row0, int64_t col0, int64_t rows,
+                                                         int64_t cols, int64_t pair0, int64_t npairs,
+                                                         void* out, int64_t ld) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * npairs) return;
+  const int64_t i = t / npairs;
+  const int64_t p = pair0 + (t - i * npairs);
+  const U4 w = philox10(U4{(uint32_t)(row0 + i), (uint32_t)p, sid, 0u}, k0, k1);
+  double z[2];
+  normal_pair(w, z[0], z[1]);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int64_t j = 2 * p + e - col0;
+    if (j >= 0 && j < cols) store_elem<DT>(out, i * ld + j, z[e]);
+  }
+}
+
+// Transposed output out[j*ld + i]: consecutive threads take consecutive rows.
+template <int DT>
+__global__ void __launch_bounds__(256) gaussian_transposed(uint32_t k0, uint32_t k1, uint32_t sid,
+                                                           int64_t row0, int64_t col0, int64_t rows,
+                                                           int64_t cols, int64_t pair0,
+                                                           int64_t npairs, void* out, int64_t ld) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * npairs) return;
+  const int64_t pl = t / rows;
+  const int64_t i = t - pl * rows;
+  const int64_t p = pair0 + pl;
+  const U4 w = philox10(U4{(uint32_t)(row0 + i), (uint32_t)p, sid, 0u}, k0, k1);
+  double z[2];
+  normal_pair(w, z[0], z[1]);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int64_t j = 2 * p + e - col0;
+    if (j >= 0 && j < cols) store_elem<DT>(out, j * ld + i, z[e]);
+  }
+}
+
+__global__ void __launch_bounds__(256) srht_signs_keys(uint32_t k0, uint32_t k1, int64_t npad,
+                                                       int8_t* signs, uint64_t* keys) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= npad) return;
+  // sign: top bit of word (j & 3) of block (j >> 2, 0, 3, 0)
+  const U4 ws = philox10(U4{(uint32_t)(j >> 2), 0u, 3u, 0u}, k0, k1);
+  const uint32_t wsel[4] = {ws.a, ws.b, ws.c, ws.d};
+  signs[j] = (wsel[j & 3] >> 31) ? (int8_t)-1 : (int8_t)1;
+  // key: words (2b, 2b+1), b = j & 1, of block (j >> 1, 0, 4, 0)
+  const U4 wk = philox10(U4{(uint32_t)(j >> 1), 0u, 4u, 0u}, k0, k1);
+  const uint32_t hi = (j & 1) ? wk.c : wk.a;
+  const uint32_t lo = (j & 1) ? wk.d : wk.b;
+  keys[j] = ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
+// Rank of each key among all npad keys (ties broken by index); the keys of
+// rank < r give idx[rank] = j.  O(npad^2) comparisons, staged through LDS.
+constexpr int kSelTile = 1024;
+__global__ void __launch_bounds__(256) srht_select(const uint64_t* keys, int64_t npad, int64_t r,
+                                                   int32_t* idx) {
+  __shared__ uint64_t tile[kSelTile];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t kj = (j < npad) ? keys[j] : ~0ull;
+  int64_t rank = 0;
+  for (int64_t t0 = 0; t0 < npad; t0 += kSelTile) {
+    const int64_t len = (npad - t0 < kSelTile) ? (npad - t0) : kSelTile;
+    __syncthreads();
+    for (int q = threadIdx.x; q < len; q += blockDim.x) tile[q] = keys[t0 + q];
+    __syncthreads();
+    for (int q = 0; q < len; ++q) {
+      const uint64_t ki = tile[q];
+      rank += (ki < kj) || (ki == kj && (t0 + q) < j);
+    }
+  }
+  if (j < npad && rank < r) idx[rank] = (int32_t)j;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) transpose_kernel(const T* in, int64_t rows, int64_t cols,
+                                                        int64_t ldi, T* out, int64_t ldo) {
+  __shared__ T tile[32][33];
+  const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t rr = r0 + y, cc = c0 + tx;
+    if (rr < rows && cc < cols) tile[y][tx] = in[rr * ldi + cc];
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t cc = c0 + y, rr = r0 + tx;
+    if (rr < rows && cc < cols) out[cc * ldo + rr] = tile[tx][y];
+  }
+}
+
+}  // namespace
+
+gn_status launch_gaussian(uint64_t seed, int32_t sid, int64_t row0, int64_t col0, int64_t rows,
+                          int64_t cols, int32_t dtype, int32_t layout, void* out, int64_t ld,
+                          hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return GN_OK;
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  const int64_t pair0 = col0 >> 1, pair1 = (col0 + cols - 1) >> 1;
+  const int64_t npairs = pair1 - pair0 + 1;
+  const int64_t total = rows * npairs;
+  const dim3 grid((unsigned)cdiv(total, 256)), block(256);
+#define GN_GAUSS(DT)                                                                       \
+  if (layout == 0)                                                                         \
+    gaussian_rowmajor<DT><<<grid, block, 0, s>>>(k0, k1, (uint32_t)sid, row0, col0, rows,  \
+                                                 cols, pair0, npairs, out, ld);            \
+  else                                                                                     \
+    gaussian_transposed<DT><<<grid, block, 0, s>>>(k0, k1, (uint32_t)sid, row0, col0, rows, \
+                                                   cols, pair0, npairs, out, ld);
+  if (dtype == GN_DT_F64) {
+    GN_GAUSS(GN_DT_F64)
+  } else if (dtype == GN_DT_F32) {
+    GN_GAUSS(GN_DT_F32)
+  } else {
+    GN_GAUSS(GN_DT_BF16)
+  }
+#undef GN_GAUSS
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+size_t srht_ws_bytes(int64_t npad) { return align_up((size_t)npad * sizeof(uint64_t)); }
+
+gn_status launch_srht(uint64_t seed, int64_t npad, int64_t r, int8_t* signs, int32_t* idx,
+                      uint64_t* keys_ws, hipStream_t s) {
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  const dim3 grid((unsigned)cdiv(npad, 256)), block(256);
+  srht_signs_keys<<<grid, block, 0, s>>>(k0, k1, npad, signs, keys_ws);
+  GN_LAUNCH_CHECK();
+  srht_select<<<grid, block, 0, s>>>(keys_ws, npad, r, idx);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+gn_status launch_transpose(const void* in, int64_t rows, int64_t cols, int64_t ldi, int32_t dtype,
+                           void* out, int64_t ldo, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return GN_OK;
+  const dim3 grid((unsigned)cdiv(cols, 32), (unsigned)cdiv(rows, 32)), block(256);
+  if (dtype == GN_DT_F64)
+    transpose_kernel<double><<<grid, block, 0, s>>>((const double*)in, rows, cols, ldi,
+                                                    (double*)out, ldo);
+  else if (dtype == GN_DT_F32)
+    transpose_kernel<float><<<grid, block, 0, s>>>((const float*)in, rows, cols, ldi,
+                                                   (float*)out, ldo);
+  else
+    transpose_kernel<uint16_t><<<grid, block, 0, s>>>((const uint16_t*)in, rows, cols, ldi,
+                                                      (uint16_t*)out, ldo);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+}  // namespace gn

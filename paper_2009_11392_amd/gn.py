@@ -1,0 +1,214 @@
+"""Python binding of libgn: the C entry points with the same names, taking torch
+tensors for device memory and torch's current HIP stream.  Argument marshalling
+only: every step of the computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _capi as C
+from ._capi import GNError  # noqa: F401  (re-export)
+
+MODES = {"f64": C.GN_MODE_F64, "f32": C.GN_MODE_F32, "bf16": C.GN_MODE_BF16_BS}
+KINDS = {"gaussian": C.GN_SKETCH_GAUSSIAN, "srht": C.GN_SKETCH_SRHT, "user": C.GN_SKETCH_USER}
+SKETCH_TORCH = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+ACCUM_TORCH = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
+DT_OF_TORCH = {torch.float64: C.GN_DT_F64, torch.float32: C.GN_DT_F32, torch.bfloat16: C.GN_DT_BF16}
+
+
+@dataclass
+class Problem:
+    """The problem statement of Algorithm 2.1: shape of A, r, l, eps, sketch kinds,
+    seed, and the pass precision."""
+    m: int
+    n: int
+    r: int
+    l: int = -1              # < 0: ceil(r/2)
+    kind_x: str = "gaussian"
+    kind_y: str = "gaussian"
+    seed: int = 0
+    mode: str = "f64"
+    eps: float = 0.0         # absolute; <= 0: plain GN
+    nu_x: float = 0.0
+    nu_y: float = 0.0
+
+    @property
+    def l_eff(self) -> int:
+        return (self.r + 1) // 2 if self.l < 0 else self.l
+
+    @property
+    def rl(self) -> int:
+        return self.r + self.l_eff
+
+    def c(self) -> C.GnProblem:
+        return C.GnProblem(self.m, self.n, self.r, self.l, KINDS[self.kind_x], KINDS[self.kind_y],
+                           self.seed & ((1 << 64) - 1), MODES[self.mode], 0, self.eps, self.nu_x,
+                           self.nu_y)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0) if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libgn takes device tensors")
+
+
+def gn_workspace_size(p: Problem, op: int, kcols: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    pc = p.c()
+    C.check(C.lib().gn_workspace_size(ctypes.byref(pc), op, kcols, ctypes.byref(out)),
+            "gn_workspace_size")
+    return int(out.value)
+
+
+def workspace(p: Problem, op: int, kcols: int = 0, device="cuda") -> torch.Tensor:
+    return torch.empty(max(gn_workspace_size(p, op, kcols), 256), dtype=torch.uint8, device=device)
+
+
+def gn_generate_gaussian(seed: int, stream: int, rows: int, cols: int, dtype=torch.float64,
+                         layout: int = 0, row0: int = 0, col0: int = 0, out=None):
+    shape = (rows, cols) if layout == 0 else (cols, rows)
+    if out is None:
+        out = torch.empty(shape, dtype=dtype, device="cuda")
+    _need_cuda(out)
+    C.check(C.lib().gn_generate_gaussian(seed & ((1 << 64) - 1), stream, row0, col0, rows, cols,
+                                         DT_OF_TORCH[out.dtype], layout, _ptr(out), out.stride(0),
+                                         _stream()), "gn_generate_gaussian")
+    return out
+
+
+def gn_srht_generate(seed: int, n: int, r: int):
+    npad = 1 << max(0, (n - 1).bit_length())
+    signs = torch.empty(npad, dtype=torch.int8, device="cuda")
+    idx = torch.empty(r, dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(8 * npad, 256), dtype=torch.uint8, device="cuda")
+    C.check(C.lib().gn_srht_generate(seed & ((1 << 64) - 1), n, r, _ptr(signs), _ptr(idx), _ptr(ws),
+                                     ws.numel(), _stream()), "gn_srht_generate")
+    return signs, idx
+
+
+def gn_sketch(p: Problem, A: torch.Tensor, scales=None, X_user=None, Y_user=None, AX=None,
+              YtA=None, want_srht: bool = False, ws=None):
+    """AX (m x r) and Y^T A ((r+l) x n); optionally the SRHT signs and sample."""
+    _need_cuda(A, scales, X_user, Y_user)
+    acc = ACCUM_TORCH[p.mode]
+    AX = torch.empty(p.m, p.r, dtype=acc, device=A.device) if AX is None else AX
+    YtA = torch.empty(p.rl, p.n, dtype=acc, device=A.device) if YtA is None else YtA
+    signs = idx = None
+    if want_srht and p.kind_x == "srht":
+        npad = 1 << max(0, (p.n - 1).bit_length())
+        signs = torch.empty(npad, dtype=torch.int8, device=A.device)
+        idx = torch.empty(p.r, dtype=torch.int32, device=A.device)
+    ws = workspace(p, C.GN_OP_SKETCH) if ws is None else ws
+    pc = p.c()
+    C.check(C.lib().gn_sketch(
+        ctypes.byref(pc), _ptr(A), A.stride(0), _ptr(scales),
+        _ptr(X_user), X_user.stride(0) if X_user is not None else 0,
+        _ptr(Y_user), Y_user.stride(0) if Y_user is not None else 0,
+        _ptr(AX), AX.stride(0), _ptr(YtA), YtA.stride(0), _ptr(signs), _ptr(idx),
+        _ptr(ws), ws.numel(), _stream()), "gn_sketch")
+    return AX, YtA, signs, idx
+
+
+@dataclass
+class CoreResult:
+    k: torch.Tensor       # int32[1] on device
+    status: torch.Tensor  # int32[1] on device
+    Q1: torch.Tensor
+    R: torch.Tensor
+    Q2: torch.Tensor
+    R2: torch.Tensor
+
+    def c(self) -> C.GnCoreOut:
+        return C.GnCoreOut(self.k.data_ptr(), self.status.data_ptr(), self.Q1.data_ptr(),
+                           self.R.data_ptr(), self.Q2.data_ptr(), self.R2.data_ptr())
+
+    def rank(self) -> int:
+        return int(self.k.item())
+
+    def flags(self) -> int:
+        return int(self.status.item())
+
+
+def new_core(p: Problem, device="cuda") -> CoreResult:
+    f = dict(dtype=torch.float64, device=device)
+    i = dict(dtype=torch.int32, device=device)
+    return CoreResult(torch.zeros(1, **i), torch.zeros(1, **i), torch.empty(p.rl, p.r, **f),
+                      torch.empty(p.r, p.r, **f), torch.empty(p.r, p.r, **f),
+                      torch.empty(p.r, p.r, **f))
+
+
+def gn_core(p: Problem, AX: torch.Tensor, Y_user=None, out: CoreResult | None = None, ws=None):
+    _need_cuda(AX, Y_user)
+    out = new_core(p, AX.device) if out is None else out
+    ws = workspace(p, C.GN_OP_CORE) if ws is None else ws
+    pc, oc = p.c(), out.c()
+    C.check(C.lib().gn_core(ctypes.byref(pc), _ptr(AX), AX.stride(0), _ptr(Y_user),
+                            Y_user.stride(0) if Y_user is not None else 0, ctypes.byref(oc),
+                            _ptr(ws), ws.numel(), _stream()), "gn_core")
+    return out
+
+
+def gn_factors(p: Problem, AX, YtA, core: CoreResult, F=None, G=None):
+    F = torch.empty(p.m, p.r, dtype=torch.float64, device=AX.device) if F is None else F
+    G = torch.empty(p.r, p.n, dtype=torch.float64, device=AX.device) if G is None else G
+    pc, oc = p.c(), core.c()
+    ws = torch.empty(256, dtype=torch.uint8, device=AX.device)
+    C.check(C.lib().gn_factors(ctypes.byref(pc), _ptr(AX), AX.stride(0), _ptr(YtA), YtA.stride(0),
+                               ctypes.byref(oc), _ptr(F), F.stride(0), _ptr(G), G.stride(0),
+                               _ptr(ws), ws.numel(), _stream()), "gn_factors")
+    return F, G
+
+
+def gn_apply(p: Problem, side: int, AX, YtA, core: CoreResult, W: torch.Tensor, out=None):
+    """side 0: A_hat W (W n x k); side 1: W A_hat (W k x m)."""
+    kc = W.shape[1] if side == 0 else W.shape[0]
+    shape = (p.m, kc) if side == 0 else (kc, p.n)
+    out = torch.empty(shape, dtype=torch.float64, device=W.device) if out is None else out
+    ws = workspace(p, C.GN_OP_APPLY, kc)
+    pc, oc = p.c(), core.c()
+    C.check(C.lib().gn_apply(ctypes.byref(pc), side, _ptr(AX), AX.stride(0), _ptr(YtA),
+                             YtA.stride(0), ctypes.byref(oc), _ptr(W), W.stride(0), kc, _ptr(out),
+                             out.stride(0), _ptr(ws), ws.numel(), _stream()), "gn_apply")
+    return out
+
+
+def gn_residual(A: torch.Tensor, F: torch.Tensor, G: torch.Tensor, k: int | None = None,
+                scales=None) -> torch.Tensor:
+    """||A - F[:, :k] G[:k]||_F^2 as a device double (fixed-order reduction)."""
+    m, n = A.shape
+    k = F.shape[1] if k is None else k
+    out = torch.empty(1, dtype=torch.float64, device=A.device)
+    nt = ((m + 63) // 64) * ((n + 63) // 64)
+    ws = torch.empty(max(8 * nt + 256, 256), dtype=torch.uint8, device=A.device)
+    C.check(C.lib().gn_residual(m, n, k, _ptr(A), A.stride(0), DT_OF_TORCH[A.dtype], _ptr(scales),
+                                _ptr(F), F.stride(0), _ptr(G), G.stride(0), _ptr(out), _ptr(ws),
+                                ws.numel(), _stream()), "gn_residual")
+    return out
+
+
+def gn_quantize_bf16_bs(A: torch.Tensor):
+    m, n = A.shape
+    out = torch.empty(m, n, dtype=torch.bfloat16, device=A.device)
+    scales = torch.empty((m + 127) // 128, (n + 127) // 128, dtype=torch.float32, device=A.device)
+    C.check(C.lib().gn_quantize_bf16_bs(m, n, _ptr(A), A.stride(0), DT_OF_TORCH[A.dtype], _ptr(out),
+                                        out.stride(0), _ptr(scales), _stream()),
+            "gn_quantize_bf16_bs")
+    return out, scales
+
+
+def solve(p: Problem, A: torch.Tensor, scales=None, X_user=None, Y_user=None):
+    """Sketch pass + core: returns (AX, YtA, core)."""
+    AX, YtA, _, _ = gn_sketch(p, A, scales=scales, X_user=X_user, Y_user=Y_user)
+    core = gn_core(p, AX, Y_user=Y_user)
+    return AX, YtA, core

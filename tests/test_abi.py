@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point declared in include/gn.h, and rejects bad arguments before any
+device work (those paths return without touching HIP)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2009_11392_amd import _capi as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "gn.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\S.*?\b(gn_[a-z0-9_]+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(C.LIB_PATH):
+        pytest.fail("libgn.so is not built (run python -m paper_2009_11392_amd.build)")
+    return C.lib()
+
+
+def test_header_declares_expected_entry_points():
+    syms = declared_symbols()
+    assert set(syms) == set(C.EXPORTED), syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+        assert ctypes.cast(getattr(lib, name), ctypes.c_void_p).value
+
+
+def test_status_strings_and_version(lib):
+    assert lib.gn_status_string(0) == b"GN_OK"
+    for code in range(1, 9):
+        assert lib.gn_status_string(code).startswith(b"GN_ERR_")
+    assert re.match(rb"\d+\.\d+\.\d+", lib.gn_version())
+
+
+def _prob(**kw):
+    base = dict(m=2000, n=1000, r=50, l=25, kind_x=0, kind_y=0, seed=1, mode=0, reserved=0,
+                eps=1e-15, nu_x=0.0, nu_y=0.0)
+    base.update(kw)
+    return C.GnProblem(**base)
+
+
+def _ws(lib, p, op, kc=0):
+    out = ctypes.c_size_t(0)
+    code = lib.gn_workspace_size(ctypes.byref(p), op, kc, ctypes.byref(out))
+    return code, out.value
+
+
+def test_workspace_sizes(lib):
+    p = _prob()
+    code, b = _ws(lib, p, C.GN_OP_SKETCH)
+    assert code == 0 and b >= 8 * (50 * 1000 + 75 * 2000)
+    code, b = _ws(lib, p, C.GN_OP_CORE)
+    assert code == 0 and b >= 8 * 75 * 50
+    assert _ws(lib, p, C.GN_OP_APPLY, 0)[0] == C.GN_ERR_SHAPE
+    assert _ws(lib, p, 99)[0] == C.GN_ERR_ARG
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(r=0), C.GN_ERR_SHAPE), (dict(r=1001), C.GN_ERR_SHAPE), (dict(m=0), C.GN_ERR_SHAPE),
+    (dict(mode=7), C.GN_ERR_ARG), (dict(kind_x=5), C.GN_ERR_ARG), (dict(kind_y=1), C.GN_ERR_ARG),
+    (dict(eps=float("nan")), C.GN_ERR_ARG), (dict(reserved=1), C.GN_ERR_ARG),
+    (dict(r=3000, l=2000, m=9000, n=9000), C.GN_ERR_UNSUPPORTED),
+    (dict(kind_x=1, n=1 << 18, m=10), C.GN_ERR_SHAPE),
+    (dict(kind_x=1, n=1 << 18, m=1 << 18), C.GN_ERR_UNSUPPORTED),
+])
+def test_problem_validation(lib, kw, code):
+    assert _ws(lib, _prob(**kw), C.GN_OP_SKETCH)[0] == code
+
+
+def test_entry_points_reject_before_enqueue(lib):
+    p = _prob()
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)                 # never dereferenced: rejected first
+    # null A
+    assert lib.gn_sketch(ctypes.byref(p), null, 1000, null, null, 0, null, 0, fake, 50, fake,
+                         1000, null, null, fake, 1 << 30, null) == C.GN_ERR_ARG
+    # lda < n
+    assert lib.gn_sketch(ctypes.byref(p), fake, 999, null, null, 0, null, 0, fake, 50, fake,
+                         1000, null, null, fake, 1 << 30, null) == C.GN_ERR_SHAPE
+    # misaligned output
+    assert lib.gn_sketch(ctypes.byref(p), fake, 1000, null, null, 0, null, 0,
+                         ctypes.c_void_p((1 << 20) + 4), 50, fake, 1000, null, null, fake,
+                         1 << 30, null) == C.GN_ERR_ALIGN
+    # workspace too small
+    assert lib.gn_sketch(ctypes.byref(p), fake, 1000, null, null, 0, null, 0, fake, 50, fake,
+                         1000, null, null, fake, 16, null) == C.GN_ERR_WORKSPACE
+    # BF16 mode needs scales
+    pb = _prob(mode=2)
+    assert lib.gn_sketch(ctypes.byref(pb), fake, 1000, null, null, 0, null, 0, fake, 50, fake,
+                         1000, null, null, fake, 1 << 30, null) == C.GN_ERR_ARG
+    # core output struct with a null member
+    out = C.GnCoreOut(1 << 20, 0, 1 << 20, 1 << 20, 1 << 20, 1 << 20)
+    assert lib.gn_core(ctypes.byref(p), fake, 50, null, 0, ctypes.byref(out), fake, 1 << 30,
+                       null) == C.GN_ERR_ARG
+    assert lib.gn_apply(ctypes.byref(p), 2, fake, 50, fake, 1000, ctypes.byref(out), fake, 1, 1,
+                        fake, 1, fake, 1 << 30, null) == C.GN_ERR_ARG
+    assert lib.gn_residual(10, 10, 2, fake, 5, 0, null, fake, 2, fake, 10, fake, fake, 1 << 20,
+                           null) == C.GN_ERR_SHAPE
+    assert lib.gn_quantize_bf16_bs(10, 10, fake, 10, 2, fake, 10, fake, null) == C.GN_ERR_DTYPE
+    assert lib.gn_generate_gaussian(1, 1, 0, 0, 4, 4, 5, 0, fake, 4, null) == C.GN_ERR_ARG
+    assert lib.gn_srht_generate(1, 100, 200, fake, fake, fake, 1 << 20, null) == C.GN_ERR_SHAPE

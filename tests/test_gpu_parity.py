@@ -1,0 +1,240 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances:
+  * sketches: Philox words feed both sides identically; FP64 normals agree to a
+    few ulp (libm differences in log/cos/sin), rounded FP32/BF16 sketches are
+    equal except at rounding ties (counted, each one unit in the last place);
+    SRHT signs and sample indices are bit-exact.
+  * FP64 pass: relative Frobenius error <= 1e-13; FP64 approximant <= 1e-10.
+  * FP32 / BF16 pass (FP32 accumulation): every entry within the inner-product
+    bound gamma_K * (|A| |X|)_ij with gamma_K = K u / (1 - K u), u = 2^-24,
+    which holds for any summation order.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import gn as OG, philox as OP  # noqa: E402
+from paper_2009_11392_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_11392_amd import gn
+    return gn
+
+
+def dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def host(t):
+    return t.detach().cpu().double().numpy() if t.dtype != torch.bfloat16 else \
+        t.detach().cpu().float().double().numpy()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def ulp_diff(a, b):
+    ai = np.asarray(a, np.float64).view(np.int64)
+    bi = np.asarray(b, np.float64).view(np.int64)
+    ai = np.where(ai < 0, np.int64(-(1 << 63)) - ai, ai)
+    bi = np.where(bi < 0, np.int64(-(1 << 63)) - bi, bi)
+    return np.abs(ai - bi)
+
+
+def gamma(K, u=U32):
+    return K * u / (1 - K * u)
+
+
+def tau_of(p, n=None):
+    nx = OG.nu_srht(p.n) if p.kind_x == "srht" else OG.nu_gaussian(p.n, p.r)
+    ny = OG.nu_gaussian(p.m, p.rl)
+    return OG.threshold(p.eps, nx, ny) if p.eps > 0 else 0.0
+
+
+# ----------------------------------------------------------------------------- sketches
+@pytest.mark.parametrize("layout", [0, 1])
+def test_gaussian_f64_matches_oracle(G, layout):
+    rows, cols, r0, c0 = 301, 77, 5, 3
+    t = G.gn_generate_gaussian(11, 2, rows, cols, torch.float64, layout=layout, row0=r0, col0=c0)
+    got = host(t)
+    if layout == 1:
+        got = got.T
+    ref = OP.gaussian(11, 2, rows, cols, row0=r0, col0=c0)
+    assert np.max(ulp_diff(got, ref)) <= 8
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_gaussian_rounded_equal_except_ties(G, dtype):
+    rows, cols = 1000, 333
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    got = host(G.gn_generate_gaussian(5, 1, rows, cols, tdt))
+    z = OP.gaussian(5, 1, rows, cols)
+    ref = OP.round_fp32(z).astype(np.float64) if dtype == "f32" else OP.round_bf16(z)
+    bad = got != ref
+    assert bad.mean() <= 1e-5
+    if bad.any():   # only rounding ties: neighbours in the target format
+        ulp = np.spacing(np.abs(ref[bad]).astype(np.float32)).astype(np.float64)
+        if dtype == "bf16":
+            ulp = ulp * 2.0 ** 16
+        assert np.all(np.abs(got[bad] - ref[bad]) <= ulp * 1.0001)
+
+
+@pytest.mark.parametrize("n,r", [(1000, 10), (4096, 1000), (100, 64), (1, 1), (32768, 1000)])
+def test_srht_parameters_bit_exact(G, n, r):
+    signs, idx = G.gn_srht_generate(77, n, r)
+    npad = OP.next_pow2(n)
+    assert np.array_equal(signs.cpu().numpy(), OP.srht_signs(77, npad))
+    assert np.array_equal(idx.cpu().numpy(), OP.srht_sample(77, npad, r))
+
+
+# ----------------------------------------------------------------------------- FP64 pipeline
+@pytest.fixture(scope="module")
+def small(G):
+    w = W.SMALL
+    A = W.host_matrix(w)
+    p = G.Problem(w.m, w.n, w.r, w.l, seed=w.seed, mode="f64", eps=w.eps)
+    X, Y = OG.gaussian_sketches(w.seed, w.m, w.n, w.r, w.l)
+    ref = OG.gn(A, X, Y, tau_of(p))
+    return w, A, p, X, Y, ref
+
+
+def test_small_pass_f64(G, small):
+    w, A, p, X, Y, ref = small
+    AX, YtA, _, _ = G.gn_sketch(p, dev(A))
+    assert relerr(host(AX), ref.AX) <= 1e-13
+    assert relerr(host(YtA), ref.YA) <= 1e-13
+
+
+def test_small_core_and_approximant_f64(G, small):
+    w, A, p, X, Y, ref = small
+    Ad = dev(A)
+    AX, YtA, core = G.solve(p, Ad)
+    assert core.rank() == ref.core.k == w.r
+    assert core.flags() == 0
+    assert relerr(host(core.R), ref.core.R) <= 1e-12
+    assert relerr(host(core.Q1), ref.core.Q) <= 1e-12
+    F, Gm = G.gn_factors(p, AX, YtA, core)
+    Ahat = host(F) @ host(Gm)
+    assert relerr(Ahat, ref.approx) <= 1e-10
+    # error measured on the device, tile by tile
+    ss = float(G.gn_residual(Ad, F, Gm).item())
+    e_ref = OG.residual_fro(A, ref.F, ref.G)
+    assert math.isclose(math.sqrt(ss), e_ref, rel_tol=1e-9)
+
+
+def test_small_apply_both_sides(G, small):
+    w, A, p, X, Y, ref = small
+    AX, YtA, core = G.solve(p, dev(A))
+    Wr = W.host_gaussian(w.n, 7, 21)
+    Wl = W.host_gaussian(5, w.m, 22)
+    outr = host(G.gn_apply(p, 0, AX, YtA, core, dev(Wr)))
+    outl = host(G.gn_apply(p, 1, AX, YtA, core, dev(Wl)))
+    assert relerr(outr, OG.apply_right(ref.AX, ref.YA, ref.core, Wr)) <= 1e-10
+    assert relerr(outl, OG.apply_left(ref.AX, ref.YA, ref.core, Wl)) <= 1e-10
+
+
+def test_exact_recovery_on_gpu(G, small):
+    w, _, p, X, Y, _ = small
+    A = W.spectrum_matrix(w.m, w.n, w.sigma()[:w.r], seed=7)
+    AX, YtA, core = G.solve(p, dev(A))
+    assert core.rank() == w.r
+    F, Gm = G.gn_factors(p, AX, YtA, core)
+    assert math.sqrt(float(G.gn_residual(dev(A), F, Gm).item())) / np.linalg.norm(A) <= 1e-12
+
+
+def test_truncation_rank_on_gpu(G, small):
+    w, _, p, X, Y, _ = small
+    A = W.spectrum_matrix(w.m, w.n, w.sigma()[:40], seed=8)
+    ref = OG.gn(A, X, Y, tau_of(p))
+    AX, YtA, core = G.solve(p, dev(A))
+    assert core.rank() == ref.core.k == 40
+    assert (core.flags() & 3) == 0
+    F, Gm = G.gn_factors(p, AX, YtA, core)
+    Fh, Gh = host(F), host(Gm)
+    assert np.all(Fh[:, 40:] == 0) and np.all(Gh[40:] == 0)
+    assert relerr(Fh[:, :40] @ Gh[:40], ref.approx) <= 1e-10
+    Wr = W.host_gaussian(w.n, 3, 5)
+    Wl = W.host_gaussian(4, w.m, 6)
+    assert relerr(host(G.gn_apply(p, 0, AX, YtA, core, dev(Wr))), ref.approx @ Wr) <= 1e-10
+    assert relerr(host(G.gn_apply(p, 1, AX, YtA, core, dev(Wl))), Wl @ ref.approx) <= 1e-10
+
+
+# ----------------------------------------------------------------------------- FP32 / BF16 pass
+def test_pass_f32_gaussian_ragged(G):
+    m, n, r, l = 777, 1234, 37, 19
+    A = W.spectrum_matrix(m, n, 0.95 ** np.arange(1, 301), seed=31).astype(np.float32)
+    p = G.Problem(m, n, r, l, seed=9, mode="f32")
+    AX, YtA, _, _ = G.gn_sketch(p, dev(A, torch.float32))
+    X, Y = OG.gaussian_sketches(9, m, n, r, l, mode="f32")
+    A64 = A.astype(np.float64)
+    ax, ya = host(AX), host(YtA)
+    assert np.all(np.abs(ax - A64 @ X) <= gamma(n) * (np.abs(A64) @ np.abs(X)))
+    assert np.all(np.abs(ya - Y.T @ A64) <= gamma(m) * (np.abs(Y.T) @ np.abs(A64)))
+    assert relerr(ax, A64 @ X) <= 1e-5 and relerr(ya, Y.T @ A64) <= 1e-5
+
+
+def test_pass_srht_integer_inputs_exact(G):
+    m, n, r = 170, 1000, 100         # n' = 1024: two 512-column chunks, ragged tail
+    A = W.integer_matrix(m, n, 41).astype(np.float32)
+    p = G.Problem(m, n, r, 50, kind_x="srht", seed=4, mode="f32")
+    AX, YtA, signs, idx = G.gn_sketch(p, dev(A, torch.float32), want_srht=True)
+    npad = OP.next_pow2(n)
+    assert np.array_equal(signs.cpu().numpy(), OP.srht_signs(4, npad))
+    assert np.array_equal(idx.cpu().numpy(), OP.srht_sample(4, npad, r))
+    X = OP.srht_matrix(4, n, r)
+    assert np.array_equal(host(AX), A.astype(np.float64) @ X)   # integers: exact
+
+
+def test_pass_srht_f64_matches_oracle(G):
+    m, n, r = 300, 700, 90
+    A = W.spectrum_matrix(m, n, 0.9 ** np.arange(1, 301), seed=12)
+    p = G.Problem(m, n, r, 45, kind_x="srht", seed=6, mode="f64")
+    AX, _, _, _ = G.gn_sketch(p, dev(A))
+    assert relerr(host(AX), A @ OP.srht_matrix(6, n, r)) <= 1e-13
+
+
+def test_quantize_bf16_bit_exact(G):
+    A = W.spectrum_matrix(300, 260, 0.9 ** np.arange(1, 261), seed=9)
+    A[:128, :128] = 0.0
+    bits, scales = G.gn_quantize_bf16_bs(dev(A))
+    rb, rs = OG.block_quantize_bf16(A)
+    assert np.array_equal(bits.view(torch.int16).cpu().numpy().view(np.uint16), rb)
+    assert np.array_equal(scales.cpu().numpy(), rs)
+
+
+def test_pass_bf16_block_scaled(G):
+    m, n, r, l = 300, 260, 40, 20
+    A = W.spectrum_matrix(m, n, 0.9 ** np.arange(1, 261), seed=13)
+    bits, scales = G.gn_quantize_bf16_bs(dev(A))
+    p = G.Problem(m, n, r, l, seed=3, mode="bf16")
+    AX, YtA, _, _ = G.gn_sketch(p, bits, scales=scales)
+    rb, rs = OG.block_quantize_bf16(A)
+    Aq = OG.block_dequantize_bf16(rb, rs)
+    X, Y = OG.gaussian_sketches(3, m, n, r, l, mode="bf16")
+    ax, ya = host(AX), host(YtA)
+    assert np.all(np.abs(ax - Aq @ X) <= gamma(n) * (np.abs(Aq) @ np.abs(X)))
+    assert np.all(np.abs(ya - Y.T @ Aq) <= gamma(m) * (np.abs(Y.T) @ np.abs(Aq)))
+
+
+# ----------------------------------------------------------------------------- edge cases
+def test_nonfinite_input_sets_status(G):
+    m, n, r = 200, 150, 10
+    A = W.spectrum_matrix(m, n, 0.9 ** np.arange(1, 151), seed=1)
+    A[3, 4] = np.nan
+    p = G.Problem(m, n, r, 5, seed=1, mode="f64", eps=1e-15)
+    _, _, core = G.solve(p, dev(A))
+    assert core.flags() & 1
