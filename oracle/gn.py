@@ -149,9 +149,11 @@ def core(AX: np.ndarray, Y: np.ndarray, tau: float) -> Core:
     r = C.shape[1]
     Q, R = _qr_nonneg(C)
     d = np.abs(np.diag(R))
-    bad = ~(d >= tau)                       # also catches NaN
+    # keep |R_ii| >= tau; with tau <= 0 (plain GN) keep every non-zero diagonal.
+    # NaN fails both comparisons.
+    bad = ~(d >= tau) if tau > 0 else ~(d > 0)
     k = int(np.argmax(bad)) if bad.any() else r
-    non_monotone = bool(np.any(d[k:] >= tau)) if k < r else False
+    non_monotone = bool(np.any(~bad[k:])) if k < r else False
     status = 0
     if not np.all(np.isfinite(np.diag(R))) or k == 0:
         status = 7
