@@ -1,0 +1,291 @@
+"""Benchmark of the GN hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--no-compare] [--no-cpu] [--no-error]
+
+One step = one generalized Nystrom solve of the workload's matrix: the sketches
+(Philox Gaussian Y, SRHT signs and sample or Gaussian X), the single fused pass
+over A (AX and Y^T A), the core (C = Y^T (AX), Householder QR, eps-truncation,
+second QR when truncated) and one product with the factors (A_hat W, 16
+columns).  The inputs are resident in HBM before timing starts.  HIP events on
+the library's stream (torch's current stream) time each stage; `value` is the
+pass's algorithmic TFLOP/s.  After timing: the error ||A - A_hat||_F (tile-wise
+on the device), a bounded CPU-oracle baseline, and the BF16-vs-FP32 comparison
+on the 32768^2, r = 2000, l = 1000 shape (same matrix).  Prints ONE JSON line on
+stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}   # dense TFLOP/s (MI355X datasheet)
+HBM_PEAK_GBS = 8000.0
+METRIC = "sketch-pass GB/s & TFLOP/s; GN solves/sec bf16 vs fp32 at equal error"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pass_algorithmic(w, npad):
+    """(flops, bytes) the pass must do / move: A once, sketches once, outputs once."""
+    m, n, r, rl = w.m, w.n, w.r, w.r + w.l
+    es = {"f64": 8, "f32": 4, "bf16": 2}[w.mode]
+    acc = 8 if w.mode == "f64" else 4
+    flops = 2.0 * m * n * rl
+    byts = m * n * es + m * rl * es + (m * r + rl * n) * acc
+    if w.kind_x == "srht":
+        flops += m * n * math.log2(npad)
+        byts += npad + 4 * r
+    else:
+        flops += 2.0 * m * n * r
+        byts += n * r * es
+    if w.mode == "bf16":
+        byts += 4 * ((m + 127) // 128) * ((n + 127) // 128)
+    return flops, byts
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("pass.hip", "gemm_tiles.h", "gn_internal.h"):
+        with open(os.path.join(ROOT, "paper_2009_11392_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload):
+    path = os.path.join(ROOT, "profiles", "pass_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    ent = rec.get(workload)
+    if not ent or ent.get("sources_sha") != source_hash():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def optimum_estimate(w):
+    """||A - A_r||_F for sigma plus i.i.d. noise: sqrt(sum_{i>r} sigma_i^2 +
+    nu^2 (m-r)(n-r)) -- an estimate (the noise spectrum is not closed-form)."""
+    s = w.sigma()
+    return math.sqrt(float((s[w.r:] ** 2).sum()) + w.noise ** 2 * (w.m - w.r) * (w.n - w.r))
+
+
+class Runner:
+    """Preallocated buffers and one timed solve for a workload."""
+
+    def __init__(self, gn, w, A, scales=None, kc=16):
+        import torch
+        self.gn, self.w, self.A, self.scales = gn, w, A, scales
+        self.p = gn.Problem(w.m, w.n, w.r, w.l, kind_x=w.kind_x, kind_y=w.kind_y, seed=w.seed,
+                            mode=w.mode, eps=w.eps)
+        acc = gn.ACCUM_TORCH[w.mode]
+        self.ws = gn.workspace(self.p, gn.C.GN_OP_SKETCH)
+        self.ws_core = gn.workspace(self.p, gn.C.GN_OP_CORE)
+        self.AX = torch.empty(w.m, w.r, dtype=acc, device="cuda")
+        self.YtA = torch.empty(self.p.rl, w.n, dtype=acc, device="cuda")
+        self.core = gn.new_core(self.p)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(99)
+        self.W = torch.randn(w.n, kc, generator=g, device="cuda", dtype=torch.float64)
+        self.out = torch.empty(w.m, kc, dtype=torch.float64, device="cuda")
+
+    def step(self, ev):
+        gn, p = self.gn, self.p
+        ev[0].record()
+        gn.gn_sketch_prepare(p, self.ws)
+        ev[1].record()
+        gn.gn_sketch_pass(p, self.A, self.ws, scales=self.scales, AX=self.AX, YtA=self.YtA)
+        ev[2].record()
+        gn.gn_core(p, self.AX, out=self.core, ws=self.ws_core)
+        ev[3].record()
+        gn.gn_apply(p, 0, self.AX, self.YtA, self.core, self.W, out=self.out)
+        ev[4].record()
+
+    def timed(self, steps, warmup):
+        import torch
+        for _ in range(warmup):
+            self.step([torch.cuda.Event(enable_timing=True) for _ in range(5)])
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+        t0 = time.perf_counter()
+        for e in evs:
+            self.step(e)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = {k: [] for k in ("prepare", "pass", "core", "apply", "step")}
+        for e in evs:
+            st["prepare"].append(e[0].elapsed_time(e[1]))
+            st["pass"].append(e[1].elapsed_time(e[2]))
+            st["core"].append(e[2].elapsed_time(e[3]))
+            st["apply"].append(e[3].elapsed_time(e[4]))
+            st["step"].append(e[0].elapsed_time(e[4]))
+        mean = {k: sum(v) / len(v) for k, v in st.items()}
+        mean["wall_ms_per_step"] = 1e3 * wall / steps
+        return mean
+
+    def error(self):
+        """||A - A_hat||_F / ||A||_F on the device, tile by tile, and the kept rank."""
+        import torch
+        gn = self.gn
+        F, G = gn.gn_factors(self.p, self.AX, self.YtA, self.core)
+        ss = float(gn.gn_residual(self.A, F, G, scales=self.scales).item())
+        z = torch.zeros(self.w.m, 1, dtype=torch.float64, device="cuda")
+        zg = torch.zeros(1, self.w.n, dtype=torch.float64, device="cuda")
+        na = float(gn.gn_residual(self.A, z, zg, k=0, scales=self.scales).item())
+        del F, G
+        return math.sqrt(ss), math.sqrt(na), self.core.rank(), self.core.flags()
+
+
+def cpu_baseline(A_dev, w, target_s=12.0):
+    """The FP64 oracle's sketch pass on a bounded block of rows of the same A."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import philox as OP
+
+    npad = OP.next_pow2(w.n)
+    if w.kind_x == "srht":
+        X = OP.srht_matrix(w.seed, w.n, w.r)
+    else:
+        X = OP.gaussian(w.seed, OP.STREAM_X, w.n, w.r)
+
+    def run(rows):
+        Ab = A_dev[:rows].double().cpu().numpy()
+        Yb = OP.gaussian(w.seed, OP.STREAM_Y, rows, w.r + w.l)
+        t0 = time.perf_counter()
+        _ = Ab @ X
+        _ = Yb.T @ Ab
+        return time.perf_counter() - t0
+
+    rows = 128
+    dt = run(rows)
+    rows = int(min(w.m, max(128, rows * target_s / max(dt, 1e-3))))
+    rows = max(128, (rows // 128) * 128)
+    dt = run(rows)
+    sub = type("S", (), {})()
+    flops = 2.0 * rows * w.n * (w.r + w.l) + (rows * w.n * math.log2(npad) if w.kind_x == "srht"
+                                               else 2.0 * rows * w.n * w.r)
+    threads = max([d.get("num_threads", 0) for d in threadpool_info()] or [os.cpu_count() or 1])
+    del sub
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle sketch pass (A@X, Y^T@A) on rows 0..{rows - 1} of the "
+                       f"same {w.m}x{w.n} matrix ({dt:.2f} s); algorithmic flops of the method"),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="srht_32768x32768_f32")
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(this build runs on a single MI355X).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2009_11392_amd import gn, workloads as W
+    from oracle import philox as OP
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    gn.C.lib()  # fail loudly if the library is not built
+    w = W.ALL[args.workload]
+    npad = OP.next_pow2(w.n)
+    log(f"generating {w.name} on the device")
+    A32 = W.device_matrix(w if w.mode != "bf16" else W.F32_32K)
+    scales = None
+    if w.mode == "bf16":
+        A, scales = gn.gn_quantize_bf16_bs(A32)
+    elif w.mode == "f64":
+        A = A32.double()
+    else:
+        A = A32
+    torch.cuda.synchronize()
+
+    run = Runner(gn, w, A, scales)
+    log(f"timing {args.steps} steps after {args.warmup} warm-up steps")
+    t = run.timed(args.steps, args.warmup)
+    flops, byts = pass_algorithmic(w, npad)
+    pass_s = t["pass"] / 1e3
+    tflops = flops / pass_s / 1e12
+    gbs = byts / pass_s / 1e9
+    solve_ms = t["prepare"] + t["pass"] + t["core"]
+    peak = PEAK[w.mode]
+    bound = "mfma" if flops / (peak * 1e12) > byts / (HBM_PEAK_GBS * 1e9) else "hbm"
+    roof = {"bound": bound, "kernel": "fused sketch pass (gn_sketch_pass)",
+            "achieved": tflops if bound == "mfma" else gbs, "peak": peak if bound == "mfma" else HBM_PEAK_GBS,
+            "unit": "TFLOP/s" if bound == "mfma" else "GB/s",
+            "traffic": traffic_from_profile(w.name),
+            "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byts,
+            "avg_launch_ms": t["pass"]}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    res = {"metric": METRIC, "value": tflops, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": t["step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": {"f32": "f32", "bf16": "bf16", "f64": "f64"}[w.mode],
+           "data": "synthetic (seeded spectrum-controlled matrix generated on the device)",
+           "config": {"workload": w.name, "m": w.m, "n": w.n, "r": w.r, "l": w.l,
+                      "sketch_x": w.kind_x, "sketch_y": w.kind_y, "pass_precision": w.mode,
+                      "core_precision": "f64", "parallelism": "single GPU"},
+           "pass_gbps": gbs, "pass_ms": t["pass"], "solves_per_sec": 1e3 / solve_ms,
+           "stage_ms": {k: t[k] for k in ("prepare", "pass", "core", "apply")},
+           "wall_ms_per_step": t["wall_ms_per_step"], "roofline": roof}
+    log(f"pass {t['pass']:.3f} ms  {tflops:.1f} TFLOP/s  {gbs:.0f} GB/s  solve {solve_ms:.2f} ms")
+
+    if not args.no_error:
+        e, na, k, flags = run.error()
+        res["error"] = {"rel_fro": e / na, "abs_fro": e, "kept_rank": k, "status_flags": flags,
+                        "optimum_estimate": optimum_estimate(w),
+                        "ratio_to_optimum": e / optimum_estimate(w)}
+        log(f"error {e / na:.4e} (abs {e:.4e}, k={k})")
+
+    if not args.no_compare and w.m == 32768 and w.n == 32768:
+        cmp = {}
+        for tag, wl in (("bf16", W.BF16_32K), ("f32", W.F32_32K)):
+            log(f"comparison: {wl.name}")
+            if tag == "bf16":
+                Ab, sc = gn.gn_quantize_bf16_bs(A32)
+            else:
+                Ab, sc = A32, None
+            rr = Runner(gn, wl, Ab, sc)
+            tt = rr.timed(3, 1)
+            fl, by = pass_algorithmic(wl, OP.next_pow2(wl.n))
+            ent = {"pass_ms": tt["pass"], "solve_ms": tt["prepare"] + tt["pass"] + tt["core"],
+                   "pass_tflops": fl / (tt["pass"] / 1e3) / 1e12,
+                   "pass_frac_of_peak": fl / (tt["pass"] / 1e3) / 1e12 / PEAK[tag]}
+            ent["solves_per_sec"] = 1e3 / ent["solve_ms"]
+            e, na, k, flags = rr.error()
+            ent.update({"rel_err": e / na, "kept_rank": k, "status_flags": flags})
+            cmp[tag] = ent
+            del rr, Ab
+            torch.cuda.empty_cache()
+        cmp["speedup_solves_per_sec"] = cmp["bf16"]["solves_per_sec"] / cmp["f32"]["solves_per_sec"]
+        cmp["speedup_pass"] = cmp["f32"]["pass_ms"] / cmp["bf16"]["pass_ms"]
+        cmp["err_ratio_bf16_over_f32"] = cmp["bf16"]["rel_err"] / cmp["f32"]["rel_err"]
+        cmp["shape"] = "32768x32768, Gaussian X and Y, r=2000, l=1000, same matrix"
+        res["bf16_vs_fp32"] = cmp
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline(A32 if w.mode != "f64" else A, w)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -7,7 +7,8 @@
  * X (n x r) and an oversampled sketch Y (m x (r+l))  (Section 2, eqs. (3)-(4);
  * Algorithm 2.1).  The library computes, on one GPU:
  *   gn_generate_gaussian / gn_srht_generate  -- the random sketches,
- *   gn_sketch     -- the single pass over A that forms AX and Y^T A,
+ *   gn_sketch_prepare / gn_sketch_pass / gn_sketch -- the sketches and the
+ *                   single pass over A that forms AX and Y^T A,
  *   gn_core       -- C = Y^T (AX), its Householder QR and the eps-truncation,
  *   gn_factors / gn_apply -- the factored approximant and products with it,
  *   gn_residual   -- ||A - F G||_F^2 formed tile by tile (error measurement),
@@ -144,19 +145,32 @@ gn_status gn_generate_gaussian(uint64_t seed, int32_t stream, int64_t row0, int6
 gn_status gn_srht_generate(uint64_t seed, int64_t n, int64_t r, int8_t* signs, int32_t* idx,
                            void* ws, size_t ws_bytes, gn_stream_t stream);
 
+/* Sketches for the pass (Algorithm 2.1, step 1), written into the workspace
+ * ws (gn_workspace_size(GN_OP_SKETCH) bytes), which gn_sketch_pass then reads:
+ * Gaussian X (stream 1) and Y (stream 2) drawn on the device from `seed` in the
+ * mode's sketch dtype (double, float or bfloat16), or the USER matrices
+ * X_user (n x r, ld ldx) / Y_user (m x (r+l), ld ldy) in that dtype, or for an
+ * SRHT X its signs and sample (copied to signs_out / idx_out when non-NULL, as
+ * in gn_srht_generate).  One prepared workspace serves any number of passes
+ * over matrices of the same problem shape. */
+gn_status gn_sketch_prepare(const gn_problem* p, const void* X_user, int64_t ldx,
+                            const void* Y_user, int64_t ldy, int8_t* signs_out, int32_t* idx_out,
+                            void* ws, size_t ws_bytes, gn_stream_t stream);
+
 /* The sketch pass (Algorithm 2.1, step 2): AX (m x r) and Y^T A ((r+l) x n)
- * from A (m x n, row stride lda >= n).
+ * from A (m x n, row stride lda >= n), with the sketches of a prepared ws.
+ * In FP32 and BF16 modes this is one kernel launch.
  *   A        : mode dtype (double, float, or bfloat16 bits for BF16_BS).
  *   A_scales : BF16_BS only: float[ceil(m/128) * ceil(n/128)], row-major, the
  *              scale of each 128 x 128 block (A = scale * stored value).
- *   X_user   : kind_x == USER only: n x r in the mode's sketch dtype, ld ldx.
- *   Y_user   : kind_y == USER only: m x (r+l) in the sketch dtype, ld ldy.
  *   AX, YtA  : outputs in the accumulation dtype (double for F64, float else),
  *              row strides ldax >= r and ldya >= n.
- *   signs_out, idx_out : optional (may be NULL); SRHT parameters as in
- *              gn_srht_generate.
- * Generated sketches are drawn on the device from `seed` (streams 1 and 2).
  * All pointers 16-byte aligned. */
+gn_status gn_sketch_pass(const gn_problem* p, const void* A, int64_t lda, const float* A_scales,
+                         void* AX, int64_t ldax, void* YtA, int64_t ldya, const void* ws,
+                         size_t ws_bytes, gn_stream_t stream);
+
+/* gn_sketch_prepare followed by gn_sketch_pass, with the arguments of both. */
 gn_status gn_sketch(const gn_problem* p, const void* A, int64_t lda, const float* A_scales,
                     const void* X_user, int64_t ldx, const void* Y_user, int64_t ldy,
                     void* AX, int64_t ldax, void* YtA, int64_t ldya, int8_t* signs_out,

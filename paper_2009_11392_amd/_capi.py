@@ -17,7 +17,8 @@ GN_DT_F64, GN_DT_F32, GN_DT_BF16 = 0, 1, 2
 GN_OP_SKETCH, GN_OP_CORE, GN_OP_FACTORS, GN_OP_APPLY, GN_OP_RESIDUAL, GN_OP_SRHT = range(6)
 
 EXPORTED = (
-    "gn_workspace_size", "gn_generate_gaussian", "gn_srht_generate", "gn_sketch", "gn_core",
+    "gn_workspace_size", "gn_generate_gaussian", "gn_srht_generate", "gn_sketch_prepare",
+    "gn_sketch_pass", "gn_sketch", "gn_core",
     "gn_factors", "gn_apply", "gn_residual", "gn_quantize_bf16_bs", "gn_status_string",
     "gn_version",
 )
@@ -63,6 +64,10 @@ def lib(path: str = LIB_PATH):
     L.gn_sketch.argtypes = [P, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p, c_int64,
                             c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
                             c_size_t, c_void_p]
+    L.gn_sketch_prepare.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p,
+                                    c_void_p, c_size_t, c_void_p]
+    L.gn_sketch_pass.argtypes = [P, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p,
+                                 c_int64, c_void_p, c_size_t, c_void_p]
     L.gn_core.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, POINTER(GnCoreOut), c_void_p,
                           c_size_t, c_void_p]
     L.gn_factors.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, POINTER(GnCoreOut), c_void_p,

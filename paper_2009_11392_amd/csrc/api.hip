@@ -206,54 +206,74 @@ gn_status gn_srht_generate(uint64_t seed, int64_t n, int64_t r, int8_t* signs, i
   return launch_srht(seed, npad, r, signs, idx, (uint64_t*)ws, (hipStream_t)stream);
 }
 
-gn_status gn_sketch(const gn_problem* p, const void* A, int64_t lda, const float* A_scales,
-                    const void* X_user, int64_t ldx, const void* Y_user, int64_t ldy, void* AX,
-                    int64_t ldax, void* YtA, int64_t ldya, int8_t* signs_out, int32_t* idx_out,
-                    void* ws, size_t ws_bytes, gn_stream_t stream_) {
+gn_status gn_sketch_prepare(const gn_problem* p, const void* X_user, int64_t ldx,
+                            const void* Y_user, int64_t ldy, int8_t* signs_out, int32_t* idx_out,
+                            void* ws, size_t ws_bytes, gn_stream_t stream_) {
   Plan P;
   GN_TRY(make_plan(p, P));
   hipStream_t s = (hipStream_t)stream_;
-  if (!A || !AX || !YtA || !ws) return GN_ERR_ARG;
-  if (P.mode == GN_MODE_BF16_BS && !A_scales) return GN_ERR_ARG;
+  if (!ws) return GN_ERR_ARG;
   if (P.kx == GN_SKETCH_USER && !X_user) return GN_ERR_ARG;
   if (P.ky == GN_SKETCH_USER && !Y_user) return GN_ERR_ARG;
-  if (lda < P.n || ldax < P.r || ldya < P.n) return GN_ERR_SHAPE;
   if (P.kx == GN_SKETCH_USER && ldx < P.r) return GN_ERR_SHAPE;
   if (P.ky == GN_SKETCH_USER && ldy < P.rl) return GN_ERR_SHAPE;
-  if (!aligned16(A) || !aligned16(AX) || !aligned16(YtA) || !aligned16(ws)) return GN_ERR_ALIGN;
+  if (!aligned16(ws)) return GN_ERR_ALIGN;
   const SketchWs W = sketch_ws(P);
   if (ws_bytes < W.total) return GN_ERR_WORKSPACE;
   char* base = (char*)ws;
-  void* Xt = base + W.xt;
-  void* Yt = base + W.yt;
-
-  // sketches (Algorithm 2.1, step 1)
+  // Algorithm 2.1, step 1: the sketches, stored transposed (k-contiguous)
   if (P.ky == GN_SKETCH_GAUSSIAN)
-    GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, P.sdt, 1, Yt, P.m, s));
+    GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, P.sdt, 1, base + W.yt, P.m, s));
   else
-    GN_TRY(launch_transpose(Y_user, P.m, P.rl, ldy, P.sdt, Yt, P.m, s));
-  if (P.kx == GN_SKETCH_GAUSSIAN)
-    GN_TRY(launch_gaussian(p->seed, 1, 0, 0, P.n, P.r, P.sdt, 1, Xt, P.n, s));
-  else if (P.kx == GN_SKETCH_USER)
-    GN_TRY(launch_transpose(X_user, P.n, P.r, ldx, P.sdt, Xt, P.n, s));
-
-  // the pass (Algorithm 2.1, step 2)
-  if (P.kx == GN_SKETCH_SRHT) {
+    GN_TRY(launch_transpose(Y_user, P.m, P.rl, ldy, P.sdt, base + W.yt, P.m, s));
+  if (P.kx == GN_SKETCH_GAUSSIAN) {
+    GN_TRY(launch_gaussian(p->seed, 1, 0, 0, P.n, P.r, P.sdt, 1, base + W.xt, P.n, s));
+  } else if (P.kx == GN_SKETCH_USER) {
+    GN_TRY(launch_transpose(X_user, P.n, P.r, ldx, P.sdt, base + W.xt, P.n, s));
+  } else {
     int8_t* signs = (int8_t*)(base + W.signs);
     int32_t* idx = (int32_t*)(base + W.idx);
     GN_TRY(launch_srht(p->seed, P.npad, P.r, signs, idx, (uint64_t*)(base + W.keys), s));
-    GN_TRY(launch_pass_srht(P.mode, P.m, P.n, P.r, A, lda, A_scales, signs, idx, AX, ldax, s));
     if (signs_out && hipMemcpyAsync(signs_out, signs, (size_t)P.npad, hipMemcpyDeviceToDevice, s) !=
                          hipSuccess)
       return GN_ERR_HIP;
     if (idx_out && hipMemcpyAsync(idx_out, idx, (size_t)P.r * 4, hipMemcpyDeviceToDevice, s) !=
                        hipSuccess)
       return GN_ERR_HIP;
-  } else {
-    GN_TRY(launch_pass_ax(P.mode, P.m, P.n, P.r, A, lda, A_scales, Xt, P.n, AX, ldax, s));
   }
-  GN_TRY(launch_pass_yta(P.mode, P.m, P.n, P.rl, A, lda, A_scales, Yt, P.m, YtA, ldya, s));
   return GN_OK;
+}
+
+gn_status gn_sketch_pass(const gn_problem* p, const void* A, int64_t lda, const float* A_scales,
+                         void* AX, int64_t ldax, void* YtA, int64_t ldya, const void* ws,
+                         size_t ws_bytes, gn_stream_t stream_) {
+  Plan P;
+  GN_TRY(make_plan(p, P));
+  if (!A || !AX || !YtA || !ws) return GN_ERR_ARG;
+  if (P.mode == GN_MODE_BF16_BS && !A_scales) return GN_ERR_ARG;
+  if (lda < P.n || ldax < P.r || ldya < P.n) return GN_ERR_SHAPE;
+  if (!aligned16(A) || !aligned16(AX) || !aligned16(YtA) || !aligned16(ws)) return GN_ERR_ALIGN;
+  const SketchWs W = sketch_ws(P);
+  if (ws_bytes < W.total) return GN_ERR_WORKSPACE;
+  const char* base = (const char*)ws;
+  return launch_pass(P.mode, P.kx, P.m, P.n, P.r, P.rl, A, lda, A_scales, base + W.xt,
+                     (const int8_t*)(base + W.signs), (const int32_t*)(base + W.idx), base + W.yt,
+                     AX, ldax, YtA, ldya, (hipStream_t)stream_);
+}
+
+gn_status gn_sketch(const gn_problem* p, const void* A, int64_t lda, const float* A_scales,
+                    const void* X_user, int64_t ldx, const void* Y_user, int64_t ldy, void* AX,
+                    int64_t ldax, void* YtA, int64_t ldya, int8_t* signs_out, int32_t* idx_out,
+                    void* ws, size_t ws_bytes, gn_stream_t stream) {
+  Plan P;
+  GN_TRY(make_plan(p, P));
+  // validate the pass arguments before anything is enqueued
+  if (!A || !AX || !YtA || !ws) return GN_ERR_ARG;
+  if (P.mode == GN_MODE_BF16_BS && !A_scales) return GN_ERR_ARG;
+  if (lda < P.n || ldax < P.r || ldya < P.n) return GN_ERR_SHAPE;
+  if (!aligned16(A) || !aligned16(AX) || !aligned16(YtA) || !aligned16(ws)) return GN_ERR_ALIGN;
+  GN_TRY(gn_sketch_prepare(p, X_user, ldx, Y_user, ldy, signs_out, idx_out, ws, ws_bytes, stream));
+  return gn_sketch_pass(p, A, lda, A_scales, AX, ldax, YtA, ldya, ws, ws_bytes, stream);
 }
 
 gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void* Y_user, int64_t ldy,

@@ -22,6 +22,7 @@ namespace gn {
   } while (0)
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ __forceinline__ int64_t cdiv_d(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // ---------------------------------------------------------------------------- Philox4x32-10
@@ -108,19 +109,14 @@ gn_status launch_transpose(const void* in, int64_t rows, int64_t cols, int64_t l
                            void* out, int64_t ldo, hipStream_t s);
 size_t srht_ws_bytes(int64_t npad);
 
-// pass.hip : sketch-pass contractions and the SRHT transform
-// AX (m x r) = A (m x n) * Xt^T, with Xt (r x n) the transposed sketch.
-gn_status launch_pass_ax(int32_t mode, int64_t m, int64_t n, int64_t r, const void* A, int64_t lda,
-                         const float* scales, const void* Xt, int64_t ldxt, void* AX, int64_t ldax,
-                         hipStream_t s);
-// YtA ((r+l) x n) = Yt ((r+l) x m) * A (m x n).
-gn_status launch_pass_yta(int32_t mode, int64_t m, int64_t n, int64_t rl, const void* A,
-                          int64_t lda, const float* scales, const void* Yt, int64_t ldyt, void* YtA,
-                          int64_t ldya, hipStream_t s);
-// AX = A * (D H S): FWHT of sign-flipped rows of A, then sampling.
-gn_status launch_pass_srht(int32_t mode, int64_t m, int64_t n, int64_t r, const void* A, int64_t lda,
-                           const float* scales, const int8_t* signs, const int32_t* idx, void* AX,
-                           int64_t ldax, hipStream_t s);
+// pass.hip : the sketch pass, AX (m x r) and Y^T A (rl x n) from one launch in
+// FP32 and BF16 modes.  Xt is the transposed Gaussian or user sketch (r x n,
+// ld n; unused for SRHT), Yt the transposed Y (rl x m, ld m); signs / idx the
+// SRHT parameters (SRHT X only).
+gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_t r, int64_t rl,
+                      const void* A, int64_t lda, const float* scales, const void* Xt,
+                      const int8_t* signs, const int32_t* idx, const void* Yt, void* AX,
+                      int64_t ldax, void* YtA, int64_t ldya, hipStream_t s);
 
 // dgemm.hip : FP64 strided GEMM  D = alpha * op(A) op(B) + beta * D
 struct MatRef {

@@ -97,6 +97,37 @@ def gn_srht_generate(seed: int, n: int, r: int):
     return signs, idx
 
 
+def gn_sketch_prepare(p: Problem, ws: torch.Tensor, X_user=None, Y_user=None,
+                      want_srht: bool = False):
+    """Draw (or take) the sketches into the workspace ws; returns SRHT signs/idx
+    copies when asked."""
+    _need_cuda(ws, X_user, Y_user)
+    signs = idx = None
+    if want_srht and p.kind_x == "srht":
+        npad = 1 << max(0, (p.n - 1).bit_length())
+        signs = torch.empty(npad, dtype=torch.int8, device=ws.device)
+        idx = torch.empty(p.r, dtype=torch.int32, device=ws.device)
+    pc = p.c()
+    C.check(C.lib().gn_sketch_prepare(
+        ctypes.byref(pc), _ptr(X_user), X_user.stride(0) if X_user is not None else 0,
+        _ptr(Y_user), Y_user.stride(0) if Y_user is not None else 0, _ptr(signs), _ptr(idx),
+        _ptr(ws), ws.numel(), _stream()), "gn_sketch_prepare")
+    return signs, idx
+
+
+def gn_sketch_pass(p: Problem, A: torch.Tensor, ws: torch.Tensor, scales=None, AX=None, YtA=None):
+    """The single pass over A: AX and Y^T A from the sketches in a prepared ws."""
+    _need_cuda(A, ws, scales)
+    acc = ACCUM_TORCH[p.mode]
+    AX = torch.empty(p.m, p.r, dtype=acc, device=A.device) if AX is None else AX
+    YtA = torch.empty(p.rl, p.n, dtype=acc, device=A.device) if YtA is None else YtA
+    pc = p.c()
+    C.check(C.lib().gn_sketch_pass(ctypes.byref(pc), _ptr(A), A.stride(0), _ptr(scales), _ptr(AX),
+                                   AX.stride(0), _ptr(YtA), YtA.stride(0), _ptr(ws), ws.numel(),
+                                   _stream()), "gn_sketch_pass")
+    return AX, YtA
+
+
 def gn_sketch(p: Problem, A: torch.Tensor, scales=None, X_user=None, Y_user=None, AX=None,
               YtA=None, want_srht: bool = False, ws=None):
     """AX (m x r) and Y^T A ((r+l) x n); optionally the SRHT signs and sample."""
