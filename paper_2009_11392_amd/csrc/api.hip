@@ -221,15 +221,27 @@ gn_status gn_sketch_prepare(const gn_problem* p, const void* X_user, int64_t ldx
   const SketchWs W = sketch_ws(P);
   if (ws_bytes < W.total) return GN_ERR_WORKSPACE;
   char* base = (char*)ws;
-  // Algorithm 2.1, step 1: the sketches, stored transposed (k-contiguous)
-  if (P.ky == GN_SKETCH_GAUSSIAN)
-    GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, P.sdt, 1, base + W.yt, P.m, s));
-  else
+  // Algorithm 2.1, step 1: the sketches.  FP64/FP32 passes read X (n x r) and
+  // Y (m x (r+l)) row-major; the BF16 pass reads them transposed (k-contiguous).
+  const int lay = (P.mode == GN_MODE_BF16_BS) ? 1 : 0;
+  const size_t es = dtype_size(P.sdt);
+  if (P.ky == GN_SKETCH_GAUSSIAN) {
+    GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, P.sdt, lay, base + W.yt, lay ? P.m : P.rl, s));
+  } else if (lay) {
     GN_TRY(launch_transpose(Y_user, P.m, P.rl, ldy, P.sdt, base + W.yt, P.m, s));
+  } else if (hipMemcpy2DAsync(base + W.yt, P.rl * es, Y_user, ldy * es, P.rl * es, P.m,
+                              hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    return GN_ERR_HIP;
+  }
   if (P.kx == GN_SKETCH_GAUSSIAN) {
-    GN_TRY(launch_gaussian(p->seed, 1, 0, 0, P.n, P.r, P.sdt, 1, base + W.xt, P.n, s));
+    GN_TRY(launch_gaussian(p->seed, 1, 0, 0, P.n, P.r, P.sdt, lay, base + W.xt, lay ? P.n : P.r, s));
   } else if (P.kx == GN_SKETCH_USER) {
-    GN_TRY(launch_transpose(X_user, P.n, P.r, ldx, P.sdt, base + W.xt, P.n, s));
+    if (lay) {
+      GN_TRY(launch_transpose(X_user, P.n, P.r, ldx, P.sdt, base + W.xt, P.n, s));
+    } else if (hipMemcpy2DAsync(base + W.xt, P.r * es, X_user, ldx * es, P.r * es, P.n,
+                                hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      return GN_ERR_HIP;
+    }
   } else {
     int8_t* signs = (int8_t*)(base + W.signs);
     int32_t* idx = (int32_t*)(base + W.idx);

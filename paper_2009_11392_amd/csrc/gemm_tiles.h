@@ -1,11 +1,10 @@
 // Matrix-core tile bodies for the sketch pass (device functions; each fused
 // pass kernel calls one of them per workgroup).
 //
-// FP32: v_mfma_f32_32x32x2_f32.  BF16: v_mfma_f32_32x32x16_bf16.  Both: 256
-// threads = 4 waves in 2 x 2, workgroup tile 128 x 128, wave tile 64 x 64 = 2 x 2
-// MFMA blocks, K staged through LDS double buffered, FP32 accumulation.  The
-// 32 x 32 accumulator of lane l holds, in register v, row 8(v/4) + 4(l/32) + v%4
-// and column l%32 of its block.
+// FP32: v_mfma_f32_32x32x2_f32 or v_mfma_f32_16x16x4_f32, tile shape a template
+// parameter (F32Cfg).  BF16: v_mfma_f32_32x32x16_bf16, 256 threads = 4 waves in
+// 2 x 2, workgroup tile 128 x 128, wave tile 64 x 64 = 2 x 2 MFMA blocks.  K is
+// staged through LDS double buffered; FP32 accumulation.
 #pragma once
 
 #include "gn_internal.h"
@@ -57,8 +56,11 @@ inline int64_t gemm_groups(int64_t M, int64_t N) {  // groups of 8 workgroups
 constexpr int T_BM = 128, T_BN = 128;
 
 // ------------------------------------------------------------------ FP32
-// D (M x N) = A (M x K) B (K x N).  A_KC: A(i,k) = A[i*lda + k], else A[k*lda + i].
-// B_KC: B(k,j) = B[j*ldb + k], else B[k*ldb + j].  LDS holds both operands k-major.
+// D (M x N) = A (M x K) B (K x N), FP32 in, FP32 accumulation.
+//   A_KC: A(i,k) = A[i*lda + k] (k-contiguous), else A[k*lda + i] (m-contiguous).
+//   B_KC: B(k,j) = B[j*ldb + k] (k-contiguous), else B[k*ldb + j] (n-contiguous).
+// LDS holds both operands k-major, S[k][row]: m/n-contiguous operands are
+// stored with 16-byte writes, k-contiguous ones are transposed on the way in.
 struct GemmF32 {
   int64_t M, N, K;
   const float* A;
@@ -70,135 +72,170 @@ struct GemmF32 {
   int inner_is_m;  // consecutive tiles walk M (share the B panel) or N (share A)
 };
 
-constexpr int F_BK = 16, F_LD = T_BM + 4;
-constexpr size_t F_SMEM = 2 * 2 * F_BK * F_LD * sizeof(float);
+// Tile shape: BM x BN per workgroup of WM x WN waves, K staged BK deep, double
+// buffered; MF = 32 (v_mfma_f32_32x32x2_f32) or 16 (v_mfma_f32_16x16x4_f32).
+template <int BM_, int BN_, int BK_, int WM_, int WN_, int MF_>
+struct F32Cfg {
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, MF = MF_;
+  static constexpr int T = 64 * WM * WN;
+  static constexpr int TM = BM / WM, TN = BN / WN;      // wave tile
+  static constexpr int FM = TM / MF, FN = TN / MF;      // MFMA blocks per wave
+  static constexpr int KSTEP = (MF == 32) ? 2 : 4;
+  static constexpr int NACC = (MF == 32) ? 16 : 4;
+  template <bool KC>
+  static constexpr int ld(int rows) { return rows + (KC ? 1 : 4); }
+  template <bool A_KC, bool B_KC>
+  static constexpr size_t smem() {
+    return 2 * (size_t)BK * (ld<A_KC>(BM) + ld<B_KC>(BN)) * sizeof(float);
+  }
+};
 
-template <bool KC, bool VEC>
-__device__ __forceinline__ void f32_load(const float* __restrict__ P, int64_t ld, int64_t rows,
-                                         int64_t K, int64_t r0, int64_t k0, f32x4 (&reg)[2]) {
-  const int tid = threadIdx.x;
+// Global -> registers for one operand tile (ROWS x BK) of the K slab at k0.
+template <int ROWS, int BK, int T, bool KC, bool VEC>
+struct F32Stage {
+  static constexpr int NV = ROWS * BK / 4 / T;  // float4 per thread
+  static_assert(NV * 4 * T == ROWS * BK, "tile not divisible");
+  f32x4 v[NV];
+  __device__ __forceinline__ void load(const float* __restrict__ P, int64_t ld, int64_t rows,
+                                       int64_t K, int64_t r0, int64_t k0) {
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int e = tid + 256 * q;
-    int64_t row, k;
-    if (KC) {
-      row = r0 + (e >> 2);
-      k = k0 + 4 * (e & 3);
-    } else {
-      k = k0 + (e >> 5);
-      row = r0 + 4 * (e & 31);
-    }
-    f32x4 v = {0.f, 0.f, 0.f, 0.f};
-    if (KC) {
-      if (row < rows) {
-        const float* src = P + row * ld + k;
-        if (VEC && k + 3 < K) {
-          v = *reinterpret_cast<const f32x4*>(src);
-        } else {
+    for (int q = 0; q < NV; ++q) {
+      const int e = threadIdx.x + T * q;
+      int64_t row, k;
+      if (KC) {
+        row = r0 + e / (BK / 4);
+        k = k0 + 4 * (e % (BK / 4));
+      } else {
+        k = k0 + e / (ROWS / 4);
+        row = r0 + 4 * (e % (ROWS / 4));
+      }
+      f32x4 x = {0.f, 0.f, 0.f, 0.f};
+      if (KC) {
+        if (row < rows) {
+          const float* src = P + row * ld + k;
+          if (VEC && k + 3 < K) {
+            x = *reinterpret_cast<const f32x4*>(src);
+          } else {
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (k + t < K) v[t] = src[t];
+            for (int t = 0; t < 4; ++t)
+              if (k + t < K) x[t] = src[t];
+          }
+        }
+      } else {
+        if (k < K) {
+          const float* src = P + k * ld + row;
+          if (VEC && row + 3 < rows) {
+            x = *reinterpret_cast<const f32x4*>(src);
+          } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (row + t < rows) x[t] = src[t];
+          }
         }
       }
-    } else {
-      if (k < K) {
-        const float* src = P + k * ld + row;
-        if (VEC && row + 3 < rows) {
-          v = *reinterpret_cast<const f32x4*>(src);
-        } else {
+      v[q] = x;
+    }
+  }
+  __device__ __forceinline__ void store(float* S) const {
+    constexpr int LD = ROWS + (KC ? 1 : 4);
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (row + t < rows) v[t] = src[t];
-        }
+    for (int q = 0; q < NV; ++q) {
+      const int e = threadIdx.x + T * q;
+      if (KC) {
+        const int row = e / (BK / 4), k = 4 * (e % (BK / 4));
+#pragma unroll
+        for (int t = 0; t < 4; ++t) S[(k + t) * LD + row] = v[q][t];
+      } else {
+        const int k = e / (ROWS / 4), row = 4 * (e % (ROWS / 4));
+        *reinterpret_cast<f32x4*>(S + k * LD + row) = v[q];
       }
     }
-    reg[q] = v;
   }
-}
+};
 
-template <bool KC>
-__device__ __forceinline__ void f32_store(float* S, const f32x4 (&reg)[2]) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int e = tid + 256 * q;
-    if (KC) {
-      const int row = e >> 2, k = 4 * (e & 3);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) S[(k + t) * F_LD + row] = reg[q][t];
-    } else {
-      const int k = e >> 5, row = 4 * (e & 31);
-      *reinterpret_cast<f32x4*>(S + k * F_LD + row) = reg[q];
-    }
-  }
-}
-
-template <bool A_KC, bool B_KC, bool VEC>
-__device__ void f32_tile(const GemmF32& g, int64_t local, char* smem) {
-  float* sA = reinterpret_cast<float*>(smem);           // [2][F_BK * F_LD]
-  float* sB = sA + 2 * F_BK * F_LD;                       // [2][F_BK * F_LD]
-  const int64_t tm_n = cdiv_d(g.M, T_BM), tn_n = cdiv_d(g.N, T_BN);
+template <class CF, bool A_KC, bool B_KC, bool VEC>
+__device__ void f32_tile_cfg(const GemmF32& g, int64_t local, char* smem) {
+  constexpr int BM = CF::BM, BN = CF::BN, BK = CF::BK, MF = CF::MF;
+  constexpr int LDA = CF::template ld<A_KC>(BM), LDB = CF::template ld<B_KC>(BN);
+  typedef float accv __attribute__((ext_vector_type(CF::NACC)));
+  float* sA = reinterpret_cast<float*>(smem);  // [2][BK * LDA]
+  float* sB = sA + 2 * BK * LDA;               // [2][BK * LDB]
+  const int64_t tm_n = cdiv_d(g.M, BM), tn_n = cdiv_d(g.N, BN);
   int64_t tm, tn;
   if (g.inner_is_m) {
     if (!xcd_tile(local, tm_n, tn_n, tm, tn)) return;
   } else {
     if (!xcd_tile(local, tn_n, tm_n, tn, tm)) return;
   }
-  const int64_t i0 = tm * T_BM, j0 = tn * T_BN;
+  const int64_t i0 = tm * BM, j0 = tn * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  const int li = lane & 31, lk = lane >> 5;
-  f32x16 acc[2][2];
+  const int wm = wave % CF::WM, wn = wave / CF::WM;
+  const int li = lane % MF, lk = lane / MF;
+  accv acc[CF::FM][CF::FN];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < CF::FM; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < CF::FN; ++y)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.f;
+      for (int v = 0; v < CF::NACC; ++v) acc[x][y][v] = 0.f;
 
-  const int64_t nk = cdiv_d(g.K, F_BK);
-  f32x4 ra[2], rb[2];
-  f32_load<A_KC, VEC>(g.A, g.lda, g.M, g.K, i0, 0, ra);
-  f32_load<B_KC, VEC>(g.B, g.ldb, g.N, g.K, j0, 0, rb);
-  f32_store<A_KC>(sA, ra);
-  f32_store<B_KC>(sB, rb);
+  F32Stage<BM, BK, CF::T, A_KC, VEC> sa;
+  F32Stage<BN, BK, CF::T, B_KC, VEC> sb;
+  const int64_t nk = cdiv_d(g.K, BK);
+  sa.load(g.A, g.lda, g.M, g.K, i0, 0);
+  sb.load(g.B, g.ldb, g.N, g.K, j0, 0);
+  sa.store(sA);
+  sb.store(sB);
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      f32_load<A_KC, VEC>(g.A, g.lda, g.M, g.K, i0, (kt + 1) * F_BK, ra);
-      f32_load<B_KC, VEC>(g.B, g.ldb, g.N, g.K, j0, (kt + 1) * F_BK, rb);
+      sa.load(g.A, g.lda, g.M, g.K, i0, (kt + 1) * BK);
+      sb.load(g.B, g.ldb, g.N, g.K, j0, (kt + 1) * BK);
     }
-    const float* a_s = sA + cur * F_BK * F_LD;
-    const float* b_s = sB + cur * F_BK * F_LD;
+    const float* a_s = sA + cur * BK * LDA + wm * CF::TM + li;
+    const float* b_s = sB + cur * BK * LDB + wn * CF::TN + li;
 #pragma unroll
-    for (int kk = 0; kk < F_BK; kk += 2) {
-      const float a0 = a_s[(kk + lk) * F_LD + wm * 64 + li];
-      const float a1 = a_s[(kk + lk) * F_LD + wm * 64 + 32 + li];
-      const float b0 = b_s[(kk + lk) * F_LD + wn * 64 + li];
-      const float b1 = b_s[(kk + lk) * F_LD + wn * 64 + 32 + li];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+    for (int kk = 0; kk < BK; kk += CF::KSTEP) {
+      float af[CF::FM], bf[CF::FN];
+#pragma unroll
+      for (int x = 0; x < CF::FM; ++x) af[x] = a_s[(kk + lk) * LDA + x * MF];
+#pragma unroll
+      for (int y = 0; y < CF::FN; ++y) bf[y] = b_s[(kk + lk) * LDB + y * MF];
+#pragma unroll
+      for (int x = 0; x < CF::FM; ++x)
+#pragma unroll
+        for (int y = 0; y < CF::FN; ++y) {
+          if constexpr (MF == 32)
+            acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[x], bf[y], acc[x][y], 0, 0, 0);
+          else
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[x], bf[y], acc[x][y], 0, 0, 0);
+        }
     }
     if (kt + 1 < nk) {
-      f32_store<A_KC>(sA + (cur ^ 1) * F_BK * F_LD, ra);
-      f32_store<B_KC>(sB + (cur ^ 1) * F_BK * F_LD, rb);
+      sa.store(sA + (cur ^ 1) * BK * LDA);
+      sb.store(sB + (cur ^ 1) * BK * LDB);
     }
     __syncthreads();
   }
+  // accumulator layouts: 32x32 -- register v of lane l is row 8(v/4) + 4(l/32) + v%4;
+  // 16x16 -- row 4(l/16) + v; column l % MF in both.
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < CF::FM; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < CF::FN; ++y)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = i0 + wm * 64 + x * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
-        const int64_t col = j0 + wn * 64 + y * 32 + li;
+      for (int v = 0; v < CF::NACC; ++v) {
+        const int rr = (MF == 32) ? (8 * (v >> 2) + 4 * lk + (v & 3)) : (4 * lk + v);
+        const int64_t row = i0 + wm * CF::TM + x * MF + rr;
+        const int64_t col = j0 + wn * CF::TN + y * MF + li;
         if (row < g.M && col < g.N) g.D[row * g.ldd + col] = acc[x][y][v];
       }
 }
+
+// The production FP32 configuration of the sketch pass: 256 x 256 tiles, 16 waves
+// (4 x 4, wave tile 64 x 64), K staged 32 deep.
+using F32Pass = F32Cfg<256, 256, 32, 4, 4, 32>;
 
 // ------------------------------------------------------------------ BF16 with block scales
 // A(i,k) = PA[i*lda + k] (k-contiguous; the matrix A when A_IS_MAT, then scaled);

@@ -24,9 +24,10 @@ namespace {
 using namespace tiles;
 
 constexpr int SR_CHUNK = 512;
-constexpr int64_t SR_ROWS_PER_WG = 16;
+constexpr int SR_MAX_WAVES = 16;
 
 struct SrhtArgs {
+  int64_t rows_per_wg;
   int64_t m, n, r;
   const void* A;
   int64_t lda;
@@ -77,15 +78,16 @@ __device__ __forceinline__ void srht_load8(const SrhtArgs& a, int64_t i, int64_t
   }
 }
 
-// Rows [local * SR_ROWS_PER_WG, ...) of AX = A D H S.  Each wave owns one row
-// at a time (rows advance by 4 per step for the 4 waves).
+// Rows [local * rows_per_wg, ...) of AX = A D H S.  Each wave owns one row at a
+// time (rows advance by the number of waves per step); at most 16 waves.
 template <typename T, int MODE, int RPL>
 __device__ void srht_rows(const SrhtArgs& a, int64_t local, char* smem) {
   T(*slot)[SR_CHUNK] = reinterpret_cast<T(*)[SR_CHUNK]>(smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t row_begin = local * SR_ROWS_PER_WG;
+  const int nw = (int)(blockDim.x >> 6);
+  const int64_t row_begin = local * a.rows_per_wg;
   if (row_begin >= a.m) return;
-  const int64_t row_end = (row_begin + SR_ROWS_PER_WG < a.m) ? row_begin + SR_ROWS_PER_WG : a.m;
+  const int64_t row_end = (row_begin + a.rows_per_wg < a.m) ? row_begin + a.rows_per_wg : a.m;
   int32_t s_lo[RPL], s_hi[RPL];
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
@@ -94,7 +96,7 @@ __device__ void srht_rows(const SrhtArgs& a, int64_t local, char* smem) {
     s_lo[t] = sv & (SR_CHUNK - 1);
     s_hi[t] = sv >> 9;
   }
-  for (int64_t ib = row_begin; ib < row_end; ib += 4) {
+  for (int64_t ib = row_begin; ib < row_end; ib += nw) {
     const int64_t i = ib + wave;
     const bool active = i < row_end;
     T acc[RPL];
@@ -171,29 +173,49 @@ __device__ void srht_rows(const SrhtArgs& a, int64_t local, char* smem) {
   }
 }
 
-constexpr size_t SR_SMEM_F32 = 4 * SR_CHUNK * sizeof(float);
-constexpr size_t SR_SMEM_F64 = 4 * SR_CHUNK * sizeof(double);
+constexpr size_t SR_SMEM_F32 = SR_MAX_WAVES * SR_CHUNK * sizeof(float);
+constexpr size_t SR_SMEM_F64 = 4 * SR_CHUNK * sizeof(double);  // launched with 4 waves
 constexpr size_t smax(size_t a, size_t b) { return a > b ? a : b; }
 
 // ------------------------------------------------------------------ fused kernels
-template <bool VEC>
-__global__ void __launch_bounds__(256) pass_f32_gauss(GemmF32 yta, GemmF32 ax, int64_t gY, int64_t gA) {
-  __shared__ __attribute__((aligned(16))) char smem[F_SMEM];
-  int64_t local;
-  if (family_split(gY, gA, local))
-    f32_tile<true, false, VEC>(yta, local, smem);
-  else
-    f32_tile<true, true, VEC>(ax, local, smem);
+// Which family a workgroup belongs to: interleaved (family_split) or, with
+// srht_first, the SRHT rows occupy the first gS groups of the grid.
+__device__ __forceinline__ bool take_first(int64_t gFirst, int64_t gSecond, int first_then_second,
+                                           int64_t& local) {
+  if (!first_then_second) return family_split(gFirst, gSecond, local);
+  const int64_t g = (int64_t)blockIdx.x >> 3, x = (int64_t)blockIdx.x & 7;
+  if (g < gFirst) {
+    local = g * 8 + x;
+    return true;
+  }
+  local = (g - gFirst) * 8 + x;
+  return false;
 }
 
-template <int RPL, bool VEC>
-__global__ void __launch_bounds__(256) pass_f32_srht(GemmF32 yta, SrhtArgs sr, int64_t gY, int64_t gS) {
-  __shared__ __attribute__((aligned(16))) char smem[smax(F_SMEM, SR_SMEM_F32)];
+// FP32: Y^T A reads Y (m x rl, row-major) and A both m/n-contiguous; AX reads A
+// k-contiguous and X (n x r, row-major) n-contiguous.
+template <class CF, bool VEC>
+__global__ void __launch_bounds__(CF::T) pass_f32_gauss(GemmF32 yta, GemmF32 ax, int64_t gY,
+                                                        int64_t gA) {
+  __shared__ __attribute__((aligned(16))) char smem[smax(CF::template smem<false, false>(),
+                                                         CF::template smem<true, false>())];
   int64_t local;
-  if (family_split(gY, gS, local))
-    f32_tile<true, false, VEC>(yta, local, smem);
+  if (family_split(gY, gA, local))
+    f32_tile_cfg<CF, false, false, VEC>(yta, local, smem);
   else
+    f32_tile_cfg<CF, true, false, VEC>(ax, local, smem);
+}
+
+template <class CF, int RPL, bool VEC>
+__global__ void __launch_bounds__(CF::T) pass_f32_srht(GemmF32 yta, SrhtArgs sr, int64_t gY,
+                                                       int64_t gS, int srht_first) {
+  __shared__ __attribute__((aligned(16))) char smem[smax(CF::template smem<false, false>(),
+                                                         SR_SMEM_F32)];
+  int64_t local;
+  if (take_first(gS, gY, srht_first, local))
     srht_rows<float, GN_MODE_F32, RPL>(sr, local, smem);
+  else
+    f32_tile_cfg<CF, false, false, VEC>(yta, local, smem);
 }
 
 __global__ void __launch_bounds__(256) pass_bf16_gauss(GemmBF16 yta, GemmBF16 ax, int64_t gY, int64_t gA) {
@@ -237,59 +259,81 @@ int srht_rpl(int64_t r) {
     default: return GN_ERR_UNSUPPORTED; \
   }
 
+// Production FP32 schedule: SRHT rows first (they are HBM-bound and short),
+// then the Y^T A tiles; 16 rows per SRHT workgroup.
+constexpr int kSrhtFirst = 1;
+constexpr int64_t kSrhtRows = 16;
+
+// FP32 pass with tile configuration CF: one launch, SRHT rows or the AX tiles as
+// the second family.
+template <class CF>
+gn_status launch_f32_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_t m, int64_t n,
+                         int64_t r, int64_t rl, const float* A, int64_t lda, const float* X,
+                         const float* Y, SrhtArgs sr, float* AX, int64_t ldax, float* YtA,
+                         int64_t ldya, hipStream_t s) {
+  GemmF32 yta{rl, n, m, Y, rl, A, lda, YtA, ldya, 1};
+  const int64_t gY = cdiv(cdiv(rl, CF::BM) * cdiv(n, CF::BN), 8);
+  bool vec = (lda % 4 == 0) && (rl % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)Y % 16 == 0);
+  if (srht) {
+    sr.rows_per_wg = rows_per_wg;
+    const int64_t gS = cdiv(cdiv(m, rows_per_wg), 8);
+    const dim3 grid((unsigned)(8 * (gY + gS)));
+    const int rpl = srht_rpl(r);
+#define GN_F32S(R)                                                                            \
+  if (vec)                                                                                    \
+    pass_f32_srht<CF, R, true><<<grid, dim3(CF::T), 0, s>>>(yta, sr, gY, gS, srht_first);      \
+  else                                                                                        \
+    pass_f32_srht<CF, R, false><<<grid, dim3(CF::T), 0, s>>>(yta, sr, gY, gS, srht_first)
+    GN_RPL_SWITCH(rpl, GN_F32S)
+#undef GN_F32S
+  } else {
+    GemmF32 ax{m, r, n, A, lda, X, r, AX, ldax, 0};
+    const int64_t gA = cdiv(cdiv(m, CF::BM) * cdiv(r, CF::BN), 8);
+    vec = vec && (r % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    const dim3 grid((unsigned)(8 * (gY + gA)));
+    if (vec)
+      pass_f32_gauss<CF, true><<<grid, dim3(CF::T), 0, s>>>(yta, ax, gY, gA);
+    else
+      pass_f32_gauss<CF, false><<<grid, dim3(CF::T), 0, s>>>(yta, ax, gY, gA);
+  }
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
 }  // namespace
 
 gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_t r, int64_t rl,
-                      const void* A, int64_t lda, const float* scales, const void* Xt,
-                      const int8_t* signs, const int32_t* idx, const void* Yt, void* AX,
+                      const void* A, int64_t lda, const float* scales, const void* Xs,
+                      const int8_t* signs, const int32_t* idx, const void* Ys, void* AX,
                       int64_t ldax, void* YtA, int64_t ldya, hipStream_t s) {
+  // F64 / F32: Xs = X (n x r, ld r), Ys = Y (m x rl, ld rl).
+  // BF16:      Xs = X^T (r x n, ld n), Ys = Y^T (rl x m, ld m).
+  const void* Xt = Xs;
+  const void* Yt = Ys;
   const bool srht = (kind_x == GN_SKETCH_SRHT);
   const int64_t nsb = cdiv(n, 128);
-  SrhtArgs sr{m, n, r, A, lda, scales, nsb, signs, idx, AX, ldax};
-  const int64_t gS = cdiv(cdiv(m, SR_ROWS_PER_WG), 8);
+  SrhtArgs sr{16, m, n, r, A, lda, scales, nsb, signs, idx, AX, ldax};
   const int rpl = srht ? srht_rpl(r) : 1;
 
   if (mode == GN_MODE_F64) {
     if (srht) {
-      const dim3 grid((unsigned)cdiv(m, SR_ROWS_PER_WG));
+      const dim3 grid((unsigned)cdiv(m, sr.rows_per_wg));
 #define GN_F64S(R) pass_f64_srht<R><<<grid, dim3(256), 0, s>>>(sr)
       GN_RPL_SWITCH(rpl, GN_F64S)
 #undef GN_F64S
       GN_LAUNCH_CHECK();
     } else {
-      GN_TRY(launch_dgemm(m, r, n, 1.0, MatRef{A, GN_DT_F64, lda, 1}, MatRef{Xt, GN_DT_F64, 1, n},
+      GN_TRY(launch_dgemm(m, r, n, 1.0, MatRef{A, GN_DT_F64, lda, 1}, MatRef{Xs, GN_DT_F64, r, 1},
                           0.0, (double*)AX, ldax, 1, nullptr, false, s));
     }
-    return launch_dgemm(rl, n, m, 1.0, MatRef{Yt, GN_DT_F64, m, 1}, MatRef{A, GN_DT_F64, lda, 1},
+    return launch_dgemm(rl, n, m, 1.0, MatRef{Ys, GN_DT_F64, 1, rl}, MatRef{A, GN_DT_F64, lda, 1},
                         0.0, (double*)YtA, ldya, 1, nullptr, false, s);
   }
 
-  if (mode == GN_MODE_F32) {
-    GemmF32 yta{rl, n, m, (const float*)Yt, m, (const float*)A, lda, (float*)YtA, ldya, 1};
-    const int64_t gY = gemm_groups(rl, n);
-    bool vec = (lda % 4 == 0) && (m % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)Yt % 16 == 0);
-    if (srht) {
-      const dim3 grid((unsigned)(8 * (gY + gS)));
-#define GN_F32S(R)                                                                   \
-  if (vec)                                                                           \
-    pass_f32_srht<R, true><<<grid, dim3(256), 0, s>>>(yta, sr, gY, gS);              \
-  else                                                                               \
-    pass_f32_srht<R, false><<<grid, dim3(256), 0, s>>>(yta, sr, gY, gS)
-      GN_RPL_SWITCH(rpl, GN_F32S)
-#undef GN_F32S
-    } else {
-      GemmF32 ax{m, r, n, (const float*)A, lda, (const float*)Xt, n, (float*)AX, ldax, 0};
-      const int64_t gA = gemm_groups(m, r);
-      vec = vec && (n % 4 == 0) && ((uintptr_t)Xt % 16 == 0);
-      const dim3 grid((unsigned)(8 * (gY + gA)));
-      if (vec)
-        pass_f32_gauss<true><<<grid, dim3(256), 0, s>>>(yta, ax, gY, gA);
-      else
-        pass_f32_gauss<false><<<grid, dim3(256), 0, s>>>(yta, ax, gY, gA);
-    }
-    GN_LAUNCH_CHECK();
-    return GN_OK;
-  }
+  if (mode == GN_MODE_F32)
+    return launch_f32_cfg<F32Pass>(srht, kSrhtFirst, kSrhtRows, m, n, r, rl, (const float*)A, lda,
+                                   (const float*)Xs, (const float*)Ys, sr, (float*)AX, ldax,
+                                   (float*)YtA, ldya, s);
 
   // BF16 with block scales
   const bool vec_y = (lda % 8 == 0) && (m % 8 == 0) && ((uintptr_t)A % 16 == 0) &&
@@ -298,6 +342,7 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
                (float*)YtA, ldya, 1, vec_y ? 1 : 0};
   const int64_t gY = gemm_groups(rl, n);
   if (srht) {
+    const int64_t gS = cdiv(cdiv(m, sr.rows_per_wg), 8);
     const dim3 grid((unsigned)(8 * (gY + gS)));
 #define GN_BFS(R) pass_bf16_srht<R><<<grid, dim3(256), 0, s>>>(yta, sr, gY, gS)
     GN_RPL_SWITCH(rpl, GN_BFS)
