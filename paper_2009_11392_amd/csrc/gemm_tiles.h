@@ -7,6 +7,8 @@
 // staged through LDS double buffered; FP32 accumulation.
 #pragma once
 
+#include <type_traits>
+
 #include "gn_internal.h"
 
 namespace gn {
@@ -49,11 +51,6 @@ __device__ __forceinline__ bool xcd_tile(int64_t local, int64_t tiles_inner, int
   return true;
 }
 
-inline int64_t gemm_groups(int64_t M, int64_t N) {  // groups of 8 workgroups
-  return cdiv(cdiv(M, 128) * cdiv(N, 128), 8);
-}
-
-constexpr int T_BM = 128, T_BN = 128;
 
 // ------------------------------------------------------------------ FP32
 // D (M x N) = A (M x K) B (K x N), FP32 in, FP32 accumulation.
@@ -240,7 +237,8 @@ using F32Pass = F32Cfg<256, 256, 32, 4, 4, 32>;
 // ------------------------------------------------------------------ BF16 with block scales
 // A(i,k) = PA[i*lda + k] (k-contiguous; the matrix A when A_IS_MAT, then scaled);
 // B(k,j) = PB[j*ldb + k] when B_KC, else PB[k*ldb + j] (the matrix A, scaled).
-// LDS holds both operands k-contiguous, S[row][k], 40 bf16 per row.
+// LDS holds both operands k-contiguous, S[row][k] (row stride BK + 8 bf16), the
+// layout the bf16 MFMA fragments read with one 16-byte load per lane.
 struct GemmBF16 {
   int64_t M, N, K;
   const uint16_t* A;
@@ -255,8 +253,15 @@ struct GemmBF16 {
   int vec;
 };
 
-constexpr int B_BK = 32, B_LD = B_BK + 8;
-constexpr size_t B_SMEM = 2 * 2 * T_BM * B_LD * sizeof(uint16_t);
+template <int BM_, int BN_, int BK_, int WM_, int WN_>
+struct BF16Cfg {
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+  static constexpr int T = 64 * WM * WN;
+  static constexpr int TM = BM / WM, TN = BN / WN;
+  static constexpr int FM = TM / 32, FN = TN / 32;
+  static constexpr int LDK = BK + 8;
+  static constexpr size_t smem() { return 2 * (size_t)(BM + BN) * LDK * sizeof(uint16_t); }
+};
 
 // Multiply two packed bfloat16 values by a power of two (exact).
 __device__ __forceinline__ uint32_t scale_bf16x2(uint32_t w, float s) {
@@ -265,175 +270,208 @@ __device__ __forceinline__ uint32_t scale_bf16x2(uint32_t w, float s) {
   return (__float_as_uint(lo) >> 16) | (__float_as_uint(hi) & 0xffff0000u);
 }
 
-template <bool SCALED>
-__device__ __forceinline__ void bf_load_kc(const uint16_t* __restrict__ P, int64_t ld, int64_t rows,
-                                           int64_t K, int64_t r0, int64_t k0,
-                                           const float* __restrict__ scales, int64_t nsb, bool vec,
-                                           u32x4 (&reg)[2]) {
+// k-contiguous operand tile (ROWS x BK): 16-byte chunks straight into S[row][k].
+// load() only issues the global loads (the prefetch of the next K slab); the
+// block scale is applied in store(), after the current slab's MFMAs.
+template <int ROWS, int BK, int T, bool SCALED>
+struct BFStageKC {
+  static constexpr int NV = ROWS * BK / 8 / T;
+  static_assert(NV * 8 * T == ROWS * BK, "tile not divisible");
+  u32x4 v[NV];
+  float sc[SCALED ? NV : 1];
+  __device__ __forceinline__ void load(const uint16_t* __restrict__ P, int64_t ld, int64_t rows,
+                                       int64_t K, int64_t r0, int64_t k0,
+                                       const float* __restrict__ scales, int64_t nsb, bool vec) {
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    const int64_t row = r0 + (e >> 2), k = k0 + 8 * (e & 3);
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (row < rows && k < K) {
-      const uint16_t* src = P + row * ld + k;
-      if (vec && k + 7 < K) {
-        v = *reinterpret_cast<const u32x4*>(src);
-      } else {
+    for (int q = 0; q < NV; ++q) {
+      const int e = threadIdx.x + T * q;
+      const int64_t row = r0 + e / (BK / 8), k = k0 + 8 * (e % (BK / 8));
+      u32x4 x = {0u, 0u, 0u, 0u};
+      float s = 0.f;
+      if (row < rows && k < K) {
+        const uint16_t* src = P + row * ld + k;
+        if (vec && k + 7 < K) {
+          x = *reinterpret_cast<const u32x4*>(src);
+        } else {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const uint32_t b = (k + t < K) ? src[t] : 0u;
-          v[t >> 1] |= b << (16 * (t & 1));
+          for (int t = 0; t < 8; ++t) {
+            const uint32_t b = (k + t < K) ? src[t] : 0u;
+            x[t >> 1] |= b << (16 * (t & 1));
+          }
         }
+        if (SCALED) s = scales[(row >> 7) * nsb + (k >> 7)];
       }
-      if (SCALED) {
-        const float s = scales[(row >> 7) * nsb + (k >> 7)];
+      v[q] = x;
+      if (SCALED) sc[q] = s;
+    }
+  }
+  __device__ __forceinline__ void store(uint16_t* S) const {
+    constexpr int LDK = BK + 8;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) v[t] = scale_bf16x2(v[t], s);
+    for (int q = 0; q < NV; ++q) {
+      const int e = threadIdx.x + T * q;
+      const int row = e / (BK / 8), kc = 8 * (e % (BK / 8));
+      u32x4 x = v[q];
+      if (SCALED) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x[t] = scale_bf16x2(x[t], sc[q]);
+      }
+      *reinterpret_cast<u32x4*>(S + row * LDK + kc) = x;
+    }
+  }
+};
+
+// n-contiguous matrix operand (BK x COLS, scaled) transposed into S[j][k]: a task
+// reads rows k, k+1 at 8 consecutive j and writes eight (k, k+1) pairs.  As in
+// BFStageKC, scaling happens in store().
+template <int COLS, int BK, int T>
+struct BFStageNC {
+  static constexpr int TASKS = (BK / 2) * (COLS / 8);
+  static constexpr int NT = (TASKS + T - 1) / T;
+  u32x4 v0[NT], v1[NT];
+  float sc[NT];
+  __device__ __forceinline__ void load(const uint16_t* __restrict__ P, int64_t ld, int64_t cols,
+                                       int64_t K, int64_t j0, int64_t k0,
+                                       const float* __restrict__ scales, int64_t nsb, bool vec) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int task = threadIdx.x + T * q;
+      v0[q] = u32x4{0u, 0u, 0u, 0u};
+      v1[q] = u32x4{0u, 0u, 0u, 0u};
+      sc[q] = 0.f;
+      if (task >= TASKS) continue;
+      // consecutive lanes take consecutive k-pairs: their (k, k+1) words land in
+      // consecutive LDS banks in store() (a j-major order would put all lanes of
+      // a wave in one bank, the row stride of 8 columns being a multiple of 128 B)
+      const int kp = task % (BK / 2), jc = task / (BK / 2);
+      const int64_t k = k0 + 2 * kp, j = j0 + 8 * jc;
+      if (j >= cols || k >= K) continue;
+      // k is even, so rows k and k+1 share one 128-row scale block
+      sc[q] = scales[(k >> 7) * nsb + (j >> 7)];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t kk = k + h;
+        if (kk >= K) continue;
+        const uint16_t* src = P + kk * ld + j;
+        u32x4 x = {0u, 0u, 0u, 0u};
+        if (vec && j + 7 < cols) {
+          x = *reinterpret_cast<const u32x4*>(src);
+        } else {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const uint32_t b = (j + t < cols) ? src[t] : 0u;
+            x[t >> 1] |= b << (16 * (t & 1));
+          }
+        }
+        if (h == 0)
+          v0[q] = x;
+        else
+          v1[q] = x;
       }
     }
-    reg[q] = v;
   }
-}
-
-__device__ __forceinline__ void bf_store_kc(uint16_t* S, const u32x4 (&reg)[2]) {
+  __device__ __forceinline__ void store(uint16_t* S) const {
+    constexpr int LDK = BK + 8;
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    const int row = e >> 2, kc = 8 * (e & 3);
-    *reinterpret_cast<u32x4*>(S + row * B_LD + kc) = reg[q];
-  }
-}
-
-// n-contiguous matrix operand: rows k, k+1 at 8 consecutive j per thread.
-__device__ __forceinline__ void bf_load_nc(const uint16_t* __restrict__ P, int64_t ld, int64_t cols,
-                                           int64_t K, int64_t j0, int64_t k0,
-                                           const float* __restrict__ scales, int64_t nsb, bool vec,
-                                           u32x4& r0, u32x4& r1) {
-  const int kp = threadIdx.x >> 4, jc = threadIdx.x & 15;
-  const int64_t k = k0 + 2 * kp, j = j0 + 8 * jc;
-  r0 = u32x4{0u, 0u, 0u, 0u};
-  r1 = u32x4{0u, 0u, 0u, 0u};
-  if (j >= cols) return;
+    for (int q = 0; q < NT; ++q) {
+      const int task = threadIdx.x + T * q;
+      if (task >= TASKS) continue;
+      const int kp = task % (BK / 2), jc = task / (BK / 2);
+      u32x4 a4 = v0[q], b4 = v1[q];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int64_t kk = k + h;
-    if (kk >= K) continue;
-    const uint16_t* src = P + kk * ld + j;
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (vec && j + 7 < cols) {
-      v = *reinterpret_cast<const u32x4*>(src);
-    } else {
+      for (int t = 0; t < 4; ++t) {
+        a4[t] = scale_bf16x2(a4[t], sc[q]);
+        b4[t] = scale_bf16x2(b4[t], sc[q]);
+      }
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
-        const uint32_t b = (j + t < cols) ? src[t] : 0u;
-        v[t >> 1] |= b << (16 * (t & 1));
+        const uint32_t a = (a4[t >> 1] >> (16 * (t & 1))) & 0xffffu;
+        const uint32_t b = (b4[t >> 1] >> (16 * (t & 1))) & 0xffffu;
+        *reinterpret_cast<uint32_t*>(S + (8 * jc + t) * LDK + 2 * kp) = a | (b << 16);
       }
     }
-    const float s = scales[(kk >> 7) * nsb + (j >> 7)];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = scale_bf16x2(v[t], s);
-    if (h == 0)
-      r0 = v;
-    else
-      r1 = v;
   }
-}
+};
 
-__device__ __forceinline__ void bf_store_nc(uint16_t* S, const u32x4& r0, const u32x4& r1) {
-  const int kp = threadIdx.x >> 4, jc = threadIdx.x & 15;
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const uint32_t a = (r0[t >> 1] >> (16 * (t & 1))) & 0xffffu;
-    const uint32_t b = (r1[t >> 1] >> (16 * (t & 1))) & 0xffffu;
-    *reinterpret_cast<uint32_t*>(S + (8 * jc + t) * B_LD + 2 * kp) = a | (b << 16);
-  }
-}
-
-__device__ __forceinline__ bf16x8 bf_frag(const uint16_t* S, int row, int k) {
-  const u32x4 w = *reinterpret_cast<const u32x4*>(S + row * B_LD + k);
-  return __builtin_bit_cast(bf16x8, w);
-}
-
-template <bool A_IS_MAT, bool B_KC>
-__device__ void bf16_tile(const GemmBF16& g, int64_t local, char* smem) {
-  uint16_t* sA = reinterpret_cast<uint16_t*>(smem);  // [2][T_BM * B_LD]
-  uint16_t* sB = sA + 2 * T_BM * B_LD;                // [2][T_BN * B_LD]
-  const int64_t tm_n = cdiv_d(g.M, T_BM), tn_n = cdiv_d(g.N, T_BN);
+template <class CF, bool A_IS_MAT, bool B_KC>
+__device__ void bf16_tile_cfg(const GemmBF16& g, int64_t local, char* smem) {
+  constexpr int BM = CF::BM, BN = CF::BN, BK = CF::BK, LDK = CF::LDK;
+  uint16_t* sA = reinterpret_cast<uint16_t*>(smem);  // [2][BM * LDK]
+  uint16_t* sB = sA + 2 * BM * LDK;                  // [2][BN * LDK]
+  const int64_t tm_n = cdiv_d(g.M, BM), tn_n = cdiv_d(g.N, BN);
   int64_t tm, tn;
   if (g.inner_is_m) {
     if (!xcd_tile(local, tm_n, tn_n, tm, tn)) return;
   } else {
     if (!xcd_tile(local, tn_n, tm_n, tn, tm)) return;
   }
-  const int64_t i0 = tm * T_BM, j0 = tn * T_BN;
+  const int64_t i0 = tm * BM, j0 = tn * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % CF::WM, wn = wave / CF::WM;
   const int li = lane & 31, lk = lane >> 5;
   const bool vec = g.vec != 0;
-  f32x16 acc[2][2];
+  f32x16 acc[CF::FM][CF::FN];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < CF::FM; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < CF::FN; ++y)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.f;
 
-  const int64_t nk = cdiv_d(g.K, B_BK);
-  u32x4 ra[2], rb[2], rn0, rn1;
-  bf_load_kc<A_IS_MAT>(g.A, g.lda, g.M, g.K, i0, 0, g.scales, g.nsb, vec, ra);
-  if (B_KC)
-    bf_load_kc<false>(g.B, g.ldb, g.N, g.K, j0, 0, g.scales, g.nsb, vec, rb);
-  else
-    bf_load_nc(g.B, g.ldb, g.N, g.K, j0, 0, g.scales, g.nsb, vec, rn0, rn1);
-  bf_store_kc(sA, ra);
-  if (B_KC)
-    bf_store_kc(sB, rb);
-  else
-    bf_store_nc(sB, rn0, rn1);
+  BFStageKC<BM, BK, CF::T, A_IS_MAT> sa;
+  typedef typename std::conditional<B_KC, BFStageKC<BN, BK, CF::T, false>,
+                                    BFStageNC<BN, BK, CF::T>>::type StageB;
+  StageB sb;
+  const int64_t nk = cdiv_d(g.K, BK);
+  sa.load(g.A, g.lda, g.M, g.K, i0, 0, g.scales, g.nsb, vec);
+  sb.load(g.B, g.ldb, g.N, g.K, j0, 0, g.scales, g.nsb, vec);
+  sa.store(sA);
+  sb.store(sB);
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      bf_load_kc<A_IS_MAT>(g.A, g.lda, g.M, g.K, i0, (kt + 1) * B_BK, g.scales, g.nsb, vec, ra);
-      if (B_KC)
-        bf_load_kc<false>(g.B, g.ldb, g.N, g.K, j0, (kt + 1) * B_BK, g.scales, g.nsb, vec, rb);
-      else
-        bf_load_nc(g.B, g.ldb, g.N, g.K, j0, (kt + 1) * B_BK, g.scales, g.nsb, vec, rn0, rn1);
+      sa.load(g.A, g.lda, g.M, g.K, i0, (kt + 1) * BK, g.scales, g.nsb, vec);
+      sb.load(g.B, g.ldb, g.N, g.K, j0, (kt + 1) * BK, g.scales, g.nsb, vec);
     }
-    const uint16_t* a_s = sA + cur * T_BM * B_LD;
-    const uint16_t* b_s = sB + cur * T_BN * B_LD;
+    const uint16_t* a_s = sA + cur * BM * LDK + (wm * CF::TM + li) * LDK + 8 * lk;
+    const uint16_t* b_s = sB + cur * BN * LDK + (wn * CF::TN + li) * LDK + 8 * lk;
 #pragma unroll
-    for (int ks = 0; ks < B_BK; ks += 16) {
-      const bf16x8 a0 = bf_frag(a_s, wm * 64 + li, ks + 8 * lk);
-      const bf16x8 a1 = bf_frag(a_s, wm * 64 + 32 + li, ks + 8 * lk);
-      const bf16x8 b0 = bf_frag(b_s, wn * 64 + li, ks + 8 * lk);
-      const bf16x8 b1 = bf_frag(b_s, wn * 64 + 32 + li, ks + 8 * lk);
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    for (int ks = 0; ks < BK; ks += 16) {
+      bf16x8 af[CF::FM], bfr[CF::FN];
+#pragma unroll
+      for (int x = 0; x < CF::FM; ++x)
+        af[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(a_s + x * 32 * LDK + ks));
+#pragma unroll
+      for (int y = 0; y < CF::FN; ++y)
+        bfr[y] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(b_s + y * 32 * LDK + ks));
+#pragma unroll
+      for (int x = 0; x < CF::FM; ++x)
+#pragma unroll
+        for (int y = 0; y < CF::FN; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[x], bfr[y], acc[x][y], 0, 0, 0);
     }
     if (kt + 1 < nk) {
-      bf_store_kc(sA + (cur ^ 1) * T_BM * B_LD, ra);
-      if (B_KC)
-        bf_store_kc(sB + (cur ^ 1) * T_BN * B_LD, rb);
-      else
-        bf_store_nc(sB + (cur ^ 1) * T_BN * B_LD, rn0, rn1);
+      sa.store(sA + (cur ^ 1) * BM * LDK);
+      sb.store(sB + (cur ^ 1) * BN * LDK);
     }
     __syncthreads();
   }
+  // 32x32 accumulator: register v of lane l holds row 8(v/4) + 4(l/32) + v%4, column l%32.
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < CF::FM; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < CF::FN; ++y)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int64_t row = i0 + wm * 64 + x * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
-        const int64_t col = j0 + wn * 64 + y * 32 + li;
+        const int64_t row = i0 + wm * CF::TM + x * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
+        const int64_t col = j0 + wn * CF::TN + y * 32 + li;
         if (row < g.M && col < g.N) g.D[row * g.ldd + col] = acc[x][y][v];
       }
 }
+
+// The production BF16 configuration: 256 x 256 tiles, 16 waves of 64 x 64.
+using BF16Pass = BF16Cfg<256, 256, 32, 4, 4>;
 
 }  // namespace tiles
 }  // namespace gn

@@ -218,23 +218,26 @@ __global__ void __launch_bounds__(CF::T) pass_f32_srht(GemmF32 yta, SrhtArgs sr,
     f32_tile_cfg<CF, false, false, VEC>(yta, local, smem);
 }
 
-__global__ void __launch_bounds__(256) pass_bf16_gauss(GemmBF16 yta, GemmBF16 ax, int64_t gY, int64_t gA) {
-  __shared__ __attribute__((aligned(16))) char smem[B_SMEM];
+template <class CF>
+__global__ void __launch_bounds__(CF::T) pass_bf16_gauss(GemmBF16 yta, GemmBF16 ax, int64_t gY,
+                                                         int64_t gA) {
+  __shared__ __attribute__((aligned(16))) char smem[CF::smem()];
   int64_t local;
   if (family_split(gY, gA, local))
-    bf16_tile<false, false>(yta, local, smem);
+    bf16_tile_cfg<CF, false, false>(yta, local, smem);
   else
-    bf16_tile<true, true>(ax, local, smem);
+    bf16_tile_cfg<CF, true, true>(ax, local, smem);
 }
 
-template <int RPL>
-__global__ void __launch_bounds__(256) pass_bf16_srht(GemmBF16 yta, SrhtArgs sr, int64_t gY, int64_t gS) {
-  __shared__ __attribute__((aligned(16))) char smem[smax(B_SMEM, SR_SMEM_F32)];
+template <class CF, int RPL>
+__global__ void __launch_bounds__(CF::T) pass_bf16_srht(GemmBF16 yta, SrhtArgs sr, int64_t gY,
+                                                        int64_t gS, int srht_first) {
+  __shared__ __attribute__((aligned(16))) char smem[smax(CF::smem(), SR_SMEM_F32)];
   int64_t local;
-  if (family_split(gY, gS, local))
-    bf16_tile<false, false>(yta, local, smem);
-  else
+  if (take_first(gS, gY, srht_first, local))
     srht_rows<float, GN_MODE_BF16_BS, RPL>(sr, local, smem);
+  else
+    bf16_tile_cfg<CF, false, false>(yta, local, smem);
 }
 
 template <int RPL>
@@ -300,6 +303,37 @@ gn_status launch_f32_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_t
   return GN_OK;
 }
 
+// BF16 pass with tile configuration CF (sketches stored transposed: Xt r x n,
+// Yt rl x m).
+template <class CF>
+gn_status launch_bf16_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_t m, int64_t n,
+                          int64_t r, int64_t rl, const uint16_t* A, int64_t lda,
+                          const float* scales, const uint16_t* Xt, const uint16_t* Yt, SrhtArgs sr,
+                          float* AX, int64_t ldax, float* YtA, int64_t ldya, hipStream_t s) {
+  const int64_t nsb = cdiv(n, 128);
+  const bool vec_y = (lda % 8 == 0) && (m % 8 == 0) && ((uintptr_t)A % 16 == 0) &&
+                     ((uintptr_t)Yt % 16 == 0);
+  GemmBF16 yta{rl, n, m, Yt, m, A, lda, scales, nsb, YtA, ldya, 1, vec_y ? 1 : 0};
+  const int64_t gY = cdiv(cdiv(rl, CF::BM) * cdiv(n, CF::BN), 8);
+  if (srht) {
+    sr.rows_per_wg = rows_per_wg;
+    const int64_t gS = cdiv(cdiv(m, rows_per_wg), 8);
+    const dim3 grid((unsigned)(8 * (gY + gS)));
+    const int rpl = srht_rpl(r);
+#define GN_BFS(R) pass_bf16_srht<CF, R><<<grid, dim3(CF::T), 0, s>>>(yta, sr, gY, gS, srht_first)
+    GN_RPL_SWITCH(rpl, GN_BFS)
+#undef GN_BFS
+  } else {
+    const bool vec_x = (lda % 8 == 0) && (n % 8 == 0) && ((uintptr_t)A % 16 == 0) &&
+                       ((uintptr_t)Xt % 16 == 0);
+    GemmBF16 ax{m, r, n, A, lda, Xt, n, scales, nsb, AX, ldax, 0, vec_x ? 1 : 0};
+    const int64_t gA = cdiv(cdiv(m, CF::BM) * cdiv(r, CF::BN), 8);
+    pass_bf16_gauss<CF><<<dim3((unsigned)(8 * (gY + gA))), dim3(CF::T), 0, s>>>(yta, ax, gY, gA);
+  }
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
 }  // namespace
 
 gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_t r, int64_t rl,
@@ -335,28 +369,9 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
                                    (const float*)Xs, (const float*)Ys, sr, (float*)AX, ldax,
                                    (float*)YtA, ldya, s);
 
-  // BF16 with block scales
-  const bool vec_y = (lda % 8 == 0) && (m % 8 == 0) && ((uintptr_t)A % 16 == 0) &&
-                     ((uintptr_t)Yt % 16 == 0);
-  GemmBF16 yta{rl, n, m, (const uint16_t*)Yt, m, (const uint16_t*)A, lda, scales, nsb,
-               (float*)YtA, ldya, 1, vec_y ? 1 : 0};
-  const int64_t gY = gemm_groups(rl, n);
-  if (srht) {
-    const int64_t gS = cdiv(cdiv(m, sr.rows_per_wg), 8);
-    const dim3 grid((unsigned)(8 * (gY + gS)));
-#define GN_BFS(R) pass_bf16_srht<R><<<grid, dim3(256), 0, s>>>(yta, sr, gY, gS)
-    GN_RPL_SWITCH(rpl, GN_BFS)
-#undef GN_BFS
-  } else {
-    const bool vec_x = (lda % 8 == 0) && (n % 8 == 0) && ((uintptr_t)A % 16 == 0) &&
-                       ((uintptr_t)Xt % 16 == 0);
-    GemmBF16 ax{m, r, n, (const uint16_t*)A, lda, (const uint16_t*)Xt, n, scales, nsb,
-                (float*)AX, ldax, 0, vec_x ? 1 : 0};
-    const int64_t gA = gemm_groups(m, r);
-    pass_bf16_gauss<<<dim3((unsigned)(8 * (gY + gA))), dim3(256), 0, s>>>(yta, ax, gY, gA);
-  }
-  GN_LAUNCH_CHECK();
-  return GN_OK;
+  return launch_bf16_cfg<BF16Pass>(srht, kSrhtFirst, kSrhtRows, m, n, r, rl,
+                                   (const uint16_t*)A, lda, scales, (const uint16_t*)Xs,
+                                   (const uint16_t*)Ys, sr, (float*)AX, ldax, (float*)YtA, ldya, s);
 }
 
 }  // namespace gn
