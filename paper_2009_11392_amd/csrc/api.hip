@@ -82,13 +82,19 @@ SketchWs sketch_ws(const Plan& P) {
 }
 
 struct CoreWs {
-  size_t yt, c, qr, z, qr2, total;
+  size_t yt, c, qr, z, qr2, split, total;
 };
 CoreWs core_ws(const Plan& P) {
   CoreWs w{};
   size_t off = 0;
   w.yt = off;
-  if (P.ky == GN_SKETCH_GAUSSIAN) off += align_up((size_t)P.rl * P.m * dtype_size(P.sdt));
+  // Y for the core product: as stored by the pass in F64 mode (regenerated
+  // unless USER); widened to float in F32 / BF16 modes.
+  if (P.mode == GN_MODE_F64) {
+    if (P.ky == GN_SKETCH_GAUSSIAN) off += align_up((size_t)P.rl * P.m * 8);
+  } else if (P.ky == GN_SKETCH_GAUSSIAN || P.mode == GN_MODE_BF16_BS) {
+    off += align_up((size_t)P.rl * P.m * 4);
+  }
   w.c = off;
   off += align_up((size_t)P.rl * P.r * 8);
   w.qr = off;
@@ -97,20 +103,28 @@ CoreWs core_ws(const Plan& P) {
   off += align_up((size_t)P.r * P.r * 8);
   w.qr2 = off;
   off += qr_ws_bytes(P.r, P.r);
+  w.split = off;
+  off += (P.mode == GN_MODE_F64) ? dgemm_split_ws_bytes(P.rl, P.r, P.m)
+                                 : core_product_ws_bytes(P.m, P.rl, P.r);
   w.total = off;
   return w;
 }
 
 struct ApplyWs {
-  size_t t1, t2, t3, total;
+  size_t t1, t2, t3, split, split_bytes, total;
 };
 ApplyWs apply_ws(const Plan& P, int64_t kc) {
   ApplyWs w{};
-  const size_t blk = align_up((size_t)P.rl * (size_t)(kc > 0 ? kc : 1) * 8);
+  const int64_t k1 = kc > 0 ? kc : 1;
+  const size_t blk = align_up((size_t)P.rl * (size_t)k1 * 8);
   w.t1 = 0;
   w.t2 = blk;
   w.t3 = 2 * blk;
-  w.total = 3 * blk;
+  w.split = 3 * blk;
+  const size_t s0 = dgemm_split_ws_bytes(P.rl, k1, P.n);  // (Y^T A) W
+  const size_t s1 = dgemm_split_ws_bytes(k1, P.r, P.m);   // W (AX)
+  w.split_bytes = s0 > s1 ? s0 : s1;
+  w.total = w.split + w.split_bytes;
   return w;
 }
 
@@ -305,17 +319,41 @@ gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void*
   double* C = (double*)(base + W.c);
   double* Z = (double*)(base + W.z);
 
-  // C = Y^T (AX) in FP64 (the order of the Section 5.1 evaluation)
-  MatRef yt;
-  if (P.ky == GN_SKETCH_GAUSSIAN) {
-    void* Yt = base + W.yt;
-    GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, P.sdt, 1, Yt, P.m, s));
-    yt = MatRef{Yt, P.sdt, P.m, 1};
+  // C = Y^T (AX) (the order of the Section 5.1 evaluation): FP64 in F64 mode;
+  // in F32 / BF16 modes on the FP32 matrix cores (the pass precision) with the
+  // K slices summed in FP64.
+  if (P.mode == GN_MODE_F64) {
+    MatRef yt;
+    if (P.ky == GN_SKETCH_GAUSSIAN) {
+      void* Yt = base + W.yt;
+      GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, P.sdt, 1, Yt, P.m, s));
+      yt = MatRef{Yt, P.sdt, P.m, 1};
+    } else {
+      yt = MatRef{Y_user, P.sdt, 1, ldy};  // Y^T(c, i) = Y[i*ldy + c]
+    }
+    MatRef ax{AX, P.adt, ldax, 1};
+    GN_TRY(launch_dgemm(P.rl, P.r, P.m, 1.0, yt, ax, 0.0, C, P.r, 1, nullptr, false, s, nullptr,
+                        0, true, (double*)(base + W.split), W.total - W.split));
   } else {
-    yt = MatRef{Y_user, P.sdt, 1, ldy};  // Y^T(c, i) = Y[i*ldy + c]
+    const float* Yf;
+    int64_t ldyf;
+    if (P.ky == GN_SKETCH_GAUSSIAN) {
+      const int32_t gdt = (P.mode == GN_MODE_BF16_BS) ? kDtBf16AsF32 : GN_DT_F32;
+      GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, gdt, 0, base + W.yt, P.rl, s));
+      Yf = (const float*)(base + W.yt);
+      ldyf = P.rl;
+    } else if (P.mode == GN_MODE_BF16_BS) {
+      GN_TRY(launch_widen_bf16(P.m, P.rl, (const uint16_t*)Y_user, ldy, (float*)(base + W.yt),
+                               P.rl, s));
+      Yf = (const float*)(base + W.yt);
+      ldyf = P.rl;
+    } else {
+      Yf = (const float*)Y_user;
+      ldyf = ldy;
+    }
+    GN_TRY(launch_core_product_f32(P.m, P.rl, P.r, Yf, ldyf, (const float*)AX, ldax,
+                                   (float*)(base + W.split), C, s));
   }
-  MatRef ax{AX, P.adt, ldax, 1};
-  GN_TRY(launch_dgemm(P.rl, P.r, P.m, 1.0, yt, ax, 0.0, C, P.r, 1, nullptr, false, s));
   // Householder QR, kept rank, and the second QR when truncated
   GN_TRY(launch_qr(P.rl, P.r, C, P.r, out->Q1, P.r, out->R, P.r, (double*)(base + W.qr), nullptr, s));
   GN_TRY(launch_truncate(P.r, out->R, P.r, P.tau, out->k, out->status, Z, P.r, s));
@@ -368,12 +406,13 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
   double* t1 = (double*)(base + Wl.t1);
   double* t2 = (double*)(base + Wl.t2);
   double* t3 = (double*)(base + Wl.t3);
+  double* sp = (double*)(base + Wl.split);
   MatRef ax{AX, P.adt, ldax, 1};
   MatRef yta{YtA, P.adt, ldya, 1};
   if (side == 0) {
     // t1 = (Y^T A) W : rl x kc
     GN_TRY(launch_dgemm(P.rl, kc, P.n, 1.0, yta, MatRef{W, GN_DT_F64, ldw, 1}, 0.0, t1, kc, 1,
-                        nullptr, false, s));
+                        nullptr, false, s, nullptr, 0, true, sp, Wl.split_bytes));
     // t2 = Q1[:, :k]^T t1 : r x kc (rows >= k zero)
     GN_TRY(launch_dgemm(P.r, kc, P.rl, 1.0, MatRef{core->Q1, GN_DT_F64, 1, P.r},
                         MatRef{t1, GN_DT_F64, kc, 1}, 0.0, t2, kc, 1, core->k, true, s));
@@ -390,7 +429,7 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
   } else {
     // t1 = W AX : kc x r
     GN_TRY(launch_dgemm(kc, P.r, P.m, 1.0, MatRef{W, GN_DT_F64, ldw, 1}, ax, 0.0, t1, P.r, 1,
-                        nullptr, false, s));
+                        nullptr, false, s, nullptr, 0, true, sp, Wl.split_bytes));
     // t2 = t1 (k == r)  or  t1 Q2 (k < r); then t2 <- t2 R^{-1}  or  t2 R2^{-T}
     GN_TRY(widen(kc, P.r, t1, GN_DT_F64, P.r, t2, P.r, core->k, P.r, s));
     GN_TRY(launch_dgemm(kc, P.r, P.r, 1.0, MatRef{t1, GN_DT_F64, P.r, 1},

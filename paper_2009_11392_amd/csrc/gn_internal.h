@@ -86,7 +86,13 @@ __device__ __forceinline__ double to_f64<float>(float v) { return (double)v; }
 template <>
 __device__ __forceinline__ double to_f64<uint16_t>(uint16_t v) { return (double)bf16_bits_to_f32(v); }
 
-inline size_t dtype_size(int32_t dt) { return dt == GN_DT_F64 ? 8 : (dt == GN_DT_F32 ? 4 : 2); }
+// Internal element type: bfloat16-rounded values stored as float (the BF16
+// sketch widened exactly, for the FP32 core product).
+constexpr int32_t kDtBf16AsF32 = 3;
+
+inline size_t dtype_size(int32_t dt) {
+  return dt == GN_DT_F64 ? 8 : ((dt == GN_DT_F32 || dt == kDtBf16AsF32) ? 4 : 2);
+}
 inline int32_t sketch_dtype(int32_t mode) {
   return mode == GN_MODE_F64 ? GN_DT_F64 : (mode == GN_MODE_F32 ? GN_DT_F32 : GN_DT_BF16);
 }
@@ -118,6 +124,17 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
                       const int8_t* signs, const int32_t* idx, const void* Yt, void* AX,
                       int64_t ldax, void* YtA, int64_t ldya, hipStream_t s);
 
+// C ((rl) x r, FP64, ld r) = Y^T (AX) on the FP32 matrix cores: Y m x rl (ld
+// ldy), AX m x r (ld ldax), both float; K = m split into slices whose FP32
+// partial products (core_product_ws_bytes) are summed in FP64 in slice order.
+gn_status launch_core_product_f32(int64_t m, int64_t rl, int64_t r, const float* Y, int64_t ldy,
+                                  const float* AX, int64_t ldax, float* partial, double* C,
+                                  hipStream_t s);
+size_t core_product_ws_bytes(int64_t m, int64_t rl, int64_t r);
+// widen a bfloat16 matrix (rows x cols, ld lds) to float (ld ldd)
+gn_status launch_widen_bf16(int64_t rows, int64_t cols, const uint16_t* src, int64_t lds, float* dst,
+                            int64_t ldd, hipStream_t s);
+
 // dgemm.hip : FP64 strided GEMM  D = alpha * op(A) op(B) + beta * D
 struct MatRef {
   const void* p;
@@ -128,20 +145,24 @@ struct MatRef {
 // >= *kmask are written as zero (used to zero factors beyond the kept rank).
 // gate: when non-null the kernel does nothing unless (*gate < gate_n) == gate_trunc
 // (launches that only matter for a truncated / untruncated core).
+// split_ws: optional scratch for splitting a long K over more workgroups
+// (dgemm_split_ws_bytes(M, N, K) bytes); the slices are summed in fixed order.
 gn_status launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, MatRef A, MatRef B,
                        double beta, double* D, int64_t rsd, int64_t csd, const int32_t* kmask,
                        bool mask_rows, hipStream_t s, const int32_t* gate = nullptr,
-                       int64_t gate_n = 0, bool gate_trunc = true);
+                       int64_t gate_n = 0, bool gate_trunc = true, double* split_ws = nullptr,
+                       size_t split_ws_bytes = 0);
+size_t dgemm_split_ws_bytes(int64_t M, int64_t N, int64_t K);
 // Per-tile sums of (Ref - A*B)^2 written to partial[], then reduced in fixed order.
 gn_status launch_residual(int64_t M, int64_t N, int64_t K, MatRef Ref, const float* ref_scales,
                           MatRef A, MatRef B, double* partial, double* out, hipStream_t s);
 size_t residual_ws_bytes(int64_t M, int64_t N);
 
-// qr.hip : Householder QR of an M x N FP64 matrix (M >= N, M <= 4096), in place.
-// On exit the upper triangle holds R (R_ii >= 0 after the sign fix) and Q
-// (M x N, ld ldq) holds the explicit orthonormal factor.  When gate_k is
-// non-null, every kernel returns immediately unless *gate_k < N (used for the
-// second QR, which is only needed when the core is truncated).
+// qr.hip : Householder QR of an M x N FP64 matrix (M >= N, M <= 4096), in place
+// (the factored matrix keeps R above and the reflectors below its diagonal).
+// R (N x N, ld ldr, R_ii >= 0 after the sign fix) and the explicit Q (M x N,
+// ld ldq) are written out.  When gate_k is non-null, every kernel returns
+// immediately unless *gate_k < N (the second QR, needed only when truncated).
 gn_status launch_qr(int64_t M, int64_t N, double* Aq, int64_t lda, double* Q, int64_t ldq,
                     double* R, int64_t ldr, double* ws, const int32_t* gate_k, hipStream_t s);
 size_t qr_ws_bytes(int64_t M, int64_t N);

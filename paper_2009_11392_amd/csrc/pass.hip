@@ -334,6 +334,53 @@ gn_status launch_bf16_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_
   return GN_OK;
 }
 
+// ------------------------------------------------------------------ core product
+// C = Y^T (AX) on the FP32 matrix cores: slice s of K = m (blockIdx.y) is a
+// Y^T A-shaped contraction (both operands m/n-contiguous) written to its own
+// partial; the slices are then summed in order in FP64.
+using CoreCfg = F32Cfg<128, 128, 16, 2, 2, 32>;
+
+template <bool VEC>
+__global__ void __launch_bounds__(CoreCfg::T) core_product_f32(GemmF32 g, int64_t kslice) {
+  __shared__ __attribute__((aligned(16))) char smem[CoreCfg::smem<false, false>()];
+  const int64_t s = blockIdx.y;
+  const int64_t k0 = s * kslice;
+  GemmF32 gs = g;
+  gs.A = g.A + k0 * g.lda;
+  gs.B = g.B + k0 * g.ldb;
+  gs.K = (k0 + kslice < g.K) ? kslice : g.K - k0;
+  gs.D = g.D + s * g.M * g.N;
+  if (gs.K <= 0) return;
+  f32_tile_cfg<CoreCfg, false, false, VEC>(gs, blockIdx.x, smem);
+}
+
+__global__ void __launch_bounds__(256) core_product_sum(const float* partial, int64_t nslice,
+                                                        int64_t mn, double* C) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mn) return;
+  double acc = 0.0;
+  for (int64_t q = 0; q < nslice; ++q) acc += (double)partial[q * mn + e];
+  C[e] = acc;
+}
+
+int64_t core_slices(int64_t m, int64_t rl, int64_t r) {
+  const int64_t tiles = cdiv(rl, CoreCfg::BM) * cdiv(r, CoreCfg::BN);
+  int64_t sl = cdiv(512, tiles);
+  const int64_t smax = cdiv(m, 2048);
+  if (sl > smax) sl = smax;
+  if (sl > 16) sl = 16;
+  return sl < 1 ? 1 : sl;
+}
+
+__global__ void __launch_bounds__(256) widen_bf16_kernel(int64_t rows, int64_t cols,
+                                                         const uint16_t* src, int64_t lds,
+                                                         float* dst, int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e / cols, j = e - i * cols;
+  dst[i * ldd + j] = bf16_bits_to_f32(src[i * lds + j]);
+}
+
 }  // namespace
 
 gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_t r, int64_t rl,
@@ -372,6 +419,38 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
   return launch_bf16_cfg<BF16Pass>(srht, kSrhtFirst, kSrhtRows, m, n, r, rl,
                                    (const uint16_t*)A, lda, scales, (const uint16_t*)Xs,
                                    (const uint16_t*)Ys, sr, (float*)AX, ldax, (float*)YtA, ldya, s);
+}
+
+size_t core_product_ws_bytes(int64_t m, int64_t rl, int64_t r) {
+  return align_up((size_t)core_slices(m, rl, r) * rl * r * sizeof(float));
+}
+
+gn_status launch_core_product_f32(int64_t m, int64_t rl, int64_t r, const float* Y, int64_t ldy,
+                                  const float* AX, int64_t ldax, float* partial, double* C,
+                                  hipStream_t s) {
+  const int64_t sl = core_slices(m, rl, r);
+  const int64_t kslice = cdiv(cdiv(m, sl), 16) * 16;
+  const int64_t tiles = cdiv(rl, CoreCfg::BM) * cdiv(r, CoreCfg::BN);
+  GemmF32 g{rl, r, m, Y, ldy, AX, ldax, partial, r, 1};
+  const bool vec = (ldy % 4 == 0) && (ldax % 4 == 0) && ((uintptr_t)Y % 16 == 0) &&
+                   ((uintptr_t)AX % 16 == 0);
+  const dim3 grid((unsigned)(8 * cdiv(tiles, 8)), (unsigned)sl);
+  if (vec)
+    core_product_f32<true><<<grid, dim3(CoreCfg::T), 0, s>>>(g, kslice);
+  else
+    core_product_f32<false><<<grid, dim3(CoreCfg::T), 0, s>>>(g, kslice);
+  GN_LAUNCH_CHECK();
+  core_product_sum<<<dim3((unsigned)cdiv(rl * r, 256)), dim3(256), 0, s>>>(partial, sl, rl * r, C);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+gn_status launch_widen_bf16(int64_t rows, int64_t cols, const uint16_t* src, int64_t lds, float* dst,
+                            int64_t ldd, hipStream_t s) {
+  widen_bf16_kernel<<<dim3((unsigned)cdiv(rows * cols, 256)), dim3(256), 0, s>>>(rows, cols, src,
+                                                                                 lds, dst, ldd);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
 }
 
 }  // namespace gn

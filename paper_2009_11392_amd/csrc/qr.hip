@@ -4,23 +4,26 @@
 // Section 5.1.1.
 //
 // Blocked right-looking QR.  Each panel of nb columns is factored by one
-// 1024-thread workgroup holding the panel in registers (row t + 1024 q of the
-// panel in thread t), with fixed-order workgroup reductions for the column norms
-// and the reflector dot products.  The panel kernel also forms the compact-WY
-// factor T (H_1 ... H_nb = I - V T V^T) and the products V T^T and V T.  The
-// trailing matrix is updated as C2 -= (V T^T) (V^T C2) and the explicit Q is
-// accumulated backwards as Q2 -= (V T) (V^T Q2), both with the FP64 GEMM.
+// 512-thread workgroup holding the panel in registers (row t + 512 q of the panel
+// in thread t), with fixed-order workgroup reductions for the column norms and
+// the reflector dot products; it leaves R and the reflectors (below the
+// diagonal, unit diagonal implicit) in place and writes the compact-WY factor T
+// (H_1 ... H_nb = I - V T V^T).  One block-update kernel then applies the block
+// reflector to the trailing columns, C2 <- (I - V T^T V^T) C2, and, walking the
+// panels backwards, accumulates the explicit Q from [I; 0] with Q2 <- (I - V T V^T) Q2.
 #include "gn_internal.h"
 
 namespace gn {
 namespace {
 
-constexpr int QR_T = 1024;
-constexpr int QR_WAVES = QR_T / 64;
+constexpr int QP_T = 512;
+constexpr int QP_WAVES = QP_T / 64;
 constexpr int QR_MAXROWS = 4096;
+constexpr int QR_NB = 16;  // largest panel width
 
 template <int NV>
-__device__ __forceinline__ void qr_block_sum(double (&v)[NV], double (*red)[NV], double* out) {
+__device__ __forceinline__ void qr_block_sum(double (&v)[NV], double* red /*[QP_WAVES][NV]*/,
+                                             double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
@@ -31,24 +34,26 @@ __device__ __forceinline__ void qr_block_sum(double (&v)[NV], double (*red)[NV],
   }
   if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
+    for (int i = 0; i < NV; ++i) red[wave * NV + i] = v[i];
   }
   __syncthreads();
   if ((int)threadIdx.x < NV) {
     double s = 0.0;
-    for (int w = 0; w < QR_WAVES; ++w) s += red[w][threadIdx.x];
+    for (int w = 0; w < QP_WAVES; ++w) s += red[w * NV + threadIdx.x];
     out[threadIdx.x] = s;
   }
   __syncthreads();
 }
 
+// The column loop runs at run time; register arrays are only ever indexed by
+// compile-time constants (the current column is selected with predicated moves),
+// so the panel stays in registers.
 template <int RPT, int NB>
-__global__ void __launch_bounds__(QR_T) qr_panel(double* __restrict__ C, int64_t ldc, int64_t M,
-                                                 int64_t j0, int nbw, double* __restrict__ V,
-                                                 double* __restrict__ VTt, double* __restrict__ VTn,
-                                                 int64_t ldv, const int32_t* gate, int64_t gate_n) {
+__global__ void __launch_bounds__(QP_T) qr_panel(double* __restrict__ C, int64_t ldc, int64_t M,
+                                                 int64_t j0, int nbw, double* __restrict__ Tout,
+                                                 const int32_t* gate, int64_t gate_n) {
   if (gate && *gate >= gate_n) return;
-  __shared__ double red[QR_WAVES][NB];
+  __shared__ double red[QP_WAVES * NB];
   __shared__ double bc[NB];
   __shared__ double T[NB][NB];
   const int t = threadIdx.x;
@@ -56,7 +61,7 @@ __global__ void __launch_bounds__(QR_T) qr_panel(double* __restrict__ C, int64_t
   double p[RPT][NB];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t row = t + (int64_t)QR_T * q;
+    const int64_t row = t + (int64_t)QP_T * q;
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       p[q][c] = (row < Mp && c < nbw) ? C[(j0 + row) * ldc + j0 + c] : 0.0;
@@ -64,90 +69,180 @@ __global__ void __launch_bounds__(QR_T) qr_panel(double* __restrict__ C, int64_t
   if (t < NB * NB) T[t / NB][t % NB] = 0.0;
   __syncthreads();
 
+#pragma unroll 1
+  for (int c = 0; c < nbw; ++c) {
+    // column c of this thread's rows
+    double vr[RPT];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    if (c < nbw) {
-      // squared norm of the column below the pivot, and the pivot itself
-      double v2[2] = {0.0, 0.0};
+    for (int q = 0; q < RPT; ++q) {
+      double x = 0.0;
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int64_t row = t + (int64_t)QR_T * q;
-        if (row > c && row < Mp) v2[0] = fma(p[q][c], p[q][c], v2[0]);
-      }
-      if (t == c) v2[1] = p[0][c];
-      qr_block_sum<2>(v2, reinterpret_cast<double(*)[2]>(&red[0][0]), bc);
-      const double sigma = bc[0], alpha = bc[1];
-      double beta = alpha, tau = 0.0, scale = 0.0;
-      if (sigma != 0.0) {
-        const double nrm = sqrt(fma(alpha, alpha, sigma));
-        beta = (alpha >= 0.0) ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      __syncthreads();  // bc is reused below
-      // reflector v (v_c = 1 implicit) stored below the pivot; R_cc = beta
-      double vrow[RPT];
+      for (int cc = 0; cc < NB; ++cc) x = (cc == c) ? p[q][cc] : x;
+      vr[q] = x;
+    }
+    // squared norm below the pivot, and the pivot (row c lives in thread c, q = 0)
+    double v2[2] = {0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int64_t row = t + (int64_t)QR_T * q;
-        if (row > c && row < Mp) {
-          if (tau != 0.0) p[q][c] *= scale;
-          vrow[q] = p[q][c];
-        } else {
-          vrow[q] = (row == c) ? 1.0 : 0.0;
-        }
+    for (int q = 0; q < RPT; ++q) {
+      const int64_t row = t + (int64_t)QP_T * q;
+      if (row > c && row < Mp) v2[0] = fma(vr[q], vr[q], v2[0]);
+    }
+    if (t == c) v2[1] = vr[0];
+    qr_block_sum<2>(v2, red, bc);
+    const double sigma = bc[0], alpha = bc[1];
+    double beta = alpha, tau = 0.0, scale = 0.0;
+    if (sigma != 0.0) {
+      const double nrm = sqrt(fma(alpha, alpha, sigma));
+      beta = (alpha >= 0.0) ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    // reflector v (v_c = 1 implicit) below the pivot
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int64_t row = t + (int64_t)QP_T * q;
+      if (row > c && row < Mp) {
+        if (tau != 0.0) vr[q] *= scale;
+      } else {
+        vr[q] = (row == c) ? 1.0 : 0.0;
       }
-      // dots of v with every panel column over rows >= c
-      double d[NB];
+    }
+    // dots of v with every panel column over rows >= c (columns < c hold earlier
+    // reflectors there: those dots are the y of the T recurrence)
+    double d[NB];
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) acc = fma(vr[q], p[q][cc], acc);
+      d[cc] = acc;
+    }
+    qr_block_sum<NB>(d, red, bc);
+    // apply H_c to the columns right of c; store v and R_cc = beta in column c
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int64_t row = t + (int64_t)QP_T * q;
 #pragma unroll
       for (int cc = 0; cc < NB; ++cc) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) s = fma(vrow[q], p[q][cc], s);
-        d[cc] = s;
+        if (cc > c) p[q][cc] = fma(-tau * bc[cc], vr[q], p[q][cc]);
+        if (cc == c && row >= c) p[q][cc] = (row == c) ? beta : vr[q];
       }
-      qr_block_sum<NB>(d, red, bc);
-      // apply H_c to the columns right of c
-#pragma unroll
-      for (int cc = c + 1; cc < NB; ++cc) {
-        const double w = tau * bc[cc];
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) p[q][cc] = fma(-w, vrow[q], p[q][cc]);
-      }
-      if (t == c) p[0][c] = beta;
-      // T(:, c) = [ -tau T(0:c, 0:c) y ; tau ],  y = V(:, 0:c)^T v
-      if (t < c) {
-        double s = 0.0;
-        for (int l = t; l < c; ++l) s = fma(T[t][l], bc[l], s);
-        T[t][c] = -tau * s;
-      }
-      if (t == c) T[c][c] = tau;
-      __syncthreads();
     }
+    // T(:, c) = [ -tau T(0:c, 0:c) y ; tau ],  y = bc[0:c]
+    if (t < c) {
+      double s = 0.0;
+      for (int l = t; l < c; ++l) s = fma(T[t][l], bc[l], s);
+      T[t][c] = -tau * s;
+    }
+    if (t == c) T[c][c] = tau;
+    __syncthreads();
   }
-
-  // write back: R (rows <= col) and reflectors (below) into C, explicit V, V T^T, V T
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t row = t + (int64_t)QR_T * q;
+    const int64_t row = t + (int64_t)QP_T * q;
     if (row >= Mp) continue;
-    double vv[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) vv[c] = (row < c) ? 0.0 : (row == c ? 1.0 : p[q][c]);
+    for (int c = 0; c < NB; ++c)
+      if (c < nbw) C[(j0 + row) * ldc + j0 + c] = p[q][c];
+  }
+  if (t < NB * NB) Tout[(t / NB) * QR_NB + (t % NB)] = T[t / NB][t % NB];  // stride QR_NB
+}
+
+// D[j0 + i, col0 + j] for 0 <= i < M - j0, 0 <= j < ncols is replaced by
+// (I - V Top V^T) D, V the unit-lower reflectors of the panel at (j0, j0) of Cp
+// (width nbw) and Top = T^T (trans) or T.  One workgroup per 16 target columns:
+// W = V^T D accumulated by 16 row groups, reduced in fixed order, W <- Top W,
+// then D -= V W.  Panel rows are staged through LDS 256 at a time.
+constexpr int QU_ROWS = 256;
+constexpr int QU_RPG = QU_ROWS / 16;  // rows of a staged chunk per row group
+__global__ void __launch_bounds__(256) qr_block_update(const double* __restrict__ Cp, int64_t ldc,
+                                                       int64_t M, int64_t j0, int nbw,
+                                                       double* __restrict__ D, int64_t ldd,
+                                                       int64_t col0, int64_t ncols,
+                                                       const double* __restrict__ T, int trans,
+                                                       const int32_t* gate, int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  __shared__ double sV[QU_ROWS][QR_NB + 1];
+  __shared__ double red[16][QR_NB][17];
+  __shared__ double W[QR_NB][17];
+  const int tid = threadIdx.x, col = tid & 15, grp = tid >> 4;
+  const int64_t j = col0 + (int64_t)blockIdx.x * 16 + col;
+  const bool jok = j < col0 + ncols;
+  const int64_t Mp = M - j0;
+  double w[QR_NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c >= nbw) continue;
-      C[(j0 + row) * ldc + j0 + c] = p[q][c];
-      V[(j0 + row) * ldv + j0 + c] = vv[c];
-      double st = 0.0, sn = 0.0;
+  for (int c = 0; c < QR_NB; ++c) w[c] = 0.0;
+
+  // stage reflector rows r0 .. r0 + 255 of the panel (explicit unit-lower form)
+  auto stage = [&](int64_t r0) {
+    const int64_t row = r0 + tid;
 #pragma unroll
-      for (int c2 = 0; c2 < NB; ++c2) {
-        if (c2 >= nbw) continue;
-        st = fma(vv[c2], T[c][c2], st);  // (V T^T)[row][c]
-        sn = fma(vv[c2], T[c2][c], sn);  // (V T)[row][c]
-      }
-      VTt[(j0 + row) * ldv + j0 + c] = st;
-      VTn[(j0 + row) * ldv + j0 + c] = sn;
+    for (int c = 0; c < QR_NB; ++c) {
+      double v = 0.0;
+      if (row < Mp && c < nbw) v = (row < c) ? 0.0 : (row == c ? 1.0 : Cp[(j0 + row) * ldc + j0 + c]);
+      sV[tid][c] = v;
+    }
+  };
+  for (int64_t r0 = 0; r0 < Mp; r0 += QU_ROWS) {
+    // this thread's 16 rows of the chunk: all loads issued before any use
+    double x[QU_RPG];
+#pragma unroll
+    for (int q = 0; q < QU_RPG; ++q) {
+      const int64_t row = r0 + grp + 16 * q;
+      x[q] = (jok && row < Mp) ? D[(j0 + row) * ldd + j] : 0.0;
+    }
+    __syncthreads();
+    stage(r0);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QU_RPG; ++q)
+#pragma unroll
+      for (int c = 0; c < QR_NB; ++c) w[c] = fma(sV[grp + 16 * q][c], x[q], w[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < QR_NB; ++c) red[grp][c][col] = w[c];
+  __syncthreads();
+  {  // fixed-order reduction over the 16 row groups, then W <- Top W
+    const int c = grp;  // 16 x 16 threads: (c, col)
+    double s = 0.0;
+    for (int g2 = 0; g2 < 16; ++g2) s += red[g2][c][col];
+    W[c][col] = s;
+  }
+  __syncthreads();
+  double wt;
+  {
+    const int c = grp;
+    double s = 0.0;
+    for (int c2 = 0; c2 < nbw; ++c2) {
+      const double top = trans ? T[c2 * QR_NB + c] : T[c * QR_NB + c2];
+      s = fma(top, W[c2][col], s);
+    }
+    wt = (c < nbw) ? s : 0.0;
+  }
+  __syncthreads();
+  W[grp][col] = wt;
+  __syncthreads();
+  double wc[QR_NB];
+#pragma unroll
+  for (int c = 0; c < QR_NB; ++c) wc[c] = W[c][col];
+  // D -= V W
+  for (int64_t r0 = 0; r0 < Mp; r0 += QU_ROWS) {
+    double x[QU_RPG];
+#pragma unroll
+    for (int q = 0; q < QU_RPG; ++q) {
+      const int64_t row = r0 + grp + 16 * q;
+      x[q] = (jok && row < Mp) ? D[(j0 + row) * ldd + j] : 0.0;
+    }
+    __syncthreads();
+    stage(r0);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QU_RPG; ++q) {
+      const int64_t row = r0 + grp + 16 * q;
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < QR_NB; ++c) s = fma(sV[grp + 16 * q][c], wc[c], s);
+      if (jok && row < Mp) D[(j0 + row) * ldd + j] = x[q] - s;
     }
   }
 }
@@ -184,7 +279,7 @@ __global__ void __launch_bounds__(256) qr_signfix(const double* C, int64_t ldc, 
 __global__ void __launch_bounds__(256) trunc_scan(int64_t r, const double* R, int64_t ldr, double tau,
                                                   int32_t* kout, int32_t* status) {
   __shared__ int64_t s_first[256];
-  __shared__ int s_nonfinite[256];
+  __shared__ int s_flag[256];
   int64_t first = r;
   int nonfinite = 0;
   for (int64_t i = threadIdx.x; i < r; i += 256) {
@@ -196,33 +291,34 @@ __global__ void __launch_bounds__(256) trunc_scan(int64_t r, const double* R, in
     if (!keep && i < first) first = i;
   }
   s_first[threadIdx.x] = first;
-  s_nonfinite[threadIdx.x] = nonfinite;
+  s_flag[threadIdx.x] = nonfinite;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       s_first[threadIdx.x] = min(s_first[threadIdx.x], s_first[threadIdx.x + w]);
-      s_nonfinite[threadIdx.x] |= s_nonfinite[threadIdx.x + w];
+      s_flag[threadIdx.x] |= s_flag[threadIdx.x + w];
     }
     __syncthreads();
   }
   const int64_t k = s_first[0];
-  // non-monotone: a kept-size diagonal after the first failing one
+  const int nf = s_flag[0];
+  __syncthreads();
+  // non-monotone: a diagonal that passes the test after the first failing one
   int nm = 0;
   for (int64_t i = k + 1 + threadIdx.x; i < r; i += 256) {
     const double d = R[i * ldr + i];
     const double a = fabs(d);
     if (isfinite(d) && ((tau > 0.0) ? (a >= tau) : (a > 0.0))) nm = 1;
   }
-  __syncthreads();
-  s_nonfinite[threadIdx.x] = nm;
+  s_flag[threadIdx.x] = nm;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) s_nonfinite[threadIdx.x] |= s_nonfinite[threadIdx.x + w];
+    if ((int)threadIdx.x < w) s_flag[threadIdx.x] |= s_flag[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     *kout = (int32_t)k;
-    *status = (nonfinite ? 1 : 0) | (k == 0 ? 2 : 0) | (s_nonfinite[0] ? 4 : 0);
+    *status = (nf ? 1 : 0) | (k == 0 ? 2 : 0) | (s_flag[0] ? 4 : 0);
   }
 }
 
@@ -238,101 +334,84 @@ __global__ void __launch_bounds__(256) build_z(int64_t r, const double* R, int64
   Z[j * ldz + i] = (i < k) ? R[i * ldr + j] : 0.0;
 }
 
-template <int RPT, int NB>
-gn_status run_panel(double* C, int64_t ldc, int64_t M, int64_t j0, int nbw, double* V, double* VTt,
-                    double* VTn, int64_t ldv, const int32_t* gate, int64_t gate_n, hipStream_t s) {
-  qr_panel<RPT, NB><<<dim3(1), dim3(QR_T), 0, s>>>(C, ldc, M, j0, nbw, V, VTt, VTn, ldv, gate,
-                                                   gate_n);
+// Panel width and rows per thread for the panel starting at j0 (Mp rows).
+struct PanelShape {
+  int nb, rpt;
+};
+inline PanelShape panel_shape(int64_t Mp) {
+  const int rpt = (int)cdiv(Mp, QP_T);
+  return PanelShape{rpt <= 4 ? 16 : 8, rpt};
+}
+
+gn_status run_panel(double* C, int64_t ldc, int64_t M, int64_t j0, int nbw, double* Tp,
+                    const int32_t* gate, int64_t gate_n, hipStream_t s) {
+  const PanelShape ps = panel_shape(M - j0);
+  const dim3 g(1), b(QP_T);
+#define GN_PANEL(R, NBV) qr_panel<R, NBV><<<g, b, 0, s>>>(C, ldc, M, j0, nbw, Tp, gate, gate_n)
+  switch (ps.rpt) {
+    case 1: GN_PANEL(1, 16); break;
+    case 2: GN_PANEL(2, 16); break;
+    case 3: GN_PANEL(3, 16); break;
+    case 4: GN_PANEL(4, 16); break;
+    case 5: GN_PANEL(5, 8); break;
+    case 6: GN_PANEL(6, 8); break;
+    case 7: GN_PANEL(7, 8); break;
+    case 8: GN_PANEL(8, 8); break;
+    default: return GN_ERR_UNSUPPORTED;
+  }
+#undef GN_PANEL
   GN_LAUNCH_CHECK();
   return GN_OK;
 }
 
-inline int panel_width(int64_t Mp) { return Mp > 2048 ? 8 : 16; }
-
 }  // namespace
 
 size_t qr_ws_bytes(int64_t M, int64_t N) {
-  return 3 * align_up((size_t)M * N * sizeof(double)) + align_up((size_t)16 * N * sizeof(double));
+  // one nb x nb T per panel (panels are at least 8 wide)
+  return align_up((size_t)(cdiv(N, 8) + 1) * QR_NB * QR_NB * sizeof(double));
 }
 
 gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int64_t ldq, double* R,
                     int64_t ldr, double* ws, const int32_t* gate_k, hipStream_t s) {
   if (M < N || M > QR_MAXROWS || N < 1) return GN_ERR_UNSUPPORTED;
-  double* V = ws;
-  double* VTt = V + align_up((size_t)M * N * sizeof(double)) / sizeof(double);
-  double* VTn = VTt + align_up((size_t)M * N * sizeof(double)) / sizeof(double);
-  double* W = VTn + align_up((size_t)M * N * sizeof(double)) / sizeof(double);
-  const int64_t ldv = N, ldw = N;
   const int64_t gate_n = N;
-
-  // factor: panels left to right
-  int64_t j0 = 0;
-  while (j0 < N) {
-    const int64_t Mp = M - j0;
-    const int nb = panel_width(Mp);
-    const int nbw = (int)((N - j0 < nb) ? (N - j0) : nb);
-    const int rpt = (int)cdiv(Mp, QR_T);
-    if (rpt <= 1)
-      GN_TRY((run_panel<1, 16>(C, ldc, M, j0, nbw, V, VTt, VTn, ldv, gate_k, gate_n, s)));
-    else if (rpt <= 2)
-      GN_TRY((run_panel<2, 16>(C, ldc, M, j0, nbw, V, VTt, VTn, ldv, gate_k, gate_n, s)));
-    else if (rpt <= 3)
-      GN_TRY((run_panel<3, 8>(C, ldc, M, j0, nbw, V, VTt, VTn, ldv, gate_k, gate_n, s)));
-    else
-      GN_TRY((run_panel<4, 8>(C, ldc, M, j0, nbw, V, VTt, VTn, ldv, gate_k, gate_n, s)));
-    const int64_t Nt = N - j0 - nbw;
-    if (Nt > 0) {
-      // W = V_p^T C2  (nbw x Nt),  C2 = C[j0:, j0+nbw:]
-      MatRef vt{V + j0 * ldv + j0, GN_DT_F64, 1, ldv};
-      MatRef c2{C + j0 * ldc + j0 + nbw, GN_DT_F64, ldc, 1};
-      GN_TRY(launch_dgemm(nbw, Nt, Mp, 1.0, vt, c2, 0.0, W, ldw, 1, nullptr, false, s, gate_k,
-                          gate_n, true));
-      // C2 -= (V T^T) W
-      MatRef vtt{VTt + j0 * ldv + j0, GN_DT_F64, ldv, 1};
-      MatRef w{W, GN_DT_F64, ldw, 1};
-      GN_TRY(launch_dgemm(Mp, Nt, nbw, -1.0, vtt, w, 1.0, C + j0 * ldc + j0 + nbw, ldc, 1, nullptr,
-                          false, s, gate_k, gate_n, true));
-    }
-    j0 += nbw;
-  }
-
-  // explicit Q: start from [I; 0] and apply the block reflectors right to left
-  {
-    const int64_t tot = M * N;
-    qr_init_q<<<dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s>>>(Q, ldq, M, N, gate_k, gate_n);
-    GN_LAUNCH_CHECK();
-  }
-  // recompute the panel boundaries and walk them backwards
   int64_t starts[QR_MAXROWS];
   int widths[QR_MAXROWS];
   int np = 0;
   for (int64_t jj = 0; jj < N;) {
-    const int nb = panel_width(M - jj);
+    const int nb = panel_shape(M - jj).nb;
     const int w = (int)((N - jj < nb) ? (N - jj) : nb);
     starts[np] = jj;
     widths[np] = w;
     ++np;
     jj += w;
   }
-  for (int pi = np - 1; pi >= 0; --pi) {
-    const int64_t jp = starts[pi];
+  // factor: panels left to right, each followed by the trailing update
+  for (int pi = 0; pi < np; ++pi) {
+    const int64_t j0 = starts[pi];
     const int nbw = widths[pi];
-    const int64_t Mp = M - jp, Nq = N - jp;
-    MatRef vt{V + jp * ldv + jp, GN_DT_F64, 1, ldv};
-    MatRef q2{Q + jp * ldq + jp, GN_DT_F64, ldq, 1};
-    GN_TRY(launch_dgemm(nbw, Nq, Mp, 1.0, vt, q2, 0.0, W, ldw, 1, nullptr, false, s, gate_k, gate_n,
-                        true));
-    MatRef vtn{VTn + jp * ldv + jp, GN_DT_F64, ldv, 1};
-    MatRef w{W, GN_DT_F64, ldw, 1};
-    GN_TRY(launch_dgemm(Mp, Nq, nbw, -1.0, vtn, w, 1.0, Q + jp * ldq + jp, ldq, 1, nullptr, false,
-                        s, gate_k, gate_n, true));
+    double* Tp = ws + (size_t)pi * QR_NB * QR_NB;
+    GN_TRY(run_panel(C, ldc, M, j0, nbw, Tp, gate_k, gate_n, s));
+    const int64_t c0 = j0 + nbw, nt = N - c0;
+    if (nt > 0) {
+      qr_block_update<<<dim3((unsigned)cdiv(nt, 16)), dim3(256), 0, s>>>(
+          C, ldc, M, j0, nbw, C, ldc, c0, nt, Tp, 1, gate_k, gate_n);
+      GN_LAUNCH_CHECK();
+    }
   }
-  {
-    const int64_t tot = M * N;
-    qr_signfix<<<dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s>>>(C, ldc, Q, ldq, R, ldr, M, N,
-                                                                     gate_k, gate_n);
+  // explicit Q: start from [I; 0] and apply the block reflectors right to left
+  qr_init_q<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(Q, ldq, M, N, gate_k, gate_n);
+  GN_LAUNCH_CHECK();
+  for (int pi = np - 1; pi >= 0; --pi) {
+    const int64_t j0 = starts[pi];
+    const double* Tp = ws + (size_t)pi * QR_NB * QR_NB;
+    qr_block_update<<<dim3((unsigned)cdiv(N - j0, 16)), dim3(256), 0, s>>>(
+        C, ldc, M, j0, widths[pi], Q, ldq, j0, N - j0, Tp, 0, gate_k, gate_n);
     GN_LAUNCH_CHECK();
   }
+  qr_signfix<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(C, ldc, Q, ldq, R, ldr, M, N,
+                                                                   gate_k, gate_n);
+  GN_LAUNCH_CHECK();
   return GN_OK;
 }
 

@@ -238,3 +238,40 @@ def test_nonfinite_input_sets_status(G):
     p = G.Problem(m, n, r, 5, seed=1, mode="f64", eps=1e-15)
     _, _, core = G.solve(p, dev(A))
     assert core.flags() & 1
+
+
+# ----------------------------------------------------------------------------- FP32 / BF16 solves
+def _noisy(m, n, seed):
+    sig = np.arange(1, min(m, n) + 1, dtype=np.float64) ** -2.0
+    return W.spectrum_matrix(m, n, sig[:512], seed=seed, noise=1e-5)
+
+
+@pytest.mark.parametrize("mode,kind_x", [("f32", "gaussian"), ("f32", "srht"),
+                                         ("bf16", "gaussian"), ("bf16", "srht")])
+def test_low_precision_solve_within_5pct_of_oracle(G, mode, kind_x):
+    """FP32 / BF16 pass + FP64 core: ||A - A_hat||_F <= 1.05 x the FP64 oracle's
+    error with the same sketches (the error is measured against the FP64 A)."""
+    m, n, r, l = 3000, 2000, 200, 100
+    A = _noisy(m, n, 21)
+    eps = 10 * U32
+    p = G.Problem(m, n, r, l, kind_x=kind_x, seed=17, mode=mode, eps=eps)
+    if mode == "f32":
+        Ad, sc = dev(A, torch.float32), None
+    else:
+        Ad, sc = G.gn_quantize_bf16_bs(dev(A))
+    AX, YtA, _, _ = G.gn_sketch(p, Ad, scales=sc)
+    core = G.gn_core(p, AX)
+    assert (core.flags() & 3) == 0
+    F, Gm = G.gn_factors(p, AX, YtA, core)
+    e_gpu = math.sqrt(float(G.gn_residual(dev(A), F, Gm).item()))
+    # oracle: FP64 GN on the FP64 A with the working-precision sketch values
+    if kind_x == "srht":
+        X = OP.srht_matrix(17, n, r)
+        Y = OG.round_mode(OP.gaussian(17, OP.STREAM_Y, m, r + l), mode)
+        nx = OG.nu_srht(n)
+    else:
+        X, Y = OG.gaussian_sketches(17, m, n, r, l, mode=mode)
+        nx = OG.nu_gaussian(n, r)
+    ref = OG.gn(A, X, Y, OG.threshold(eps, nx, OG.nu_gaussian(m, r + l)))
+    e_ref = OG.residual_fro(A, ref.F, ref.G)
+    assert e_gpu <= 1.05 * e_ref, (e_gpu, e_ref)
