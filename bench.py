@@ -36,6 +36,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def srht_pad(n):
+    """Hadamard order n' = smallest power of two >= n (Section 3.1)."""
+    return 1 << max(0, int(n - 1).bit_length())
+
+
 def pass_algorithmic(w, npad):
     """(flops, bytes) the pass must do / move: A once, sketches once, outputs once."""
     m, n, r, rl = w.m, w.n, w.r, w.r + w.l
@@ -193,6 +198,11 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (reference for HBM counters)")
+    ap.add_argument("--host-factors", action="store_true",
+                    help="build the test matrix's orthonormal factors on the host (no library "
+                         "kernels on the device; used for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -202,14 +212,13 @@ def main():
     import torch
 
     from paper_2009_11392_amd import gn, workloads as W
-    from oracle import philox as OP
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     gn.C.lib()  # fail loudly if the library is not built
     w = W.ALL[args.workload]
-    npad = OP.next_pow2(w.n)
+    npad = srht_pad(w.n)
     log(f"generating {w.name} on the device")
-    A32 = W.device_matrix(w if w.mode != "bf16" else W.F32_32K)
+    A32 = W.device_matrix(w if w.mode != "bf16" else W.F32_32K, host_factors=args.host_factors)
     scales = None
     if w.mode == "bf16":
         A, scales = gn.gn_quantize_bf16_bs(A32)
@@ -218,6 +227,15 @@ def main():
     else:
         A = A32
     torch.cuda.synchronize()
+
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: 3 x 1 GiB device-to-device")
 
     run = Runner(gn, w, A, scales)
     log(f"timing {args.steps} steps after {args.warmup} warm-up steps")
@@ -265,7 +283,7 @@ def main():
                 Ab, sc = A32, None
             rr = Runner(gn, wl, Ab, sc)
             tt = rr.timed(3, 1)
-            fl, by = pass_algorithmic(wl, OP.next_pow2(wl.n))
+            fl, by = pass_algorithmic(wl, srht_pad(wl.n))
             ent = {"pass_ms": tt["pass"], "solve_ms": tt["prepare"] + tt["pass"] + tt["core"],
                    "pass_tflops": fl / (tt["pass"] / 1e3) / 1e12,
                    "pass_frac_of_peak": fl / (tt["pass"] / 1e3) / 1e12 / PEAK[tag]}

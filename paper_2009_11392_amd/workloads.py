@@ -127,29 +127,42 @@ def host_gaussian(rows: int, cols: int, seed: int) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------- device (torch)
-def device_matrix(w: Workload, device="cuda", dtype=None):
+def device_matrix(w: Workload, device="cuda", dtype=None, host_factors: bool = False):
     """A of workload `w` built on the device in FP32 (or `dtype`), seeded.
 
     U and V are the Q factors of Gaussian (m x k) and (n x k) matrices drawn with
     torch's device generator; A = (U * sigma) V^T, then entrywise noise is added
     block by block to bound temporary memory.
+
+    With `host_factors` the orthonormal factors and their FP32 product are made
+    on the host instead (NumPy PCG64 and LAPACK; the same recipe with other
+    random numbers) and only the noise is drawn on the device.  That route runs
+    no library kernel on the device (no QR, no GEMM), which is what hardware
+    counter collection needs; it takes tens of seconds of host time at 32768^2.
     """
     import torch
     dtype = dtype or torch.float32
     g = torch.Generator(device=device)
     g.manual_seed(w.input_seed)
-    sig = torch.tensor(w.sigma(), dtype=torch.float64, device=device)
-    k = len(sig)
+    k = w.rank
+    if host_factors:
+        rng = np.random.default_rng(w.input_seed)
+        Us = (_orth_host(rng, w.m, k) * w.sigma()[None, :]).astype(np.float32)
+        Vt = np.ascontiguousarray(_orth_host(rng, w.n, k).T.astype(np.float32))
+        A = torch.from_numpy(Us @ Vt).to(device)
+        del Us, Vt
+    else:
+        sig = torch.tensor(w.sigma(), dtype=torch.float64, device=device)
 
-    def orth(rows):
-        G = torch.randn(rows, k, generator=g, device=device, dtype=torch.float64)
-        q, _ = torch.linalg.qr(G)
-        return q
+        def orth(rows):
+            G = torch.randn(rows, k, generator=g, device=device, dtype=torch.float64)
+            q, _ = torch.linalg.qr(G)
+            return q
 
-    U = orth(w.m)
-    V = orth(w.n)
-    A = ((U * sig[None, :]).to(torch.float32) @ V.to(torch.float32).T)
-    del U, V
+        U = orth(w.m)
+        V = orth(w.n)
+        A = ((U * sig[None, :]).to(torch.float32) @ V.to(torch.float32).T)
+        del U, V
     if w.noise:
         step = max(1, (1 << 26) // w.n)
         for i0 in range(0, w.m, step):
