@@ -5,13 +5,23 @@
 //
 // Blocked right-looking QR.  Each panel of nb columns is factored by one
 // 512-thread workgroup holding the panel in registers (row t + 512 q of the panel
-// in thread t), with fixed-order workgroup reductions for the column norms and
-// the reflector dot products; it leaves R and the reflectors (below the
-// diagonal, unit diagonal implicit) in place and writes the compact-WY factor T
-// (H_1 ... H_nb = I - V T V^T).  One block-update kernel then applies the block
-// reflector to the trailing columns, C2 <- (I - V T^T V^T) C2, and, walking the
-// panels backwards, accumulates the explicit Q from [I; 0] with Q2 <- (I - V T V^T) Q2.
+// in thread t).  A column step needs one workgroup reduction: the dots of the
+// current column x with every panel column over the rows at and below the pivot,
+// with the slot of x itself holding the squared norm strictly below the pivot;
+// with the pivot row (passed through LDS) these give beta, tau, the dots
+// v^T p_j = (x.p_j - beta p_j[c]) / (alpha - beta) used by the update of the
+// columns to the right, and the same expression for the earlier reflectors
+// (the y of the compact-WY recurrence for T, H_1 ... H_nb = I - V T V^T).
+// Reductions are in a fixed order, so results do not depend on scheduling.
+//
+// The block reflector is applied to the trailing columns, C2 <- (I - V T^T V^T) C2,
+// and, walking the panels backwards from [I; 0], to the explicit Q with
+// Q2 <- (I - V T V^T) Q2, by two kernels over (128-row chunk) x (64-column group)
+// tiles: partial W = V^T D per chunk, then W summed over chunks in chunk order,
+// multiplied by T^T (or T) and subtracted, D -= V W.
 #include "gn_internal.h"
+
+#include <utility>
 
 namespace gn {
 namespace {
@@ -21,42 +31,162 @@ constexpr int QP_WAVES = QP_T / 64;
 constexpr int QR_MAXROWS = 4096;
 constexpr int QR_NB = 16;  // largest panel width
 
-template <int NV>
-__device__ __forceinline__ void qr_block_sum(double (&v)[NV], double* red /*[QP_WAVES][NV]*/,
-                                             double* out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double x = v[i];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    v[i] = x;
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) red[wave * NV + i] = v[i];
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < NV) {
-    double s = 0.0;
-    for (int w = 0; w < QP_WAVES; ++w) s += red[w * NV + threadIdx.x];
-    out[threadIdx.x] = s;
-  }
-  __syncthreads();
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// The column loop runs at run time; register arrays are only ever indexed by
-// compile-time constants (the current column is selected with predicated moves),
-// so the panel stays in registers.
+// Per-lane choice between two doubles with the lane mask as a constant SGPR
+// pair: lanes whose bit is set take `hi`.  (Written as a plain select, the
+// compiler merges the choice into a run-time index of the register array and
+// expands it into a compare-and-select chain over every element.)
+__device__ __forceinline__ double lane_select(double lo, double hi, unsigned long long lanes) {
+  const unsigned long long a = (unsigned long long)__double_as_longlong(lo);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(hi);
+  unsigned r0, r1;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r0) : "v"((unsigned)a), "v"((unsigned)b), "s"(lanes));
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3"
+      : "=v"(r1)
+      : "v"((unsigned)(a >> 32)), "v"((unsigned)(b >> 32)), "s"(lanes));
+  return __longlong_as_double((long long)(((unsigned long long)r1 << 32) | r0));
+}
+
+// Lanes whose lane-index bit `bit` is set.
+__host__ __device__ constexpr unsigned long long lanes_with_bit(int bit) {
+  unsigned long long m = 0;
+  for (int l = 0; l < 64; ++l)
+    if (l & bit) m |= 1ull << l;
+  return m;
+}
+
+// Sum of a[0..NV) over the 64 lanes of a wave, spread over the lanes: halving
+// exchanges (xor 32, 16, ...) leave each lane one slot, then full exchanges over
+// the remaining lane bits.  Returns the lane's sum; *slot receives its index.
+template <int NV>
+__device__ __forceinline__ double wave_transpose_sum(double (&a)[NV], int lane, int* slot) {
+  static_assert(NV >= 1 && NV <= 32 && (NV & (NV - 1)) == 0, "NV must be a power of two");
+  int sl = 0;
+  int mask = 32;
+#pragma unroll
+  for (int h = NV; h > 1; h >>= 1) {
+    const bool up = (lane & mask) != 0;
+    const unsigned long long lm = lanes_with_bit(mask);
+#pragma unroll
+    for (int i = 0; i < h / 2; ++i) {
+      const double mine = lane_select(a[i], a[i + h / 2], lm);
+      const double other = lane_select(a[i + h / 2], a[i], lm);
+      a[i] = mine + __shfl_xor(other, mask, 64);
+    }
+    sl = 2 * sl + (up ? 1 : 0);
+    mask >>= 1;
+  }
+  double v = a[0];
+  for (; mask > 0; mask >>= 1) v += __shfl_xor(v, mask, 64);
+  *slot = sl;
+  return v;
+}
+
+// One column step of the panel, c a compile-time column index: every register
+// array is indexed by constants, and only row c's thread and the rows above the
+// pivot (all in the first register row, c < NB) need run-time predicates.
+template <int RPT, int NB, int c>
+__device__ __forceinline__ void qr_column(double (&p)[RPT][NB], int t, int lane, int wave,
+                                          double (*part)[QP_WAVES][NB], double (*prow)[NB],
+                                          double (*T)[NB + 1]) {
+  constexpr int buf = c & 1;
+  constexpr int kLowBits = 64 / NB;  // lanes sharing a reduction slot
+  double x[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) x[q] = p[q][c];
+  // slot cc: x . p_cc over rows >= c; slot c: |x|^2 over rows > c.  Rows of
+  // register row q >= 1 are >= 512 > c.
+  const double x_ge = (t >= c) ? x[0] : 0.0;
+  const double x_gt = (t > c) ? x[0] : 0.0;
+  double acc[NB];
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc) {
+    double s = (cc == c ? x_gt : x_ge) * p[0][cc];
+#pragma unroll
+    for (int q = 1; q < RPT; ++q) s = fma(x[q], p[q][cc], s);
+    acc[cc] = s;
+  }
+  if (t == c) {
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc) prow[buf][cc] = p[0][cc];
+  }
+  int slot;
+  const double ws = wave_transpose_sum<NB>(acc, lane, &slot);
+  if ((lane & (kLowBits - 1)) == 0) part[buf][wave][slot] = ws;
+  __syncthreads();
+  // totals, summed over waves in a fixed order, made uniform via readlane
+  double tot_l = 0.0;
+  {
+    const int sl = lane % NB;
+#pragma unroll
+    for (int w = 0; w < QP_WAVES; ++w) tot_l += part[buf][w][sl];
+  }
+  double D[NB], P[NB];
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc) {
+    D[cc] = readlane_f64(tot_l, cc);  // lane cc holds slot cc
+    P[cc] = prow[buf][cc];
+  }
+  const double sigma = D[c], alpha = P[c];
+  double beta = alpha, tau = 0.0, scale = 0.0;
+  if (sigma != 0.0) {
+    const double nrm = sqrt(fma(alpha, alpha, sigma));
+    beta = (alpha >= 0.0) ? -nrm : nrm;
+    tau = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  // w_j = v^T p_j for every j != c (earlier reflectors: y of the T recurrence)
+  double w[NB];
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc) w[cc] = (tau != 0.0) ? scale * fma(-beta, P[cc], D[cc]) : P[cc];
+  // apply H_c to the columns right of c; store v and R_cc = beta in column c
+  const double v0 = (t > c) ? x[0] * scale : (t == c ? 1.0 : 0.0);
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const double v = (q == 0) ? v0 : x[q] * scale;
+#pragma unroll
+    for (int cc = c + 1; cc < NB; ++cc) p[q][cc] = fma(-tau * w[cc], v, p[q][cc]);
+  }
+  if (tau != 0.0) {
+    p[0][c] = (t > c) ? v0 : (t == c ? beta : p[0][c]);
+#pragma unroll
+    for (int q = 1; q < RPT; ++q) p[q][c] = x[q] * scale;
+  }
+  // T(:, c) = [ -tau T(0:c, 0:c) y ; tau ]; thread t < c owns row t of T, whose
+  // entries left of the diagonal are zero
+  if (t < c) {
+    double s = 0.0;
+#pragma unroll
+    for (int l = 0; l < c; ++l) s = fma(T[t][l], w[l], s);
+    T[t][c] = -tau * s;
+  }
+  if (t == c) T[c][c] = tau;
+}
+
+template <int RPT, int NB, int... Cs>
+__device__ __forceinline__ void qr_columns(std::integer_sequence<int, Cs...>, int nbw,
+                                           double (&p)[RPT][NB], int t, int lane, int wave,
+                                           double (*part)[QP_WAVES][NB], double (*prow)[NB],
+                                           double (*T)[NB + 1]) {
+  // nbw is uniform: columns past the panel width are skipped by a scalar branch
+  ((Cs < nbw ? (qr_column<RPT, NB, Cs>(p, t, lane, wave, part, prow, T), 0) : 0), ...);
+}
+
 template <int RPT, int NB>
 __global__ void __launch_bounds__(QP_T) qr_panel(double* __restrict__ C, int64_t ldc, int64_t M,
                                                  int64_t j0, int nbw, double* __restrict__ Tout,
                                                  const int32_t* gate, int64_t gate_n) {
   if (gate && *gate >= gate_n) return;
-  __shared__ double red[QP_WAVES * NB];
-  __shared__ double bc[NB];
-  __shared__ double T[NB][NB];
-  const int t = threadIdx.x;
+  __shared__ double part[2][QP_WAVES][NB];
+  __shared__ double prow[2][NB];
+  __shared__ double T[NB][NB + 1];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t Mp = M - j0;
   double p[RPT][NB];
 #pragma unroll
@@ -66,77 +196,11 @@ __global__ void __launch_bounds__(QP_T) qr_panel(double* __restrict__ C, int64_t
     for (int c = 0; c < NB; ++c)
       p[q][c] = (row < Mp && c < nbw) ? C[(j0 + row) * ldc + j0 + c] : 0.0;
   }
-  if (t < NB * NB) T[t / NB][t % NB] = 0.0;
-  __syncthreads();
-
-#pragma unroll 1
-  for (int c = 0; c < nbw; ++c) {
-    // column c of this thread's rows
-    double vr[RPT];
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      double x = 0.0;
-#pragma unroll
-      for (int cc = 0; cc < NB; ++cc) x = (cc == c) ? p[q][cc] : x;
-      vr[q] = x;
-    }
-    // squared norm below the pivot, and the pivot (row c lives in thread c, q = 0)
-    double v2[2] = {0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int64_t row = t + (int64_t)QP_T * q;
-      if (row > c && row < Mp) v2[0] = fma(vr[q], vr[q], v2[0]);
-    }
-    if (t == c) v2[1] = vr[0];
-    qr_block_sum<2>(v2, red, bc);
-    const double sigma = bc[0], alpha = bc[1];
-    double beta = alpha, tau = 0.0, scale = 0.0;
-    if (sigma != 0.0) {
-      const double nrm = sqrt(fma(alpha, alpha, sigma));
-      beta = (alpha >= 0.0) ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    // reflector v (v_c = 1 implicit) below the pivot
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int64_t row = t + (int64_t)QP_T * q;
-      if (row > c && row < Mp) {
-        if (tau != 0.0) vr[q] *= scale;
-      } else {
-        vr[q] = (row == c) ? 1.0 : 0.0;
-      }
-    }
-    // dots of v with every panel column over rows >= c (columns < c hold earlier
-    // reflectors there: those dots are the y of the T recurrence)
-    double d[NB];
-#pragma unroll
-    for (int cc = 0; cc < NB; ++cc) {
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) acc = fma(vr[q], p[q][cc], acc);
-      d[cc] = acc;
-    }
-    qr_block_sum<NB>(d, red, bc);
-    // apply H_c to the columns right of c; store v and R_cc = beta in column c
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int64_t row = t + (int64_t)QP_T * q;
-#pragma unroll
-      for (int cc = 0; cc < NB; ++cc) {
-        if (cc > c) p[q][cc] = fma(-tau * bc[cc], vr[q], p[q][cc]);
-        if (cc == c && row >= c) p[q][cc] = (row == c) ? beta : vr[q];
-      }
-    }
-    // T(:, c) = [ -tau T(0:c, 0:c) y ; tau ],  y = bc[0:c]
-    if (t < c) {
-      double s = 0.0;
-      for (int l = t; l < c; ++l) s = fma(T[t][l], bc[l], s);
-      T[t][c] = -tau * s;
-    }
-    if (t == c) T[c][c] = tau;
-    __syncthreads();
+  if (t < NB) {
+    for (int l = 0; l < NB; ++l) T[t][l] = 0.0;  // row t of T is only touched by thread t
   }
+  qr_columns<RPT, NB>(std::make_integer_sequence<int, NB>{}, nbw, p, t, lane, wave, part, prow, T);
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int64_t row = t + (int64_t)QP_T * q;
@@ -148,102 +212,128 @@ __global__ void __launch_bounds__(QP_T) qr_panel(double* __restrict__ C, int64_t
   if (t < NB * NB) Tout[(t / NB) * QR_NB + (t % NB)] = T[t / NB][t % NB];  // stride QR_NB
 }
 
-// D[j0 + i, col0 + j] for 0 <= i < M - j0, 0 <= j < ncols is replaced by
-// (I - V Top V^T) D, V the unit-lower reflectors of the panel at (j0, j0) of Cp
-// (width nbw) and Top = T^T (trans) or T.  One workgroup per 16 target columns:
-// W = V^T D accumulated by 16 row groups, reduced in fixed order, W <- Top W,
-// then D -= V W.  Panel rows are staged through LDS 256 at a time.
-constexpr int QU_ROWS = 256;
-constexpr int QU_RPG = QU_ROWS / 16;  // rows of a staged chunk per row group
-__global__ void __launch_bounds__(256) qr_block_update(const double* __restrict__ Cp, int64_t ldc,
-                                                       int64_t M, int64_t j0, int nbw,
-                                                       double* __restrict__ D, int64_t ldd,
-                                                       int64_t col0, int64_t ncols,
-                                                       const double* __restrict__ T, int trans,
-                                                       const int32_t* gate, int64_t gate_n) {
-  if (gate && *gate >= gate_n) return;
-  __shared__ double sV[QU_ROWS][QR_NB + 1];
-  __shared__ double red[16][QR_NB][17];
-  __shared__ double W[QR_NB][17];
-  const int tid = threadIdx.x, col = tid & 15, grp = tid >> 4;
-  const int64_t j = col0 + (int64_t)blockIdx.x * 16 + col;
-  const bool jok = j < col0 + ncols;
-  const int64_t Mp = M - j0;
-  double w[QR_NB];
-#pragma unroll
-  for (int c = 0; c < QR_NB; ++c) w[c] = 0.0;
+// Block-reflector update of D[j0 + i, col0 + j] (0 <= i < M - j0, 0 <= j < ncols)
+// by the panel at (j0, j0) of Cp (width nbw, unit-lower reflectors below the
+// diagonal).  Stage 1: Wp[chunk][c][j] = sum over the chunk's rows of V[i][c] D[i][j].
+constexpr int QU_CH = 128;  // rows per chunk
+constexpr int QU_CG = 64;   // target columns per workgroup
 
-  // stage reflector rows r0 .. r0 + 255 of the panel (explicit unit-lower form)
-  auto stage = [&](int64_t r0) {
-    const int64_t row = r0 + tid;
-#pragma unroll
-    for (int c = 0; c < QR_NB; ++c) {
-      double v = 0.0;
-      if (row < Mp && c < nbw) v = (row < c) ? 0.0 : (row == c ? 1.0 : Cp[(j0 + row) * ldc + j0 + c]);
-      sV[tid][c] = v;
-    }
-  };
-  for (int64_t r0 = 0; r0 < Mp; r0 += QU_ROWS) {
-    // this thread's 16 rows of the chunk: all loads issued before any use
-    double x[QU_RPG];
-#pragma unroll
-    for (int q = 0; q < QU_RPG; ++q) {
-      const int64_t row = r0 + grp + 16 * q;
-      x[q] = (jok && row < Mp) ? D[(j0 + row) * ldd + j] : 0.0;
-    }
-    __syncthreads();
-    stage(r0);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < QU_RPG; ++q)
-#pragma unroll
-      for (int c = 0; c < QR_NB; ++c) w[c] = fma(sV[grp + 16 * q][c], x[q], w[c]);
+__device__ __forceinline__ void qr_stage_v(double (*sV)[QR_NB + 1], const double* Cp, int64_t ldc,
+                                           int64_t j0, int nbw, int64_t Mp, int64_t r0) {
+  for (int e = threadIdx.x; e < QU_CH * QR_NB; e += blockDim.x) {
+    const int rr = e / QR_NB, c = e % QR_NB;
+    const int64_t row = r0 + rr;
+    double v = 0.0;
+    if (row < Mp && c < nbw) v = (row < c) ? 0.0 : (row == c ? 1.0 : Cp[(j0 + row) * ldc + j0 + c]);
+    sV[rr][c] = v;
   }
+}
+
+__global__ void __launch_bounds__(256) qr_upd_w(const double* __restrict__ Cp, int64_t ldc,
+                                                int64_t M, int64_t j0, int nbw,
+                                                const double* __restrict__ D, int64_t ldd,
+                                                int64_t col0, int64_t ncols, double* __restrict__ Wp,
+                                                const int32_t* gate, int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  __shared__ double sV[QU_CH][QR_NB + 1];
+  __shared__ double red[4][QR_NB][QU_CG + 1];
+  const int tid = threadIdx.x, j = tid & 63, wq = tid >> 6;
+  const int64_t Mp = M - j0;
+  const int64_t r0 = (int64_t)blockIdx.x * QU_CH;
+  const int64_t jg = (int64_t)blockIdx.y * QU_CG + j;
+  const bool jok = jg < ncols;
+  double d[QU_CH / 4];
 #pragma unroll
-  for (int c = 0; c < QR_NB; ++c) red[grp][c][col] = w[c];
-  __syncthreads();
-  {  // fixed-order reduction over the 16 row groups, then W <- Top W
-    const int c = grp;  // 16 x 16 threads: (c, col)
-    double s = 0.0;
-    for (int g2 = 0; g2 < 16; ++g2) s += red[g2][c][col];
-    W[c][col] = s;
+  for (int q = 0; q < QU_CH / 4; ++q) {
+    const int64_t row = r0 + wq + 4 * q;
+    d[q] = (jok && row < Mp) ? D[(j0 + row) * ldd + col0 + jg] : 0.0;
   }
+  qr_stage_v(sV, Cp, ldc, j0, nbw, Mp, r0);
   __syncthreads();
-  double wt;
+  double acc[QR_NB];
+#pragma unroll
+  for (int c = 0; c < QR_NB; ++c) acc[c] = 0.0;
+#pragma unroll
+  for (int q = 0; q < QU_CH / 4; ++q)
+#pragma unroll
+    for (int c = 0; c < QR_NB; ++c) acc[c] = fma(sV[wq + 4 * q][c], d[q], acc[c]);
+#pragma unroll
+  for (int c = 0; c < QR_NB; ++c) red[wq][c][j] = acc[c];
+  __syncthreads();
+  // 256 threads: (c4 = tid / 64 -> slots 4 c4 .. 4 c4 + 3, column j)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = 4 * wq + i;
+    const double s = ((red[0][c][j] + red[1][c][j]) + red[2][c][j]) + red[3][c][j];
+    if (jok) Wp[((int64_t)blockIdx.x * QR_NB + c) * ncols + jg] = s;
+  }
+}
+
+// Stage 2: W = sum over chunks of Wp (chunk order), W <- Top W (Top = T^T when
+// trans, else T), D -= V W over this workgroup's chunk of rows.
+__global__ void __launch_bounds__(256) qr_upd_apply(const double* __restrict__ Cp, int64_t ldc,
+                                                    int64_t M, int64_t j0, int nbw,
+                                                    double* __restrict__ D, int64_t ldd,
+                                                    int64_t col0, int64_t ncols,
+                                                    const double* __restrict__ Wp, int nchunks,
+                                                    const double* __restrict__ T, int trans,
+                                                    const int32_t* gate, int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  __shared__ double sV[QU_CH][QR_NB + 1];
+  __shared__ double W[QR_NB][QU_CG + 1];
+  __shared__ double sT[QR_NB][QR_NB + 1];
+  const int tid = threadIdx.x, j = tid & 63, wq = tid >> 6;
+  const int64_t Mp = M - j0;
+  const int64_t r0 = (int64_t)blockIdx.x * QU_CH;
+  const int64_t jg = (int64_t)blockIdx.y * QU_CG + j;
+  const bool jok = jg < ncols;
+  double d[QU_CH / 4];
+#pragma unroll
+  for (int q = 0; q < QU_CH / 4; ++q) {
+    const int64_t row = r0 + wq + 4 * q;
+    d[q] = (jok && row < Mp) ? D[(j0 + row) * ldd + col0 + jg] : 0.0;
+  }
+  {  // sum over chunks in chunk order; loads issued four chunks at a time
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int ch = 0; ch < nchunks; ch += 4) {
+      double v[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          v[u][i] = (jok && ch + u < nchunks)
+                        ? Wp[((int64_t)(ch + u) * QR_NB + 4 * wq + i) * ncols + jg]
+                        : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] += v[u][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) W[4 * wq + i][j] = s[i];
+  }
   {
-    const int c = grp;
-    double s = 0.0;
-    for (int c2 = 0; c2 < nbw; ++c2) {
-      const double top = trans ? T[c2 * QR_NB + c] : T[c * QR_NB + c2];
-      s = fma(top, W[c2][col], s);
-    }
-    wt = (c < nbw) ? s : 0.0;
+    const int c = tid / QR_NB, c2 = tid % QR_NB;  // 256 = 16 x 16
+    const double v = trans ? T[c2 * QR_NB + c] : T[c * QR_NB + c2];
+    sT[c][c2] = (c < nbw && c2 < nbw) ? v : 0.0;
   }
+  qr_stage_v(sV, Cp, ldc, j0, nbw, Mp, r0);
   __syncthreads();
-  W[grp][col] = wt;
-  __syncthreads();
-  double wc[QR_NB];
+  double wt[QR_NB];
 #pragma unroll
-  for (int c = 0; c < QR_NB; ++c) wc[c] = W[c][col];
-  // D -= V W
-  for (int64_t r0 = 0; r0 < Mp; r0 += QU_ROWS) {
-    double x[QU_RPG];
+  for (int c = 0; c < QR_NB; ++c) {
+    double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < QU_RPG; ++q) {
-      const int64_t row = r0 + grp + 16 * q;
-      x[q] = (jok && row < Mp) ? D[(j0 + row) * ldd + j] : 0.0;
-    }
-    __syncthreads();
-    stage(r0);
-    __syncthreads();
+    for (int c2 = 0; c2 < QR_NB; ++c2) s = fma(sT[c][c2], W[c2][j], s);
+    wt[c] = s;
+  }
 #pragma unroll
-    for (int q = 0; q < QU_RPG; ++q) {
-      const int64_t row = r0 + grp + 16 * q;
-      double s = 0.0;
+  for (int q = 0; q < QU_CH / 4; ++q) {
+    const int64_t row = r0 + wq + 4 * q;
+    double s = 0.0;
 #pragma unroll
-      for (int c = 0; c < QR_NB; ++c) s = fma(sV[grp + 16 * q][c], wc[c], s);
-      if (jok && row < Mp) D[(j0 + row) * ldd + j] = x[q] - s;
-    }
+    for (int c = 0; c < QR_NB; ++c) s = fma(sV[wq + 4 * q][c], wt[c], s);
+    if (jok && row < Mp) D[(j0 + row) * ldd + col0 + jg] = d[q] - s;
   }
 }
 
@@ -340,7 +430,7 @@ struct PanelShape {
 };
 inline PanelShape panel_shape(int64_t Mp) {
   const int rpt = (int)cdiv(Mp, QP_T);
-  return PanelShape{rpt <= 4 ? 16 : 8, rpt};
+  return PanelShape{rpt <= 3 ? 16 : 8, rpt};  // 4 x 16 doubles per thread would spill
 }
 
 gn_status run_panel(double* C, int64_t ldc, int64_t M, int64_t j0, int nbw, double* Tp,
@@ -352,7 +442,7 @@ gn_status run_panel(double* C, int64_t ldc, int64_t M, int64_t j0, int nbw, doub
     case 1: GN_PANEL(1, 16); break;
     case 2: GN_PANEL(2, 16); break;
     case 3: GN_PANEL(3, 16); break;
-    case 4: GN_PANEL(4, 16); break;
+    case 4: GN_PANEL(4, 8); break;
     case 5: GN_PANEL(5, 8); break;
     case 6: GN_PANEL(6, 8); break;
     case 7: GN_PANEL(7, 8); break;
@@ -364,17 +454,36 @@ gn_status run_panel(double* C, int64_t ldc, int64_t M, int64_t j0, int nbw, doub
   return GN_OK;
 }
 
+gn_status run_update(const double* Cp, int64_t ldc, int64_t M, int64_t j0, int nbw, double* D,
+                     int64_t ldd, int64_t col0, int64_t ncols, const double* Tp, int trans,
+                     double* Wp, const int32_t* gate, int64_t gate_n, hipStream_t s) {
+  if (ncols <= 0) return GN_OK;
+  const int nch = (int)cdiv(M - j0, QU_CH);
+  const dim3 g((unsigned)nch, (unsigned)cdiv(ncols, QU_CG)), b(256);
+  qr_upd_w<<<g, b, 0, s>>>(Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Wp, gate, gate_n);
+  GN_LAUNCH_CHECK();
+  qr_upd_apply<<<g, b, 0, s>>>(Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Wp, nch, Tp, trans, gate,
+                               gate_n);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
 }  // namespace
 
-size_t qr_ws_bytes(int64_t M, int64_t N) {
-  // one nb x nb T per panel (panels are at least 8 wide)
+// one nb x nb T per panel (panels are at least 8 wide), then the per-chunk
+// partial products of the block update
+static size_t qr_t_bytes(int64_t N) {
   return align_up((size_t)(cdiv(N, 8) + 1) * QR_NB * QR_NB * sizeof(double));
+}
+size_t qr_ws_bytes(int64_t M, int64_t N) {
+  return qr_t_bytes(N) + align_up((size_t)cdiv(M, QU_CH) * QR_NB * N * sizeof(double));
 }
 
 gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int64_t ldq, double* R,
                     int64_t ldr, double* ws, const int32_t* gate_k, hipStream_t s) {
   if (M < N || M > QR_MAXROWS || N < 1) return GN_ERR_UNSUPPORTED;
   const int64_t gate_n = N;
+  double* Wp = ws + qr_t_bytes(N) / sizeof(double);
   int64_t starts[QR_MAXROWS];
   int widths[QR_MAXROWS];
   int np = 0;
@@ -393,11 +502,7 @@ gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int
     double* Tp = ws + (size_t)pi * QR_NB * QR_NB;
     GN_TRY(run_panel(C, ldc, M, j0, nbw, Tp, gate_k, gate_n, s));
     const int64_t c0 = j0 + nbw, nt = N - c0;
-    if (nt > 0) {
-      qr_block_update<<<dim3((unsigned)cdiv(nt, 16)), dim3(256), 0, s>>>(
-          C, ldc, M, j0, nbw, C, ldc, c0, nt, Tp, 1, gate_k, gate_n);
-      GN_LAUNCH_CHECK();
-    }
+    GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, c0, nt, Tp, 1, Wp, gate_k, gate_n, s));
   }
   // explicit Q: start from [I; 0] and apply the block reflectors right to left
   qr_init_q<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(Q, ldq, M, N, gate_k, gate_n);
@@ -405,9 +510,7 @@ gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int
   for (int pi = np - 1; pi >= 0; --pi) {
     const int64_t j0 = starts[pi];
     const double* Tp = ws + (size_t)pi * QR_NB * QR_NB;
-    qr_block_update<<<dim3((unsigned)cdiv(N - j0, 16)), dim3(256), 0, s>>>(
-        C, ldc, M, j0, widths[pi], Q, ldq, j0, N - j0, Tp, 0, gate_k, gate_n);
-    GN_LAUNCH_CHECK();
+    GN_TRY(run_update(C, ldc, M, j0, widths[pi], Q, ldq, j0, N - j0, Tp, 0, Wp, gate_k, gate_n, s));
   }
   qr_signfix<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(C, ldc, Q, ldq, R, ldr, M, N,
                                                                    gate_k, gate_n);

@@ -75,26 +75,74 @@ __global__ void __launch_bounds__(256) srht_signs_keys(uint32_t k0, uint32_t k1,
   keys[j] = ((uint64_t)hi << 32) | (uint64_t)lo;
 }
 
-// Rank of each key among all npad keys (ties broken by index); the keys of
-// rank < r give idx[rank] = j.  O(npad^2) comparisons, staged through LDS.
-constexpr int kSelTile = 1024;
-__global__ void __launch_bounds__(256) srht_select(const uint64_t* keys, int64_t npad, int64_t r,
-                                                   int32_t* idx) {
-  __shared__ uint64_t tile[kSelTile];
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t kj = (j < npad) ? keys[j] : ~0ull;
-  int64_t rank = 0;
-  for (int64_t t0 = 0; t0 < npad; t0 += kSelTile) {
-    const int64_t len = (npad - t0 < kSelTile) ? (npad - t0) : kSelTile;
-    __syncthreads();
-    for (int q = threadIdx.x; q < len; q += blockDim.x) tile[q] = keys[t0 + q];
-    __syncthreads();
-    for (int q = 0; q < len; ++q) {
-      const uint64_t ki = tile[q];
-      rank += (ki < kj) || (ki == kj && (t0 + q) < j);
+// The r smallest (key, j) pairs in ascending order: idx[rank] = j.  One
+// workgroup: a histogram of the top kSelBits key bits finds the first bin at
+// which the cumulative count reaches r; every key in a later bin is larger than
+// the >= r keys before it, so only the keys of bins up to that one (about
+// r + npad / 2^kSelBits for uniform keys) are compacted into cand_* and ranked
+// against each other.  Ties between equal keys are broken by the index j, so
+// the result does not depend on the order of the atomic compaction.
+constexpr int kSelBits = 12, kSelBins = 1 << kSelBits, kSelT = 1024;
+__global__ void __launch_bounds__(kSelT) srht_select(const uint64_t* keys, int64_t npad, int64_t r,
+                                                     uint64_t* cand_k, int32_t* cand_j,
+                                                     int32_t* idx) {
+  __shared__ int hist[kSelBins];
+  __shared__ uint64_t tk[kSelT];
+  __shared__ int32_t tj[kSelT];
+  __shared__ int s_bin, s_cnt;
+  const int t = threadIdx.x;
+  for (int b = t; b < kSelBins; b += kSelT) hist[b] = 0;
+  if (t == 0) {
+    s_cnt = 0;
+    s_bin = kSelBins - 1;
+  }
+  __syncthreads();
+  for (int64_t j = t; j < npad; j += kSelT) atomicAdd(&hist[(int)(keys[j] >> (64 - kSelBits))], 1);
+  __syncthreads();
+  if (t < 64) {  // wave 0: lane t owns bins [64 t, 64 t + 64)
+    int own = 0;
+    for (int q = 0; q < kSelBins / 64; ++q) own += hist[t * (kSelBins / 64) + q];
+    int inc = own;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(inc, d, 64);
+      if (t >= d) inc += v;
+    }
+    const int exc = inc - own;
+    if (exc < r && inc >= r) {
+      int c = exc, b = t * (kSelBins / 64);
+      while (c + hist[b] < r) c += hist[b++];
+      s_bin = b;
     }
   }
-  if (j < npad && rank < r) idx[rank] = (int32_t)j;
+  __syncthreads();
+  const int bsel = s_bin;
+  for (int64_t j = t; j < npad; j += kSelT) {
+    const uint64_t k = keys[j];
+    if ((int)(k >> (64 - kSelBits)) <= bsel) {
+      const int pos = atomicAdd(&s_cnt, 1);
+      cand_k[pos] = k;
+      cand_j[pos] = (int32_t)j;
+    }
+  }
+  __syncthreads();
+  const int c = s_cnt;
+  for (int base = 0; base < c; base += kSelT) {
+    const int me = base + t;
+    const uint64_t kme = (me < c) ? cand_k[me] : ~0ull;
+    const int32_t jme = (me < c) ? cand_j[me] : 0x7fffffff;
+    int rank = 0;
+    for (int t0 = 0; t0 < c; t0 += kSelT) {
+      __syncthreads();
+      if (t0 + t < c) {
+        tk[t] = cand_k[t0 + t];
+        tj[t] = cand_j[t0 + t];
+      }
+      __syncthreads();
+      const int len = (c - t0 < kSelT) ? (c - t0) : kSelT;
+      for (int q = 0; q < len; ++q) rank += (tk[q] < kme) || (tk[q] == kme && tj[q] < jme);
+    }
+    if (me < c && rank < r) idx[rank] = jme;
+  }
 }
 
 template <typename T>
@@ -146,7 +194,10 @@ gn_status launch_gaussian(uint64_t seed, int32_t sid, int64_t row0, int64_t col0
   return GN_OK;
 }
 
-size_t srht_ws_bytes(int64_t npad) { return align_up((size_t)npad * sizeof(uint64_t)); }
+// keys (npad u64) | candidate keys (npad u64) | candidate indices (npad i32)
+size_t srht_ws_bytes(int64_t npad) {
+  return 2 * align_up((size_t)npad * sizeof(uint64_t)) + align_up((size_t)npad * sizeof(int32_t));
+}
 
 gn_status launch_srht(uint64_t seed, int64_t npad, int64_t r, int8_t* signs, int32_t* idx,
                       uint64_t* keys_ws, hipStream_t s) {
@@ -154,7 +205,10 @@ gn_status launch_srht(uint64_t seed, int64_t npad, int64_t r, int8_t* signs, int
   const dim3 grid((unsigned)cdiv(npad, 256)), block(256);
   srht_signs_keys<<<grid, block, 0, s>>>(k0, k1, npad, signs, keys_ws);
   GN_LAUNCH_CHECK();
-  srht_select<<<grid, block, 0, s>>>(keys_ws, npad, r, idx);
+  char* base = reinterpret_cast<char*>(keys_ws);
+  const size_t kb = align_up((size_t)npad * sizeof(uint64_t));
+  srht_select<<<1, kSelT, 0, s>>>(keys_ws, npad, r, reinterpret_cast<uint64_t*>(base + kb),
+                                  reinterpret_cast<int32_t*>(base + 2 * kb), idx);
   GN_LAUNCH_CHECK();
   return GN_OK;
 }

@@ -91,7 +91,8 @@ def gn_srht_generate(seed: int, n: int, r: int):
     npad = 1 << max(0, (n - 1).bit_length())
     signs = torch.empty(npad, dtype=torch.int8, device="cuda")
     idx = torch.empty(r, dtype=torch.int32, device="cuda")
-    ws = torch.empty(max(8 * npad, 256), dtype=torch.uint8, device="cuda")
+    # the workspace depends on n' only; any valid problem with this n sizes it
+    ws = workspace(Problem(n, n, max(1, min(r, n)), kind_x="srht"), C.GN_OP_SRHT)
     C.check(C.lib().gn_srht_generate(seed & ((1 << 64) - 1), n, r, _ptr(signs), _ptr(idx), _ptr(ws),
                                      ws.numel(), _stream()), "gn_srht_generate")
     return signs, idx

@@ -275,3 +275,29 @@ def test_low_precision_solve_within_5pct_of_oracle(G, mode, kind_x):
     ref = OG.gn(A, X, Y, OG.threshold(eps, nx, OG.nu_gaussian(m, r + l)))
     e_ref = OG.residual_fro(A, ref.F, ref.G)
     assert e_gpu <= 1.05 * e_ref, (e_gpu, e_ref)
+
+
+# ----------------------------------------------------------------------------- larger cores
+# Core shapes that exercise every panel configuration of the QR (1 to 8 rows per
+# thread, panel widths 16 and 8) and the second QR of a truncated core.
+@pytest.mark.parametrize("m,r,l,drop", [(2048, 1000, 500, 0), (2048, 1200, 600, 0),
+                                        (3072, 2000, 1000, 0), (4096, 2700, 1350, 0),
+                                        (2048, 900, 450, 60)])
+def test_core_large_f64(G, m, r, l, drop):
+    rng = np.random.default_rng(r + drop)
+    AX = rng.standard_normal((m, r))
+    if drop:   # the last `drop` columns are combinations of the others: rank r - drop
+        AX[:, r - drop:] = AX[:, :r - drop] @ rng.standard_normal((r - drop, drop))
+    eps = 1e-9 if drop else 0.0
+    p = G.Problem(m, m, r, l, seed=11, mode="f64", eps=eps)
+    Y = OP.gaussian(p.seed, OP.STREAM_Y, m, p.rl)
+    ref = OG.core(AX, Y, tau_of(p))
+    core = G.gn_core(p, dev(AX))
+    k = ref.k
+    assert core.rank() == k == r - drop
+    assert (core.flags() & 3) == 0
+    assert relerr(host(core.R)[:k], ref.R[:k]) <= 1e-12
+    assert relerr(host(core.Q1)[:, :k], ref.Q[:, :k]) <= 1e-12
+    if drop:
+        assert relerr(host(core.Q2)[:, :k], ref.Q2) <= 1e-11
+        assert relerr(np.triu(host(core.R2)[:k, :k]), ref.R2) <= 1e-11
