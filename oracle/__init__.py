@@ -16,6 +16,9 @@ Modules
              plus the comparison formulas used as pins (HMT, Tropp17, SVD
              epsilon-pseudoinverse, Nystrom, CUR) and the theorem bounds.
   exact   -- exact rational GN on tiny integer inputs (brute-force pin).
+  grad    -- reverse mode of the approximant with the kept rank held fixed
+             (dL/dA for L = <Gbar, A_hat>), pinned by finite differences and by
+             torch's FP64 autograd through an independent forward.
 
 Parity status of each function is stated in its module header.
 """
