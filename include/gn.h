@@ -10,7 +10,9 @@
  *   gn_sketch_prepare / gn_sketch_pass / gn_sketch -- the sketches and the
  *                   single pass over A that forms AX and Y^T A,
  *   gn_core       -- C = Y^T (AX), its Householder QR and the eps-truncation,
- *   gn_factors / gn_apply -- the factored approximant and products with it,
+ *   gn_factors / gn_apply -- the factored approximant, products with it, and
+ *                   the approximant itself,
+ *   gn_backward   -- the reverse mode: dL/dA from dL/dA_hat,
  *   gn_residual   -- ||A - F G||_F^2 formed tile by tile (error measurement),
  *   gn_quantize_bf16_bs -- bfloat16 storage of A with power-of-two block scales.
  *
@@ -116,7 +118,9 @@ typedef enum {
   GN_OP_FACTORS = 2,
   GN_OP_APPLY = 3,     /* with kcols = the number of right-hand sides         */
   GN_OP_RESIDUAL = 4,
-  GN_OP_SRHT = 5
+  GN_OP_SRHT = 5,
+  GN_OP_BACKWARD = 6,  /* gn_backward                                          */
+  GN_OP_MATERIALIZE = 7 /* gn_apply side 2                                     */
 } gn_op;
 
 /* Bytes of device workspace the given operation needs for problem p.  For
@@ -198,12 +202,36 @@ gn_status gn_factors(const gn_problem* p, const void* AX, int64_t ldax, const vo
  *   side 0: out (m x kcols, ld ldo) = A_hat W,  W n x kcols (ld ldw),
  *           evaluated as AX (R^{-1} (Q^T (Y^T A W)));
  *   side 1: out (kcols x n, ld ldo) = W A_hat,  W kcols x m (ld ldw),
- *           evaluated as (((W AX) R^{-1}) Q^T) Y^T A.
- * (with Q2 R2^{-T} in place of R^{-1} when k < r).  W and out are double. */
+ *           evaluated as (((W AX) R^{-1}) Q^T) Y^T A;
+ * (with Q2 R2^{-T} in place of R^{-1} when k < r); W and out are double.
+ *   side 2: out (m x n, ld ldo) = A_hat itself, F G with the factors of
+ *           gn_factors, in the mode's accumulation dtype (double in F64 mode,
+ *           float otherwise); W and kcols are ignored; workspace
+ *           gn_workspace_size(GN_OP_MATERIALIZE).  Costs O(mnr): for
+ *           evaluation and for callers (autograd) that need A_hat as a tensor. */
 gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ldax,
                    const void* YtA, int64_t ldya, const gn_core_out* core, const double* W,
-                   int64_t ldw, int64_t kcols, double* out, int64_t ldo, void* ws,
+                   int64_t ldw, int64_t kcols, void* out, int64_t ldo, void* ws,
                    size_t ws_bytes, gn_stream_t stream);
+
+/* Reverse mode of the approximant.  For L with dL/dA_hat = Gbar (m x n, ld ldg),
+ * writes dA = dL/dA (m x n, ld ldda) for the map A -> A_hat = AX M Y^T A with
+ * M = R_1^+ Q_1^T the eps-truncated core pseudoinverse (Section 5.1.1) and the
+ * kept rank k held at the value the forward gn_core chose:
+ *   G1 = Gbar (Y^T A)^T, G2 = (AX)^T Gbar  (one fused pass over Gbar),
+ *   H = (AX)^T G1,  Cbar = the adjoint of M at H through the core (FP64),
+ *   dA = [G1 M^T + Y Cbar] X^T + Y [M^T G2]   (one rank-(r + l) product).
+ * Modes GN_MODE_F64 (A, Gbar, AX, YtA, dA double) and GN_MODE_F32 (float; the
+ * core adjoint is FP64 in both).  X and Y must be GN_SKETCH_GAUSSIAN (they are
+ * regenerated from p->seed); other kinds return GN_ERR_UNSUPPORTED.  AX (ld
+ * ldax) and YtA (ld ldya) are the forward pass's outputs; AX may be NULL, in
+ * which case it is recomputed from A (ld lda) -- A is read only then.  `core`
+ * is the forward gn_core output (read only).  Workspace:
+ * gn_workspace_size(GN_OP_BACKWARD) bytes, 256-byte aligned. */
+gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const void* Gbar,
+                      int64_t ldg, const void* AX, int64_t ldax, const void* YtA, int64_t ldya,
+                      const gn_core_out* core, void* dA, int64_t ldda, void* ws,
+                      size_t ws_bytes, gn_stream_t stream);
 
 /* ||A - F G||_F^2 accumulated in FP64, tile by tile (no Gram-matrix shortcut),
  * written to *out_sumsq (device double).  A is m x n in `a_dtype` (for

@@ -14,12 +14,14 @@ GN_ERR_WORKSPACE, GN_ERR_HIP, GN_ERR_NUMERIC, GN_ERR_UNSUPPORTED = 5, 6, 7, 8
 GN_SKETCH_GAUSSIAN, GN_SKETCH_SRHT, GN_SKETCH_USER = 0, 1, 2
 GN_MODE_F64, GN_MODE_F32, GN_MODE_BF16_BS = 0, 1, 2
 GN_DT_F64, GN_DT_F32, GN_DT_BF16 = 0, 1, 2
-GN_OP_SKETCH, GN_OP_CORE, GN_OP_FACTORS, GN_OP_APPLY, GN_OP_RESIDUAL, GN_OP_SRHT = range(6)
+(GN_OP_SKETCH, GN_OP_CORE, GN_OP_FACTORS, GN_OP_APPLY, GN_OP_RESIDUAL, GN_OP_SRHT,
+ GN_OP_BACKWARD, GN_OP_MATERIALIZE) = range(8)
 
 EXPORTED = (
     "gn_workspace_size", "gn_generate_gaussian", "gn_srht_generate", "gn_sketch_prepare",
     "gn_sketch_pass", "gn_sketch", "gn_core",
-    "gn_factors", "gn_apply", "gn_residual", "gn_quantize_bf16_bs", "gn_status_string",
+    "gn_factors", "gn_apply", "gn_backward", "gn_residual", "gn_quantize_bf16_bs",
+    "gn_status_string",
     "gn_version",
 )
 
@@ -75,6 +77,9 @@ def lib(path: str = LIB_PATH):
     L.gn_apply.argtypes = [P, c_int32, c_void_p, c_int64, c_void_p, c_int64, POINTER(GnCoreOut),
                            c_void_p, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_size_t,
                            c_void_p]
+    L.gn_backward.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                              c_void_p, c_int64, POINTER(GnCoreOut), c_void_p, c_int64, c_void_p,
+                              c_size_t, c_void_p]
     L.gn_residual.argtypes = [c_int64, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
                               c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_size_t,
                               c_void_p]

@@ -128,6 +128,51 @@ ApplyWs apply_ws(const Plan& P, int64_t kc) {
   return w;
 }
 
+// Reverse mode: sketch-dtype (sd) buffers for [U | Y] (m x (r+l)), [X^T ; V]
+// ((r+l) x n), S^T (n x (r+l)), AX (m x r, when recomputed or re-strided),
+// G1 (m x (r+l)) and G2 (r x n); FP64 buffers for H and the core adjoint.
+struct BackWs {
+  size_t lcat, rcat, st, p, g1, g2, h, m0, m1, c, bbar, x2, z, y5, t1, t2, t3, t4, split, total;
+};
+BackWs back_ws(const Plan& P) {
+  BackWs w{};
+  const size_t sd = (P.mode == GN_MODE_F64) ? 8 : 4;
+  const size_t rl = P.rl, r = P.r, m = P.m, n = P.n;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  w.lcat = take(m * (r + rl) * sd);
+  w.rcat = take((r + rl) * n * sd);
+  w.st = take(n * rl * sd);
+  w.p = take(m * r * sd);
+  w.g1 = take(m * rl * sd);
+  w.g2 = take(r * n * sd);
+  w.h = take(r * rl * 8);
+  w.m0 = take(r * rl * 8);
+  w.m1 = take(r * rl * 8);
+  w.c = take(rl * r * 8);
+  w.bbar = take(rl * r * 8);
+  w.x2 = take(rl * r * 8);
+  w.z = take(rl * r * 8);
+  w.y5 = take(rl * r * 8);
+  w.t1 = take(r * r * 8);
+  w.t2 = take(r * r * 8);
+  w.t3 = take(r * r * 8);
+  w.t4 = take(r * r * 8);
+  w.split = off;
+  off += (P.mode == GN_MODE_F64) ? dgemm_split_ws_bytes(P.r, P.rl, P.m)
+                                 : core_product_ws_bytes(P.m, P.r, P.rl);
+  w.total = off;
+  return w;
+}
+
+size_t materialize_ws(const Plan& P) {
+  return align_up((size_t)P.m * P.r * 8) + align_up((size_t)P.r * P.n * 8) + 256;
+}
+
 // copy (and widen) an m x r matrix of dtype dt into double, run only when the
 // gate says the core was not truncated.
 __global__ void __launch_bounds__(256) widen_gated(int64_t rows, int64_t cols, const void* src,
@@ -190,6 +235,8 @@ gn_status gn_workspace_size(const gn_problem* p, int32_t op, int64_t kcols, size
       break;
     case GN_OP_RESIDUAL: *bytes = residual_ws_bytes(P.m, P.n); break;
     case GN_OP_SRHT: *bytes = srht_ws_bytes(P.npad); break;
+    case GN_OP_BACKWARD: *bytes = back_ws(P).total; break;
+    case GN_OP_MATERIALIZE: *bytes = materialize_ws(P); break;
     default: return GN_ERR_ARG;
   }
   return GN_OK;
@@ -388,10 +435,23 @@ gn_status gn_factors(const gn_problem* p, const void* AX, int64_t ldax, const vo
 
 gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ldax, const void* YtA,
                    int64_t ldya, const gn_core_out* core, const double* W, int64_t ldw, int64_t kc,
-                   double* out, int64_t ldo, void* ws, size_t ws_bytes, gn_stream_t stream_) {
+                   void* out_, int64_t ldo, void* ws, size_t ws_bytes, gn_stream_t stream_) {
   Plan P;
   GN_TRY(make_plan(p, P));
   hipStream_t s = (hipStream_t)stream_;
+  if (side == 2) {  // A_hat = F G, in the accumulation dtype
+    if (!AX || !YtA || !core || !out_ || !ws) return GN_ERR_ARG;
+    if (ldo < P.n) return GN_ERR_SHAPE;
+    if (ws_bytes < materialize_ws(P)) return GN_ERR_WORKSPACE;
+    if (((uintptr_t)ws & 7u) != 0) return GN_ERR_ALIGN;
+    double* F = (double*)ws;
+    double* G = (double*)((char*)ws + align_up((size_t)P.m * P.r * 8));
+    GN_TRY(gn_factors(p, AX, ldax, YtA, ldya, core, F, P.r, G, P.n, nullptr, 0, stream_));
+    return launch_dgemm_to(P.m, P.n, P.r, 1.0, MatRef{F, GN_DT_F64, P.r, 1},
+                           MatRef{G, GN_DT_F64, P.n, 1}, 0.0, out_, P.adt, ldo, 1, nullptr, false,
+                           s);
+  }
+  double* out = (double*)out_;
   if (!AX || !YtA || !core || !W || !out || !ws || !core->k || !core->Q1 || !core->R || !core->Q2 ||
       !core->R2)
     return GN_ERR_ARG;
@@ -444,6 +504,146 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
                         nullptr, false, s));
   }
   return GN_OK;
+}
+
+gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const void* Gbar,
+                      int64_t ldg, const void* AX, int64_t ldax, const void* YtA, int64_t ldya,
+                      const gn_core_out* core, void* dA, int64_t ldda, void* ws, size_t ws_bytes,
+                      gn_stream_t stream_) {
+  Plan P;
+  GN_TRY(make_plan(p, P));
+  hipStream_t s = (hipStream_t)stream_;
+  if (P.mode != GN_MODE_F64 && P.mode != GN_MODE_F32) return GN_ERR_UNSUPPORTED;
+  if (P.kx != GN_SKETCH_GAUSSIAN || P.ky != GN_SKETCH_GAUSSIAN) return GN_ERR_UNSUPPORTED;
+  if (!Gbar || !YtA || !core || !dA || !ws || !core->k || !core->Q1 || !core->R || !core->Q2 ||
+      !core->R2)
+    return GN_ERR_ARG;
+  if (!AX && !A) return GN_ERR_ARG;
+  if (ldg < P.n || ldya < P.n || ldda < P.n) return GN_ERR_SHAPE;
+  if (AX && ldax < P.r) return GN_ERR_SHAPE;
+  if (!AX && lda < P.n) return GN_ERR_SHAPE;
+  if (!aligned16(ws)) return GN_ERR_ALIGN;
+  const BackWs W = back_ws(P);
+  if (ws_bytes < W.total) return GN_ERR_WORKSPACE;
+
+  const bool f32 = (P.mode == GN_MODE_F32);
+  const int32_t sdt = P.sdt, adt = P.adt;  // both the mode's dtype here
+  const size_t sd = f32 ? 4 : 8;
+  const int64_t m = P.m, n = P.n, r = P.r, rl = P.rl, K2 = P.r + P.rl;
+  char* base = (char*)ws;
+  char* lcat = base + W.lcat;  // [U | Y], m x (r + rl)
+  char* rcat = base + W.rcat;  // [X^T ; V], (r + rl) x n
+  void* St = base + W.st;
+  void* G1 = base + W.g1;
+  void* G2 = base + W.g2;
+  double* H = (double*)(base + W.h);
+  double* M0 = (double*)(base + W.m0);
+  double* M = (double*)(base + W.m1);
+  double* Cm = (double*)(base + W.c);
+  double* Bb = (double*)(base + W.bbar);
+  double* X2 = (double*)(base + W.x2);
+  double* Z = (double*)(base + W.z);
+  double* Y5 = (double*)(base + W.y5);
+  double* T1 = (double*)(base + W.t1);
+  double* T2 = (double*)(base + W.t2);
+  double* T3 = (double*)(base + W.t3);
+  double* T4 = (double*)(base + W.t4);
+  const int32_t* kd = core->k;
+  constexpr int32_t F64 = GN_DT_F64;
+
+  // sketches, as the forward pass drew them: X^T in rows [0, r) of rcat, Y in
+  // columns [r, r + rl) of lcat
+  GN_TRY(launch_gaussian(p->seed, 1, 0, 0, n, r, sdt, 1, rcat, n, s));
+  GN_TRY(launch_gaussian(p->seed, 2, 0, 0, m, rl, sdt, 0, lcat + r * sd, K2, s));
+  // AX with row stride r: the caller's, re-strided, or recomputed from A
+  const void* Pm = AX;
+  if (AX && ldax != r) {
+    if (hipMemcpy2DAsync(base + W.p, r * sd, AX, ldax * sd, r * sd, m, hipMemcpyDeviceToDevice,
+                         s) != hipSuccess)
+      return GN_ERR_HIP;
+    Pm = base + W.p;
+  } else if (!AX) {
+    if (f32)
+      GN_TRY(launch_gemm_f32(m, r, n, (const float*)A, lda, true, (const float*)rcat, n, true,
+                             (float*)(base + W.p), r, s));
+    else
+      GN_TRY(launch_dgemm(m, r, n, 1.0, MatRef{A, F64, lda, 1}, MatRef{rcat, F64, 1, n}, 0.0,
+                          (double*)(base + W.p), r, 1, nullptr, false, s));
+    Pm = base + W.p;
+  }
+  // G1 = Gbar (Y^T A)^T and G2 = (AX)^T Gbar: the sketch pass over Gbar with
+  // sketches (Y^T A)^T (n x rl) and AX (m x r)
+  GN_TRY(launch_transpose(YtA, rl, n, ldya, adt, St, rl, s));
+  GN_TRY(launch_pass(P.mode, GN_SKETCH_GAUSSIAN, m, n, rl, r, Gbar, ldg, nullptr, St, nullptr,
+                     nullptr, Pm, G1, rl, G2, n, s));
+  // H = (AX)^T G1 = dL/dM
+  if (f32)
+    GN_TRY(launch_core_product_f32(m, r, rl, (const float*)Pm, r, (const float*)G1, rl,
+                                   (float*)(base + W.split), H, s));
+  else
+    GN_TRY(launch_dgemm(r, rl, m, 1.0, MatRef{Pm, F64, 1, r}, MatRef{G1, F64, rl, 1}, 0.0, H, rl, 1,
+                        nullptr, false, s, nullptr, 0, true, (double*)(base + W.split),
+                        W.total - W.split));
+
+  // ---- the core adjoint in FP64 (k from the forward pass, on the device)
+  const MatRef Mr{M, F64, rl, 1}, Mt{M, F64, 1, rl};
+  const MatRef Hr{H, F64, rl, 1}, Ht{H, F64, 1, rl};
+  const MatRef Q1r{core->Q1, F64, r, 1}, Q1t{core->Q1, F64, 1, r};
+  const MatRef Q2r{core->Q2, F64, r, 1}, Q2t{core->Q2, F64, 1, r};
+  auto sq = [&](double* T) { return MatRef{T, F64, r, 1}; };  // ld r (r x r and rl x r)
+  // M = R^{-1} Q1^T (k == r) or Q2 R2^{-T} Q1[:, :k]^T (k < r)
+  GN_TRY(launch_transpose_rows_masked(rl, r, core->Q1, r, kd, M0, rl, s));
+  GN_TRY(launch_trsm_core(rl, r, core->R, core->R2, r, kd, M0, 1, rl, true, true, s));
+  GN_TRY(widen(r, rl, M0, F64, rl, M, rl, kd, r, s));
+  GN_TRY(launch_dgemm(r, rl, r, 1.0, Q2r, MatRef{M0, F64, rl, 1}, 0.0, M, rl, 1, nullptr, false, s,
+                      kd, r, true));
+  // C = Q1 R
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, Q1r, MatRef{core->R, F64, r, 1}, 0.0, Cm, r, 1, nullptr,
+                      false, s));
+  // Bbar = -M^T H M^T
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, Hr, Mt, 0.0, T1, r, 1, nullptr, false, s));
+  GN_TRY(launch_dgemm(rl, r, r, -1.0, Mt, sq(T1), 0.0, Bb, r, 1, nullptr, false, s));
+  // Bbar += (I - Q1k Q1k^T) H^T M M^T
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, Mr, Mt, 0.0, T2, r, 1, nullptr, false, s));
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, Ht, sq(T2), 0.0, X2, r, 1, nullptr, false, s));
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, Q1t, sq(X2), 0.0, T3, r, 1, kd, true, s));
+  GN_TRY(launch_dgemm(rl, r, r, -1.0, Q1r, sq(T3), 1.0, X2, r, 1, nullptr, false, s));
+  GN_TRY(launch_axpy(rl, r, 1.0, X2, r, Bb, r, s));
+  // k < r: Bbar += M^T (M H^T)(I - Q2k Q2k^T)
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, Mr, Ht, 0.0, T1, r, 1, nullptr, false, s, kd, r, true));
+  GN_TRY(launch_dgemm(r, r, r, 1.0, sq(T1), Q2r, 0.0, T4, r, 1, kd, false, s, kd, r, true));
+  GN_TRY(launch_dgemm(r, r, r, -1.0, sq(T4), Q2t, 1.0, T1, r, 1, nullptr, false, s, kd, r, true));
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, Mt, sq(T1), 1.0, Bb, r, 1, nullptr, false, s, kd, r, true));
+  // Z = Q1k R11^{-T} (columns >= k zero)
+  if (hipMemcpyAsync(Z, core->Q1, (size_t)rl * r * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return GN_ERR_HIP;
+  GN_TRY(launch_trsm_core(rl, r, core->R, core->R2, r, kd, Z, r, 1, true, true, s, true));
+  // Y5 = Bbar (C^T Z) + C (Bbar^T Z)
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, MatRef{Cm, F64, 1, r}, sq(Z), 0.0, T2, r, 1, nullptr, false,
+                      s));
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, MatRef{Bb, F64, 1, r}, sq(Z), 0.0, T3, r, 1, nullptr, false,
+                      s));
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, sq(Bb), sq(T2), 0.0, Y5, r, 1, nullptr, false, s));
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, sq(Cm), sq(T3), 1.0, Y5, r, 1, nullptr, false, s));
+  // Cbar = Y5 + Q1k Q1k^T (Bbar - Y5)   (kept in Y5)
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, Q1t, sq(Bb), 0.0, T4, r, 1, kd, true, s));
+  GN_TRY(launch_dgemm(r, r, rl, -1.0, Q1t, sq(Y5), 1.0, T4, r, 1, kd, true, s));
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, Q1r, sq(T4), 1.0, Y5, r, 1, nullptr, false, s));
+
+  // U = G1 M^T + Y Cbar into columns [0, r) of lcat; V = M^T G2 into rows
+  // [r, r + rl) of rcat
+  GN_TRY(launch_dgemm_to(m, r, rl, 1.0, MatRef{G1, adt, rl, 1}, Mt, 0.0, lcat, sdt, K2, 1, nullptr,
+                         false, s));
+  GN_TRY(launch_dgemm_to(m, r, rl, 1.0, MatRef{lcat + r * sd, sdt, K2, 1}, sq(Y5), 1.0, lcat,
+                         sdt, K2, 1, nullptr, false, s));
+  GN_TRY(launch_dgemm_to(rl, n, r, 1.0, Mt, MatRef{G2, adt, n, 1}, 0.0, rcat + (size_t)r * n * sd,
+                         sdt, n, 1, nullptr, false, s));
+  // dA = [U | Y] [X^T ; V]
+  if (f32)
+    return launch_gemm_f32(m, n, K2, (const float*)lcat, K2, true, (const float*)rcat, n, false,
+                           (float*)dA, ldda, s);
+  return launch_dgemm(m, n, K2, 1.0, MatRef{lcat, F64, K2, 1}, MatRef{rcat, F64, n, 1}, 0.0,
+                      (double*)dA, ldda, 1, nullptr, false, s);
 }
 
 gn_status gn_residual(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, int32_t a_dtype,

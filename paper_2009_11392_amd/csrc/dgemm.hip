@@ -29,7 +29,7 @@ struct DArgs {
   int64_t M, N, K;
   MatRef A, B;
   double alpha, beta;
-  double* D;
+  void* D;              // double, or float when d_dtype == GN_DT_F32 (rounded to nearest)
   int64_t rsd, csd;
   const int32_t* kmask;
   int32_t mask_rows;
@@ -39,7 +39,26 @@ struct DArgs {
   int32_t ksplit;       // > 1: slice s of K written to partial + s*M*N
   int64_t kslice;
   double* partial;
+  int32_t d_dtype;
 };
+
+// D(i, j) = alpha * sum + beta * D(i, j), zeroed beyond the mask.
+__device__ __forceinline__ void store_d(const DArgs& g, int64_t i, int64_t j, double sum,
+                                        int32_t kk) {
+  const int64_t off = i * g.rsd + j * g.csd;
+  double val = g.alpha * sum;
+  if (g.d_dtype == GN_DT_F32) {
+    float* d = reinterpret_cast<float*>(g.D) + off;
+    if (g.beta != 0.0) val += g.beta * (double)(*d);
+    if (g.kmask && (g.mask_rows ? (i >= kk) : (j >= kk))) val = 0.0;
+    *d = __double2float_rn(val);
+  } else {
+    double* d = reinterpret_cast<double*>(g.D) + off;
+    if (g.beta != 0.0) val += g.beta * (*d);
+    if (g.kmask && (g.mask_rows ? (i >= kk) : (j >= kk))) val = 0.0;
+    *d = val;
+  }
+}
 
 __device__ __forceinline__ bool gated_off(const DArgs& g) {
   if (!g.gate) return false;
@@ -174,11 +193,7 @@ __global__ void __launch_bounds__(256) dgemm_kernel(DArgs g) {
         int64_t i, j;
         d_coord(x, y, v, i0, j0, i, j);
         if (i >= g.M || j >= g.N) continue;
-        double* d = g.D + i * g.rsd + j * g.csd;
-        double val = g.alpha * acc[x][y][v];
-        if (g.beta != 0.0) val += g.beta * (*d);
-        if (g.kmask && (g.mask_rows ? (i >= kk) : (j >= kk))) val = 0.0;
-        *d = val;
+        store_d(g, i, j, acc[x][y][v], kk);
       }
 }
 
@@ -190,11 +205,7 @@ __global__ void __launch_bounds__(256) dgemm_reduce(DArgs g) {
   const int64_t i = e / g.N, j = e - i * g.N;
   double s = 0.0;
   for (int q = 0; q < g.ksplit; ++q) s += g.partial[q * g.M * g.N + e];
-  double* d = g.D + i * g.rsd + j * g.csd;
-  double val = g.alpha * s;
-  if (g.beta != 0.0) val += g.beta * (*d);
-  if (g.kmask && (g.mask_rows ? (i >= *g.kmask) : (j >= *g.kmask))) val = 0.0;
-  *d = val;
+  store_d(g, i, j, s, g.kmask ? *g.kmask : 0);
 }
 
 struct RArgs {
@@ -269,13 +280,14 @@ size_t dgemm_split_ws_bytes(int64_t M, int64_t N, int64_t K) {
   return s > 1 ? align_up((size_t)s * M * N * sizeof(double)) : 0;
 }
 
-gn_status launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, MatRef A, MatRef B,
-                       double beta, double* D, int64_t rsd, int64_t csd, const int32_t* kmask,
-                       bool mask_rows, hipStream_t s, const int32_t* gate, int64_t gate_n,
-                       bool gate_trunc, double* split_ws, size_t split_ws_bytes) {
+gn_status launch_dgemm_to(int64_t M, int64_t N, int64_t K, double alpha, MatRef A, MatRef B,
+                          double beta, void* D, int32_t d_dtype, int64_t rsd, int64_t csd,
+                          const int32_t* kmask, bool mask_rows, hipStream_t s, const int32_t* gate,
+                          int64_t gate_n, bool gate_trunc, double* split_ws,
+                          size_t split_ws_bytes) {
   if (M <= 0 || N <= 0) return GN_OK;
   DArgs g{M,    N,          K,          A,   B,   alpha, beta, D, rsd, csd, kmask, mask_rows ? 1 : 0,
-          gate, gate_n, gate_trunc ? 1 : 0, 1, K > 0 ? K : 1, nullptr};
+          gate, gate_n, gate_trunc ? 1 : 0, 1, K > 0 ? K : 1, nullptr, d_dtype};
   const int64_t tiles = cdiv(M, D_BM) * cdiv(N, D_BN);
   int32_t ks = split_ws ? dgemm_split(M, N, K) : 1;
   if (ks > 1 && split_ws_bytes < (size_t)ks * M * N * sizeof(double)) ks = 1;
@@ -292,6 +304,14 @@ gn_status launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, MatRef A, 
   dgemm_kernel<<<dim3((unsigned)tiles), dim3(256), 0, s>>>(g);
   GN_LAUNCH_CHECK();
   return GN_OK;
+}
+
+gn_status launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, MatRef A, MatRef B,
+                       double beta, double* D, int64_t rsd, int64_t csd, const int32_t* kmask,
+                       bool mask_rows, hipStream_t s, const int32_t* gate, int64_t gate_n,
+                       bool gate_trunc, double* split_ws, size_t split_ws_bytes) {
+  return launch_dgemm_to(M, N, K, alpha, A, B, beta, D, GN_DT_F64, rsd, csd, kmask, mask_rows, s,
+                         gate, gate_n, gate_trunc, split_ws, split_ws_bytes);
 }
 
 size_t residual_ws_bytes(int64_t M, int64_t N) {

@@ -132,6 +132,12 @@ gn_status launch_core_product_f32(int64_t m, int64_t rl, int64_t r, const float*
                                   hipStream_t s);
 size_t core_product_ws_bytes(int64_t m, int64_t rl, int64_t r);
 // widen a bfloat16 matrix (rows x cols, ld lds) to float (ld ldd)
+// D (M x N, FP32) = A (M x K) B (K x N), FP32 MFMA with FP32 accumulation.
+// a_kc: A(i,k) = A[i*lda + k], else A[k*lda + i]; b_kc: B(k,j) = B[j*ldb + k],
+// else B[k*ldb + j].
+gn_status launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, bool a_kc,
+                          const float* B, int64_t ldb, bool b_kc, float* D, int64_t ldd,
+                          hipStream_t s);
 gn_status launch_widen_bf16(int64_t rows, int64_t cols, const uint16_t* src, int64_t lds, float* dst,
                             int64_t ldd, hipStream_t s);
 
@@ -153,6 +159,14 @@ gn_status launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, MatRef A, 
                        int64_t gate_n = 0, bool gate_trunc = true, double* split_ws = nullptr,
                        size_t split_ws_bytes = 0);
 size_t dgemm_split_ws_bytes(int64_t M, int64_t N, int64_t K);
+// The same product with D stored as d_dtype (GN_DT_F64 or GN_DT_F32, rounded to
+// nearest; beta * D is read in that dtype).
+gn_status launch_dgemm_to(int64_t M, int64_t N, int64_t K, double alpha, MatRef A, MatRef B,
+                          double beta, void* D, int32_t d_dtype, int64_t rsd, int64_t csd,
+                          const int32_t* kmask, bool mask_rows, hipStream_t s,
+                          const int32_t* gate = nullptr, int64_t gate_n = 0,
+                          bool gate_trunc = true, double* split_ws = nullptr,
+                          size_t split_ws_bytes = 0);
 // Per-tile sums of (Ref - A*B)^2 written to partial[], then reduced in fixed order.
 gn_status launch_residual(int64_t M, int64_t N, int64_t K, MatRef Ref, const float* ref_scales,
                           MatRef A, MatRef B, double* partial, double* out, hipStream_t s);
@@ -181,9 +195,19 @@ gn_status launch_truncate(int64_t r, const double* R, int64_t ldr, double tau, i
 //               of R^{-1} B^T or R2^{-T} B^T (left-side products), on a
 //               transposed view of the data.
 // Columns >= k of X are zeroed when k < r.  Solved in place on X (rows x r).
+// r_only = true: both cases use the leading kk x kk block of R (kk = r, or k
+// when k < r), transposed when left: X R^{-1} or X R_11^{-T} on the kept columns.
 gn_status launch_trsm_core(int64_t rows, int64_t r, const double* R, const double* R2, int64_t ldt,
                            const int32_t* k, double* X, int64_t rsx, int64_t csx, bool left,
-                           bool maybe_trunc, hipStream_t s);
+                           bool maybe_trunc, hipStream_t s, bool r_only = false);
+
+// grad.hip : helpers of the reverse mode.
+// out (cols x rows) = src^T with rows >= *k of out zeroed (src rows x cols).
+gn_status launch_transpose_rows_masked(int64_t rows, int64_t cols, const double* src, int64_t lds,
+                                       const int32_t* k, double* out, int64_t ldo, hipStream_t s);
+// Y += alpha X (rows x cols, FP64).
+gn_status launch_axpy(int64_t rows, int64_t cols, double alpha, const double* X, int64_t ldx,
+                      double* Y, int64_t ldy, hipStream_t s);
 
 // quant.hip
 gn_status launch_quantize(int64_t m, int64_t n, const void* A, int64_t lda, int32_t dtype,

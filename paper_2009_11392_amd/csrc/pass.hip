@@ -372,6 +372,14 @@ int64_t core_slices(int64_t m, int64_t rl, int64_t r) {
   return sl < 1 ? 1 : sl;
 }
 
+// Plain FP32 GEMM D = A B with the sketch pass's tile configuration (used by the
+// reverse mode for AX recomputation and the final rank-(r + l) product).
+template <bool A_KC, bool B_KC, bool VEC>
+__global__ void __launch_bounds__(F32Pass::T) gemm_f32_kernel(GemmF32 g) {
+  __shared__ __attribute__((aligned(16))) char smem[F32Pass::smem<A_KC, B_KC>()];
+  f32_tile_cfg<F32Pass, A_KC, B_KC, VEC>(g, blockIdx.x, smem);
+}
+
 __global__ void __launch_bounds__(256) widen_bf16_kernel(int64_t rows, int64_t cols,
                                                          const uint16_t* src, int64_t lds,
                                                          float* dst, int64_t ldd) {
@@ -441,6 +449,34 @@ gn_status launch_core_product_f32(int64_t m, int64_t rl, int64_t r, const float*
     core_product_f32<false><<<grid, dim3(CoreCfg::T), 0, s>>>(g, kslice);
   GN_LAUNCH_CHECK();
   core_product_sum<<<dim3((unsigned)cdiv(rl * r, 256)), dim3(256), 0, s>>>(partial, sl, rl * r, C);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+gn_status launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, bool a_kc,
+                          const float* B, int64_t ldb, bool b_kc, float* D, int64_t ldd,
+                          hipStream_t s) {
+  if (M <= 0 || N <= 0) return GN_OK;
+  GemmF32 g{M, N, K, A, lda, B, ldb, D, ldd, 1};
+  const int64_t tiles = cdiv(M, F32Pass::BM) * cdiv(N, F32Pass::BN);
+  const dim3 grid((unsigned)(8 * cdiv(tiles, 8)));
+  const bool vec = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) &&
+                   ((uintptr_t)B % 16 == 0);
+#define GN_GEMM(AK, BK)                                                         \
+  if (vec)                                                                      \
+    gemm_f32_kernel<AK, BK, true><<<grid, dim3(F32Pass::T), 0, s>>>(g);         \
+  else                                                                          \
+    gemm_f32_kernel<AK, BK, false><<<grid, dim3(F32Pass::T), 0, s>>>(g)
+  if (a_kc && b_kc) {
+    GN_GEMM(true, true);
+  } else if (a_kc) {
+    GN_GEMM(true, false);
+  } else if (b_kc) {
+    GN_GEMM(false, true);
+  } else {
+    GN_GEMM(false, false);
+  }
+#undef GN_GEMM
   GN_LAUNCH_CHECK();
   return GN_OK;
 }

@@ -17,13 +17,14 @@ constexpr int TB = 64;
 __global__ void __launch_bounds__(TB) trsm_diag(int64_t rows, int64_t r, const double* __restrict__ R,
                                                 const double* __restrict__ R2, int64_t ldt,
                                                 const int32_t* __restrict__ kdev, int want_trunc,
-                                                int left, double* __restrict__ X, int64_t rsx,
-                                                int64_t csx, int64_t jb, int w) {
+                                                int left, int r_only, double* __restrict__ X,
+                                                int64_t rsx, int64_t csx, int64_t jb, int w) {
   const int32_t k = *kdev;
   const bool trunc = k < r;
   if (trunc != (want_trunc != 0)) return;
-  const double* S = trunc ? R2 : R;
-  const bool trans = left ? !trunc : trunc;  // R, R2 are upper; their transposes lower
+  const double* S = (trunc && !r_only) ? R2 : R;
+  // R, R2 are upper; their transposes lower
+  const bool trans = r_only ? (left != 0) : (left ? !trunc : trunc);
   const bool upper = !trans;
   const int64_t kk = trunc ? k : r;
   __shared__ double Ts[TB][TB + 1];
@@ -68,13 +69,13 @@ __global__ void __launch_bounds__(TB) trsm_diag(int64_t rows, int64_t r, const d
 
 gn_status launch_trsm_core(int64_t rows, int64_t r, const double* R, const double* R2, int64_t ldt,
                            const int32_t* k, double* X, int64_t rsx, int64_t csx, bool left,
-                           bool maybe_trunc, hipStream_t s) {
+                           bool maybe_trunc, hipStream_t s, bool r_only) {
   if (rows <= 0) return GN_OK;
   const dim3 grid((unsigned)cdiv(rows, TB)), block(TB);
   const int64_t nblk = cdiv(r, TB);
   for (int want_trunc = 0; want_trunc <= (maybe_trunc ? 1 : 0); ++want_trunc) {
-    const double* S = want_trunc ? R2 : R;
-    const bool trans = left ? !want_trunc : (bool)want_trunc;
+    const double* S = (want_trunc && !r_only) ? R2 : R;
+    const bool trans = r_only ? left : (left ? !want_trunc : (bool)want_trunc);
     const bool upper = !trans;
     for (int64_t bi = 0; bi < nblk; ++bi) {
       const int64_t b = upper ? bi : (nblk - 1 - bi);
@@ -90,8 +91,8 @@ gn_status launch_trsm_core(int64_t rows, int64_t r, const double* R, const doubl
         GN_TRY(launch_dgemm(rows, w, t1 - t0, -1.0, xa, tm, 1.0, X + jb * csx, rsx, csx, nullptr,
                             false, s, k, r, want_trunc != 0));
       }
-      trsm_diag<<<grid, block, 0, s>>>(rows, r, R, R2, ldt, k, want_trunc, left ? 1 : 0, X, rsx,
-                                       csx, jb, w);
+      trsm_diag<<<grid, block, 0, s>>>(rows, r, R, R2, ldt, k, want_trunc, left ? 1 : 0,
+                                       r_only ? 1 : 0, X, rsx, csx, jb, w);
       GN_LAUNCH_CHECK();
     }
   }

@@ -244,3 +244,66 @@ def solve(p: Problem, A: torch.Tensor, scales=None, X_user=None, Y_user=None):
     AX, YtA, _, _ = gn_sketch(p, A, scales=scales, X_user=X_user, Y_user=Y_user)
     core = gn_core(p, AX, Y_user=Y_user)
     return AX, YtA, core
+
+
+def gn_materialize(p: Problem, AX, YtA, core: CoreResult, out=None):
+    """A_hat (m x n) in the mode's accumulation dtype (gn_apply side 2)."""
+    out = torch.empty(p.m, p.n, dtype=ACCUM_TORCH[p.mode], device=AX.device) if out is None else out
+    ws = workspace(p, C.GN_OP_MATERIALIZE)
+    pc, oc = p.c(), core.c()
+    C.check(C.lib().gn_apply(ctypes.byref(pc), 2, _ptr(AX), AX.stride(0), _ptr(YtA), YtA.stride(0),
+                             ctypes.byref(oc), None, 0, 0, _ptr(out), out.stride(0), _ptr(ws),
+                             ws.numel(), _stream()), "gn_apply(side 2)")
+    return out
+
+
+def gn_backward(p: Problem, Gbar: torch.Tensor, YtA: torch.Tensor, core: CoreResult,
+                AX: torch.Tensor | None = None, A: torch.Tensor | None = None, dA=None, ws=None):
+    """dL/dA from dL/dA_hat = Gbar, with the forward's kept rank held fixed.
+    AX None: recomputed from A."""
+    _need_cuda(Gbar, YtA, AX, A)
+    dA = torch.empty(p.m, p.n, dtype=ACCUM_TORCH[p.mode], device=Gbar.device) if dA is None else dA
+    ws = workspace(p, C.GN_OP_BACKWARD) if ws is None else ws
+    pc, oc = p.c(), core.c()
+    C.check(C.lib().gn_backward(ctypes.byref(pc), _ptr(A), A.stride(0) if A is not None else 0,
+                                _ptr(Gbar), Gbar.stride(0), _ptr(AX),
+                                AX.stride(0) if AX is not None else 0, _ptr(YtA), YtA.stride(0),
+                                ctypes.byref(oc), _ptr(dA), dA.stride(0), _ptr(ws), ws.numel(),
+                                _stream()), "gn_backward")
+    return dA
+
+
+class GNApprox(torch.autograd.Function):
+    """A -> A_hat = AX (Y^T A X)_eps^+ Y^T A as a differentiable torch op.
+
+    forward runs the sketch pass, the core and materializes A_hat; backward calls
+    gn_backward with the kept rank of this forward held fixed.  With
+    store_ax=False the forward keeps A instead of AX and the backward recomputes
+    AX = A X (less memory when r is large relative to the batch of saved tensors).
+    """
+
+    @staticmethod
+    def forward(ctx, A, p: Problem, store_ax: bool = True):
+        AX, YtA, core = solve(p, A)
+        Ahat = gn_materialize(p, AX, YtA, core)
+        ctx.p, ctx.core, ctx.store_ax = p, core, store_ax
+        if store_ax:
+            ctx.save_for_backward(AX, YtA)
+        else:
+            ctx.save_for_backward(A, YtA)
+        return Ahat
+
+    @staticmethod
+    def backward(ctx, gout):
+        first, YtA = ctx.saved_tensors
+        gout = gout.contiguous()
+        if ctx.store_ax:
+            dA = gn_backward(ctx.p, gout, YtA, ctx.core, AX=first)
+        else:
+            dA = gn_backward(ctx.p, gout, YtA, ctx.core, A=first)
+        return dA, None, None
+
+
+def gn_approx(A: torch.Tensor, p: Problem, store_ax: bool = True) -> torch.Tensor:
+    """Differentiable A_hat (see GNApprox)."""
+    return GNApprox.apply(A, p, store_ax)

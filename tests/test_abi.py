@@ -63,6 +63,10 @@ def test_workspace_sizes(lib):
     code, b = _ws(lib, p, C.GN_OP_CORE)
     assert code == 0 and b >= 8 * 75 * 50
     assert _ws(lib, p, C.GN_OP_APPLY, 0)[0] == C.GN_ERR_SHAPE
+    code, b = _ws(lib, p, C.GN_OP_BACKWARD)
+    assert code == 0 and b >= 4 * 2000 * (50 + 75)
+    code, b = _ws(lib, p, C.GN_OP_MATERIALIZE)
+    assert code == 0 and b >= 8 * (2000 * 50 + 50 * 1000)
     assert _ws(lib, p, 99)[0] == C.GN_ERR_ARG
 
 
@@ -103,8 +107,29 @@ def test_entry_points_reject_before_enqueue(lib):
     out = C.GnCoreOut(1 << 20, 0, 1 << 20, 1 << 20, 1 << 20, 1 << 20)
     assert lib.gn_core(ctypes.byref(p), fake, 50, null, 0, ctypes.byref(out), fake, 1 << 30,
                        null) == C.GN_ERR_ARG
-    assert lib.gn_apply(ctypes.byref(p), 2, fake, 50, fake, 1000, ctypes.byref(out), fake, 1, 1,
+    assert lib.gn_apply(ctypes.byref(p), 3, fake, 50, fake, 1000, ctypes.byref(out), fake, 1, 1,
                         fake, 1, fake, 1 << 30, null) == C.GN_ERR_ARG
+    good = C.GnCoreOut(1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20)
+    # side 2 (materialize): ldo < n, then a workspace too small
+    assert lib.gn_apply(ctypes.byref(p), 2, fake, 50, fake, 1000, ctypes.byref(good), null, 0, 0,
+                        fake, 999, fake, 1 << 30, null) == C.GN_ERR_SHAPE
+    assert lib.gn_apply(ctypes.byref(p), 2, fake, 50, fake, 1000, ctypes.byref(good), null, 0, 0,
+                        fake, 1000, fake, 64, null) == C.GN_ERR_WORKSPACE
+    # gn_backward: unsupported kinds / modes, missing operands, strides, workspace
+    big = 1 << 34
+    def back(prob, A=fake, lda=1000, G=fake, ldg=1000, AX=fake, ldax=50, ws_bytes=big, core=good):
+        return lib.gn_backward(ctypes.byref(prob), A, lda, G, ldg, AX, ldax, fake, 1000,
+                               ctypes.byref(core), fake, 1000, fake, ws_bytes, null)
+    assert back(_prob(kind_x=1)) == C.GN_ERR_UNSUPPORTED
+    assert back(_prob(mode=2)) == C.GN_ERR_UNSUPPORTED
+    assert back(p, G=null) == C.GN_ERR_ARG
+    assert back(p, A=null, AX=null) == C.GN_ERR_ARG
+    nok = C.GnCoreOut(0, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20)   # k pointer null
+    assert back(p, core=nok) == C.GN_ERR_ARG
+    assert back(p, ldg=999) == C.GN_ERR_SHAPE
+    assert back(p, ldax=49) == C.GN_ERR_SHAPE
+    assert back(p, AX=null, lda=999) == C.GN_ERR_SHAPE
+    assert back(p, ws_bytes=1 << 10) == C.GN_ERR_WORKSPACE
     assert lib.gn_residual(10, 10, 2, fake, 5, 0, null, fake, 2, fake, 10, fake, fake, 1 << 20,
                            null) == C.GN_ERR_SHAPE
     assert lib.gn_quantize_bf16_bs(10, 10, fake, 10, 2, fake, 10, fake, null) == C.GN_ERR_DTYPE
