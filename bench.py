@@ -11,8 +11,9 @@ columns).  The inputs are resident in HBM before timing starts.  HIP events on
 the library's stream (torch's current stream) time each stage; `value` is the
 pass's algorithmic TFLOP/s.  After timing: the error ||A - A_hat||_F (tile-wise
 on the device), a bounded CPU-oracle baseline, and the BF16-vs-FP32 comparison
-on the 32768^2, r = 2000, l = 1000 shape (same matrix).  Prints ONE JSON line on
-stdout; progress goes to stderr.
+on the 32768^2, r = 2000, l = 1000 shape (same matrix), the reverse mode on the
+8192 x 4096 gradient workload (forward, backward, backward with AX recomputed).
+Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -152,6 +153,65 @@ class Runner:
         return math.sqrt(ss), math.sqrt(na), self.core.rank(), self.core.flags()
 
 
+def grad_bench(gn, W, steps=5, warmup=2):
+    """Forward and reverse mode on the gradient workload (8192 x 4096 FP32, sigma_i =
+    i^-1.5, Gaussian X and Y, r = 256, l = 128; loss weights Gbar on Philox stream 5).
+    The forward is the sketch pass, the core and the materialized A_hat; the
+    backward is gn_backward with AX kept from the forward, and with AX recomputed."""
+    import torch
+    wl = W.GRAD8K
+    A = W.device_matrix(wl)
+    p = gn.Problem(wl.m, wl.n, wl.r, wl.l, seed=wl.seed, mode="f32", eps=wl.eps)
+    Gbar = gn.gn_generate_gaussian(wl.seed, 5, wl.m, wl.n, dtype=torch.float32)
+    ws_s, ws_c = gn.workspace(p, gn.C.GN_OP_SKETCH), gn.workspace(p, gn.C.GN_OP_CORE)
+    ws_b = gn.workspace(p, gn.C.GN_OP_BACKWARD)
+    AX = torch.empty(wl.m, wl.r, dtype=torch.float32, device="cuda")
+    YtA = torch.empty(p.rl, wl.n, dtype=torch.float32, device="cuda")
+    Ahat = torch.empty(wl.m, wl.n, dtype=torch.float32, device="cuda")
+    dA = torch.empty_like(Ahat)
+    core = gn.new_core(p)
+
+    def fwd():
+        gn.gn_sketch(p, A, AX=AX, YtA=YtA, ws=ws_s)
+        gn.gn_core(p, AX, out=core, ws=ws_c)
+        gn.gn_materialize(p, AX, YtA, core, out=Ahat)
+
+    def bwd(recompute):
+        gn.gn_backward(p, Gbar, YtA, core, AX=None if recompute else AX, A=A, dA=dA, ws=ws_b)
+
+    def timeit(f):
+        for _ in range(warmup):
+            f()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(steps):
+            f()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / steps
+
+    t_f = timeit(fwd)
+    t_b = timeit(lambda: bwd(False))
+    t_br = timeit(lambda: bwd(True))
+    m, n, r, rl = wl.m, wl.n, wl.r, p.rl
+    fl_b = 4.0 * m * n * (r + rl) + 2.0 * m * r * rl + 4.0 * m * r * rl + 2.0 * rl * n * r
+    fl_f = 2.0 * m * n * (r + rl) + 2.0 * m * r * n
+    out = {"workload": wl.name, "m": m, "n": n, "r": r, "l": wl.l, "mode": "f32",
+           "kept_rank": core.rank(), "forward_ms": t_f, "backward_ms": t_b,
+           "backward_recompute_ax_ms": t_br,
+           "backward_algorithmic_flops": fl_b,
+           "backward_tflops": fl_b / (t_b / 1e3) / 1e12,
+           "backward_frac_of_fp32_peak": fl_b / (t_b / 1e3) / 1e12 / PEAK["f32"],
+           "forward_algorithmic_flops": fl_f,
+           "note": "forward = sketch pass + core + materialized A_hat (F G, 2mnr); "
+                   "backward flops = pass over Gbar 2mn(r+rl) + final product 2mn(r+rl) + "
+                   "core-size terms"}
+    del A, Gbar, AX, YtA, Ahat, dA, ws_s, ws_c, ws_b
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(A_dev, w, target_s=12.0):
     """The FP64 oracle's sketch pass on a bounded block of rows of the same A."""
     import numpy as np
@@ -198,6 +258,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--no-grad", action="store_true", help="skip the reverse-mode measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--host-factors", action="store_true",
@@ -298,6 +359,13 @@ def main():
         cmp["err_ratio_bf16_over_f32"] = cmp["bf16"]["rel_err"] / cmp["f32"]["rel_err"]
         cmp["shape"] = "32768x32768, Gaussian X and Y, r=2000, l=1000, same matrix"
         res["bf16_vs_fp32"] = cmp
+
+    if not args.no_grad:
+        log("reverse mode: grad_8192x4096_f32")
+        res["gradient"] = grad_bench(gn, W)
+        log(f"forward {res['gradient']['forward_ms']:.3f} ms, backward "
+            f"{res['gradient']['backward_ms']:.3f} ms "
+            f"({res['gradient']['backward_tflops']:.1f} TFLOP/s)")
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -169,9 +169,13 @@ gn_status gn_sketch_prepare(const gn_problem* p, const void* X_user, int64_t ldx
  *              scale of each 128 x 128 block (A = scale * stored value).
  *   AX, YtA  : outputs in the accumulation dtype (double for F64, float else),
  *              row strides ldax >= r and ldya >= n.
- * All pointers 16-byte aligned. */
+ * All pointers 16-byte aligned.  When the problem has too few 256 x 256 output
+ * tiles to fill the GPU (FP32 mode, Gaussian or user X), the pass splits the
+ * contraction length into slices whose partial products go to a scratch region
+ * at the end of ws and are summed in slice order (deterministic): passes that
+ * run concurrently need separate workspaces. */
 gn_status gn_sketch_pass(const gn_problem* p, const void* A, int64_t lda, const float* A_scales,
-                         void* AX, int64_t ldax, void* YtA, int64_t ldya, const void* ws,
+                         void* AX, int64_t ldax, void* YtA, int64_t ldya, void* ws,
                          size_t ws_bytes, gn_stream_t stream);
 
 /* gn_sketch_prepare followed by gn_sketch_pass, with the arguments of both. */

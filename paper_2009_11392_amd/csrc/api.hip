@@ -56,7 +56,7 @@ gn_status make_plan(const gn_problem* p, Plan& P) {
 
 // ---- workspace layouts (offsets in bytes, each region 256-byte aligned)
 struct SketchWs {
-  size_t xt, yt, signs, idx, keys, total;
+  size_t xt, yt, signs, idx, keys, split, split_bytes, total;
 };
 SketchWs sketch_ws(const Plan& P) {
   SketchWs w{};
@@ -77,6 +77,9 @@ SketchWs sketch_ws(const Plan& P) {
     w.keys = off;
     off += srht_ws_bytes(P.npad);
   }
+  w.split = off;  // K-split partials of a pass with few output tiles
+  w.split_bytes = pass_split_ws_bytes(P.mode, P.kx, P.m, P.n, P.r, P.rl);
+  off += w.split_bytes;
   w.total = off;
   return w;
 }
@@ -132,7 +135,8 @@ ApplyWs apply_ws(const Plan& P, int64_t kc) {
 // ((r+l) x n), S^T (n x (r+l)), AX (m x r, when recomputed or re-strided),
 // G1 (m x (r+l)) and G2 (r x n); FP64 buffers for H and the core adjoint.
 struct BackWs {
-  size_t lcat, rcat, st, p, g1, g2, h, m0, m1, c, bbar, x2, z, y5, t1, t2, t3, t4, split, total;
+  size_t lcat, rcat, st, p, g1, g2, h, m0, m1, c, bbar, x2, z, y5, t1, t2, t3, t4, psplit,
+      psplit_bytes, gsplit, gsplit_bytes, dsplit, dsplit_bytes, split, total;
 };
 BackWs back_ws(const Plan& P) {
   BackWs w{};
@@ -162,6 +166,22 @@ BackWs back_ws(const Plan& P) {
   w.t2 = take(r * r * 8);
   w.t3 = take(r * r * 8);
   w.t4 = take(r * r * 8);
+  w.psplit_bytes = pass_split_ws_bytes(P.mode, GN_SKETCH_GAUSSIAN, P.m, P.n, P.rl, P.r);
+  w.psplit = take(w.psplit_bytes);
+  w.gsplit_bytes = (P.mode == GN_MODE_F32) ? gemm_f32_split_ws_bytes(P.m, P.r, P.n) : 0;
+  w.gsplit = take(w.gsplit_bytes);
+  {
+    const int64_t shapes[][3] = {{P.r, P.rl, P.r},  {P.rl, P.r, P.r},  {P.r, P.r, P.rl},
+                                 {P.r, P.r, P.r},   {P.m, P.r, P.rl},  {P.rl, P.n, P.r},
+                                 {P.m, P.n, P.r + P.rl}};
+    size_t mx = 0;
+    for (const auto& sh : shapes) {
+      const size_t b = dgemm_split_ws_bytes(sh[0], sh[1], sh[2]);
+      if (b > mx) mx = b;
+    }
+    w.dsplit_bytes = mx;
+    w.dsplit = take(mx);
+  }
   w.split = off;
   off += (P.mode == GN_MODE_F64) ? dgemm_split_ws_bytes(P.r, P.rl, P.m)
                                  : core_product_ws_bytes(P.m, P.r, P.rl);
@@ -318,7 +338,7 @@ gn_status gn_sketch_prepare(const gn_problem* p, const void* X_user, int64_t ldx
 }
 
 gn_status gn_sketch_pass(const gn_problem* p, const void* A, int64_t lda, const float* A_scales,
-                         void* AX, int64_t ldax, void* YtA, int64_t ldya, const void* ws,
+                         void* AX, int64_t ldax, void* YtA, int64_t ldya, void* ws,
                          size_t ws_bytes, gn_stream_t stream_) {
   Plan P;
   GN_TRY(make_plan(p, P));
@@ -328,10 +348,10 @@ gn_status gn_sketch_pass(const gn_problem* p, const void* A, int64_t lda, const 
   if (!aligned16(A) || !aligned16(AX) || !aligned16(YtA) || !aligned16(ws)) return GN_ERR_ALIGN;
   const SketchWs W = sketch_ws(P);
   if (ws_bytes < W.total) return GN_ERR_WORKSPACE;
-  const char* base = (const char*)ws;
+  char* base = (char*)ws;
   return launch_pass(P.mode, P.kx, P.m, P.n, P.r, P.rl, A, lda, A_scales, base + W.xt,
                      (const int8_t*)(base + W.signs), (const int32_t*)(base + W.idx), base + W.yt,
-                     AX, ldax, YtA, ldya, (hipStream_t)stream_);
+                     AX, ldax, YtA, ldya, (hipStream_t)stream_, base + W.split, W.split_bytes);
 }
 
 gn_status gn_sketch(const gn_problem* p, const void* A, int64_t lda, const float* A_scales,
@@ -565,7 +585,8 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
   } else if (!AX) {
     if (f32)
       GN_TRY(launch_gemm_f32(m, r, n, (const float*)A, lda, true, (const float*)rcat, n, true,
-                             (float*)(base + W.p), r, s));
+                             (float*)(base + W.p), r, s, (float*)(base + W.gsplit),
+                             W.gsplit_bytes));
     else
       GN_TRY(launch_dgemm(m, r, n, 1.0, MatRef{A, F64, lda, 1}, MatRef{rcat, F64, 1, n}, 0.0,
                           (double*)(base + W.p), r, 1, nullptr, false, s));
@@ -575,7 +596,7 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
   // sketches (Y^T A)^T (n x rl) and AX (m x r)
   GN_TRY(launch_transpose(YtA, rl, n, ldya, adt, St, rl, s));
   GN_TRY(launch_pass(P.mode, GN_SKETCH_GAUSSIAN, m, n, rl, r, Gbar, ldg, nullptr, St, nullptr,
-                     nullptr, Pm, G1, rl, G2, n, s));
+                     nullptr, Pm, G1, rl, G2, n, s, base + W.psplit, W.psplit_bytes));
   // H = (AX)^T G1 = dL/dM
   if (f32)
     GN_TRY(launch_core_product_f32(m, r, rl, (const float*)Pm, r, (const float*)G1, rl,
@@ -585,7 +606,10 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
                         nullptr, false, s, nullptr, 0, true, (double*)(base + W.split),
                         W.total - W.split));
 
-  // ---- the core adjoint in FP64 (k from the forward pass, on the device)
+  // ---- the core adjoint in FP64 (k from the forward pass, on the device); the
+  // small products split their contraction through the DS scratch region
+  double* DS = (double*)(base + W.dsplit);
+  const size_t DSB = W.dsplit_bytes;
   const MatRef Mr{M, F64, rl, 1}, Mt{M, F64, 1, rl};
   const MatRef Hr{H, F64, rl, 1}, Ht{H, F64, 1, rl};
   const MatRef Q1r{core->Q1, F64, r, 1}, Q1t{core->Q1, F64, 1, r};
@@ -596,54 +620,54 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
   GN_TRY(launch_trsm_core(rl, r, core->R, core->R2, r, kd, M0, 1, rl, true, true, s));
   GN_TRY(widen(r, rl, M0, F64, rl, M, rl, kd, r, s));
   GN_TRY(launch_dgemm(r, rl, r, 1.0, Q2r, MatRef{M0, F64, rl, 1}, 0.0, M, rl, 1, nullptr, false, s,
-                      kd, r, true));
+                      kd, r, true, DS, DSB));
   // C = Q1 R
   GN_TRY(launch_dgemm(rl, r, r, 1.0, Q1r, MatRef{core->R, F64, r, 1}, 0.0, Cm, r, 1, nullptr,
-                      false, s));
+                      false, s, nullptr, 0, true, DS, DSB));
   // Bbar = -M^T H M^T
-  GN_TRY(launch_dgemm(r, r, rl, 1.0, Hr, Mt, 0.0, T1, r, 1, nullptr, false, s));
-  GN_TRY(launch_dgemm(rl, r, r, -1.0, Mt, sq(T1), 0.0, Bb, r, 1, nullptr, false, s));
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, Hr, Mt, 0.0, T1, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
+  GN_TRY(launch_dgemm(rl, r, r, -1.0, Mt, sq(T1), 0.0, Bb, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
   // Bbar += (I - Q1k Q1k^T) H^T M M^T
-  GN_TRY(launch_dgemm(r, r, rl, 1.0, Mr, Mt, 0.0, T2, r, 1, nullptr, false, s));
-  GN_TRY(launch_dgemm(rl, r, r, 1.0, Ht, sq(T2), 0.0, X2, r, 1, nullptr, false, s));
-  GN_TRY(launch_dgemm(r, r, rl, 1.0, Q1t, sq(X2), 0.0, T3, r, 1, kd, true, s));
-  GN_TRY(launch_dgemm(rl, r, r, -1.0, Q1r, sq(T3), 1.0, X2, r, 1, nullptr, false, s));
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, Mr, Mt, 0.0, T2, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, Ht, sq(T2), 0.0, X2, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, Q1t, sq(X2), 0.0, T3, r, 1, kd, true, s, nullptr, 0, true, DS, DSB));
+  GN_TRY(launch_dgemm(rl, r, r, -1.0, Q1r, sq(T3), 1.0, X2, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
   GN_TRY(launch_axpy(rl, r, 1.0, X2, r, Bb, r, s));
   // k < r: Bbar += M^T (M H^T)(I - Q2k Q2k^T)
-  GN_TRY(launch_dgemm(r, r, rl, 1.0, Mr, Ht, 0.0, T1, r, 1, nullptr, false, s, kd, r, true));
-  GN_TRY(launch_dgemm(r, r, r, 1.0, sq(T1), Q2r, 0.0, T4, r, 1, kd, false, s, kd, r, true));
-  GN_TRY(launch_dgemm(r, r, r, -1.0, sq(T4), Q2t, 1.0, T1, r, 1, nullptr, false, s, kd, r, true));
-  GN_TRY(launch_dgemm(rl, r, r, 1.0, Mt, sq(T1), 1.0, Bb, r, 1, nullptr, false, s, kd, r, true));
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, Mr, Ht, 0.0, T1, r, 1, nullptr, false, s, kd, r, true, DS, DSB));
+  GN_TRY(launch_dgemm(r, r, r, 1.0, sq(T1), Q2r, 0.0, T4, r, 1, kd, false, s, kd, r, true, DS, DSB));
+  GN_TRY(launch_dgemm(r, r, r, -1.0, sq(T4), Q2t, 1.0, T1, r, 1, nullptr, false, s, kd, r, true, DS, DSB));
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, Mt, sq(T1), 1.0, Bb, r, 1, nullptr, false, s, kd, r, true, DS, DSB));
   // Z = Q1k R11^{-T} (columns >= k zero)
   if (hipMemcpyAsync(Z, core->Q1, (size_t)rl * r * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return GN_ERR_HIP;
   GN_TRY(launch_trsm_core(rl, r, core->R, core->R2, r, kd, Z, r, 1, true, true, s, true));
   // Y5 = Bbar (C^T Z) + C (Bbar^T Z)
   GN_TRY(launch_dgemm(r, r, rl, 1.0, MatRef{Cm, F64, 1, r}, sq(Z), 0.0, T2, r, 1, nullptr, false,
-                      s));
+                      s, nullptr, 0, true, DS, DSB));
   GN_TRY(launch_dgemm(r, r, rl, 1.0, MatRef{Bb, F64, 1, r}, sq(Z), 0.0, T3, r, 1, nullptr, false,
-                      s));
-  GN_TRY(launch_dgemm(rl, r, r, 1.0, sq(Bb), sq(T2), 0.0, Y5, r, 1, nullptr, false, s));
-  GN_TRY(launch_dgemm(rl, r, r, 1.0, sq(Cm), sq(T3), 1.0, Y5, r, 1, nullptr, false, s));
+                      s, nullptr, 0, true, DS, DSB));
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, sq(Bb), sq(T2), 0.0, Y5, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, sq(Cm), sq(T3), 1.0, Y5, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
   // Cbar = Y5 + Q1k Q1k^T (Bbar - Y5)   (kept in Y5)
-  GN_TRY(launch_dgemm(r, r, rl, 1.0, Q1t, sq(Bb), 0.0, T4, r, 1, kd, true, s));
-  GN_TRY(launch_dgemm(r, r, rl, -1.0, Q1t, sq(Y5), 1.0, T4, r, 1, kd, true, s));
-  GN_TRY(launch_dgemm(rl, r, r, 1.0, Q1r, sq(T4), 1.0, Y5, r, 1, nullptr, false, s));
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, Q1t, sq(Bb), 0.0, T4, r, 1, kd, true, s, nullptr, 0, true, DS, DSB));
+  GN_TRY(launch_dgemm(r, r, rl, -1.0, Q1t, sq(Y5), 1.0, T4, r, 1, kd, true, s, nullptr, 0, true, DS, DSB));
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, Q1r, sq(T4), 1.0, Y5, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
 
   // U = G1 M^T + Y Cbar into columns [0, r) of lcat; V = M^T G2 into rows
   // [r, r + rl) of rcat
   GN_TRY(launch_dgemm_to(m, r, rl, 1.0, MatRef{G1, adt, rl, 1}, Mt, 0.0, lcat, sdt, K2, 1, nullptr,
-                         false, s));
+                         false, s, nullptr, 0, true, DS, DSB));
   GN_TRY(launch_dgemm_to(m, r, rl, 1.0, MatRef{lcat + r * sd, sdt, K2, 1}, sq(Y5), 1.0, lcat,
-                         sdt, K2, 1, nullptr, false, s));
+                         sdt, K2, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
   GN_TRY(launch_dgemm_to(rl, n, r, 1.0, Mt, MatRef{G2, adt, n, 1}, 0.0, rcat + (size_t)r * n * sd,
-                         sdt, n, 1, nullptr, false, s));
+                         sdt, n, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
   // dA = [U | Y] [X^T ; V]
   if (f32)
     return launch_gemm_f32(m, n, K2, (const float*)lcat, K2, true, (const float*)rcat, n, false,
                            (float*)dA, ldda, s);
   return launch_dgemm(m, n, K2, 1.0, MatRef{lcat, F64, K2, 1}, MatRef{rcat, F64, n, 1}, 0.0,
-                      (double*)dA, ldda, 1, nullptr, false, s);
+                      (double*)dA, ldda, 1, nullptr, false, s, nullptr, 0, true, DS, DSB);
 }
 
 gn_status gn_residual(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, int32_t a_dtype,

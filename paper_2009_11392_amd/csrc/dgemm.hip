@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(256) reduce_partials(const double* partial, in
 }
 
 constexpr int64_t kTargetWG = 512;  // two workgroups per CU
-constexpr int64_t kMinSlice = 1024;
+constexpr int64_t kMinSlice = 64;   // slices of at least 64 (four staged K blocks)
 
 }  // namespace
 

@@ -1,0 +1,205 @@
+// FP32 matrix-core products outside the fused pass:
+//   * the core product C = Y^T (AX) of the FP32 and BF16 modes (Section 5.1
+//     order), split along K = m into slices summed in order in FP64;
+//   * a plain FP32 GEMM D = A B with the pass's 256 x 256 tile, optionally split
+//     along K when there are too few output tiles to fill the chip (slices
+//     written to their own partials and summed in slice order, in FP64, then
+//     rounded once: deterministic);
+//   * bfloat16 -> float widening of user sketches.
+#include "gn_internal.h"
+#include "gemm_tiles.h"
+
+namespace gn {
+namespace {
+
+using namespace tiles;
+
+using CoreCfg = F32Cfg<128, 128, 16, 2, 2, 32>;
+
+template <bool VEC>
+__global__ void __launch_bounds__(CoreCfg::T) core_product_f32(GemmF32 g, int64_t kslice) {
+  __shared__ __attribute__((aligned(16))) char smem[CoreCfg::smem<false, false>()];
+  const int64_t s = blockIdx.y;
+  const int64_t k0 = s * kslice;
+  GemmF32 gs = g;
+  gs.A = g.A + k0 * g.lda;
+  gs.B = g.B + k0 * g.ldb;
+  gs.K = (k0 + kslice < g.K) ? kslice : g.K - k0;
+  gs.D = g.D + s * g.M * g.N;
+  if (gs.K <= 0) return;
+  f32_tile_cfg<CoreCfg, false, false, VEC>(gs, blockIdx.x, smem);
+}
+
+__global__ void __launch_bounds__(256) core_product_sum(const float* partial, int64_t nslice,
+                                                        int64_t mn, double* C) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mn) return;
+  double acc = 0.0;
+  for (int64_t q = 0; q < nslice; ++q) acc += (double)partial[q * mn + e];
+  C[e] = acc;
+}
+
+int64_t core_slices(int64_t m, int64_t rl, int64_t r) {
+  const int64_t tiles = cdiv(rl, CoreCfg::BM) * cdiv(r, CoreCfg::BN);
+  int64_t sl = cdiv(512, tiles);
+  const int64_t smax = cdiv(m, 512);
+  if (sl > smax) sl = smax;
+  if (sl > 16) sl = 16;
+  return sl < 1 ? 1 : sl;
+}
+
+// D = A B; with `partial`, slice blockIdx.y of K (length kslice) goes to
+// partial + slice * M * N (row stride N).
+template <bool A_KC, bool B_KC, bool VEC>
+__global__ void __launch_bounds__(F32Pass::T) gemm_f32_kernel(GemmF32 g, int64_t kslice,
+                                                              float* partial) {
+  __shared__ __attribute__((aligned(16))) char smem[F32Pass::smem<A_KC, B_KC>()];
+  GemmF32 gs = g;
+  if (partial) {
+    const int64_t s = blockIdx.y, k0 = s * kslice;
+    gs.A = A_KC ? g.A + k0 : g.A + k0 * g.lda;
+    gs.B = B_KC ? g.B + k0 : g.B + k0 * g.ldb;
+    gs.K = (k0 + kslice < g.K) ? kslice : g.K - k0;
+    gs.D = partial + s * g.M * g.N;
+    gs.ldd = g.N;
+  }
+  f32_tile_cfg<F32Pass, A_KC, B_KC, VEC>(gs, blockIdx.x, smem);
+}
+
+// D[i*ldd + j] = sum over slices (in order, FP64) of partial[s][i][j], rounded.
+__global__ void __launch_bounds__(256) splitk_sum_f32(const float* partial, int64_t nslice,
+                                                      int64_t M, int64_t N, float* D,
+                                                      int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  const int64_t i = e / N, j = e - i * N;
+  double acc = 0.0;
+  for (int64_t q = 0; q < nslice; ++q) acc += (double)partial[q * M * N + e];
+  D[i * ldd + j] = (float)acc;
+}
+
+__global__ void __launch_bounds__(256) widen_bf16_kernel(int64_t rows, int64_t cols,
+                                                         const uint16_t* src, int64_t lds,
+                                                         float* dst, int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e / cols, j = e - i * cols;
+  dst[i * ldd + j] = bf16_bits_to_f32(src[i * lds + j]);
+}
+
+}  // namespace
+
+// Common K slice for up to two product families (tiles1 with length K1, tiles2
+// with K2) with few output tiles.  Cost model: workgroups run in waves of
+// kSplitTargetWG (one per CU) and a workgroup's time grows with its slice
+// length plus a fixed prologue/epilogue of about 256 K steps; the candidate
+// slices are multiples of kSplitMinSlice.  kslice == 0: no split.
+SplitK f32_split2(int64_t tiles1, int64_t K1, int64_t tiles2, int64_t K2) {
+  SplitK best{1, 0};
+  const int64_t tiles = tiles1 + tiles2;
+  const int64_t Kmax = K1 > K2 ? K1 : K2;
+  if (tiles >= kSplitMinTiles || Kmax < 2 * kSplitMinSlice) return best;
+  auto cost = [&](int64_t wgs, int64_t klen) {
+    return cdiv(wgs, kSplitTargetWG) * (klen + 256);
+  };
+  int64_t best_cost = cost(tiles, Kmax);  // unsplit
+  for (int64_t ks = kSplitMinSlice; ks < Kmax; ks += kSplitMinSlice) {
+    const int64_t wgs = tiles1 * cdiv(K1, ks) + tiles2 * cdiv(K2, ks);
+    if (cdiv(K1, ks) > 32 || cdiv(K2, ks) > 32) continue;
+    const int64_t c = cost(wgs, ks);
+    if (c < best_cost) {
+      best_cost = c;
+      best.kslice = ks;
+    }
+  }
+  best.slices = best.kslice ? cdiv(K1 > 0 ? K1 : 1, best.kslice) : 1;
+  return best;
+}
+
+SplitK f32_split(int64_t tiles, int64_t K) {
+  SplitK sk = f32_split2(tiles, K, 0, 0);
+  if (sk.kslice == 0) return SplitK{1, K};
+  sk.slices = cdiv(K, sk.kslice);
+  return sk;
+}
+
+gn_status launch_splitk_sum_f32(const float* partial, int64_t nslice, int64_t M, int64_t N,
+                                float* D, int64_t ldd, hipStream_t s) {
+  if (M <= 0 || N <= 0) return GN_OK;
+  splitk_sum_f32<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(partial, nslice, M, N, D,
+                                                                        ldd);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+size_t core_product_ws_bytes(int64_t m, int64_t rl, int64_t r) {
+  return align_up((size_t)core_slices(m, rl, r) * rl * r * sizeof(float));
+}
+
+gn_status launch_core_product_f32(int64_t m, int64_t rl, int64_t r, const float* Y, int64_t ldy,
+                                  const float* AX, int64_t ldax, float* partial, double* C,
+                                  hipStream_t s) {
+  const int64_t sl = core_slices(m, rl, r);
+  const int64_t kslice = cdiv(cdiv(m, sl), 16) * 16;
+  const int64_t tiles = cdiv(rl, CoreCfg::BM) * cdiv(r, CoreCfg::BN);
+  GemmF32 g{rl, r, m, Y, ldy, AX, ldax, partial, r, 1};
+  const bool vec = (ldy % 4 == 0) && (ldax % 4 == 0) && ((uintptr_t)Y % 16 == 0) &&
+                   ((uintptr_t)AX % 16 == 0);
+  const dim3 grid((unsigned)(8 * cdiv(tiles, 8)), (unsigned)sl);
+  if (vec)
+    core_product_f32<true><<<grid, dim3(CoreCfg::T), 0, s>>>(g, kslice);
+  else
+    core_product_f32<false><<<grid, dim3(CoreCfg::T), 0, s>>>(g, kslice);
+  GN_LAUNCH_CHECK();
+  core_product_sum<<<dim3((unsigned)cdiv(rl * r, 256)), dim3(256), 0, s>>>(partial, sl, rl * r, C);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+size_t gemm_f32_split_ws_bytes(int64_t M, int64_t N, int64_t K) {
+  const SplitK sk = f32_split(cdiv(M, F32Pass::BM) * cdiv(N, F32Pass::BN), K);
+  return sk.slices > 1 ? align_up((size_t)sk.slices * M * N * sizeof(float)) : 0;
+}
+
+gn_status launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, bool a_kc,
+                          const float* B, int64_t ldb, bool b_kc, float* D, int64_t ldd,
+                          hipStream_t s, float* split_ws, size_t split_bytes) {
+  if (M <= 0 || N <= 0) return GN_OK;
+  GemmF32 g{M, N, K, A, lda, B, ldb, D, ldd, 1};
+  const int64_t tiles = cdiv(M, F32Pass::BM) * cdiv(N, F32Pass::BN);
+  SplitK sk = f32_split(tiles, K);
+  if (sk.slices > 1 && (!split_ws || split_bytes < (size_t)sk.slices * M * N * sizeof(float)))
+    sk = SplitK{1, K};
+  float* partial = sk.slices > 1 ? split_ws : nullptr;
+  const dim3 grid((unsigned)(8 * cdiv(tiles, 8)), (unsigned)sk.slices);
+  const bool vec = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) &&
+                   ((uintptr_t)B % 16 == 0);
+#define GN_GEMM(AK, BK)                                                                          \
+  if (vec)                                                                                       \
+    gemm_f32_kernel<AK, BK, true><<<grid, dim3(F32Pass::T), 0, s>>>(g, sk.kslice, partial);      \
+  else                                                                                           \
+    gemm_f32_kernel<AK, BK, false><<<grid, dim3(F32Pass::T), 0, s>>>(g, sk.kslice, partial)
+  if (a_kc && b_kc) {
+    GN_GEMM(true, true);
+  } else if (a_kc) {
+    GN_GEMM(true, false);
+  } else if (b_kc) {
+    GN_GEMM(false, true);
+  } else {
+    GN_GEMM(false, false);
+  }
+#undef GN_GEMM
+  GN_LAUNCH_CHECK();
+  if (partial) return launch_splitk_sum_f32(partial, sk.slices, M, N, D, ldd, s);
+  return GN_OK;
+}
+
+gn_status launch_widen_bf16(int64_t rows, int64_t cols, const uint16_t* src, int64_t lds, float* dst,
+                            int64_t ldd, hipStream_t s) {
+  widen_bf16_kernel<<<dim3((unsigned)cdiv(rows * cols, 256)), dim3(256), 0, s>>>(rows, cols, src,
+                                                                                 lds, dst, ldd);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+}  // namespace gn

@@ -119,10 +119,31 @@ size_t srht_ws_bytes(int64_t npad);
 // FP32 and BF16 modes.  Xt is the transposed Gaussian or user sketch (r x n,
 // ld n; unused for SRHT), Yt the transposed Y (rl x m, ld m); signs / idx the
 // SRHT parameters (SRHT X only).
+// split_ws (pass_split_ws_bytes) lets an FP32 Gaussian pass with few output
+// tiles split K; without it (or too small) the pass runs unsplit.
 gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_t r, int64_t rl,
                       const void* A, int64_t lda, const float* scales, const void* Xt,
                       const int8_t* signs, const int32_t* idx, const void* Yt, void* AX,
-                      int64_t ldax, void* YtA, int64_t ldya, hipStream_t s);
+                      int64_t ldax, void* YtA, int64_t ldya, hipStream_t s,
+                      void* split_ws = nullptr, size_t split_bytes = 0);
+size_t pass_split_ws_bytes(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_t r,
+                           int64_t rl);
+
+// K splitting of FP32 products with few output tiles: a slice length kslice (a
+// multiple of kSplitMinSlice) chosen by a wave-quantized cost model.
+struct SplitK {
+  int64_t slices, kslice;
+};
+constexpr int64_t kSplitMinTiles = 192;  // at or above: no split
+constexpr int64_t kSplitTargetWG = 256;  // one 1024-thread workgroup per CU
+constexpr int64_t kSplitMinSlice = 512;
+SplitK f32_split(int64_t tiles, int64_t K);
+// Two families sharing one slice length (kslice == 0: no split).
+SplitK f32_split2(int64_t tiles1, int64_t K1, int64_t tiles2, int64_t K2);
+// D[i*ldd + j] = sum over nslice partials (each M x N, row stride N) in slice
+// order in FP64, rounded to float.
+gn_status launch_splitk_sum_f32(const float* partial, int64_t nslice, int64_t M, int64_t N,
+                                float* D, int64_t ldd, hipStream_t s);
 
 // C ((rl) x r, FP64, ld r) = Y^T (AX) on the FP32 matrix cores: Y m x rl (ld
 // ldy), AX m x r (ld ldax), both float; K = m split into slices whose FP32
@@ -131,13 +152,15 @@ gn_status launch_core_product_f32(int64_t m, int64_t rl, int64_t r, const float*
                                   const float* AX, int64_t ldax, float* partial, double* C,
                                   hipStream_t s);
 size_t core_product_ws_bytes(int64_t m, int64_t rl, int64_t r);
-// widen a bfloat16 matrix (rows x cols, ld lds) to float (ld ldd)
 // D (M x N, FP32) = A (M x K) B (K x N), FP32 MFMA with FP32 accumulation.
 // a_kc: A(i,k) = A[i*lda + k], else A[k*lda + i]; b_kc: B(k,j) = B[j*ldb + k],
-// else B[k*ldb + j].
+// else B[k*ldb + j].  With split_ws (gemm_f32_split_ws_bytes) a product with few
+// output tiles is split along K.
 gn_status launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, bool a_kc,
                           const float* B, int64_t ldb, bool b_kc, float* D, int64_t ldd,
-                          hipStream_t s);
+                          hipStream_t s, float* split_ws = nullptr, size_t split_bytes = 0);
+size_t gemm_f32_split_ws_bytes(int64_t M, int64_t N, int64_t K);
+// widen a bfloat16 matrix (rows x cols, ld lds) to float (ld ldd)
 gn_status launch_widen_bf16(int64_t rows, int64_t cols, const uint16_t* src, int64_t lds, float* dst,
                             int64_t ldd, hipStream_t s);
 

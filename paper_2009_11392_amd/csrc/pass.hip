@@ -206,6 +206,42 @@ __global__ void __launch_bounds__(CF::T) pass_f32_gauss(GemmF32 yta, GemmF32 ax,
     f32_tile_cfg<CF, true, false, VEC>(ax, local, smem);
 }
 
+// The same two families with K split into slices (blockIdx.y): slice s of Y^T A
+// covers rows [s kslY, ...) of A, slice s of AX its columns [s kslA, ...); each
+// writes its own partial (summed afterwards in slice order).  For problems with
+// too few output tiles to fill the chip.
+template <class CF, bool VEC>
+__global__ void __launch_bounds__(CF::T) pass_f32_gauss_split(GemmF32 yta, GemmF32 ax, int64_t gY,
+                                                              int64_t gA, int64_t kslY,
+                                                              int64_t kslA, int64_t sY, int64_t sA,
+                                                              float* partY, float* partA) {
+  __shared__ __attribute__((aligned(16))) char smem[smax(CF::template smem<false, false>(),
+                                                         CF::template smem<true, false>())];
+  const int64_t sl = blockIdx.y;
+  int64_t local;
+  if (family_split(gY, gA, local)) {
+    if (sl >= sY) return;
+    const int64_t k0 = sl * kslY;
+    GemmF32 g = yta;
+    g.A = yta.A + k0 * yta.lda;  // Y (m x rl): A(i, k) = Y[k * rl + i]
+    g.B = yta.B + k0 * yta.ldb;  // A (m x n):  B(k, j) = A[k * lda + j]
+    g.K = (k0 + kslY < yta.K) ? kslY : yta.K - k0;
+    g.D = partY + sl * yta.M * yta.N;
+    g.ldd = yta.N;
+    f32_tile_cfg<CF, false, false, VEC>(g, local, smem);
+  } else {
+    if (sl >= sA) return;
+    const int64_t k0 = sl * kslA;
+    GemmF32 g = ax;
+    g.A = ax.A + k0;             // A (m x n):  A(i, k) = A[i * lda + k]
+    g.B = ax.B + k0 * ax.ldb;    // X (n x r):  B(k, j) = X[k * r + j]
+    g.K = (k0 + kslA < ax.K) ? kslA : ax.K - k0;
+    g.D = partA + sl * ax.M * ax.N;
+    g.ldd = ax.N;
+    f32_tile_cfg<CF, true, false, VEC>(g, local, smem);
+  }
+}
+
 template <class CF, int RPL, bool VEC>
 __global__ void __launch_bounds__(CF::T) pass_f32_srht(GemmF32 yta, SrhtArgs sr, int64_t gY,
                                                        int64_t gS, int srht_first) {
@@ -303,6 +339,52 @@ gn_status launch_f32_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_t
   return GN_OK;
 }
 
+struct PassSplit {
+  int64_t sY, kslY, sA, kslA;
+  size_t bytes;
+};
+PassSplit pass_split(int64_t m, int64_t n, int64_t r, int64_t rl) {
+  const int64_t tY = cdiv(rl, F32Pass::BM) * cdiv(n, F32Pass::BN);
+  const int64_t tA = cdiv(m, F32Pass::BM) * cdiv(r, F32Pass::BN);
+  const SplitK sk = f32_split2(tY, m, tA, n);
+  PassSplit ps{1, m, 1, n, 0};
+  if (sk.kslice == 0) return ps;
+  ps.kslY = sk.kslice;
+  ps.sY = cdiv(m, ps.kslY);
+  ps.kslA = sk.kslice;
+  ps.sA = cdiv(n, ps.kslA);
+  ps.bytes = align_up((size_t)ps.sY * rl * n * sizeof(float)) +
+             align_up((size_t)ps.sA * m * r * sizeof(float));
+  return ps;
+}
+
+// FP32 Gaussian pass split along K (pass_split), then the slice sums.
+gn_status launch_f32_split(const PassSplit& ps, int64_t m, int64_t n, int64_t r, int64_t rl,
+                           const float* A, int64_t lda, const float* X, const float* Y, float* AX,
+                           int64_t ldax, float* YtA, int64_t ldya, char* ws, hipStream_t s) {
+  using CF = F32Pass;
+  float* partY = (float*)ws;
+  float* partA = (float*)(ws + align_up((size_t)ps.sY * rl * n * sizeof(float)));
+  GemmF32 yta{rl, n, m, Y, rl, A, lda, YtA, ldya, 1};
+  GemmF32 ax{m, r, n, A, lda, X, r, AX, ldax, 0};
+  const int64_t gY = cdiv(cdiv(rl, CF::BM) * cdiv(n, CF::BN), 8);
+  const int64_t gA = cdiv(cdiv(m, CF::BM) * cdiv(r, CF::BN), 8);
+  const bool vec = (lda % 4 == 0) && (rl % 4 == 0) && (r % 4 == 0) && ((uintptr_t)A % 16 == 0) &&
+                   ((uintptr_t)Y % 16 == 0) && ((uintptr_t)X % 16 == 0);
+  const int64_t sl = ps.sY > ps.sA ? ps.sY : ps.sA;
+  const dim3 grid((unsigned)(8 * (gY + gA)), (unsigned)sl);
+  if (vec)
+    pass_f32_gauss_split<CF, true><<<grid, dim3(CF::T), 0, s>>>(yta, ax, gY, gA, ps.kslY, ps.kslA,
+                                                                ps.sY, ps.sA, partY, partA);
+  else
+    pass_f32_gauss_split<CF, false><<<grid, dim3(CF::T), 0, s>>>(yta, ax, gY, gA, ps.kslY,
+                                                                 ps.kslA, ps.sY, ps.sA, partY,
+                                                                 partA);
+  GN_LAUNCH_CHECK();
+  GN_TRY(launch_splitk_sum_f32(partY, ps.sY, rl, n, YtA, ldya, s));
+  return launch_splitk_sum_f32(partA, ps.sA, m, r, AX, ldax, s);
+}
+
 // BF16 pass with tile configuration CF (sketches stored transposed: Xt r x n,
 // Yt rl x m).
 template <class CF>
@@ -334,67 +416,13 @@ gn_status launch_bf16_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_
   return GN_OK;
 }
 
-// ------------------------------------------------------------------ core product
-// C = Y^T (AX) on the FP32 matrix cores: slice s of K = m (blockIdx.y) is a
-// Y^T A-shaped contraction (both operands m/n-contiguous) written to its own
-// partial; the slices are then summed in order in FP64.
-using CoreCfg = F32Cfg<128, 128, 16, 2, 2, 32>;
-
-template <bool VEC>
-__global__ void __launch_bounds__(CoreCfg::T) core_product_f32(GemmF32 g, int64_t kslice) {
-  __shared__ __attribute__((aligned(16))) char smem[CoreCfg::smem<false, false>()];
-  const int64_t s = blockIdx.y;
-  const int64_t k0 = s * kslice;
-  GemmF32 gs = g;
-  gs.A = g.A + k0 * g.lda;
-  gs.B = g.B + k0 * g.ldb;
-  gs.K = (k0 + kslice < g.K) ? kslice : g.K - k0;
-  gs.D = g.D + s * g.M * g.N;
-  if (gs.K <= 0) return;
-  f32_tile_cfg<CoreCfg, false, false, VEC>(gs, blockIdx.x, smem);
-}
-
-__global__ void __launch_bounds__(256) core_product_sum(const float* partial, int64_t nslice,
-                                                        int64_t mn, double* C) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= mn) return;
-  double acc = 0.0;
-  for (int64_t q = 0; q < nslice; ++q) acc += (double)partial[q * mn + e];
-  C[e] = acc;
-}
-
-int64_t core_slices(int64_t m, int64_t rl, int64_t r) {
-  const int64_t tiles = cdiv(rl, CoreCfg::BM) * cdiv(r, CoreCfg::BN);
-  int64_t sl = cdiv(512, tiles);
-  const int64_t smax = cdiv(m, 2048);
-  if (sl > smax) sl = smax;
-  if (sl > 16) sl = 16;
-  return sl < 1 ? 1 : sl;
-}
-
-// Plain FP32 GEMM D = A B with the sketch pass's tile configuration (used by the
-// reverse mode for AX recomputation and the final rank-(r + l) product).
-template <bool A_KC, bool B_KC, bool VEC>
-__global__ void __launch_bounds__(F32Pass::T) gemm_f32_kernel(GemmF32 g) {
-  __shared__ __attribute__((aligned(16))) char smem[F32Pass::smem<A_KC, B_KC>()];
-  f32_tile_cfg<F32Pass, A_KC, B_KC, VEC>(g, blockIdx.x, smem);
-}
-
-__global__ void __launch_bounds__(256) widen_bf16_kernel(int64_t rows, int64_t cols,
-                                                         const uint16_t* src, int64_t lds,
-                                                         float* dst, int64_t ldd) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= rows * cols) return;
-  const int64_t i = e / cols, j = e - i * cols;
-  dst[i * ldd + j] = bf16_bits_to_f32(src[i * lds + j]);
-}
-
 }  // namespace
 
 gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_t r, int64_t rl,
                       const void* A, int64_t lda, const float* scales, const void* Xs,
                       const int8_t* signs, const int32_t* idx, const void* Ys, void* AX,
-                      int64_t ldax, void* YtA, int64_t ldya, hipStream_t s) {
+                      int64_t ldax, void* YtA, int64_t ldya, hipStream_t s, void* split_ws,
+                      size_t split_bytes) {
   // F64 / F32: Xs = X (n x r, ld r), Ys = Y (m x rl, ld rl).
   // BF16:      Xs = X^T (r x n, ld n), Ys = Y^T (rl x m, ld m).
   const void* Xt = Xs;
@@ -419,6 +447,13 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
                         0.0, (double*)YtA, ldya, 1, nullptr, false, s);
   }
 
+  if (mode == GN_MODE_F32 && !srht) {
+    const PassSplit ps = pass_split(m, n, r, rl);
+    if (ps.bytes > 0 && split_ws && split_bytes >= ps.bytes)
+      return launch_f32_split(ps, m, n, r, rl, (const float*)A, lda, (const float*)Xs,
+                              (const float*)Ys, (float*)AX, ldax, (float*)YtA, ldya,
+                              (char*)split_ws, s);
+  }
   if (mode == GN_MODE_F32)
     return launch_f32_cfg<F32Pass>(srht, kSrhtFirst, kSrhtRows, m, n, r, rl, (const float*)A, lda,
                                    (const float*)Xs, (const float*)Ys, sr, (float*)AX, ldax,
@@ -429,64 +464,10 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
                                    (const uint16_t*)Ys, sr, (float*)AX, ldax, (float*)YtA, ldya, s);
 }
 
-size_t core_product_ws_bytes(int64_t m, int64_t rl, int64_t r) {
-  return align_up((size_t)core_slices(m, rl, r) * rl * r * sizeof(float));
-}
-
-gn_status launch_core_product_f32(int64_t m, int64_t rl, int64_t r, const float* Y, int64_t ldy,
-                                  const float* AX, int64_t ldax, float* partial, double* C,
-                                  hipStream_t s) {
-  const int64_t sl = core_slices(m, rl, r);
-  const int64_t kslice = cdiv(cdiv(m, sl), 16) * 16;
-  const int64_t tiles = cdiv(rl, CoreCfg::BM) * cdiv(r, CoreCfg::BN);
-  GemmF32 g{rl, r, m, Y, ldy, AX, ldax, partial, r, 1};
-  const bool vec = (ldy % 4 == 0) && (ldax % 4 == 0) && ((uintptr_t)Y % 16 == 0) &&
-                   ((uintptr_t)AX % 16 == 0);
-  const dim3 grid((unsigned)(8 * cdiv(tiles, 8)), (unsigned)sl);
-  if (vec)
-    core_product_f32<true><<<grid, dim3(CoreCfg::T), 0, s>>>(g, kslice);
-  else
-    core_product_f32<false><<<grid, dim3(CoreCfg::T), 0, s>>>(g, kslice);
-  GN_LAUNCH_CHECK();
-  core_product_sum<<<dim3((unsigned)cdiv(rl * r, 256)), dim3(256), 0, s>>>(partial, sl, rl * r, C);
-  GN_LAUNCH_CHECK();
-  return GN_OK;
-}
-
-gn_status launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, bool a_kc,
-                          const float* B, int64_t ldb, bool b_kc, float* D, int64_t ldd,
-                          hipStream_t s) {
-  if (M <= 0 || N <= 0) return GN_OK;
-  GemmF32 g{M, N, K, A, lda, B, ldb, D, ldd, 1};
-  const int64_t tiles = cdiv(M, F32Pass::BM) * cdiv(N, F32Pass::BN);
-  const dim3 grid((unsigned)(8 * cdiv(tiles, 8)));
-  const bool vec = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) &&
-                   ((uintptr_t)B % 16 == 0);
-#define GN_GEMM(AK, BK)                                                         \
-  if (vec)                                                                      \
-    gemm_f32_kernel<AK, BK, true><<<grid, dim3(F32Pass::T), 0, s>>>(g);         \
-  else                                                                          \
-    gemm_f32_kernel<AK, BK, false><<<grid, dim3(F32Pass::T), 0, s>>>(g)
-  if (a_kc && b_kc) {
-    GN_GEMM(true, true);
-  } else if (a_kc) {
-    GN_GEMM(true, false);
-  } else if (b_kc) {
-    GN_GEMM(false, true);
-  } else {
-    GN_GEMM(false, false);
-  }
-#undef GN_GEMM
-  GN_LAUNCH_CHECK();
-  return GN_OK;
-}
-
-gn_status launch_widen_bf16(int64_t rows, int64_t cols, const uint16_t* src, int64_t lds, float* dst,
-                            int64_t ldd, hipStream_t s) {
-  widen_bf16_kernel<<<dim3((unsigned)cdiv(rows * cols, 256)), dim3(256), 0, s>>>(rows, cols, src,
-                                                                                 lds, dst, ldd);
-  GN_LAUNCH_CHECK();
-  return GN_OK;
+size_t pass_split_ws_bytes(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_t r,
+                           int64_t rl) {
+  if (mode != GN_MODE_F32 || kind_x == GN_SKETCH_SRHT) return 0;
+  return pass_split(m, n, r, rl).bytes;
 }
 
 }  // namespace gn

@@ -6,7 +6,7 @@
 //   left products  (left = true) : T = R^T (k == r) or T = R2 (k < r),
 // the latter applied to a transposed view of the right-hand sides.
 // Blocked by 64 columns: off-diagonal updates with the FP64 GEMM, diagonal
-// blocks by one thread per row with the block of T and the 64 unknowns in LDS.
+// blocks by one thread per row with the 64 unknowns in registers.
 #include "gn_internal.h"
 
 namespace gn {
@@ -14,55 +14,66 @@ namespace {
 
 constexpr int TB = 64;
 
+// Diagonal block [jb, jb + w) of X T = B: one thread per row of X holding its w
+// unknowns in registers (indices are compile-time after unrolling), T's block
+// read from LDS by broadcast, stored column-major (Tt[j][t] = T(t, j)) so that
+// each unknown's dot product reads consecutive entries.  UPPER: T upper, forward
+// substitution; else lower, backward (each dot product in four interleaved
+// partial sums to shorten the dependency chain).  Columns at or beyond the kept size kk are
+// set to zero.  The host picks UPPER from (left, truncated, r_only); the gate
+// on the device kept rank makes the launch a no-op when it is the other case.
+template <bool UPPER>
 __global__ void __launch_bounds__(TB) trsm_diag(int64_t rows, int64_t r, const double* __restrict__ R,
                                                 const double* __restrict__ R2, int64_t ldt,
                                                 const int32_t* __restrict__ kdev, int want_trunc,
-                                                int left, int r_only, double* __restrict__ X,
+                                                int trans, int r_only, double* __restrict__ X,
                                                 int64_t rsx, int64_t csx, int64_t jb, int w) {
   const int32_t k = *kdev;
   const bool trunc = k < r;
   if (trunc != (want_trunc != 0)) return;
   const double* S = (trunc && !r_only) ? R2 : R;
-  // R, R2 are upper; their transposes lower
-  const bool trans = r_only ? (left != 0) : (left ? !trunc : trunc);
-  const bool upper = !trans;
   const int64_t kk = trunc ? k : r;
-  __shared__ double Ts[TB][TB + 1];
-  __shared__ double Xs[TB][TB + 1];  // Xs[col][row]
+  __shared__ __attribute__((aligned(16))) double Tt[TB][TB + 2];
   const int tid = threadIdx.x;
-  for (int e = tid; e < TB * TB; e += TB) {
-    const int t = e / TB, j = e - t * TB;
+  // consecutive threads read consecutive addresses of T's storage
+#pragma unroll 16
+  for (int q = 0; q < TB; ++q) {
+    const int a = q, b = tid;  // a: outer index of the stored row, b: within it
+    const int t = trans ? b : a, j = trans ? a : b;
     double v = 0.0;
     if (t < w && j < w) v = trans ? S[(jb + j) * ldt + jb + t] : S[(jb + t) * ldt + jb + j];
-    Ts[t][j] = v;
+    Tt[j][t] = v;
   }
   const int64_t row = (int64_t)blockIdx.x * TB + tid;
-  for (int j = 0; j < w; ++j) Xs[j][tid] = (row < rows) ? X[row * rsx + (jb + j) * csx] : 0.0;
+  const bool rok = row < rows;
+  double x[TB];
+#pragma unroll
+  for (int j = 0; j < TB; ++j) x[j] = (rok && j < w) ? X[row * rsx + (jb + j) * csx] : 0.0;
   __syncthreads();
-  if (upper) {
-    for (int j = 0; j < w; ++j) {
-      if (jb + j >= kk) {
-        Xs[j][tid] = 0.0;
-        continue;
-      }
-      double x = Xs[j][tid];
-      for (int t = 0; t < j; ++t) x = fma(-Xs[t][tid], Ts[t][j], x);
-      Xs[j][tid] = x / Ts[j][j];
+  if (UPPER) {
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < j; ++t) a[t & 3] = fma(x[t], Tt[j][t], a[t & 3]);
+      const double v = x[j] - ((a[0] + a[1]) + (a[2] + a[3]));
+      x[j] = (j < w && jb + j < kk) ? v / Tt[j][j] : 0.0;
     }
   } else {
-    for (int j = w - 1; j >= 0; --j) {
-      if (jb + j >= kk) {
-        Xs[j][tid] = 0.0;
-        continue;
-      }
-      double x = Xs[j][tid];
-      for (int t = j + 1; t < w; ++t)
-        if (jb + t < kk) x = fma(-Xs[t][tid], Ts[t][j], x);
-      Xs[j][tid] = x / Ts[j][j];
+#pragma unroll
+    for (int j = TB - 1; j >= 0; --j) {
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = j + 1; t < TB; ++t) a[t & 3] = fma(x[t], Tt[j][t], a[t & 3]);
+      const double v = x[j] - ((a[0] + a[1]) + (a[2] + a[3]));
+      x[j] = (j < w && jb + j < kk) ? v / Tt[j][j] : 0.0;
     }
   }
-  if (row < rows)
-    for (int j = 0; j < w; ++j) X[row * rsx + (jb + j) * csx] = Xs[j][tid];
+  if (rok) {
+#pragma unroll
+    for (int j = 0; j < TB; ++j)
+      if (j < w) X[row * rsx + (jb + j) * csx] = x[j];
+  }
 }
 
 }  // namespace
@@ -91,8 +102,12 @@ gn_status launch_trsm_core(int64_t rows, int64_t r, const double* R, const doubl
         GN_TRY(launch_dgemm(rows, w, t1 - t0, -1.0, xa, tm, 1.0, X + jb * csx, rsx, csx, nullptr,
                             false, s, k, r, want_trunc != 0));
       }
-      trsm_diag<<<grid, block, 0, s>>>(rows, r, R, R2, ldt, k, want_trunc, left ? 1 : 0,
-                                       r_only ? 1 : 0, X, rsx, csx, jb, w);
+      if (upper)
+        trsm_diag<true><<<grid, block, 0, s>>>(rows, r, R, R2, ldt, k, want_trunc, trans ? 1 : 0,
+                                               r_only ? 1 : 0, X, rsx, csx, jb, w);
+      else
+        trsm_diag<false><<<grid, block, 0, s>>>(rows, r, R, R2, ldt, k, want_trunc, trans ? 1 : 0,
+                                                r_only ? 1 : 0, X, rsx, csx, jb, w);
       GN_LAUNCH_CHECK();
     }
   }
