@@ -122,3 +122,22 @@ def test_truncated_core_pinv_matches_svd_definition():
     B = c.Q[:, :c.k] @ c.R[:c.k, :]
     assert np.linalg.norm(OGR.core_pinv(c) - np.linalg.pinv(B, rcond=1e-10)) <= \
         1e-10 * np.linalg.norm(np.linalg.pinv(B, rcond=1e-10))
+
+
+def test_all_entries_finite_differences_64x32():
+    """Every entry of dL/dA at 64 x 32, r = 4, l = 2 against central differences
+    with h = u^(1/3) ||A||_2 (the finite-difference check of the gradient
+    workload's recipe at its test size)."""
+    A, X, Y, Gb, _ = _problem(64, 32, 4, 2, np.arange(1, 33, dtype=float) ** -1.5, seed=21)
+    c = OG.gn(A, X, Y, 0.0).core
+    assert c.k == 4
+    dA = OGR.gn_backward(A, X, Y, c, Gb)
+    h = (2.0 ** -53) ** (1.0 / 3.0) * np.linalg.norm(A, 2)
+    fd = np.empty_like(A)
+    for i in range(A.shape[0]):
+        for j in range(A.shape[1]):
+            E = np.zeros_like(A)
+            E[i, j] = h
+            fd[i, j] = (OGR.loss_fixed_rank(A + E, X, Y, 4, Gb)
+                        - OGR.loss_fixed_rank(A - E, X, Y, 4, Gb)) / (2 * h)
+    assert np.linalg.norm(fd - dA) <= 1e-7 * np.linalg.norm(dA)
