@@ -12,7 +12,8 @@ the library's stream (torch's current stream) time each stage; `value` is the
 pass's algorithmic TFLOP/s.  After timing: the error ||A - A_hat||_F (tile-wise
 on the device), a bounded CPU-oracle baseline, and the BF16-vs-FP32 comparison
 on the 32768^2, r = 2000, l = 1000 shape (same matrix), the reverse mode on the
-8192 x 4096 gradient workload (forward, backward, backward with AX recomputed).
+8192 x 4096 gradient workload (forward, backward, backward with AX recomputed),
+and the 512-problem batched workload (persistent pass, whole solve, graph replay).
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -212,6 +213,58 @@ def grad_bench(gn, W, steps=5, warmup=2):
     return out
 
 
+def batch_bench(gn, W, steps=5, warmup=2, count=512):
+    """The batched workload: 512 FP32 problems (m ~ U[256,4096], n ~ U[128,m],
+    r ~ U[8,128], l = ceil(r/2), sigma_i = 10^(-8i/n), Gaussian X and Y) solved by
+    gn_batch_solve: the persistent pass launch alone, the whole solve, and the
+    whole solve replayed from a captured HIP graph."""
+    import torch
+    from paper_2009_11392_amd.autotune import build_batch_problems
+    probs = build_batch_problems(gn, W, count)
+    batch = gn.Batch(probs)
+    plan = batch.plan
+
+    def timeit(f):
+        for _ in range(warmup):
+            f()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(steps):
+            f()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / steps
+
+    t_pass = timeit(lambda: batch.solve(gn.C.GN_BATCH_PASS))
+    t_solve = timeit(lambda: batch.solve(gn.C.GN_BATCH_ALL))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.solve()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.solve()
+    t_graph = timeit(graph.replay)
+    ks = [c.rank() for c in batch.core]
+    flops, byts = plan.pass_flops, plan.pass_bytes
+    out = {"workload": f"batch{count}_f32", "problems": count, "pass_ms": t_pass,
+           "solve_ms": t_solve, "graph_solve_ms": t_graph,
+           "pass_algorithmic_flops": flops, "pass_algorithmic_bytes": byts,
+           "pass_tflops": flops / (t_pass / 1e3) / 1e12,
+           "pass_frac_of_fp32_peak": flops / (t_pass / 1e3) / 1e12 / PEAK["f32"],
+           "roofline_ms": max(flops / (PEAK["f32"] * 1e12), byts / (HBM_PEAK_GBS * 1e9)) * 1e3,
+           "work_items": plan.n_pass_items, "core_items": plan.n_core_items,
+           "persistent_workgroups": plan.grid, "tile_policy": list(plan.tile_policy),
+           "truncated_problems": sum(1 for k, p in zip(ks, batch.problems) if k < p.r),
+           "solves_per_sec": count * 1e3 / t_graph}
+    del batch, probs, graph
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(A_dev, w, target_s=12.0):
     """The FP64 oracle's sketch pass on a bounded block of rows of the same A."""
     import numpy as np
@@ -259,6 +312,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the reverse-mode measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--host-factors", action="store_true",
@@ -366,6 +420,13 @@ def main():
         log(f"forward {res['gradient']['forward_ms']:.3f} ms, backward "
             f"{res['gradient']['backward_ms']:.3f} ms "
             f"({res['gradient']['backward_tflops']:.1f} TFLOP/s)")
+
+    if not args.no_batch:
+        log("batched workload: 512 problems")
+        res["batched"] = batch_bench(gn, W)
+        log(f"batched pass {res['batched']['pass_ms']:.3f} ms "
+            f"({res['batched']['pass_tflops']:.1f} TFLOP/s), solve {res['batched']['solve_ms']:.3f} ms, "
+            f"graph {res['batched']['graph_solve_ms']:.3f} ms")
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

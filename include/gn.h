@@ -237,6 +237,74 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
                       const gn_core_out* core, void* dA, int64_t ldda, void* ws,
                       size_t ws_bytes, gn_stream_t stream);
 
+/* ---- Batches of independent problems (many GN solves of uneven m, n, r) ----
+ * One problem of a batch: the problem statement of gn_problem restricted to FP32
+ * mode with Gaussian X and Y (stream 1 / stream 2 of its own seed), its input A
+ * and its outputs.  All pointers are device pointers.
+ *   A   : float, m x n, row stride lda >= n, lda % 4 == 0, 16-byte aligned.
+ *   AX  : float, m x r (ldax >= r, ldax % 4 == 0, 16-byte aligned); YtA: float,
+ *         (r+l) x n (ldya >= n).
+ *   core: as for gn_core (Q1 (r+l) x r, R, Q2, R2 r x r, k, status).
+ * Limits: 1 <= r <= min(m, n), r + l <= 512. */
+typedef struct {
+  int64_t m, n, r, l;          /* l < 0 -> ceil(r/2) */
+  uint64_t seed;
+  double eps;                  /* as gn_problem (tau = eps * nu_X * nu_Y, Gaussian nu) */
+  const void* A;
+  int64_t lda;
+  void* AX;
+  int64_t ldax;
+  void* YtA;
+  int64_t ldya;
+  gn_core_out core;
+} gn_batch_problem;
+
+/* Filled by gn_batch_prepare (host); passed unchanged to gn_batch_solve. */
+typedef struct {
+  int32_t count;               /* problems */
+  int32_t n_pass_items;        /* (problem, product, tile) work items of the pass */
+  int32_t n_core_items;        /* work items of the core products Y^T (AX) */
+  int32_t grid;                /* persistent workgroups per launch */
+  int64_t max_m, max_n, max_r, max_rl;
+  size_t ws_bytes;             /* workspace the plan was laid out in */
+  size_t off_desc, off_items, off_qr, off_qr2, off_trunc, off_widen;
+  double pass_flops;           /* algorithmic FLOPs of all sketch passes */
+  double pass_bytes;           /* algorithmic bytes of all sketch passes */
+  int32_t tile_policy[4];      /* the tile configurations used (see gn_batch_prepare) */
+} gn_batch_plan;
+
+/* Workspace bytes for a batch (probs: host array of count problems). */
+gn_status gn_batch_workspace_size(const gn_batch_problem* probs /*host*/, int32_t count,
+                                  size_t* bytes /*host*/);
+
+/* Validates the batch, lays out the workspace, copies the device tables (problem
+ * descriptors, the work items of the pass, QR and truncation jobs) into ws and
+ * draws every problem's X and Y into it (FP32, the values gn_sketch would use).
+ * tile_policy (host, 4 entries, or NULL for the built-in choice) picks the
+ * 256-thread MFMA tile of each product: [0] Y^T A with r + l <= 64, [1] Y^T A
+ * with r + l > 64, [2] AX with r <= 64, [3] AX with r > 64; values 0 = 64 x 256,
+ * 1 = 128 x 128, 2 = 256 x 64 (output rows x columns).  Returns after the tables
+ * are copied (the call synchronizes with `stream`).  Independent of the values
+ * of A: one prepared workspace serves any number of gn_batch_solve calls. */
+gn_status gn_batch_prepare(const gn_batch_problem* probs /*host*/, int32_t count,
+                           const int32_t* tile_policy /*host or NULL*/,
+                           gn_batch_plan* plan /*host*/, void* ws, size_t ws_bytes,
+                           gn_stream_t stream);
+
+/* Stages of gn_batch_solve. */
+typedef enum { GN_BATCH_PASS = 1, GN_BATCH_CORE = 2, GN_BATCH_ALL = 3 } gn_batch_stage;
+
+/* The sketch passes and cores of every problem of a prepared batch (Algorithm 2.1
+ * steps 2-3 and Section 5.1.1 for each).  stages & GN_BATCH_PASS: one persistent
+ * launch over the pass's work items (AX, Y^T A of every problem); stages &
+ * GN_BATCH_CORE: one persistent launch over the core products C = Y^T (AX)
+ * (reading the AX of an earlier pass), then the batched FP64 Householder QR,
+ * truncation and second QR.  Every parameter is read from ws and `plan`: nothing
+ * is allocated, copied from the host or synchronized, so the call can be captured
+ * in a HIP graph and replayed. */
+gn_status gn_batch_solve(const gn_batch_plan* plan /*host*/, int32_t stages, void* ws,
+                         size_t ws_bytes, gn_stream_t stream);
+
 /* ||A - F G||_F^2 accumulated in FP64, tile by tile (no Gram-matrix shortcut),
  * written to *out_sumsq (device double).  A is m x n in `a_dtype` (for
  * GN_DT_BF16, A_scales as in gn_sketch, else NULL); F m x k (ld ldf), G k x n

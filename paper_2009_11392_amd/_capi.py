@@ -13,6 +13,7 @@ GN_OK, GN_ERR_ARG, GN_ERR_SHAPE, GN_ERR_DTYPE, GN_ERR_ALIGN = 0, 1, 2, 3, 4
 GN_ERR_WORKSPACE, GN_ERR_HIP, GN_ERR_NUMERIC, GN_ERR_UNSUPPORTED = 5, 6, 7, 8
 GN_SKETCH_GAUSSIAN, GN_SKETCH_SRHT, GN_SKETCH_USER = 0, 1, 2
 GN_MODE_F64, GN_MODE_F32, GN_MODE_BF16_BS = 0, 1, 2
+GN_BATCH_PASS, GN_BATCH_CORE, GN_BATCH_ALL = 1, 2, 3
 GN_DT_F64, GN_DT_F32, GN_DT_BF16 = 0, 1, 2
 (GN_OP_SKETCH, GN_OP_CORE, GN_OP_FACTORS, GN_OP_APPLY, GN_OP_RESIDUAL, GN_OP_SRHT,
  GN_OP_BACKWARD, GN_OP_MATERIALIZE) = range(8)
@@ -21,7 +22,7 @@ EXPORTED = (
     "gn_workspace_size", "gn_generate_gaussian", "gn_srht_generate", "gn_sketch_prepare",
     "gn_sketch_pass", "gn_sketch", "gn_core",
     "gn_factors", "gn_apply", "gn_backward", "gn_residual", "gn_quantize_bf16_bs",
-    "gn_status_string",
+    "gn_batch_workspace_size", "gn_batch_prepare", "gn_batch_solve", "gn_status_string",
     "gn_version",
 )
 
@@ -36,6 +37,22 @@ class GnProblem(ctypes.Structure):
 class GnCoreOut(ctypes.Structure):
     _fields_ = [("k", c_void_p), ("status", c_void_p), ("Q1", c_void_p), ("R", c_void_p),
                 ("Q2", c_void_p), ("R2", c_void_p)]
+
+
+class GnBatchProblem(ctypes.Structure):
+    _fields_ = [("m", c_int64), ("n", c_int64), ("r", c_int64), ("l", c_int64),
+                ("seed", c_uint64), ("eps", c_double), ("A", c_void_p), ("lda", c_int64),
+                ("AX", c_void_p), ("ldax", c_int64), ("YtA", c_void_p), ("ldya", c_int64),
+                ("core", GnCoreOut)]
+
+
+class GnBatchPlan(ctypes.Structure):
+    _fields_ = [("count", c_int32), ("n_pass_items", c_int32), ("n_core_items", c_int32),
+                ("grid", c_int32), ("max_m", c_int64), ("max_n", c_int64), ("max_r", c_int64),
+                ("max_rl", c_int64), ("ws_bytes", c_size_t), ("off_desc", c_size_t),
+                ("off_items", c_size_t), ("off_qr", c_size_t), ("off_qr2", c_size_t),
+                ("off_trunc", c_size_t), ("off_widen", c_size_t), ("pass_flops", c_double),
+                ("pass_bytes", c_double), ("tile_policy", c_int32 * 4)]
 
 
 class GNError(RuntimeError):
@@ -80,6 +97,11 @@ def lib(path: str = LIB_PATH):
     L.gn_backward.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                               c_void_p, c_int64, POINTER(GnCoreOut), c_void_p, c_int64, c_void_p,
                               c_size_t, c_void_p]
+    BP = POINTER(GnBatchProblem)
+    L.gn_batch_workspace_size.argtypes = [BP, c_int32, POINTER(c_size_t)]
+    L.gn_batch_prepare.argtypes = [BP, c_int32, c_void_p, POINTER(GnBatchPlan), c_void_p, c_size_t,
+                                   c_void_p]
+    L.gn_batch_solve.argtypes = [POINTER(GnBatchPlan), c_int32, c_void_p, c_size_t, c_void_p]
     L.gn_residual.argtypes = [c_int64, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
                               c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_size_t,
                               c_void_p]

@@ -150,21 +150,14 @@ struct F32Stage {
   }
 };
 
+// One BM x BN output tile at (i0, j0) of D = A B (the whole K range).
 template <class CF, bool A_KC, bool B_KC, bool VEC>
-__device__ void f32_tile_cfg(const GemmF32& g, int64_t local, char* smem) {
+__device__ void f32_tile_at(const GemmF32& g, int64_t i0, int64_t j0, char* smem) {
   constexpr int BM = CF::BM, BN = CF::BN, BK = CF::BK, MF = CF::MF;
   constexpr int LDA = CF::template ld<A_KC>(BM), LDB = CF::template ld<B_KC>(BN);
   typedef float accv __attribute__((ext_vector_type(CF::NACC)));
   float* sA = reinterpret_cast<float*>(smem);  // [2][BK * LDA]
   float* sB = sA + 2 * BK * LDA;               // [2][BK * LDB]
-  const int64_t tm_n = cdiv_d(g.M, BM), tn_n = cdiv_d(g.N, BN);
-  int64_t tm, tn;
-  if (g.inner_is_m) {
-    if (!xcd_tile(local, tm_n, tn_n, tm, tn)) return;
-  } else {
-    if (!xcd_tile(local, tn_n, tm_n, tn, tm)) return;
-  }
-  const int64_t i0 = tm * BM, j0 = tn * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % CF::WM, wn = wave / CF::WM;
   const int li = lane % MF, lk = lane / MF;
@@ -228,6 +221,19 @@ __device__ void f32_tile_cfg(const GemmF32& g, int64_t local, char* smem) {
         const int64_t col = j0 + wn * CF::TN + y * MF + li;
         if (row < g.M && col < g.N) g.D[row * g.ldd + col] = acc[x][y][v];
       }
+}
+
+// The tile of XCD-mapped index `local` (tiles of one XCD walk the inner index).
+template <class CF, bool A_KC, bool B_KC, bool VEC>
+__device__ void f32_tile_cfg(const GemmF32& g, int64_t local, char* smem) {
+  const int64_t tm_n = cdiv_d(g.M, CF::BM), tn_n = cdiv_d(g.N, CF::BN);
+  int64_t tm, tn;
+  if (g.inner_is_m) {
+    if (!xcd_tile(local, tm_n, tn_n, tm, tn)) return;
+  } else {
+    if (!xcd_tile(local, tn_n, tm_n, tn, tm)) return;
+  }
+  f32_tile_at<CF, A_KC, B_KC, VEC>(g, tm * CF::BM, tn * CF::BN, smem);
 }
 
 // The production FP32 configuration of the sketch pass: 256 x 256 tiles, 16 waves

@@ -114,6 +114,16 @@ gn_status launch_srht(uint64_t seed, int64_t npad, int64_t r, int8_t* signs, int
 gn_status launch_transpose(const void* in, int64_t rows, int64_t cols, int64_t ldi, int32_t dtype,
                            void* out, int64_t ldo, hipStream_t s);
 size_t srht_ws_bytes(int64_t npad);
+// Batched row-major Gaussian blocks (rows x cols from (0, 0), stream sid, seed)
+// in GN_DT_F64 or GN_DT_F32.
+struct GaussJob {
+  uint64_t seed;
+  int64_t sid;
+  int64_t rows, cols;
+  void* out;
+  int64_t ld;
+};
+gn_status launch_gaussian_batched(const GaussJob* jobs, int32_t count, int32_t dtype, hipStream_t s);
 
 // pass.hip : the sketch pass, AX (m x r) and Y^T A (rl x n) from one launch in
 // FP32 and BF16 modes.  Xt is the transposed Gaussian or user sketch (r x n,
@@ -203,6 +213,40 @@ size_t residual_ws_bytes(int64_t M, int64_t N);
 gn_status launch_qr(int64_t M, int64_t N, double* Aq, int64_t lda, double* Q, int64_t ldq,
                     double* R, int64_t ldr, double* ws, const int32_t* gate_k, hipStream_t s);
 size_t qr_ws_bytes(int64_t M, int64_t N);
+
+// Batched QR: job z factors C (M x N, M <= 512) in place, writes Q, R (R_ii >=
+// 0) and uses T (qr_batch_t_bytes(N)) and Wp (qr_batch_wp_bytes(M, N)) as
+// scratch; a job is skipped unless !gate || *gate < gate_n.
+struct QrJob {
+  int64_t M, N;
+  double* C;
+  int64_t ldc;
+  double* Q;
+  int64_t ldq;
+  double* R;
+  int64_t ldr;
+  double* T;
+  double* Wp;
+  const int32_t* gate;
+  int64_t gate_n;
+};
+size_t qr_batch_t_bytes(int64_t N);
+size_t qr_batch_wp_bytes(int64_t M, int64_t N);
+gn_status launch_qr_batched(const QrJob* jobs, int32_t count, int64_t maxM, int64_t maxN,
+                            hipStream_t s);
+// Batched truncation scan (k, status) and Z = [R[:k, :]^T, 0] (when k < r).
+struct TruncJob {
+  int64_t r;
+  const double* R;
+  int64_t ldr;
+  double tau;
+  int32_t* k;
+  int32_t* status;
+  double* Z;
+  int64_t ldz;
+};
+gn_status launch_truncate_batched(const TruncJob* jobs, int32_t count, int64_t maxr,
+                                  hipStream_t s);
 // k = prefix count of |R_ii| >= tau; status flags; builds R[:k,:]^T (r x r,
 // zero beyond column k) in Z.
 gn_status launch_truncate(int64_t r, const double* R, int64_t ldr, double tau, int32_t* k,

@@ -179,10 +179,8 @@ __device__ __forceinline__ void qr_columns(std::integer_sequence<int, Cs...>, in
 }
 
 template <int RPT, int NB>
-__global__ void __launch_bounds__(QP_T) qr_panel(double* __restrict__ C, int64_t ldc, int64_t M,
-                                                 int64_t j0, int nbw, double* __restrict__ Tout,
-                                                 const int32_t* gate, int64_t gate_n) {
-  if (gate && *gate >= gate_n) return;
+__device__ __forceinline__ void qr_panel_body(double* __restrict__ C, int64_t ldc, int64_t M,
+                                              int64_t j0, int nbw, double* __restrict__ Tout) {
   __shared__ double part[2][QP_WAVES][NB];
   __shared__ double prow[2][NB];
   __shared__ double T[NB][NB + 1];
@@ -212,6 +210,24 @@ __global__ void __launch_bounds__(QP_T) qr_panel(double* __restrict__ C, int64_t
   if (t < NB * NB) Tout[(t / NB) * QR_NB + (t % NB)] = T[t / NB][t % NB];  // stride QR_NB
 }
 
+template <int RPT, int NB>
+__global__ void __launch_bounds__(QP_T) qr_panel(double* __restrict__ C, int64_t ldc, int64_t M,
+                                                 int64_t j0, int nbw, double* __restrict__ Tout,
+                                                 const int32_t* gate, int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  qr_panel_body<RPT, NB>(C, ldc, M, j0, nbw, Tout);
+}
+
+// Batched: job blockIdx.z, panel of width 16 at column j0 (every job has at most
+// QP_T rows, so one row per thread).
+__global__ void __launch_bounds__(QP_T) qr_panel_b(const QrJob* __restrict__ jobs, int64_t j0) {
+  const QrJob J = jobs[blockIdx.z];
+  if (J.gate && *J.gate >= J.gate_n) return;
+  if (j0 >= J.N) return;
+  const int nbw = (int)((J.N - j0 < QR_NB) ? (J.N - j0) : QR_NB);
+  qr_panel_body<1, QR_NB>(J.C, J.ldc, J.M, j0, nbw, J.T + (j0 / QR_NB) * QR_NB * QR_NB);
+}
+
 // Block-reflector update of D[j0 + i, col0 + j] (0 <= i < M - j0, 0 <= j < ncols)
 // by the panel at (j0, j0) of Cp (width nbw, unit-lower reflectors below the
 // diagonal).  Stage 1: Wp[chunk][c][j] = sum over the chunk's rows of V[i][c] D[i][j].
@@ -229,18 +245,18 @@ __device__ __forceinline__ void qr_stage_v(double (*sV)[QR_NB + 1], const double
   }
 }
 
-__global__ void __launch_bounds__(256) qr_upd_w(const double* __restrict__ Cp, int64_t ldc,
-                                                int64_t M, int64_t j0, int nbw,
-                                                const double* __restrict__ D, int64_t ldd,
-                                                int64_t col0, int64_t ncols, double* __restrict__ Wp,
-                                                const int32_t* gate, int64_t gate_n) {
-  if (gate && *gate >= gate_n) return;
+__device__ __forceinline__ void qr_upd_w_body(const double* __restrict__ Cp, int64_t ldc,
+                                              int64_t M, int64_t j0, int nbw,
+                                              const double* __restrict__ D, int64_t ldd,
+                                              int64_t col0, int64_t ncols,
+                                              double* __restrict__ Wp, int64_t chunk,
+                                              int64_t grp) {
   __shared__ double sV[QU_CH][QR_NB + 1];
   __shared__ double red[4][QR_NB][QU_CG + 1];
   const int tid = threadIdx.x, j = tid & 63, wq = tid >> 6;
   const int64_t Mp = M - j0;
-  const int64_t r0 = (int64_t)blockIdx.x * QU_CH;
-  const int64_t jg = (int64_t)blockIdx.y * QU_CG + j;
+  const int64_t r0 = chunk * QU_CH;
+  const int64_t jg = grp * QU_CG + j;
   const bool jok = jg < ncols;
   double d[QU_CH / 4];
 #pragma unroll
@@ -265,27 +281,71 @@ __global__ void __launch_bounds__(256) qr_upd_w(const double* __restrict__ Cp, i
   for (int i = 0; i < 4; ++i) {
     const int c = 4 * wq + i;
     const double s = ((red[0][c][j] + red[1][c][j]) + red[2][c][j]) + red[3][c][j];
-    if (jok) Wp[((int64_t)blockIdx.x * QR_NB + c) * ncols + jg] = s;
+    if (jok) Wp[(chunk * QR_NB + c) * ncols + jg] = s;
   }
+}
+
+__global__ void __launch_bounds__(256) qr_upd_w(const double* __restrict__ Cp, int64_t ldc,
+                                                int64_t M, int64_t j0, int nbw,
+                                                const double* __restrict__ D, int64_t ldd,
+                                                int64_t col0, int64_t ncols, double* __restrict__ Wp,
+                                                const int32_t* gate, int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  qr_upd_w_body(Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Wp, blockIdx.x, blockIdx.y);
+}
+
+// Batched update target of job J for the panel at j0: the trailing columns of C
+// (phase 0) or the columns j0.. of Q (phase 1).  Returns false when this
+// workgroup has nothing to do.
+struct UpdTarget {
+  double* D;
+  int64_t ldd, col0, ncols, nch;
+  int nbw;
+};
+__device__ __forceinline__ bool qr_upd_target(const QrJob& J, int64_t j0, int phase,
+                                              UpdTarget& u) {
+  if (J.gate && *J.gate >= J.gate_n) return false;
+  if (j0 >= J.N) return false;
+  u.nbw = (int)((J.N - j0 < QR_NB) ? (J.N - j0) : QR_NB);
+  u.nch = (J.M - j0 + QU_CH - 1) / QU_CH;
+  if (phase == 0) {
+    u.D = J.C;
+    u.ldd = J.ldc;
+    u.col0 = j0 + u.nbw;
+  } else {
+    u.D = J.Q;
+    u.ldd = J.ldq;
+    u.col0 = j0;
+  }
+  u.ncols = J.N - u.col0;
+  return u.ncols > 0 && (int64_t)blockIdx.x < u.nch && (int64_t)blockIdx.y * QU_CG < u.ncols;
+}
+
+__global__ void __launch_bounds__(256) qr_upd_w_b(const QrJob* __restrict__ jobs, int64_t j0,
+                                                  int phase) {
+  const QrJob J = jobs[blockIdx.z];
+  UpdTarget u;
+  if (!qr_upd_target(J, j0, phase, u)) return;
+  qr_upd_w_body(J.C, J.ldc, J.M, j0, u.nbw, u.D, u.ldd, u.col0, u.ncols, J.Wp, blockIdx.x,
+                blockIdx.y);
 }
 
 // Stage 2: W = sum over chunks of Wp (chunk order), W <- Top W (Top = T^T when
 // trans, else T), D -= V W over this workgroup's chunk of rows.
-__global__ void __launch_bounds__(256) qr_upd_apply(const double* __restrict__ Cp, int64_t ldc,
-                                                    int64_t M, int64_t j0, int nbw,
-                                                    double* __restrict__ D, int64_t ldd,
-                                                    int64_t col0, int64_t ncols,
-                                                    const double* __restrict__ Wp, int nchunks,
-                                                    const double* __restrict__ T, int trans,
-                                                    const int32_t* gate, int64_t gate_n) {
-  if (gate && *gate >= gate_n) return;
+__device__ __forceinline__ void qr_upd_apply_body(const double* __restrict__ Cp, int64_t ldc,
+                                                  int64_t M, int64_t j0, int nbw,
+                                                  double* __restrict__ D, int64_t ldd,
+                                                  int64_t col0, int64_t ncols,
+                                                  const double* __restrict__ Wp, int nchunks,
+                                                  const double* __restrict__ T, int trans,
+                                                  int64_t chunk, int64_t grp) {
   __shared__ double sV[QU_CH][QR_NB + 1];
   __shared__ double W[QR_NB][QU_CG + 1];
   __shared__ double sT[QR_NB][QR_NB + 1];
   const int tid = threadIdx.x, j = tid & 63, wq = tid >> 6;
   const int64_t Mp = M - j0;
-  const int64_t r0 = (int64_t)blockIdx.x * QU_CH;
-  const int64_t jg = (int64_t)blockIdx.y * QU_CG + j;
+  const int64_t r0 = chunk * QU_CH;
+  const int64_t jg = grp * QU_CG + j;
   const bool jok = jg < ncols;
   double d[QU_CH / 4];
 #pragma unroll
@@ -337,21 +397,52 @@ __global__ void __launch_bounds__(256) qr_upd_apply(const double* __restrict__ C
   }
 }
 
-__global__ void __launch_bounds__(256) qr_init_q(double* Q, int64_t ldq, int64_t M, int64_t N,
-                                                 const int32_t* gate, int64_t gate_n) {
+__global__ void __launch_bounds__(256) qr_upd_apply(const double* __restrict__ Cp, int64_t ldc,
+                                                    int64_t M, int64_t j0, int nbw,
+                                                    double* __restrict__ D, int64_t ldd,
+                                                    int64_t col0, int64_t ncols,
+                                                    const double* __restrict__ Wp, int nchunks,
+                                                    const double* __restrict__ T, int trans,
+                                                    const int32_t* gate, int64_t gate_n) {
   if (gate && *gate >= gate_n) return;
+  qr_upd_apply_body(Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Wp, nchunks, T, trans, blockIdx.x,
+                    blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) qr_upd_apply_b(const QrJob* __restrict__ jobs, int64_t j0,
+                                                      int phase) {
+  const QrJob J = jobs[blockIdx.z];
+  UpdTarget u;
+  if (!qr_upd_target(J, j0, phase, u)) return;
+  qr_upd_apply_body(J.C, J.ldc, J.M, j0, u.nbw, u.D, u.ldd, u.col0, u.ncols, J.Wp, (int)u.nch,
+                    J.T + (j0 / QR_NB) * QR_NB * QR_NB, phase == 0 ? 1 : 0, blockIdx.x,
+                    blockIdx.y);
+}
+
+__device__ __forceinline__ void qr_init_q_body(double* Q, int64_t ldq, int64_t M, int64_t N) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= M * N) return;
   const int64_t i = e / N, j = e - i * N;
   Q[i * ldq + j] = (i == j) ? 1.0 : 0.0;
 }
 
+__global__ void __launch_bounds__(256) qr_init_q(double* Q, int64_t ldq, int64_t M, int64_t N,
+                                                 const int32_t* gate, int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  qr_init_q_body(Q, ldq, M, N);
+}
+
+__global__ void __launch_bounds__(256) qr_init_q_b(const QrJob* __restrict__ jobs) {
+  const QrJob J = jobs[blockIdx.z];
+  if (J.gate && *J.gate >= J.gate_n) return;
+  qr_init_q_body(J.Q, J.ldq, J.M, J.N);
+}
+
 // R_ii >= 0: flip row i of R and column i of Q where the Householder diagonal is
 // negative; copy the upper triangle of the factored matrix into R.
-__global__ void __launch_bounds__(256) qr_signfix(const double* C, int64_t ldc, double* Q,
-                                                  int64_t ldq, double* R, int64_t ldr, int64_t M,
-                                                  int64_t N, const int32_t* gate, int64_t gate_n) {
-  if (gate && *gate >= gate_n) return;
+__device__ __forceinline__ void qr_signfix_body(const double* C, int64_t ldc, double* Q,
+                                                int64_t ldq, double* R, int64_t ldr, int64_t M,
+                                                int64_t N) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < M * N) {
     const int64_t i = e / N, j = e - i * N;
@@ -364,10 +455,23 @@ __global__ void __launch_bounds__(256) qr_signfix(const double* C, int64_t ldc, 
   }
 }
 
+__global__ void __launch_bounds__(256) qr_signfix(const double* C, int64_t ldc, double* Q,
+                                                  int64_t ldq, double* R, int64_t ldr, int64_t M,
+                                                  int64_t N, const int32_t* gate, int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  qr_signfix_body(C, ldc, Q, ldq, R, ldr, M, N);
+}
+
+__global__ void __launch_bounds__(256) qr_signfix_b(const QrJob* __restrict__ jobs) {
+  const QrJob J = jobs[blockIdx.z];
+  if (J.gate && *J.gate >= J.gate_n) return;
+  qr_signfix_body(J.C, J.ldc, J.Q, J.ldq, J.R, J.ldr, J.M, J.N);
+}
+
 // Kept rank: k = first i whose diagonal fails the keep test (|R_ii| >= tau, or
 // |R_ii| > 0 when tau <= 0; non-finite always fails); status flags.
-__global__ void __launch_bounds__(256) trunc_scan(int64_t r, const double* R, int64_t ldr, double tau,
-                                                  int32_t* kout, int32_t* status) {
+__device__ __forceinline__ void trunc_scan_body(int64_t r, const double* R, int64_t ldr,
+                                                double tau, int32_t* kout, int32_t* status) {
   __shared__ int64_t s_first[256];
   __shared__ int s_flag[256];
   int64_t first = r;
@@ -412,16 +516,36 @@ __global__ void __launch_bounds__(256) trunc_scan(int64_t r, const double* R, in
   }
 }
 
+__global__ void __launch_bounds__(256) trunc_scan(int64_t r, const double* R, int64_t ldr, double tau,
+                                                  int32_t* kout, int32_t* status) {
+  trunc_scan_body(r, R, ldr, tau, kout, status);
+}
+
+__global__ void __launch_bounds__(256) trunc_scan_b(const TruncJob* __restrict__ jobs) {
+  const TruncJob J = jobs[blockIdx.z];
+  trunc_scan_body(J.r, J.R, J.ldr, J.tau, J.k, J.status);
+}
+
 // Z (r x r) = [R[:k, :]^T, 0]: the matrix whose leading k columns are factored
 // by the second QR (Section 5.1.1).  Runs only when k < r.
-__global__ void __launch_bounds__(256) build_z(int64_t r, const double* R, int64_t ldr,
-                                               const int32_t* kdev, double* Z, int64_t ldz) {
+__device__ __forceinline__ void build_z_body(int64_t r, const double* R, int64_t ldr,
+                                             const int32_t* kdev, double* Z, int64_t ldz) {
   const int32_t k = *kdev;
   if (k >= r) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= r * r) return;
   const int64_t j = e / r, i = e - j * r;  // Z[j][i] = R[i][j] for i < k
   Z[j * ldz + i] = (i < k) ? R[i * ldr + j] : 0.0;
+}
+
+__global__ void __launch_bounds__(256) build_z(int64_t r, const double* R, int64_t ldr,
+                                               const int32_t* kdev, double* Z, int64_t ldz) {
+  build_z_body(r, R, ldr, kdev, Z, ldz);
+}
+
+__global__ void __launch_bounds__(256) build_z_b(const TruncJob* __restrict__ jobs) {
+  const TruncJob J = jobs[blockIdx.z];
+  build_z_body(J.r, J.R, J.ldr, J.k, J.Z, J.ldz);
 }
 
 // Panel width and rows per thread for the panel starting at j0 (Mp rows).
@@ -523,6 +647,52 @@ gn_status launch_truncate(int64_t r, const double* R, int64_t ldr, double tau, i
   trunc_scan<<<dim3(1), dim3(256), 0, s>>>(r, R, ldr, tau, k, status);
   GN_LAUNCH_CHECK();
   build_z<<<dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, s>>>(r, R, ldr, k, Z, ldz);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+size_t qr_batch_t_bytes(int64_t N) { return qr_t_bytes(N); }
+size_t qr_batch_wp_bytes(int64_t M, int64_t N) {
+  return align_up((size_t)cdiv(M, QU_CH) * QR_NB * N * sizeof(double));
+}
+
+gn_status launch_qr_batched(const QrJob* jobs, int32_t count, int64_t maxM, int64_t maxN,
+                            hipStream_t s) {
+  if (count <= 0 || maxN <= 0) return GN_OK;
+  if (maxM > QP_T) return GN_ERR_UNSUPPORTED;
+  const unsigned z = (unsigned)count;
+  const int64_t np = cdiv(maxN, QR_NB);
+  for (int64_t pi = 0; pi < np; ++pi) {
+    const int64_t j0 = pi * QR_NB;
+    qr_panel_b<<<dim3(1, 1, z), dim3(QP_T), 0, s>>>(jobs, j0);
+    GN_LAUNCH_CHECK();
+    const dim3 g((unsigned)cdiv(maxM - j0, QU_CH), (unsigned)cdiv(maxN - j0, QU_CG), z);
+    qr_upd_w_b<<<g, dim3(256), 0, s>>>(jobs, j0, 0);
+    GN_LAUNCH_CHECK();
+    qr_upd_apply_b<<<g, dim3(256), 0, s>>>(jobs, j0, 0);
+    GN_LAUNCH_CHECK();
+  }
+  qr_init_q_b<<<dim3((unsigned)cdiv(maxM * maxN, 256), 1, z), dim3(256), 0, s>>>(jobs);
+  GN_LAUNCH_CHECK();
+  for (int64_t pi = np - 1; pi >= 0; --pi) {
+    const int64_t j0 = pi * QR_NB;
+    const dim3 g((unsigned)cdiv(maxM - j0, QU_CH), (unsigned)cdiv(maxN - j0, QU_CG), z);
+    qr_upd_w_b<<<g, dim3(256), 0, s>>>(jobs, j0, 1);
+    GN_LAUNCH_CHECK();
+    qr_upd_apply_b<<<g, dim3(256), 0, s>>>(jobs, j0, 1);
+    GN_LAUNCH_CHECK();
+  }
+  qr_signfix_b<<<dim3((unsigned)cdiv(maxM * maxN, 256), 1, z), dim3(256), 0, s>>>(jobs);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+gn_status launch_truncate_batched(const TruncJob* jobs, int32_t count, int64_t maxr,
+                                  hipStream_t s) {
+  if (count <= 0) return GN_OK;
+  trunc_scan_b<<<dim3(1, 1, (unsigned)count), dim3(256), 0, s>>>(jobs);
+  GN_LAUNCH_CHECK();
+  build_z_b<<<dim3((unsigned)cdiv(maxr * maxr, 256), 1, (unsigned)count), dim3(256), 0, s>>>(jobs);
   GN_LAUNCH_CHECK();
   return GN_OK;
 }

@@ -60,6 +60,29 @@ __global__ void __launch_bounds__(256) gaussian_transposed(uint32_t k0, uint32_t
   }
 }
 
+// Batched row-major Gaussian blocks: job blockIdx.z, grid-stride over its
+// rows x column pairs (counter layout as gaussian_rowmajor with row0 = col0 = 0).
+template <int DT>
+__global__ void __launch_bounds__(256) gaussian_rowmajor_b(const GaussJob* __restrict__ jobs) {
+  const GaussJob J = jobs[blockIdx.z];
+  const uint32_t k0 = (uint32_t)(J.seed & 0xffffffffu), k1 = (uint32_t)(J.seed >> 32);
+  const int64_t npairs = (J.cols + 1) >> 1;
+  const int64_t total = J.rows * npairs;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t / npairs;
+    const int64_t p = t - i * npairs;
+    const U4 w = philox10(U4{(uint32_t)i, (uint32_t)p, (uint32_t)J.sid, 0u}, k0, k1);
+    double z[2];
+    normal_pair(w, z[0], z[1]);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int64_t j = 2 * p + e;
+      if (j < J.cols) store_elem<DT>(J.out, i * J.ld + j, z[e]);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) srht_signs_keys(uint32_t k0, uint32_t k1, int64_t npad,
                                                        int8_t* signs, uint64_t* keys) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -195,6 +218,19 @@ gn_status launch_gaussian(uint64_t seed, int32_t sid, int64_t row0, int64_t col0
 }
 
 // keys (npad u64) | candidate keys (npad u64) | candidate indices (npad i32)
+gn_status launch_gaussian_batched(const GaussJob* jobs, int32_t count, int32_t dtype, hipStream_t s) {
+  if (count <= 0) return GN_OK;
+  const dim3 grid(256, 1, (unsigned)count), block(256);
+  if (dtype == GN_DT_F64)
+    gaussian_rowmajor_b<GN_DT_F64><<<grid, block, 0, s>>>(jobs);
+  else if (dtype == GN_DT_F32)
+    gaussian_rowmajor_b<GN_DT_F32><<<grid, block, 0, s>>>(jobs);
+  else
+    return GN_ERR_DTYPE;
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
 size_t srht_ws_bytes(int64_t npad) {
   return 2 * align_up((size_t)npad * sizeof(uint64_t)) + align_up((size_t)npad * sizeof(int32_t));
 }

@@ -307,3 +307,52 @@ class GNApprox(torch.autograd.Function):
 def gn_approx(A: torch.Tensor, p: Problem, store_ax: bool = True) -> torch.Tensor:
     """Differentiable A_hat (see GNApprox)."""
     return GNApprox.apply(A, p, store_ax)
+
+
+class Batch:
+    """Many independent FP32 problems (Gaussian X and Y) solved by gn_batch_solve.
+
+    problems: list of (Problem, A) with Problem.mode "f32"; A float32 (m x n, row
+    stride a multiple of 4).  Allocates AX, YtA and the core outputs of every
+    problem and the workspace, then calls gn_batch_prepare.  solve() enqueues the
+    passes and cores of all problems (graph-capturable).
+    """
+
+    def __init__(self, problems, tile_policy=None, device="cuda"):
+        if tile_policy is None:   # the autotuner's table, when one has been written
+            from .autotune import load_policy
+            tile_policy = load_policy("batch_f32")
+        self.problems = [p for p, _ in problems]
+        self.A = [a for _, a in problems]
+        self.AX, self.YtA, self.core = [], [], []
+        arr = (C.GnBatchProblem * len(problems))()
+        for i, (p, A) in enumerate(problems):
+            if p.mode != "f32" or p.kind_x != "gaussian" or p.kind_y != "gaussian":
+                raise ValueError("batches are FP32 with Gaussian X and Y")
+            _need_cuda(A)
+            if A.dtype != torch.float32:
+                raise ValueError("A must be float32")
+            ldax = (p.r + 3) // 4 * 4
+            AX = torch.empty(p.m, ldax, dtype=torch.float32, device=device)[:, :p.r]
+            YtA = torch.empty(p.rl, p.n, dtype=torch.float32, device=device)
+            core = new_core(p, device)
+            self.AX.append(AX)
+            self.YtA.append(YtA)
+            self.core.append(core)
+            arr[i] = C.GnBatchProblem(p.m, p.n, p.r, p.l, p.seed & ((1 << 64) - 1), p.eps,
+                                      A.data_ptr(), A.stride(0), AX.data_ptr(), AX.stride(0),
+                                      YtA.data_ptr(), YtA.stride(0), core.c())
+        self._arr = arr
+        nbytes = ctypes.c_size_t(0)
+        C.check(C.lib().gn_batch_workspace_size(arr, len(problems), ctypes.byref(nbytes)),
+                "gn_batch_workspace_size")
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=device)
+        self.plan = C.GnBatchPlan()
+        pol = None if tile_policy is None else (ctypes.c_int32 * 4)(*tile_policy)
+        C.check(C.lib().gn_batch_prepare(arr, len(problems), pol, ctypes.byref(self.plan),
+                                         _ptr(self.ws), self.ws.numel(), _stream()),
+                "gn_batch_prepare")
+
+    def solve(self, stages: int = C.GN_BATCH_ALL):
+        C.check(C.lib().gn_batch_solve(ctypes.byref(self.plan), stages, _ptr(self.ws),
+                                       self.ws.numel(), _stream()), "gn_batch_solve")

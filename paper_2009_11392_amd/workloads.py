@@ -92,6 +92,55 @@ GRAD8K = Workload("grad_8192x4096_f32", 8192, 4096, 256, 128, "gaussian", "gauss
 ALL = {w.name: w for w in (SMALL, SRHT32K, BF16_32K, F32_32K, GRAD8K)}
 
 
+@dataclass(frozen=True)
+class BatchSpec:
+    """One problem of the batched workload: sizes, sketch seed, input seed."""
+    m: int
+    n: int
+    r: int
+    l: int
+    seed: int
+    input_seed: int
+
+    def sigma(self) -> np.ndarray:
+        """sigma_i = 10^(-8 i / n), i = 1 .. n."""
+        i = np.arange(1, self.n + 1, dtype=np.float64)
+        return 10.0 ** (-8.0 * i / self.n)
+
+
+def batch_specs(count: int = 512, seed: int = 4, m_range=(256, 4096), r_range=(8, 128)):
+    """The batched workload: m ~ U[m_range], n ~ U[128, m], r ~ U[r_range] (integers,
+    inclusive), l = ceil(r/2); sketch seed of problem p = (seed << 32) + p."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for p in range(count):
+        m = int(rng.integers(m_range[0], m_range[1] + 1))
+        n = int(rng.integers(128, m + 1))
+        r = int(rng.integers(r_range[0], r_range[1] + 1))
+        out.append(BatchSpec(m, n, r, (r + 1) // 2, (seed << 32) + p, 40000 + p))
+    return out
+
+
+def batch_host_matrix(b: BatchSpec) -> np.ndarray:
+    return spectrum_matrix(b.m, b.n, b.sigma(), b.input_seed)
+
+
+def batch_device_matrix(b: BatchSpec, device="cuda"):
+    """A of problem b built on the device in FP32 (torch generator seeded with the
+    input seed; U, V Q factors of Gaussians), row stride a multiple of 4."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(b.input_seed)
+    k = b.n
+    sig = torch.tensor(b.sigma(), dtype=torch.float64, device=device)
+    U, _ = torch.linalg.qr(torch.randn(b.m, k, generator=g, device=device, dtype=torch.float64))
+    V, _ = torch.linalg.qr(torch.randn(b.n, k, generator=g, device=device, dtype=torch.float64))
+    ld = (b.n + 3) // 4 * 4
+    A = torch.zeros(b.m, ld, dtype=torch.float32, device=device)
+    A[:, :b.n] = ((U * sig[None, :]) @ V.T).to(torch.float32)
+    return A[:, :b.n]
+
+
 # ----------------------------------------------------------------------------- host (NumPy)
 def _orth_host(rng: np.random.Generator, rows: int, k: int) -> np.ndarray:
     q, _ = np.linalg.qr(rng.standard_normal((rows, k)))

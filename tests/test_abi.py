@@ -135,3 +135,38 @@ def test_entry_points_reject_before_enqueue(lib):
     assert lib.gn_quantize_bf16_bs(10, 10, fake, 10, 2, fake, 10, fake, null) == C.GN_ERR_DTYPE
     assert lib.gn_generate_gaussian(1, 1, 0, 0, 4, 4, 5, 0, fake, 4, null) == C.GN_ERR_ARG
     assert lib.gn_srht_generate(1, 100, 200, fake, fake, fake, 1 << 20, null) == C.GN_ERR_SHAPE
+
+
+def test_batch_validation_rejects_before_enqueue(lib):
+    fake = 1 << 20
+    core = C.GnCoreOut(fake, fake, fake, fake, fake, fake)
+
+    def arr(**kw):
+        base = dict(m=300, n=200, r=20, l=10, seed=1, eps=1e-7, A=fake, lda=200, AX=fake, ldax=20,
+                    YtA=fake, ldya=200, core=core)
+        base.update(kw)
+        a = (C.GnBatchProblem * 2)()
+        a[0] = C.GnBatchProblem(**base)
+        a[1] = C.GnBatchProblem(**dict(base, m=base["m"] + 17))
+        return a
+
+    nb = ctypes.c_size_t(0)
+    assert lib.gn_batch_workspace_size(arr(), 2, ctypes.byref(nb)) == C.GN_OK and nb.value > 0
+    assert lib.gn_batch_workspace_size(arr(), 0, ctypes.byref(nb)) == C.GN_ERR_ARG
+    assert lib.gn_batch_workspace_size(arr(r=201), 2, ctypes.byref(nb)) == C.GN_ERR_SHAPE
+    assert lib.gn_batch_workspace_size(arr(lda=201), 2, ctypes.byref(nb)) == C.GN_ERR_ALIGN
+    assert lib.gn_batch_workspace_size(arr(ldax=21), 2, ctypes.byref(nb)) == C.GN_ERR_ALIGN
+    assert lib.gn_batch_workspace_size(arr(m=600, n=600, r=400, l=200, lda=600, ldya=600, ldax=400), 2,
+                                       ctypes.byref(nb)) == C.GN_ERR_UNSUPPORTED
+    assert lib.gn_batch_workspace_size(arr(A=0), 2, ctypes.byref(nb)) == C.GN_ERR_ARG
+    plan = C.GnBatchPlan()
+    # workspace too small / bad tile policy: rejected before any copy or launch
+    assert lib.gn_batch_prepare(arr(), 2, None, ctypes.byref(plan), ctypes.c_void_p(fake), 64,
+                                None) == C.GN_ERR_WORKSPACE
+    bad = (ctypes.c_int32 * 4)(0, 1, 3, 1)
+    assert lib.gn_batch_prepare(arr(), 2, bad, ctypes.byref(plan), ctypes.c_void_p(fake),
+                                nb.value, None) == C.GN_ERR_ARG
+    assert lib.gn_batch_solve(ctypes.byref(C.GnBatchPlan()), 3, ctypes.c_void_p(fake), 1 << 30,
+                              None) == C.GN_ERR_ARG
+    assert lib.gn_batch_solve(ctypes.byref(C.GnBatchPlan()), 0, ctypes.c_void_p(fake), 1 << 30,
+                              None) == C.GN_ERR_ARG
