@@ -271,6 +271,7 @@ typedef struct {
   double pass_flops;           /* algorithmic FLOPs of all sketch passes */
   double pass_bytes;           /* algorithmic bytes of all sketch passes */
   int32_t tile_policy[4];      /* the tile configurations used (see gn_batch_prepare) */
+  int32_t pass_threads;        /* workgroup size of the pass launch (256 or 512) */
 } gn_batch_plan;
 
 /* Workspace bytes for a batch (probs: host array of count problems). */
@@ -280,10 +281,12 @@ gn_status gn_batch_workspace_size(const gn_batch_problem* probs /*host*/, int32_
 /* Validates the batch, lays out the workspace, copies the device tables (problem
  * descriptors, the work items of the pass, QR and truncation jobs) into ws and
  * draws every problem's X and Y into it (FP32, the values gn_sketch would use).
- * tile_policy (host, 4 entries, or NULL for the built-in choice) picks the
- * 256-thread MFMA tile of each product: [0] Y^T A with r + l <= 64, [1] Y^T A
- * with r + l > 64, [2] AX with r <= 64, [3] AX with r > 64; values 0 = 64 x 256,
- * 1 = 128 x 128, 2 = 256 x 64 (output rows x columns).  Returns after the tables
+ * tile_policy (host, 4 entries, or NULL for the built-in choice) picks the MFMA
+ * tile of each product: [0] Y^T A with r + l <= 64, [1] Y^T A with r + l > 64,
+ * [2] AX with r <= 64, [3] AX with r > 64; values (output rows x columns) with
+ * 256-thread workgroups 0 = 64 x 256, 1 = 128 x 128, 2 = 256 x 64, or with
+ * 512-thread workgroups 3 = 128 x 256, 4 = 256 x 128;
+ * all four from the same workgroup size (GN_ERR_ARG otherwise).  Returns after the tables
  * are copied (the call synchronizes with `stream`).  Independent of the values
  * of A: one prepared workspace serves any number of gn_batch_solve calls. */
 gn_status gn_batch_prepare(const gn_batch_problem* probs /*host*/, int32_t count,

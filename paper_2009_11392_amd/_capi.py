@@ -52,7 +52,8 @@ class GnBatchPlan(ctypes.Structure):
                 ("max_rl", c_int64), ("ws_bytes", c_size_t), ("off_desc", c_size_t),
                 ("off_items", c_size_t), ("off_qr", c_size_t), ("off_qr2", c_size_t),
                 ("off_trunc", c_size_t), ("off_widen", c_size_t), ("pass_flops", c_double),
-                ("pass_bytes", c_double), ("tile_policy", c_int32 * 4)]
+                ("pass_bytes", c_double), ("tile_policy", c_int32 * 4),
+                ("pass_threads", c_int32)]
 
 
 class GNError(RuntimeError):

@@ -20,8 +20,11 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tile_table.json")
 
-# candidate tile configurations per slot: 0 = 64 x 256, 1 = 128 x 128, 2 = 256 x 64
-CANDIDATES = ([0, 1], [1, 0, 2], [2, 1], [1, 2])
+# candidate tile configurations per slot (rows x columns): 256-thread workgroups
+# 0 = 64 x 256, 1 = 128 x 128, 2 = 256 x 64; 512-thread workgroups 3 = 128 x 256,
+# 4 = 256 x 128.  One launch uses one workgroup size.
+CANDIDATES_256 = ([0, 1], [1, 0, 2], [2, 1], [1, 2])
+CANDIDATES_512 = ([3, 4], [3, 4], [4, 3], [4, 3])
 
 
 def load_policy(key: str = "batch_f32"):
@@ -63,7 +66,8 @@ def tune(count: int = 512, out: str = TABLE):
     assert torch.cuda.is_available(), "the autotuner measures on the GPU"
     probs = build_batch_problems(gn, W, count)
     results = []
-    for pol in itertools.product(*CANDIDATES):
+    for pol in itertools.chain(itertools.product(*CANDIDATES_256),
+                               itertools.product(*CANDIDATES_512)):
         batch = gn.Batch(probs, tile_policy=pol)
         ms = time_pass(gn, batch)
         results.append({"policy": list(pol), "pass_ms": ms,

@@ -5,8 +5,9 @@
 // The sketch passes of all problems are one persistent launch over a table of
 // work items (problem, product, tile configuration, tile).  Each item is one
 // output tile of Y^T A or AX on the FP32 matrix cores with one of three
-// 256-thread tile shapes (64 x 256, 128 x 128, 256 x 64, chosen per product from
-// the size of its narrow side by a tile policy that the autotuner can replace);
+// tile shapes (256 threads: 64 x 256, 128 x 128, 256 x 64; 512 threads: 128 x 256,
+// 256 x 128), chosen per product from the size of its
+// narrow side by a tile policy that the autotuner can replace);
 // items are ordered by decreasing cost and taken round-robin by the persistent
 // workgroups.  The core products C = Y^T (AX) are a second persistent launch of
 // the same kernel, and the FP64 Householder QR, truncation scan and second QR run
@@ -24,22 +25,31 @@ namespace {
 
 using namespace tiles;
 
+// Tile configurations (output rows x columns per workgroup; every wave owns a
+// 64 x 64 block of 2 x 2 v_mfma_f32_32x32x2_f32 tiles, K staged 16 deep):
+// 0-2 with 256 threads, 3-4 with 512 threads.
 using BC0 = F32Cfg<64, 256, 16, 1, 4, 32>;
 using BC1 = F32Cfg<128, 128, 16, 2, 2, 32>;
 using BC2 = F32Cfg<256, 64, 16, 4, 1, 32>;
-constexpr int kBT = 256;
-static_assert(BC0::T == kBT && BC1::T == kBT && BC2::T == kBT, "one block size for all tiles");
-constexpr int kTileBM[3] = {BC0::BM, BC1::BM, BC2::BM};
-constexpr int kTileBN[3] = {BC0::BN, BC1::BN, BC2::BN};
+using BC3 = F32Cfg<128, 256, 16, 2, 4, 32>;
+using BC4 = F32Cfg<256, 128, 16, 4, 2, 32>;
+constexpr int kNumCfg = 5;
+constexpr int kTileBM[kNumCfg] = {BC0::BM, BC1::BM, BC2::BM, BC3::BM, BC4::BM};
+constexpr int kTileBN[kNumCfg] = {BC0::BN, BC1::BN, BC2::BN, BC3::BN, BC4::BN};
+constexpr int kCfgThreads[kNumCfg] = {BC0::T, BC1::T, BC2::T, BC3::T, BC4::T};
+constexpr int kCoreCfg = 1;  // the core products Y^T (AX) (a 256-thread launch)
 
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-constexpr size_t kBatchSmem =
-    cmax(cmax(cmax(BC0::smem<false, false>(), BC0::smem<true, false>()),
-              cmax(BC1::smem<false, false>(), BC1::smem<true, false>())),
-         cmax(BC2::smem<false, false>(), BC2::smem<true, false>()));
+template <class CF>
+constexpr size_t cfg_smem() {
+  return cmax(CF::template smem<false, false>(), CF::template smem<true, false>());
+}
+constexpr size_t kSmem256 = cmax(cmax(cfg_smem<BC0>(), cfg_smem<BC1>()), cfg_smem<BC2>());
+constexpr size_t kSmem512 = cmax(cfg_smem<BC3>(), cfg_smem<BC4>());
 
 constexpr int kMaxCoreRows = 512;   // r + l: one QR row per thread
-constexpr int kWGPerCU = 3;         // resident 256-thread workgroups per CU (LDS-limited)
+constexpr int kWGPerCU256 = 2;      // resident workgroups per CU (registers)
+constexpr int kWGPerCU512 = 1;
 constexpr int kCUs = 256;
 
 struct BatchDesc {
@@ -71,10 +81,14 @@ __device__ __forceinline__ void batch_tile(const GemmF32& g, int fam, int tm, in
     f32_tile_at<CF, false, false, true>(g, (int64_t)tm * CF::BM, (int64_t)tn * CF::BN, smem);
 }
 
-__global__ void __launch_bounds__(kBT) batch_pass(const BatchDesc* __restrict__ probs,
-                                                   const PassItem* __restrict__ items,
-                                                   int64_t n_items) {
-  __shared__ __attribute__((aligned(16))) char smem[kBatchSmem];
+// The register budget of either instantiation (about 170 VGPRs) leaves 2 waves
+// per SIMD: 2 workgroups of 4 waves, or 1 of 8 waves, resident per CU; the
+// persistent grid is sized for exactly that (a tighter budget spills).
+template <int NT, size_t SMEM>
+__global__ void __launch_bounds__(NT) batch_pass(const BatchDesc* __restrict__ probs,
+                                                 const PassItem* __restrict__ items,
+                                                 int64_t n_items) {
+  __shared__ __attribute__((aligned(16))) char smem[SMEM];
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const PassItem w = items[it];
     const BatchDesc d = probs[w.prob];
@@ -85,12 +99,19 @@ __global__ void __launch_bounds__(kBT) batch_pass(const BatchDesc* __restrict__ 
       g = GemmF32{d.m, d.r, d.n, d.A, d.lda, d.X, d.ldx, d.AX, d.ldax, 0};
     else
       g = GemmF32{d.rl, d.r, d.m, d.Y, d.ldy, d.AX, d.ldax, d.Cf, d.r, 1};
-    if (w.cfg == 0)
-      batch_tile<BC0>(g, w.fam, w.tm, w.tn, smem);
-    else if (w.cfg == 1)
-      batch_tile<BC1>(g, w.fam, w.tm, w.tn, smem);
-    else
-      batch_tile<BC2>(g, w.fam, w.tm, w.tn, smem);
+    if constexpr (NT == 256) {
+      if (w.cfg == 0)
+        batch_tile<BC0>(g, w.fam, w.tm, w.tn, smem);
+      else if (w.cfg == 1)
+        batch_tile<BC1>(g, w.fam, w.tm, w.tn, smem);
+      else
+        batch_tile<BC2>(g, w.fam, w.tm, w.tn, smem);
+    } else {
+      if (w.cfg == 3)
+        batch_tile<BC3>(g, w.fam, w.tm, w.tn, smem);
+      else
+        batch_tile<BC4>(g, w.fam, w.tm, w.tn, smem);
+    }
     __syncthreads();  // the next item restages LDS
   }
 }
@@ -161,7 +182,7 @@ void build_items(const gn_batch_problem* probs, int32_t count, const int32_t* po
     const int64_t l = b.l < 0 ? (b.r + 1) / 2 : b.l, rl = b.r + l;
     add_items(pass, cp, p, 0, policy[rl <= 64 ? 0 : 1], rl, b.n, b.m);
     add_items(pass, cp, p, 1, policy[b.r <= 64 ? 2 : 3], b.m, b.r, b.n);
-    add_items(core, cc, p, 2, 1, rl, b.r, b.m);
+    add_items(core, cc, p, 2, kCoreCfg, rl, b.r, b.m);
   }
   auto order = [](const std::vector<PassItem>& v, const std::vector<double>& c) {
     std::vector<size_t> idx(v.size());
@@ -187,11 +208,11 @@ int64_t max_items(const gn_batch_problem* probs, int32_t count) {
     const gn_batch_problem& b = probs[p];
     const int64_t l = b.l < 0 ? (b.r + 1) / 2 : b.l, rl = b.r + l;
     int64_t t0 = 0, t1 = 0;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < kNumCfg; ++c) {
       t0 = std::max(t0, cdiv(rl, kTileBM[c]) * cdiv(b.n, kTileBN[c]));
       t1 = std::max(t1, cdiv(b.m, kTileBM[c]) * cdiv(b.r, kTileBN[c]));
     }
-    total += t0 + t1 + cdiv(rl, kTileBM[1]) * cdiv(b.r, kTileBN[1]);
+    total += t0 + t1 + cdiv(rl, kTileBM[kCoreCfg]) * cdiv(b.r, kTileBN[kCoreCfg]);
   }
   return total;
 }
@@ -251,8 +272,10 @@ gn_status gn_batch_prepare(const gn_batch_problem* probs, int32_t count, const i
   int32_t pol[4];
   for (int i = 0; i < 4; ++i) {
     pol[i] = tile_policy ? tile_policy[i] : default_cfg(i);
-    if (pol[i] < 0 || pol[i] > 2) return GN_ERR_ARG;
+    if (pol[i] < 0 || pol[i] >= kNumCfg) return GN_ERR_ARG;
   }
+  for (int i = 1; i < 4; ++i)  // one launch, one workgroup size
+    if (kCfgThreads[pol[i]] != kCfgThreads[pol[0]]) return GN_ERR_ARG;
   std::vector<PassItem> items;
   int64_t n_pass, n_core;
   build_items(probs, count, pol, items, n_pass, n_core);
@@ -298,7 +321,9 @@ gn_status gn_batch_prepare(const gn_batch_problem* probs, int32_t count, const i
     P.pass_bytes += 4.0 * ((double)b.m * b.n + (double)b.m * rl + (double)b.n * b.r +
                            (double)b.m * b.r + (double)rl * b.n);
   }
-  P.grid = (int32_t)std::min<int64_t>((int64_t)kCUs * kWGPerCU, std::max<int64_t>(n_pass, 1));
+  P.pass_threads = kCfgThreads[pol[0]];
+  const int64_t per_cu = (P.pass_threads == 256) ? kWGPerCU256 : kWGPerCU512;
+  P.grid = (int32_t)std::min<int64_t>((int64_t)kCUs * per_cu, std::max<int64_t>(n_pass, 1));
   P.ws_bytes = L.total;
   P.off_desc = L.desc;
   P.off_items = L.items;
@@ -338,13 +363,20 @@ gn_status gn_batch_solve(const gn_batch_plan* plan, int32_t stages, void* ws, si
   const unsigned z = (unsigned)plan->count;
   // sketch passes, then the core products (which read AX)
   if (stages & GN_BATCH_PASS) {
-    batch_pass<<<dim3((unsigned)plan->grid), dim3(kBT), 0, s>>>(desc, items, plan->n_pass_items);
+    if (plan->pass_threads == 256)
+      batch_pass<256, kSmem256><<<dim3((unsigned)plan->grid), dim3(256), 0, s>>>(
+          desc, items, plan->n_pass_items);
+    else if (plan->pass_threads == 512)
+      batch_pass<512, kSmem512><<<dim3((unsigned)plan->grid), dim3(512), 0, s>>>(
+          desc, items, plan->n_pass_items);
+    else
+      return GN_ERR_ARG;
     GN_LAUNCH_CHECK();
   }
   if (!(stages & GN_BATCH_CORE)) return GN_OK;
   const int64_t gcore =
-      std::min<int64_t>((int64_t)kCUs * kWGPerCU, std::max<int64_t>(plan->n_core_items, 1));
-  batch_pass<<<dim3((unsigned)gcore), dim3(kBT), 0, s>>>(desc, items + plan->n_pass_items,
+      std::min<int64_t>((int64_t)kCUs * kWGPerCU256, std::max<int64_t>(plan->n_core_items, 1));
+  batch_pass<256, kSmem256><<<dim3((unsigned)gcore), dim3(256), 0, s>>>(desc, items + plan->n_pass_items,
                                                          plan->n_core_items);
   GN_LAUNCH_CHECK();
   batch_widen<<<dim3(16, 1, z), dim3(256), 0, s>>>(desc);

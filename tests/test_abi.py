@@ -163,7 +163,10 @@ def test_batch_validation_rejects_before_enqueue(lib):
     # workspace too small / bad tile policy: rejected before any copy or launch
     assert lib.gn_batch_prepare(arr(), 2, None, ctypes.byref(plan), ctypes.c_void_p(fake), 64,
                                 None) == C.GN_ERR_WORKSPACE
-    bad = (ctypes.c_int32 * 4)(0, 1, 3, 1)
+    bad = (ctypes.c_int32 * 4)(0, 1, 5, 1)
+    assert lib.gn_batch_prepare(arr(), 2, bad, ctypes.byref(plan), ctypes.c_void_p(fake),
+                                nb.value, None) == C.GN_ERR_ARG
+    bad = (ctypes.c_int32 * 4)(0, 1, 3, 1)   # mixes 256- and 512-thread tiles
     assert lib.gn_batch_prepare(arr(), 2, bad, ctypes.byref(plan), ctypes.c_void_p(fake),
                                 nb.value, None) == C.GN_ERR_ARG
     assert lib.gn_batch_solve(ctypes.byref(C.GnBatchPlan()), 3, ctypes.c_void_p(fake), 1 << 30,

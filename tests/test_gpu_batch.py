@@ -97,7 +97,8 @@ def test_batch_matches_oracle(G, batch_inputs):
     _check(G, specs, mats, batch)
 
 
-@pytest.mark.parametrize("policy", [(1, 1, 1, 1), (0, 0, 2, 2), (2, 1, 0, 1)])
+@pytest.mark.parametrize("policy", [(1, 1, 1, 1), (0, 0, 2, 2), (2, 1, 0, 1), (3, 3, 4, 4),
+                                    (4, 4, 3, 3)])
 def test_batch_tile_policies(G, batch_inputs, policy):
     specs, mats, probs = batch_inputs
     batch = G.Batch(probs, tile_policy=policy)
