@@ -19,6 +19,8 @@ Modules
   grad    -- reverse mode of the approximant with the kept rank held fixed
              (dL/dA for L = <Gbar, A_hat>), pinned by finite differences and by
              torch's FP64 autograd through an independent forward.
+  update  -- the Section 6 updates of the sketch products (resampling r -> r+dr,
+             appended rows / columns, A -> A + E), pinned against fresh passes.
 
 Parity status of each function is stated in its module header.
 """
