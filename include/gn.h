@@ -120,7 +120,8 @@ typedef enum {
   GN_OP_RESIDUAL = 4,
   GN_OP_SRHT = 5,
   GN_OP_BACKWARD = 6,  /* gn_backward                                          */
-  GN_OP_MATERIALIZE = 7 /* gn_apply side 2                                     */
+  GN_OP_MATERIALIZE = 7, /* gn_apply side 2                                    */
+  GN_OP_UPDATE = 8     /* gn_sketch_extend / _append / _update (p = the enlarged problem) */
 } gn_op;
 
 /* Bytes of device workspace the given operation needs for problem p.  For
@@ -236,6 +237,39 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
                       int64_t ldg, const void* AX, int64_t ldax, const void* YtA, int64_t ldya,
                       const gn_core_out* core, void* dA, int64_t ldda, void* ws,
                       size_t ws_bytes, gn_stream_t stream);
+
+/* ---- Section 6: resampling and updating the matrix ----
+ * The sketches are counter-based (Philox, see gn_generate_gaussian; SRHT sample =
+ * the r smallest keys), so a larger r, extra rows or extra columns only add
+ * entries at new indices of the same streams: the updated AX and Y^T A equal the
+ * products a fresh gn_sketch of the enlarged problem would give (up to rounding).
+ * The core is then recomputed with gn_core on the enlarged problem (O(r^3)).
+ * FP64 and FP32 modes, Gaussian Y; X Gaussian or SRHT except where noted; BF16
+ * and USER sketches return GN_ERR_UNSUPPORTED.  Workspace:
+ * gn_workspace_size(<enlarged problem>, GN_OP_UPDATE). */
+
+/* Resampling r -> r + dr: p_old and p_new differ only in r (and l; r_new > r_old,
+ * l_new >= l_old).  AX is m x r_new (ld ldax) with the old AX in its first r_old
+ * columns; YtA is (r_new + l_new) x n (ld ldya) with the old Y^T A in its first
+ * r_old + l_old rows.  Fills the new columns A X_new and rows Y_new^T A from one
+ * pass over A (m x n, ld lda). */
+gn_status gn_sketch_extend(const gn_problem* p_old, const gn_problem* p_new, const void* A,
+                           int64_t lda, void* AX, int64_t ldax, void* YtA, int64_t ldya, void* ws,
+                           size_t ws_bytes, gn_stream_t stream);
+
+/* Appended data.  p is the problem after the append.  axis 0: rows, A -> [A; B]
+ * with B (m - old_size) x n (ld ldb): AX rows old_size.. receive B X and Y^T A +=
+ * Y_B^T B (Y_B = rows old_size.. of Y).  axis 1: columns, A -> [A, B] with B
+ * m x (n - old_size) (ld ldb; Gaussian X only): AX += B X_B (X_B = rows
+ * old_size.. of X) and columns old_size.. of Y^T A receive Y^T B.  AX and YtA
+ * hold the old products in their old positions. */
+gn_status gn_sketch_append(const gn_problem* p, int32_t axis, int64_t old_size, const void* B,
+                           int64_t ldb, void* AX, int64_t ldax, void* YtA, int64_t ldya, void* ws,
+                           size_t ws_bytes, gn_stream_t stream);
+
+/* Perturbation A -> A + E (E m x n, ld lde): AX += E X and Y^T A += Y^T E. */
+gn_status gn_sketch_update(const gn_problem* p, const void* E, int64_t lde, void* AX, int64_t ldax,
+                           void* YtA, int64_t ldya, void* ws, size_t ws_bytes, gn_stream_t stream);
 
 /* ---- Batches of independent problems (many GN solves of uneven m, n, r) ----
  * One problem of a batch: the problem statement of gn_problem restricted to FP32

@@ -16,12 +16,13 @@ GN_MODE_F64, GN_MODE_F32, GN_MODE_BF16_BS = 0, 1, 2
 GN_BATCH_PASS, GN_BATCH_CORE, GN_BATCH_ALL = 1, 2, 3
 GN_DT_F64, GN_DT_F32, GN_DT_BF16 = 0, 1, 2
 (GN_OP_SKETCH, GN_OP_CORE, GN_OP_FACTORS, GN_OP_APPLY, GN_OP_RESIDUAL, GN_OP_SRHT,
- GN_OP_BACKWARD, GN_OP_MATERIALIZE) = range(8)
+ GN_OP_BACKWARD, GN_OP_MATERIALIZE, GN_OP_UPDATE) = range(9)
 
 EXPORTED = (
     "gn_workspace_size", "gn_generate_gaussian", "gn_srht_generate", "gn_sketch_prepare",
     "gn_sketch_pass", "gn_sketch", "gn_core",
-    "gn_factors", "gn_apply", "gn_backward", "gn_residual", "gn_quantize_bf16_bs",
+    "gn_factors", "gn_apply", "gn_backward", "gn_sketch_extend", "gn_sketch_append",
+    "gn_sketch_update", "gn_residual", "gn_quantize_bf16_bs",
     "gn_batch_workspace_size", "gn_batch_prepare", "gn_batch_solve", "gn_status_string",
     "gn_version",
 )
@@ -98,6 +99,12 @@ def lib(path: str = LIB_PATH):
     L.gn_backward.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                               c_void_p, c_int64, POINTER(GnCoreOut), c_void_p, c_int64, c_void_p,
                               c_size_t, c_void_p]
+    L.gn_sketch_extend.argtypes = [P, P, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                                   c_void_p, c_size_t, c_void_p]
+    L.gn_sketch_append.argtypes = [P, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                                   c_void_p, c_int64, c_void_p, c_size_t, c_void_p]
+    L.gn_sketch_update.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                                   c_void_p, c_size_t, c_void_p]
     BP = POINTER(GnBatchProblem)
     L.gn_batch_workspace_size.argtypes = [BP, c_int32, POINTER(c_size_t)]
     L.gn_batch_prepare.argtypes = [BP, c_int32, c_void_p, POINTER(GnBatchPlan), c_void_p, c_size_t,

@@ -189,6 +189,36 @@ BackWs back_ws(const Plan& P) {
   return w;
 }
 
+// Section 6 updates: sketch blocks X (up to n x r) and Y (up to m x (r+l)) in the
+// sketch dtype, SRHT signs / sample / keys, temporaries for the products to be
+// accumulated (m x r and (r+l) x n in the accumulation dtype), K-split scratch.
+struct UpdWs {
+  size_t xs, ys, signs, idx, keys, tax, tya, split, split_bytes, total;
+};
+UpdWs upd_ws(const Plan& P) {
+  UpdWs w{};
+  const size_t es = dtype_size(P.sdt), ac = dtype_size(P.adt);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  w.xs = take((size_t)P.n * P.r * es);
+  w.ys = take((size_t)P.m * P.rl * es);
+  if (P.kx == GN_SKETCH_SRHT) {
+    w.signs = take((size_t)P.npad);
+    w.idx = take((size_t)P.r * 4);
+    w.keys = take(srht_ws_bytes(P.npad));
+  }
+  w.tax = take((size_t)P.m * P.r * ac);
+  w.tya = take((size_t)P.rl * P.n * ac);
+  w.split_bytes = pass_split_ws_bytes(P.mode, P.kx, P.m, P.n, P.r, P.rl);
+  w.split = take(w.split_bytes);
+  w.total = off;
+  return w;
+}
+
 size_t materialize_ws(const Plan& P) {
   return align_up((size_t)P.m * P.r * 8) + align_up((size_t)P.r * P.n * 8) + 256;
 }
@@ -257,6 +287,7 @@ gn_status gn_workspace_size(const gn_problem* p, int32_t op, int64_t kcols, size
     case GN_OP_SRHT: *bytes = srht_ws_bytes(P.npad); break;
     case GN_OP_BACKWARD: *bytes = back_ws(P).total; break;
     case GN_OP_MATERIALIZE: *bytes = materialize_ws(P); break;
+    case GN_OP_UPDATE: *bytes = upd_ws(P).total; break;
     default: return GN_ERR_ARG;
   }
   return GN_OK;
@@ -668,6 +699,130 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
                            (float*)dA, ldda, s);
   return launch_dgemm(m, n, K2, 1.0, MatRef{lcat, F64, K2, 1}, MatRef{rcat, F64, n, 1}, 0.0,
                       (double*)dA, ldda, 1, nullptr, false, s, nullptr, 0, true, DS, DSB);
+}
+
+// ---- Section 6: resampling, appended rows / columns, A <- A + E
+namespace {
+gn_status upd_common(const Plan& P, bool allow_srht) {
+  if (P.mode != GN_MODE_F64 && P.mode != GN_MODE_F32) return GN_ERR_UNSUPPORTED;
+  if (P.ky != GN_SKETCH_GAUSSIAN) return GN_ERR_UNSUPPORTED;
+  if (P.kx != GN_SKETCH_GAUSSIAN && !(allow_srht && P.kx == GN_SKETCH_SRHT))
+    return GN_ERR_UNSUPPORTED;
+  return GN_OK;
+}
+}  // namespace
+
+gn_status gn_sketch_extend(const gn_problem* p_old, const gn_problem* p_new, const void* A,
+                           int64_t lda, void* AX, int64_t ldax, void* YtA, int64_t ldya, void* ws,
+                           size_t ws_bytes, gn_stream_t stream_) {
+  Plan Po, Pn;
+  GN_TRY(make_plan(p_old, Po));
+  GN_TRY(make_plan(p_new, Pn));
+  GN_TRY(upd_common(Pn, true));
+  if (Po.mode != Pn.mode || Po.kx != Pn.kx || Po.ky != Pn.ky || p_old->seed != p_new->seed)
+    return GN_ERR_ARG;
+  if (!A || !AX || !YtA || !ws) return GN_ERR_ARG;
+  if (Po.m != Pn.m || Po.n != Pn.n) return GN_ERR_SHAPE;
+  const int64_t dr = Pn.r - Po.r, drl = Pn.rl - Po.rl;
+  if (dr < 1 || drl < 1 || Pn.l < Po.l) return GN_ERR_SHAPE;
+  if (lda < Pn.n || ldax < Pn.r || ldya < Pn.n) return GN_ERR_SHAPE;
+  if (!aligned16(A) || !aligned16(ws)) return GN_ERR_ALIGN;
+  const UpdWs W = upd_ws(Pn);
+  if (ws_bytes < W.total) return GN_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream_;
+  char* base = (char*)ws;
+  const size_t ac = dtype_size(Pn.adt);
+  // the new columns of X (or the enlarged SRHT sample) and of Y
+  const int32_t* idx = nullptr;
+  const int8_t* signs = nullptr;
+  if (Pn.kx == GN_SKETCH_SRHT) {
+    GN_TRY(launch_srht(p_new->seed, Pn.npad, Pn.r, (int8_t*)(base + W.signs),
+                       (int32_t*)(base + W.idx), (uint64_t*)(base + W.keys), s));
+    signs = (const int8_t*)(base + W.signs);
+    idx = (const int32_t*)(base + W.idx) + Po.r;  // prefix-stable: the first r are the old sample
+  } else {
+    GN_TRY(launch_gaussian(p_new->seed, 1, 0, Po.r, Pn.n, dr, Pn.sdt, 0, base + W.xs, dr, s));
+  }
+  GN_TRY(launch_gaussian(p_new->seed, 2, 0, Po.rl, Pn.m, drl, Pn.sdt, 0, base + W.ys, drl, s));
+  return launch_pass(Pn.mode, Pn.kx, Pn.m, Pn.n, dr, drl, A, lda, nullptr, base + W.xs, signs, idx,
+                     base + W.ys, (char*)AX + Po.r * ac, ldax, (char*)YtA + Po.rl * ldya * ac, ldya,
+                     s, base + W.split, W.split_bytes);
+}
+
+gn_status gn_sketch_append(const gn_problem* p, int32_t axis, int64_t old_size, const void* B,
+                           int64_t ldb, void* AX, int64_t ldax, void* YtA, int64_t ldya, void* ws,
+                           size_t ws_bytes, gn_stream_t stream_) {
+  Plan P;
+  GN_TRY(make_plan(p, P));
+  if (axis != 0 && axis != 1) return GN_ERR_ARG;
+  GN_TRY(upd_common(P, axis == 0));
+  if (!B || !AX || !YtA || !ws) return GN_ERR_ARG;
+  const int64_t full = (axis == 0) ? P.m : P.n;
+  if (old_size < P.r || old_size >= full) return GN_ERR_SHAPE;
+  const int64_t add = full - old_size;
+  if (ldb < ((axis == 0) ? P.n : add) || ldax < P.r || ldya < P.n) return GN_ERR_SHAPE;
+  if (!aligned16(B) || !aligned16(ws)) return GN_ERR_ALIGN;
+  const UpdWs W = upd_ws(P);
+  if (ws_bytes < W.total) return GN_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream_;
+  char* base = (char*)ws;
+  const size_t ac = dtype_size(P.adt);
+  if (axis == 0) {
+    // A -> [A; B]: X as before, Y_B = rows old_size.. of Y; AX gains B X, Y^T A += Y_B^T B
+    const int32_t* idx = nullptr;
+    const int8_t* signs = nullptr;
+    if (P.kx == GN_SKETCH_SRHT) {
+      GN_TRY(launch_srht(p->seed, P.npad, P.r, (int8_t*)(base + W.signs), (int32_t*)(base + W.idx),
+                         (uint64_t*)(base + W.keys), s));
+      signs = (const int8_t*)(base + W.signs);
+      idx = (const int32_t*)(base + W.idx);
+    } else {
+      GN_TRY(launch_gaussian(p->seed, 1, 0, 0, P.n, P.r, P.sdt, 0, base + W.xs, P.r, s));
+    }
+    GN_TRY(launch_gaussian(p->seed, 2, old_size, 0, add, P.rl, P.sdt, 0, base + W.ys, P.rl, s));
+    GN_TRY(launch_pass(P.mode, P.kx, add, P.n, P.r, P.rl, B, ldb, nullptr, base + W.xs, signs, idx,
+                       base + W.ys, (char*)AX + old_size * ldax * ac, ldax, base + W.tya, P.n, s,
+                       base + W.split, W.split_bytes));
+    return launch_add(P.rl, P.n, P.adt, base + W.tya, P.n, YtA, ldya, s);
+  }
+  // A -> [A, B]: X_B = rows old_size.. of X, Y as before; AX += B X_B, Y^T A gains Y^T B
+  GN_TRY(launch_gaussian(p->seed, 1, old_size, 0, add, P.r, P.sdt, 0, base + W.xs, P.r, s));
+  GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, P.sdt, 0, base + W.ys, P.rl, s));
+  GN_TRY(launch_pass(P.mode, P.kx, P.m, add, P.r, P.rl, B, ldb, nullptr, base + W.xs, nullptr,
+                     nullptr, base + W.ys, base + W.tax, P.r, (char*)YtA + old_size * ac, ldya, s,
+                     base + W.split, W.split_bytes));
+  return launch_add(P.m, P.r, P.adt, base + W.tax, P.r, AX, ldax, s);
+}
+
+gn_status gn_sketch_update(const gn_problem* p, const void* E, int64_t lde, void* AX, int64_t ldax,
+                           void* YtA, int64_t ldya, void* ws, size_t ws_bytes,
+                           gn_stream_t stream_) {
+  Plan P;
+  GN_TRY(make_plan(p, P));
+  GN_TRY(upd_common(P, true));
+  if (!E || !AX || !YtA || !ws) return GN_ERR_ARG;
+  if (lde < P.n || ldax < P.r || ldya < P.n) return GN_ERR_SHAPE;
+  if (!aligned16(E) || !aligned16(ws)) return GN_ERR_ALIGN;
+  const UpdWs W = upd_ws(P);
+  if (ws_bytes < W.total) return GN_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream_;
+  char* base = (char*)ws;
+  const int32_t* idx = nullptr;
+  const int8_t* signs = nullptr;
+  if (P.kx == GN_SKETCH_SRHT) {
+    GN_TRY(launch_srht(p->seed, P.npad, P.r, (int8_t*)(base + W.signs), (int32_t*)(base + W.idx),
+                       (uint64_t*)(base + W.keys), s));
+    signs = (const int8_t*)(base + W.signs);
+    idx = (const int32_t*)(base + W.idx);
+  } else {
+    GN_TRY(launch_gaussian(p->seed, 1, 0, 0, P.n, P.r, P.sdt, 0, base + W.xs, P.r, s));
+  }
+  GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, P.sdt, 0, base + W.ys, P.rl, s));
+  GN_TRY(launch_pass(P.mode, P.kx, P.m, P.n, P.r, P.rl, E, lde, nullptr, base + W.xs, signs, idx,
+                     base + W.ys, base + W.tax, P.r, base + W.tya, P.n, s, base + W.split,
+                     W.split_bytes));
+  GN_TRY(launch_add(P.m, P.r, P.adt, base + W.tax, P.r, AX, ldax, s));
+  return launch_add(P.rl, P.n, P.adt, base + W.tya, P.n, YtA, ldya, s);
 }
 
 gn_status gn_residual(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, int32_t a_dtype,

@@ -272,6 +272,9 @@ gn_status launch_trsm_core(int64_t rows, int64_t r, const double* R, const doubl
 // out (cols x rows) = src^T with rows >= *k of out zeroed (src rows x cols).
 gn_status launch_transpose_rows_masked(int64_t rows, int64_t cols, const double* src, int64_t lds,
                                        const int32_t* k, double* out, int64_t ldo, hipStream_t s);
+// dst += src (rows x cols) in GN_DT_F64 or GN_DT_F32.
+gn_status launch_add(int64_t rows, int64_t cols, int32_t dt, const void* src, int64_t lds, void* dst,
+                     int64_t ldd, hipStream_t s);
 // Y += alpha X (rows x cols, FP64).
 gn_status launch_axpy(int64_t rows, int64_t cols, double alpha, const double* X, int64_t ldx,
                       double* Y, int64_t ldy, hipStream_t s);

@@ -1,6 +1,7 @@
-// Small kernels of the reverse mode (the adjoint of A -> A_hat with the kept
-// rank k held at its forward value): the masked transpose that starts the
-// explicit core pseudoinverse M = R_1^+ Q_1^T, and matrix accumulation.
+// Small kernels of the reverse mode (the adjoint of A -> A_hat with the kept rank
+// k held at its forward value) and of the sketch updates: the masked transpose
+// that starts the explicit core pseudoinverse M = R_1^+ Q_1^T, and matrix
+// accumulation.
 #include "gn_internal.h"
 
 namespace gn {
@@ -37,7 +38,30 @@ __global__ void __launch_bounds__(256) mat_axpy(int64_t rows, int64_t cols, doub
   Y[i * ldy + j] = fma(alpha, X[i * ldx + j], Y[i * ldy + j]);
 }
 
+// dst += src (rows x cols), FP64 or FP32 (dt).
+__global__ void __launch_bounds__(256) mat_add(int64_t rows, int64_t cols, int32_t dt,
+                                               const void* __restrict__ src, int64_t lds,
+                                               void* __restrict__ dst, int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e / cols, j = e - i * cols;
+  if (dt == GN_DT_F64)
+    reinterpret_cast<double*>(dst)[i * ldd + j] += reinterpret_cast<const double*>(src)[i * lds + j];
+  else
+    reinterpret_cast<float*>(dst)[i * ldd + j] += reinterpret_cast<const float*>(src)[i * lds + j];
+}
+
 }  // namespace
+
+gn_status launch_add(int64_t rows, int64_t cols, int32_t dt, const void* src, int64_t lds, void* dst,
+                     int64_t ldd, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return GN_OK;
+  if (dt != GN_DT_F64 && dt != GN_DT_F32) return GN_ERR_DTYPE;
+  mat_add<<<dim3((unsigned)cdiv(rows * cols, 256)), dim3(256), 0, s>>>(rows, cols, dt, src, lds, dst,
+                                                                       ldd);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
 
 gn_status launch_transpose_rows_masked(int64_t rows, int64_t cols, const double* src, int64_t lds,
                                        const int32_t* k, double* out, int64_t ldo, hipStream_t s) {

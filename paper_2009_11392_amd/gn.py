@@ -273,6 +273,41 @@ def gn_backward(p: Problem, Gbar: torch.Tensor, YtA: torch.Tensor, core: CoreRes
     return dA
 
 
+def gn_sketch_extend(p_old: Problem, p_new: Problem, A, AX, YtA, ws=None):
+    """Resampling r -> r + dr (Section 6): AX (m x r_new) and YtA (rl_new x n) hold
+    the old products in their leading columns / rows; the new ones are filled in."""
+    _need_cuda(A, AX, YtA)
+    ws = workspace(p_new, C.GN_OP_UPDATE) if ws is None else ws
+    po, pn = p_old.c(), p_new.c()
+    C.check(C.lib().gn_sketch_extend(ctypes.byref(po), ctypes.byref(pn), _ptr(A), A.stride(0),
+                                     _ptr(AX), AX.stride(0), _ptr(YtA), YtA.stride(0), _ptr(ws),
+                                     ws.numel(), _stream()), "gn_sketch_extend")
+    return AX, YtA
+
+
+def gn_sketch_append(p: Problem, axis: int, old_size: int, B, AX, YtA, ws=None):
+    """Appended rows (axis 0) or columns (axis 1) B (Section 6); p is the enlarged
+    problem, AX / YtA its buffers holding the old products in place."""
+    _need_cuda(B, AX, YtA)
+    ws = workspace(p, C.GN_OP_UPDATE) if ws is None else ws
+    pc = p.c()
+    C.check(C.lib().gn_sketch_append(ctypes.byref(pc), axis, old_size, _ptr(B), B.stride(0),
+                                     _ptr(AX), AX.stride(0), _ptr(YtA), YtA.stride(0), _ptr(ws),
+                                     ws.numel(), _stream()), "gn_sketch_append")
+    return AX, YtA
+
+
+def gn_sketch_update(p: Problem, E, AX, YtA, ws=None):
+    """A -> A + E (Section 6): AX += E X, Y^T A += Y^T E in place."""
+    _need_cuda(E, AX, YtA)
+    ws = workspace(p, C.GN_OP_UPDATE) if ws is None else ws
+    pc = p.c()
+    C.check(C.lib().gn_sketch_update(ctypes.byref(pc), _ptr(E), E.stride(0), _ptr(AX), AX.stride(0),
+                                     _ptr(YtA), YtA.stride(0), _ptr(ws), ws.numel(), _stream()),
+            "gn_sketch_update")
+    return AX, YtA
+
+
 class GNApprox(torch.autograd.Function):
     """A -> A_hat = AX (Y^T A X)_eps^+ Y^T A as a differentiable torch op.
 

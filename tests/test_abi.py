@@ -173,3 +173,40 @@ def test_batch_validation_rejects_before_enqueue(lib):
                               None) == C.GN_ERR_ARG
     assert lib.gn_batch_solve(ctypes.byref(C.GnBatchPlan()), 0, ctypes.c_void_p(fake), 1 << 30,
                               None) == C.GN_ERR_ARG
+
+
+def test_update_entry_points_reject_before_enqueue(lib):
+    fake = ctypes.c_void_p(1 << 20)
+    big = 1 << 34
+    p = _prob()                                   # 2000 x 1000, r = 50, l = 25, FP64
+    pn = _prob(r=60, l=30)
+    # extend: r must grow, kinds / seeds must agree, BF16 unsupported, workspace
+    assert lib.gn_sketch_extend(ctypes.byref(pn), ctypes.byref(p), fake, 1000, fake, 60, fake,
+                                1000, fake, big, None) == C.GN_ERR_SHAPE
+    assert lib.gn_sketch_extend(ctypes.byref(p), ctypes.byref(_prob(r=60, l=30, seed=2)), fake,
+                                1000, fake, 60, fake, 1000, fake, big, None) == C.GN_ERR_ARG
+    assert lib.gn_sketch_extend(ctypes.byref(_prob(mode=2)), ctypes.byref(_prob(mode=2, r=60)),
+                                fake, 1000, fake, 60, fake, 1000, fake, big, None) == \
+        C.GN_ERR_UNSUPPORTED
+    assert lib.gn_sketch_extend(ctypes.byref(p), ctypes.byref(pn), fake, 1000, fake, 59, fake,
+                                1000, fake, big, None) == C.GN_ERR_SHAPE
+    assert lib.gn_sketch_extend(ctypes.byref(p), ctypes.byref(pn), fake, 1000, fake, 60, fake,
+                                1000, fake, 64, None) == C.GN_ERR_WORKSPACE
+    # append: axis, old size range, SRHT columns unsupported, ldb
+    assert lib.gn_sketch_append(ctypes.byref(p), 2, 1500, fake, 1000, fake, 50, fake, 1000, fake,
+                                big, None) == C.GN_ERR_ARG
+    assert lib.gn_sketch_append(ctypes.byref(p), 0, 2000, fake, 1000, fake, 50, fake, 1000, fake,
+                                big, None) == C.GN_ERR_SHAPE
+    assert lib.gn_sketch_append(ctypes.byref(p), 0, 40, fake, 1000, fake, 50, fake, 1000, fake,
+                                big, None) == C.GN_ERR_SHAPE
+    assert lib.gn_sketch_append(ctypes.byref(_prob(kind_x=1)), 1, 900, fake, 100, fake, 50, fake,
+                                1000, fake, big, None) == C.GN_ERR_UNSUPPORTED
+    assert lib.gn_sketch_append(ctypes.byref(p), 1, 900, fake, 99, fake, 50, fake, 1000, fake,
+                                big, None) == C.GN_ERR_SHAPE
+    # update: strides, null E, workspace
+    assert lib.gn_sketch_update(ctypes.byref(p), fake, 999, fake, 50, fake, 1000, fake, big,
+                                None) == C.GN_ERR_SHAPE
+    assert lib.gn_sketch_update(ctypes.byref(p), None, 1000, fake, 50, fake, 1000, fake, big,
+                                None) == C.GN_ERR_ARG
+    assert lib.gn_sketch_update(ctypes.byref(p), fake, 1000, fake, 50, fake, 1000, fake, 64,
+                                None) == C.GN_ERR_WORKSPACE
