@@ -21,6 +21,9 @@ Modules
              torch's FP64 autograd through an independent forward.
   update  -- the Section 6 updates of the sketch products (resampling r -> r+dr,
              appended rows / columns, A -> A + E), pinned against fresh passes.
+  stabilize -- the other Section 5.1.1 stabilizations (SVD epsilon-pseudoinverse,
+             perturbations (a), (b), (c)) and the Section 5.1.2 power-method check
+             of plain GN, pinned by closed forms on designed cores.
 
 Parity status of each function is stated in its module header.
 """

@@ -21,7 +21,8 @@ Counter layout (prefix-stable in rows and columns):
   SRHT keys: key_j is the 64-bit integer (w[2b] << 32) | w[2b+1] with b = j & 1 of
              counter (j >> 1, 0, 4, 0); the sample is the r columns with the
              smallest (key_j, j), listed in ascending key order.
-Streams: 1 = X, 2 = Y, 3 = SRHT signs, 4 = SRHT sample keys, 5 = loss weights G.
+Streams: 1 = X, 2 = Y, 3 = SRHT signs, 4 = SRHT sample keys, 5 = loss weights G,
+6 = start vectors of the power-method norm estimate.
 
 Gaussian transform (Box-Muller in FP64): from words (w0, w1, w2, w3)
   ka = (w0 >> 5) * 2**26 + (w1 >> 6),  kb = (w2 >> 5) * 2**26 + (w3 >> 6)  (53 bits)
@@ -53,6 +54,7 @@ STREAM_Y = 2
 STREAM_SRHT_SIGN = 3
 STREAM_SRHT_KEY = 4
 STREAM_G = 5
+STREAM_POWER = 6
 
 TWO_PI = 6.283185307179586  # the double nearest to 2*pi
 TWO_M53 = 2.0 ** -53
