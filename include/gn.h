@@ -68,6 +68,25 @@ typedef enum {
 
 typedef enum { GN_DT_F64 = 0, GN_DT_F32 = 1, GN_DT_BF16 = 2 } gn_dtype;
 
+/* How gn_core stabilizes the core pseudoinverse (Section 5.1.1).  tau is the
+ * threshold of gn_problem; the perturbations (LIFT_*) need eps > 0.
+ *   QR        : truncated QR: keep the prefix of |R_ii| >= tau, then the QR of
+ *               R[:k, :]^T (the method of the paper's experiments; default).
+ *   SVD       : the SVD of the core, singular values below tau dropped.
+ *   LIFT_SVD  : perturbation (a): singular values below tau raised to tau.
+ *   LIFT_RRQR : perturbation (b): QR with column pivoting, diagonal entries of
+ *               R below tau in magnitude raised to tau.
+ *   LIFT_DIAG : perturbation (c): the unpivoted R's diagonal entries below tau
+ *               raised to tau.
+ * gn_backward and the batched solves support QR only. */
+typedef enum {
+  GN_CORE_QR = 0,
+  GN_CORE_SVD = 1,
+  GN_CORE_LIFT_SVD = 2,
+  GN_CORE_LIFT_RRQR = 3,
+  GN_CORE_LIFT_DIAG = 4
+} gn_core_method;
+
 /* Problem statement (Algorithm 2.1 inputs: A's shape, r, l, eps, sketch type,
  * seed).  l < 0 selects l = ceil(r/2) (Algorithm 2.1, step 1); l = 0 means no
  * oversampling (the Nystrom and HMT special cases with USER sketches).  Requires
@@ -83,25 +102,35 @@ typedef struct {
   int32_t kind_y;   /* gn_sketch_kind: GAUSSIAN or USER                   */
   uint64_t seed;    /* Philox4x32-10 key for X, Y and the SRHT            */
   int32_t mode;     /* gn_mode                                            */
-  int32_t reserved; /* must be 0                                          */
+  int32_t core_method; /* gn_core_method (0 = truncated QR)                */
   double eps, nu_x, nu_y;
 } gn_problem;
 
 /* Output of gn_core.  k and status live in device memory so that nothing on
  * the path synchronizes; read them back only when needed.
- *   k      : kept rank, 0 <= k <= r (prefix of |R_ii| >= tau).
- *   status : bit flags, 0 = fine.  1 = non-finite diagonal in R, 2 = k == 0
- *            (both are GN_ERR_NUMERIC conditions), 4 = some |R_jj| >= tau after
- *            the first diagonal below tau (diagnostic only: the QR was not
- *            rank revealing there).
- *   Q1     : (r+l) x r, ld r: Householder Q of C = Y^T (AX), columns scaled so
- *            that R_ii >= 0.
- *   R      : r x r, ld r: upper triangular R of C (strictly lower part zero).
- *   Q2, R2 : r x r, ld r: when k < r, the QR factors of R[:k,:]^T
- *            (Q2: first k columns; R2: upper k x k block, R2_ii >= 0), so that
- *            the eps-pseudoinverse of C is Q2 R2^{-T} Q1[:, :k]^T
- *            (Section 5.1.1; see the design notes for the transpose).  When
- *            k == r they are left unchanged and unused. */
+ *   k      : kept rank, 0 <= k <= r.
+ *   status : bit flags, 0 = fine.  1 = non-finite diagonal or singular value,
+ *            2 = k == 0 (both are GN_ERR_NUMERIC conditions), 4 = some |R_jj| >=
+ *            tau after the first diagonal below tau (QR method; diagnostic: the
+ *            QR was not rank revealing there), 8 = set by gn_core_check, 16 =
+ *            something was raised to tau (LIFT_* methods), 32 = the Jacobi SVD
+ *            stopped at its sweep limit (SVD, LIFT_SVD).
+ * The buffers (all FP64, row-major, ld r): Q1 (r+l) x r, R, Q2, R2 r x r.
+ *   QR        : Q1, R = the Householder QR of C = Y^T (AX) with R_ii >= 0; k =
+ *               the prefix of |R_ii| >= tau; when k < r, Q2 and R2 are the QR
+ *               factors of R[:k,:]^T (Q2: first k columns; R2: upper k x k
+ *               block, R2_ii >= 0), and as R[:k,:] = R2^T Q2^T the
+ *               eps-pseudoinverse of C is Q2 R2^{-T} Q1[:, :k]^T.  When k == r
+ *               Q2 and R2 are left unchanged and unused, the inverse is R^{-1} Q1^T.
+ *   SVD, LIFT_SVD : C = Q1 diag(s) Q2^T with the singular values s descending:
+ *               Q1 the left and Q2 the right singular vectors, R2 = diag(s)
+ *               (LIFT_SVD: diag(max(s, tau))), R the R of C's QR; k = the count of
+ *               s >= tau (SVD) or r (LIFT_SVD).
+ *   LIFT_RRQR : C P = Q1 R with column pivoting (R = the pivoted R before
+ *               lifting); the lifted R equals R2^T Q3^T and Q2 = P Q3; k = r.
+ *   LIFT_DIAG : Q1, R the QR of C with R's diagonal raised to tau; k = r; Q2, R2
+ *               unused.
+ * SVD, LIFT_SVD and LIFT_RRQR cores are always applied as Q2 R2^{-T} Q1[:, :k]^T. */
 typedef struct {
   int32_t* k;
   int32_t* status;
@@ -121,7 +150,8 @@ typedef enum {
   GN_OP_SRHT = 5,
   GN_OP_BACKWARD = 6,  /* gn_backward                                          */
   GN_OP_MATERIALIZE = 7, /* gn_apply side 2                                    */
-  GN_OP_UPDATE = 8     /* gn_sketch_extend / _append / _update (p = the enlarged problem) */
+  GN_OP_UPDATE = 8,    /* gn_sketch_extend / _append / _update (p = the enlarged problem) */
+  GN_OP_CHECK = 9      /* gn_core_check, with kcols = nv                      */
 } gn_op;
 
 /* Bytes of device workspace the given operation needs for problem p.  For
@@ -187,15 +217,38 @@ gn_status gn_sketch(const gn_problem* p, const void* A, int64_t lda, const float
 
 /* The core (Algorithm 2.1 step 2 and Section 5.1.1): C = Y^T (AX) accumulated
  * in FP64 (Y regenerated from the seed unless kind_y == USER), Householder QR
- * C = Q R with R_ii >= 0, the kept rank k, and, when k < r, the QR of
- * R[:k,:]^T.  AX as produced by gn_sketch (ld ldax). */
+ * C = Q R with R_ii >= 0, then the stabilization p->core_method selects: the
+ * kept rank k and, when k < r, the QR of R[:k,:]^T (QR); the SVD of R by
+ * one-sided Jacobi (SVD, LIFT_SVD; r <= 4096); QR with column pivoting of R
+ * followed by two QRs (LIFT_RRQR); or R's diagonal raised (LIFT_DIAG).  See
+ * gn_core_out for what each leaves in `out`.  AX as produced by gn_sketch (ld
+ * ldax).  The cost beyond the QR is O(r^3) for SVD / LIFT_SVD (a few sweeps of
+ * r^3 rotations) and LIFT_RRQR (2 r launches for the pivot order, two QRs). */
 gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void* Y_user,
                   int64_t ldy, const gn_core_out* out /*host struct of device ptrs*/, void* ws,
                   size_t ws_bytes, gn_stream_t stream);
 
+/* Section 5.1.2: check a core for the instability plain GN can show.  A power
+ * method estimates ||T^{-1}||_2 for T the triangular factor whose inverse
+ * multiplies AX in gn_factors / gn_apply (R, or R2^T for a truncated or
+ * factored core): nv start vectors (Philox stream 6 of p->seed; the first k
+ * entries of each row of an nv x r Gaussian block) are normalized and driven
+ * through y = T^{-T} v, z = T^{-1} y, v = z / ||z|| for `iters` steps of two
+ * triangular solves (O(nv r^2) each).  The estimate, the largest ||y||, is a
+ * lower bound of ||T^{-1}||_2.  When est * delta * nu_x * nu_y > 1 (delta <= 0
+ * selects p->eps; both <= 0 is GN_ERR_ARG) bit 8 of core->status is set: the
+ * core has a singular value below the threshold SGN with eps = delta would
+ * truncate at, and the caller should switch to an SGN core.  est (device
+ * double, or NULL) receives the estimate.  1 <= nv <= 16, 1 <= iters <= 64.
+ * Workspace: gn_workspace_size(p, GN_OP_CHECK, nv). */
+gn_status gn_core_check(const gn_problem* p, const gn_core_out* core /*host struct*/, double delta,
+                        int32_t nv, int32_t iters, double* est, void* ws, size_t ws_bytes,
+                        gn_stream_t stream);
+
 /* The factored approximant A_hat = F G in FP64 (Section 5.1, the stable order):
  *   k == r : F = (AX) R^{-1} by triangular solves,  G = Q1^T (Y^T A)
  *   k <  r : F = (AX Q2) R2^{-T},                   G = Q1[:, :k]^T (Y^T A)
+ * (the second form whatever k is for SVD, LIFT_SVD and LIFT_RRQR cores)
  * F is m x r (ld ldf), G is r x n (ld ldg); columns of F and rows of G beyond
  * k are set to zero.  Forming F costs O(m r^2) (the paper advises it only for
  * evaluation); use gn_apply for products. */

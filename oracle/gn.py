@@ -16,7 +16,7 @@ What is computed, and where the paper defines it:
   * products with the factors, A_hat W = AX(R^-1(Q^T(Y^T A W))) and
     W A_hat = (((W AX) R^-1) Q^T) Y^T A                   -- Section 2, after Alg. 2.1
 
-Readings taken where the paper is silent or garbled (listed in the design notes):
+Readings taken where the paper is silent or garbled:
   * the core is formed as Y^T (AX) (the order of the Section 5.1 MATLAB line);
   * Householder QR without pivoting; R's diagonal made non-negative by flipping
     the matching columns of Q (the approximant does not depend on it);

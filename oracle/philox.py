@@ -10,7 +10,7 @@ same published counter-based generator, Philox4x32-10 (Salmon, Moraes, Dror and
 Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11), each from that
 definition.  Everything below the generator (the counter layout, the Gaussian
 transform, the SRHT signs and column selection) is this project's convention and is
-documented in the design notes.
+stated here.
 
 Counter layout (prefix-stable in rows and columns):
   key      = (seed & 0xffffffff, seed >> 32)

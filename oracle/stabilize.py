@@ -22,12 +22,14 @@ inverse triangular factor (two triangular solves per step, O(r^2)), and switches
 to SGN only when the estimate exceeds one over the threshold (inv_norm_power,
 check, gn_checked).
 
-Readings (listed in the design notes): the threshold is the same tau = eps nu_X
+Readings where the paper leaves a choice open: the threshold is the same tau = eps nu_X
 nu_Y as the truncated QR; a kept singular value is one >= tau (ties go to the
 kept side, as for R's diagonal); a lifted value is set to tau (with the sign of
 the diagonal entry it replaces, + for zero); the power method runs on a block of
-start vectors drawn from Philox stream 6 and reports the largest ||T^{-T} x|| over
-unit iterates x, a lower bound of ||T^{-1}||_2; the check flags when
+start vectors drawn from Philox stream 6 (the first k entries of each row of an
+nv x r block) and reports the largest ||T^{-T} x|| over unit iterates x, a lower
+bound of ||T^{-1}||_2, with T the factor whose inverse multiplies AX (R, or R_2^T
+when truncated); the check flags when
 estimate * delta * nu_X * nu_Y > 1, i.e. when plain GN's triangular factor has a
 singular value below the threshold that eps = delta would use.
 
@@ -147,35 +149,38 @@ def power_start(seed: int, nv: int, k: int) -> np.ndarray:
     return philox.gaussian(seed, philox.STREAM_POWER, nv, k)
 
 
-def inv_norm_power(T: np.ndarray, V0: np.ndarray, iters: int) -> float:
-    """Power-method estimate of ||T^{-1}||_2 for upper triangular T (k x k).
+def inv_norm_power(T: np.ndarray, V0: np.ndarray, iters: int, lower: bool = False) -> float:
+    """Power-method estimate of ||T^{-1}||_2 for triangular T (k x k).
 
     Each row v of V0 is normalized, then per step y = T^{-T} v and z = T^{-1} y by
     substitution (O(k^2)); the estimate is the largest ||y|| seen, a lower bound
-    of ||T^{-1}||_2 = sqrt(lambda_max((T^T T)^{-1})); v <- z / ||z||."""
+    of ||T^{-1}||_2 = sqrt(lambda_max((T T^T)^{-1})); v <- z / ||z||."""
     k = T.shape[0]
     if k == 0 or V0.shape[0] == 0:
         return 0.0
     V = V0 / np.linalg.norm(V0, axis=1, keepdims=True)
     est = 0.0
     for _ in range(iters):
-        Yv = sla.solve_triangular(T, V.T, trans="T", lower=False)   # columns y_i
+        Yv = sla.solve_triangular(T, V.T, trans="T", lower=lower)   # columns y_i
         est = max(est, float(np.max(np.linalg.norm(Yv, axis=0))))
-        Z = sla.solve_triangular(T, Yv, trans="N", lower=False)
+        Z = sla.solve_triangular(T, Yv, trans="N", lower=lower)
         V = (Z / np.linalg.norm(Z, axis=0, keepdims=True)).T
     return est
 
 
-def applied_triangle(c) -> np.ndarray:
-    """The triangular factor whose inverse the factor application uses for an
-    oracle.gn.Core: R (k == r) or R_2 (k < r); ||R_2^{-1}|| = ||R_1^+||."""
-    return c.R2
+def applied_triangle(c):
+    """(T, lower): the triangular factor whose inverse the factor application
+    applies to AX, for an oracle.gn.Core: T = R when k == r (F = AX R^{-1}) and
+    T = R_2^T when k < r (F = (AX Q_2) R_2^{-T}); ||R_2^{-1}|| = ||R_1^+||."""
+    if c.k == c.R.shape[0]:
+        return c.R, False
+    return c.R2.T, True
 
 
 def check(c, delta: float, nu_x: float, nu_y: float, seed: int, nv: int = 8, iters: int = 4):
     """Section 5.1.2: (estimate, flag) with flag = estimate * delta nu_x nu_y > 1."""
-    T = applied_triangle(c)
-    est = inv_norm_power(T, power_start(seed, nv, T.shape[0]), iters)
+    T, lower = applied_triangle(c)
+    est = inv_norm_power(T, power_start(seed, nv, T.shape[0]), iters, lower)
     return est, bool(est * delta * nu_x * nu_y > 1.0)
 
 

@@ -16,11 +16,12 @@ GN_MODE_F64, GN_MODE_F32, GN_MODE_BF16_BS = 0, 1, 2
 GN_BATCH_PASS, GN_BATCH_CORE, GN_BATCH_ALL = 1, 2, 3
 GN_DT_F64, GN_DT_F32, GN_DT_BF16 = 0, 1, 2
 (GN_OP_SKETCH, GN_OP_CORE, GN_OP_FACTORS, GN_OP_APPLY, GN_OP_RESIDUAL, GN_OP_SRHT,
- GN_OP_BACKWARD, GN_OP_MATERIALIZE, GN_OP_UPDATE) = range(9)
+ GN_OP_BACKWARD, GN_OP_MATERIALIZE, GN_OP_UPDATE, GN_OP_CHECK) = range(10)
+(GN_CORE_QR, GN_CORE_SVD, GN_CORE_LIFT_SVD, GN_CORE_LIFT_RRQR, GN_CORE_LIFT_DIAG) = range(5)
 
 EXPORTED = (
     "gn_workspace_size", "gn_generate_gaussian", "gn_srht_generate", "gn_sketch_prepare",
-    "gn_sketch_pass", "gn_sketch", "gn_core",
+    "gn_sketch_pass", "gn_sketch", "gn_core", "gn_core_check",
     "gn_factors", "gn_apply", "gn_backward", "gn_sketch_extend", "gn_sketch_append",
     "gn_sketch_update", "gn_residual", "gn_quantize_bf16_bs",
     "gn_batch_workspace_size", "gn_batch_prepare", "gn_batch_solve", "gn_status_string",
@@ -31,7 +32,7 @@ EXPORTED = (
 class GnProblem(ctypes.Structure):
     _fields_ = [("m", c_int64), ("n", c_int64), ("r", c_int64), ("l", c_int64),
                 ("kind_x", c_int32), ("kind_y", c_int32), ("seed", c_uint64),
-                ("mode", c_int32), ("reserved", c_int32),
+                ("mode", c_int32), ("core_method", c_int32),
                 ("eps", c_double), ("nu_x", c_double), ("nu_y", c_double)]
 
 
@@ -91,6 +92,8 @@ def lib(path: str = LIB_PATH):
                                  c_int64, c_void_p, c_size_t, c_void_p]
     L.gn_core.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, POINTER(GnCoreOut), c_void_p,
                           c_size_t, c_void_p]
+    L.gn_core_check.argtypes = [P, POINTER(GnCoreOut), c_double, c_int32, c_int32, c_void_p,
+                                c_void_p, c_size_t, c_void_p]
     L.gn_factors.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, POINTER(GnCoreOut), c_void_p,
                              c_int64, c_void_p, c_int64, c_void_p, c_size_t, c_void_p]
     L.gn_apply.argtypes = [P, c_int32, c_void_p, c_int64, c_void_p, c_int64, POINTER(GnCoreOut),

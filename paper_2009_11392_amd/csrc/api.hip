@@ -16,6 +16,10 @@ constexpr int64_t kMaxSrhtR = 2048;       // sampled columns per row in register
 struct Plan {
   int64_t m, n, r, l, rl, npad;
   int32_t mode, kx, ky, sdt, adt;
+  int32_t method;   // gn_core_method
+  bool pinv_form;   // core applied as Q2 R2^{-T} Q1^T whatever k is
+  int64_t gate_r;   // k is compared with this to pick the factored form
+  double nux, nuy;
   double tau;
 };
 
@@ -23,7 +27,7 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 gn_status make_plan(const gn_problem* p, Plan& P) {
   if (!p) return GN_ERR_ARG;
-  if (p->reserved != 0) return GN_ERR_ARG;
+  if (p->core_method < GN_CORE_QR || p->core_method > GN_CORE_LIFT_DIAG) return GN_ERR_ARG;
   if (p->mode < GN_MODE_F64 || p->mode > GN_MODE_BF16_BS) return GN_ERR_ARG;
   if (p->kind_x < GN_SKETCH_GAUSSIAN || p->kind_x > GN_SKETCH_USER) return GN_ERR_ARG;
   if (p->kind_y != GN_SKETCH_GAUSSIAN && p->kind_y != GN_SKETCH_USER) return GN_ERR_ARG;
@@ -50,7 +54,14 @@ gn_status make_plan(const gn_problem* p, Plan& P) {
                                          : 1.0;
   if (nuy <= 0.0)
     nuy = (P.ky == GN_SKETCH_GAUSSIAN) ? sqrt((double)P.m) + sqrt((double)P.rl) : 1.0;
+  P.nux = nux;
+  P.nuy = nuy;
   P.tau = (p->eps > 0.0) ? p->eps * nux * nuy : 0.0;
+  P.method = p->core_method;
+  if (P.method >= GN_CORE_LIFT_SVD && !(P.tau > 0.0)) return GN_ERR_ARG;  // nothing to lift to
+  P.pinv_form = P.method == GN_CORE_SVD || P.method == GN_CORE_LIFT_SVD ||
+                P.method == GN_CORE_LIFT_RRQR;
+  P.gate_r = P.r + (P.pinv_form ? 1 : 0);
   return GN_OK;
 }
 
@@ -85,7 +96,7 @@ SketchWs sketch_ws(const Plan& P) {
 }
 
 struct CoreWs {
-  size_t yt, c, qr, z, qr2, split, total;
+  size_t yt, c, qr, z, qr2, split, q1, stab, total;
 };
 CoreWs core_ws(const Plan& P) {
   CoreWs w{};
@@ -109,6 +120,11 @@ CoreWs core_ws(const Plan& P) {
   w.split = off;
   off += (P.mode == GN_MODE_F64) ? dgemm_split_ws_bytes(P.rl, P.r, P.m)
                                  : core_product_ws_bytes(P.m, P.rl, P.r);
+  // the QR's Q before the SVD / pivoting turns it into Q1, and that method's scratch
+  w.q1 = off;
+  if (P.pinv_form) off += align_up((size_t)P.rl * P.r * 8);
+  w.stab = off;
+  off += align_up(stabilize_ws_bytes(P.method, P.r));
   w.total = off;
   return w;
 }
@@ -288,6 +304,10 @@ gn_status gn_workspace_size(const gn_problem* p, int32_t op, int64_t kcols, size
     case GN_OP_BACKWARD: *bytes = back_ws(P).total; break;
     case GN_OP_MATERIALIZE: *bytes = materialize_ws(P); break;
     case GN_OP_UPDATE: *bytes = upd_ws(P).total; break;
+    case GN_OP_CHECK:
+      if (kcols < 1 || kcols > 16) return GN_ERR_ARG;
+      *bytes = power_ws_bytes(P.r, (int32_t)kcols);
+      break;
     default: return GN_ERR_ARG;
   }
   return GN_OK;
@@ -452,11 +472,55 @@ gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void*
     GN_TRY(launch_core_product_f32(P.m, P.rl, P.r, Yf, ldyf, (const float*)AX, ldax,
                                    (float*)(base + W.split), C, s));
   }
-  // Householder QR, kept rank, and the second QR when truncated
-  GN_TRY(launch_qr(P.rl, P.r, C, P.r, out->Q1, P.r, out->R, P.r, (double*)(base + W.qr), nullptr, s));
-  GN_TRY(launch_truncate(P.r, out->R, P.r, P.tau, out->k, out->status, Z, P.r, s));
-  GN_TRY(launch_qr(P.r, P.r, Z, P.r, out->Q2, P.r, out->R2, P.r, (double*)(base + W.qr2), out->k, s));
+  double* qws = (double*)(base + W.qr);
+  switch (P.method) {
+    case GN_CORE_QR:
+      // Householder QR, kept rank, and the second QR when truncated
+      GN_TRY(launch_qr(P.rl, P.r, C, P.r, out->Q1, P.r, out->R, P.r, qws, nullptr, s));
+      GN_TRY(launch_truncate(P.r, out->R, P.r, P.tau, out->k, out->status, Z, P.r, s));
+      GN_TRY(launch_qr(P.r, P.r, Z, P.r, out->Q2, P.r, out->R2, P.r, (double*)(base + W.qr2),
+                       out->k, s));
+      break;
+    case GN_CORE_LIFT_DIAG:
+      GN_TRY(launch_qr(P.rl, P.r, C, P.r, out->Q1, P.r, out->R, P.r, qws, nullptr, s));
+      GN_TRY(launch_lift_diag(P.r, out->R, P.r, P.tau, out->k, out->status, s));
+      break;
+    case GN_CORE_SVD:
+    case GN_CORE_LIFT_SVD: {
+      double* q1 = (double*)(base + W.q1);
+      GN_TRY(launch_qr(P.rl, P.r, C, P.r, q1, P.r, out->R, P.r, qws, nullptr, s));
+      GN_TRY(launch_svd_core(P.r, P.rl, out->R, P.r, q1, P.tau,
+                             P.method == GN_CORE_LIFT_SVD ? 1 : 0, out->k, out->status, out->Q1,
+                             out->Q2, out->R2, base + W.stab, s));
+      break;
+    }
+    case GN_CORE_LIFT_RRQR: {
+      double* q1 = (double*)(base + W.q1);
+      GN_TRY(launch_qr(P.rl, P.r, C, P.r, q1, P.r, out->R, P.r, qws, nullptr, s));
+      GN_TRY(launch_rrqr_core(P.r, P.rl, out->R, P.r, q1, P.tau, out->k, out->status, out->Q1,
+                              out->R, out->Q2, out->R2, base + W.stab, s));
+      break;
+    }
+    default:
+      return GN_ERR_ARG;
+  }
   return GN_OK;
+}
+
+gn_status gn_core_check(const gn_problem* p, const gn_core_out* core, double delta, int32_t nv,
+                        int32_t iters, double* est, void* ws, size_t ws_bytes, gn_stream_t stream_) {
+  Plan P;
+  GN_TRY(make_plan(p, P));
+  hipStream_t s = (hipStream_t)stream_;
+  if (!core || !ws || !core->k || !core->status || !core->R || !core->R2) return GN_ERR_ARG;
+  if (nv < 1 || nv > 16 || iters < 1 || iters > 64) return GN_ERR_ARG;
+  if (!isfinite(delta)) return GN_ERR_ARG;
+  const double tau_d = (delta > 0.0) ? delta * P.nux * P.nuy : P.tau;
+  if (!(tau_d > 0.0)) return GN_ERR_ARG;
+  if (ws_bytes < power_ws_bytes(P.r, nv)) return GN_ERR_WORKSPACE;
+  if (((uintptr_t)ws & 7u) != 0) return GN_ERR_ALIGN;
+  return launch_power_check(P.r, p->seed, nv, iters, core->R, core->R2, core->k, P.pinv_form,
+                            tau_d, core->status, est, ws, s);
 }
 
 gn_status gn_factors(const gn_problem* p, const void* AX, int64_t ldax, const void* YtA,
@@ -471,12 +535,13 @@ gn_status gn_factors(const gn_problem* p, const void* AX, int64_t ldax, const vo
     return GN_ERR_ARG;
   if (ldax < P.r || ldya < P.n || ldf < P.r || ldg < P.n) return GN_ERR_SHAPE;
   // F = AX R^{-1}  or  (AX Q2) R2^{-T}
-  GN_TRY(widen(P.m, P.r, AX, P.adt, ldax, F, ldf, core->k, P.r, s));
+  GN_TRY(widen(P.m, P.r, AX, P.adt, ldax, F, ldf, core->k, P.gate_r, s));
   MatRef ax{AX, P.adt, ldax, 1};
   MatRef q2{core->Q2, GN_DT_F64, P.r, 1};
-  GN_TRY(launch_dgemm(P.m, P.r, P.r, 1.0, ax, q2, 0.0, F, ldf, 1, nullptr, false, s, core->k, P.r,
-                      true));
-  GN_TRY(launch_trsm_core(P.m, P.r, core->R, core->R2, P.r, core->k, F, ldf, 1, false, true, s));
+  GN_TRY(launch_dgemm(P.m, P.r, P.r, 1.0, ax, q2, 0.0, F, ldf, 1, nullptr, false, s, core->k,
+                      P.gate_r, true));
+  GN_TRY(launch_trsm_core(P.m, P.r, core->R, core->R2, P.r, core->k, F, ldf, 1, false, true, s,
+                          false, P.pinv_form));
   // G = Q1[:, :k]^T (Y^T A), rows >= k zero
   MatRef q1t{core->Q1, GN_DT_F64, 1, P.r};
   MatRef yta{YtA, P.adt, ldya, 1};
@@ -528,12 +593,13 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
     GN_TRY(launch_dgemm(P.r, kc, P.rl, 1.0, MatRef{core->Q1, GN_DT_F64, 1, P.r},
                         MatRef{t1, GN_DT_F64, kc, 1}, 0.0, t2, kc, 1, core->k, true, s));
     // t2 <- R^{-1} t2  or  R2^{-T} t2   (left solve on the transposed view)
-    GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, 1, kc, true, true, s));
+    GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, 1, kc, true, true, s,
+                            false, P.pinv_form));
     // t3 = t2 (k == r)  or  Q2 t2 (k < r)
-    GN_TRY(widen(P.r, kc, t2, GN_DT_F64, kc, t3, kc, core->k, P.r, s));
+    GN_TRY(widen(P.r, kc, t2, GN_DT_F64, kc, t3, kc, core->k, P.gate_r, s));
     GN_TRY(launch_dgemm(P.r, kc, P.r, 1.0, MatRef{core->Q2, GN_DT_F64, P.r, 1},
                         MatRef{t2, GN_DT_F64, kc, 1}, 0.0, t3, kc, 1, nullptr, false, s, core->k,
-                        P.r, true));
+                        P.gate_r, true));
     // out = AX t3 : m x kc
     GN_TRY(launch_dgemm(P.m, kc, P.r, 1.0, ax, MatRef{t3, GN_DT_F64, kc, 1}, 0.0, out, ldo, 1,
                         nullptr, false, s));
@@ -542,11 +608,12 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
     GN_TRY(launch_dgemm(kc, P.r, P.m, 1.0, MatRef{W, GN_DT_F64, ldw, 1}, ax, 0.0, t1, P.r, 1,
                         nullptr, false, s, nullptr, 0, true, sp, Wl.split_bytes));
     // t2 = t1 (k == r)  or  t1 Q2 (k < r); then t2 <- t2 R^{-1}  or  t2 R2^{-T}
-    GN_TRY(widen(kc, P.r, t1, GN_DT_F64, P.r, t2, P.r, core->k, P.r, s));
+    GN_TRY(widen(kc, P.r, t1, GN_DT_F64, P.r, t2, P.r, core->k, P.gate_r, s));
     GN_TRY(launch_dgemm(kc, P.r, P.r, 1.0, MatRef{t1, GN_DT_F64, P.r, 1},
                         MatRef{core->Q2, GN_DT_F64, P.r, 1}, 0.0, t2, P.r, 1, nullptr, false, s,
-                        core->k, P.r, true));
-    GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, P.r, 1, false, true, s));
+                        core->k, P.gate_r, true));
+    GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, P.r, 1, false, true, s,
+                            false, P.pinv_form));
     // t3 = t2 Q1^T : kc x rl   (columns of t2 beyond k are zero)
     GN_TRY(launch_dgemm(kc, P.rl, P.r, 1.0, MatRef{t2, GN_DT_F64, P.r, 1},
                         MatRef{core->Q1, GN_DT_F64, 1, P.r}, 0.0, t3, P.rl, 1, nullptr, false, s));
@@ -566,6 +633,7 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
   hipStream_t s = (hipStream_t)stream_;
   if (P.mode != GN_MODE_F64 && P.mode != GN_MODE_F32) return GN_ERR_UNSUPPORTED;
   if (P.kx != GN_SKETCH_GAUSSIAN || P.ky != GN_SKETCH_GAUSSIAN) return GN_ERR_UNSUPPORTED;
+  if (P.method != GN_CORE_QR) return GN_ERR_UNSUPPORTED;  // differentiates the truncated QR only
   if (!Gbar || !YtA || !core || !dA || !ws || !core->k || !core->Q1 || !core->R || !core->Q2 ||
       !core->R2)
     return GN_ERR_ARG;

@@ -266,7 +266,27 @@ gn_status launch_truncate(int64_t r, const double* R, int64_t ldr, double tau, i
 // when k < r), transposed when left: X R^{-1} or X R_11^{-T} on the kept columns.
 gn_status launch_trsm_core(int64_t rows, int64_t r, const double* R, const double* R2, int64_t ldt,
                            const int32_t* k, double* X, int64_t rsx, int64_t csx, bool left,
-                           bool maybe_trunc, hipStream_t s, bool r_only = false);
+                           bool maybe_trunc, hipStream_t s, bool r_only = false,
+                           bool force_trunc = false);
+
+// stabilize.hip : the other Section 5.1.1 stabilizations and the Section 5.1.2
+// check.  R (r x r, ld ldr) and Q1 ((r+l) x r, ld r) are C's QR; the outputs
+// follow gn_core_out for the method.  R may alias Rp.
+size_t stabilize_ws_bytes(int32_t method, int64_t r);
+gn_status launch_svd_core(int64_t r, int64_t rl, const double* R, int64_t ldr, const double* Q1,
+                          double tau, int lift, int32_t* k, int32_t* status, double* Q1_out,
+                          double* Q2, double* R2, void* ws, hipStream_t s);
+gn_status launch_rrqr_core(int64_t r, int64_t rl, const double* R, int64_t ldr, const double* Q1,
+                           double tau, int32_t* k, int32_t* status, double* Q1_out, double* Rp,
+                           double* Q2, double* R2, void* ws, hipStream_t s);
+gn_status launch_lift_diag(int64_t r, double* R, int64_t ldr, double tau, int32_t* k,
+                           int32_t* status, hipStream_t s);
+size_t power_ws_bytes(int64_t r, int32_t nv);
+// force_trunc: the core is in the factored form Q2 R2^{-T} Q1^T whatever k is.
+gn_status launch_power_check(int64_t r, uint64_t seed, int32_t nv, int32_t iters,
+                             const double* R, const double* R2, const int32_t* k, bool force_trunc,
+                             double tau_d, int32_t* status, double* est_out, void* ws,
+                             hipStream_t s);
 
 // grad.hip : helpers of the reverse mode.
 // out (cols x rows) = src^T with rows >= *k of out zeroed (src rows x cols).

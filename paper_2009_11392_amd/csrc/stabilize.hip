@@ -1,0 +1,797 @@
+// The other stabilizations of the GN core (Section 5.1.1) and the power-method
+// check of plain GN (Section 5.1.2), all in FP64.
+//
+// SVD route and perturbation (a).  After the Householder QR C = Q1 R, the SVD of
+// R comes from one-sided (Hestenes) Jacobi on the rows of R: the vectors w_c =
+// R[c, :] are rotated in pairs until mutually orthogonal, W J = [w'_c] with J
+// orthogonal, so R^T J = U' Sigma and R = J Sigma U'^T, C = (Q1 J) Sigma U'^T.
+// The rotation of a pair zeroes its inner product (Rutishauser's formulas) and
+// is skipped when |w_p . w_q| <= sqrt(r) u ||w_p|| ||w_q||; one-sided Jacobi
+// keeps the singular values accurate relative to the scale of each vector.
+// Vectors are grouped in blocks of B; a launch pairs every block with one other
+// (round robin over blocks, the circle method), so a sweep over all pairs takes
+// nbe - 1 launches.  One 256-thread workgroup holds the 2B vectors of its pair
+// in registers (element i of every vector in thread i mod 256) and runs B inner
+// rounds of B disjoint pairs between the two blocks (the first launch of a sweep
+// runs the full 2B - 1 rounds, which also covers the pairs inside each block).
+// Each inner round needs one workgroup reduction of 3B dots; lane p then
+// computes the rotation of pair p and every lane applies the B rotations to its
+// elements.  The rotations are accumulated in a 2B x 2B matrix in LDS and applied
+// to J once per launch.  A sweep in which no workgroup rotated sets the converged
+// flag, after which every launch returns at once; the sweep count is bounded.
+//
+// Perturbation (b).  Householder QR with column pivoting (largest remaining
+// column norm, lowest index on ties; norms recomputed at every step, not
+// downdated) run on R, whose column norms are C's, gives the permutation P; the
+// blocked QR of R P then gives R P = Q_R R_p, so C P = (Q1 Q_R) R_p.  R_p's small
+// diagonal entries are raised to tau and the QR of the lifted R_p^T = Q3 R3 puts
+// the inverse in the factored form of the truncated core: the core
+// pseudoinverse is (P Q3) R3^{-T} (Q1 Q_R)^T.
+//
+// Perturbation (c).  R's diagonal (non-negative after the sign fix) raised to tau.
+//
+// Power-method check.  nv start vectors (Philox stream 6) are driven through
+// y = T^{-T} v and z = T^{-1} y by the blocked triangular solves of the factor
+// application, T being the factor whose inverse multiplies AX; the estimate is
+// the largest ||y|| over unit iterates v.
+#include "gn_internal.h"
+#include "wave_ops.h"
+
+#include <math.h>
+
+#include <utility>
+
+namespace gn {
+namespace {
+
+constexpr int JT = 256;      // threads of a Jacobi workgroup
+constexpr int JW = JT / 64;  // its waves
+constexpr int kMaxSweeps = 20;
+constexpr int kSortMax = 4096;
+
+constexpr int pow2_at_least(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Position q of a circle-method round robin over n players in round t.
+__host__ __device__ constexpr int rr_pos(int q, int t, int n) {
+  return q == 0 ? 0 : 1 + (q - 1 + t) % (n - 1);
+}
+// Pair p of inner round s over the 2B columns of a block pair: FULL covers every
+// pair of the 2B columns in 2B - 1 rounds; otherwise only pairs across the two
+// blocks, in B rounds.
+template <int B, bool FULL>
+__host__ __device__ constexpr int pair_a(int p, int s) {
+  return FULL ? rr_pos(p, s, 2 * B) : p;
+}
+template <int B, bool FULL>
+__host__ __device__ constexpr int pair_b(int p, int s) {
+  return FULL ? rr_pos(2 * B - 1 - p, s, 2 * B) : B + (p + s) % B;
+}
+
+__device__ __forceinline__ void jacobi_rotation(double a, double b, double g, double tol, double& c,
+                                                double& s, int& rot) {
+  c = 1.0;
+  s = 0.0;
+  rot = 0;
+  if (g != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+    const double zeta = (b - a) / (2.0 * g);
+    const double az = fabs(zeta);
+    double t = (az < 1e150) ? 1.0 / (az + sqrt(fma(az, az, 1.0))) : 0.5 / az;
+    if (zeta < 0.0) t = -t;
+    c = 1.0 / sqrt(fma(t, t, 1.0));
+    s = c * t;
+    rot = 1;
+  }
+}
+
+template <int RPT, int B, bool FULL, int S>
+__device__ __forceinline__ void jacobi_inner(double (&w)[RPT][2 * B],
+                                             double (*part)[JW][pow2_at_least(3 * B)],
+                                             double (*Gm)[2 * B + 1], int tid, int lane, int wave,
+                                             double tol, int* rotated) {
+  constexpr int NV = pow2_at_least(3 * B);
+  constexpr int C2 = 2 * B;
+  constexpr int buf = S & 1;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+  for (int p = 0; p < B; ++p) {
+    const int a = pair_a<B, FULL>(p, S), b = pair_b<B, FULL>(p, S);
+    double sa = 0.0, sb = 0.0, sg = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      sa = fma(w[q][a], w[q][a], sa);
+      sb = fma(w[q][b], w[q][b], sb);
+      sg = fma(w[q][a], w[q][b], sg);
+    }
+    acc[p] = sa;
+    acc[B + p] = sb;
+    acc[2 * B + p] = sg;
+  }
+  int slot;
+  const double ws = wave_transpose_sum<NV>(acc, lane, &slot);
+  constexpr int kLowBits = 64 / NV;
+  if ((lane & (kLowBits - 1)) == 0) part[buf][wave][slot] = ws;
+  __syncthreads();
+  // lane p < B of every wave forms the rotation of pair p from the same sums
+  double c = 1.0, s = 0.0;
+  int rot = 0;
+  if (lane < B) {
+    double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+    for (int v = 0; v < JW; ++v) {
+      a += part[buf][v][lane];
+      b += part[buf][v][B + lane];
+      g += part[buf][v][2 * B + lane];
+    }
+    jacobi_rotation(a, b, g, tol, c, s, rot);
+  }
+  if (rot && wave == 0) *rotated = 1;
+#pragma unroll
+  for (int p = 0; p < B; ++p) {
+    const int a = pair_a<B, FULL>(p, S), b = pair_b<B, FULL>(p, S);
+    const double cp = readlane_f64(c, p), sp = readlane_f64(s, p);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const double wa = w[q][a], wb = w[q][b];
+      w[q][a] = fma(cp, wa, -sp * wb);
+      w[q][b] = fma(sp, wa, cp * wb);
+    }
+    if (tid < C2) {
+      const double ga = Gm[tid][a], gb = Gm[tid][b];
+      Gm[tid][a] = fma(cp, ga, -sp * gb);
+      Gm[tid][b] = fma(sp, ga, cp * gb);
+    }
+  }
+}
+
+template <int RPT, int B, bool FULL, int... S>
+__device__ __forceinline__ void jacobi_rounds(std::integer_sequence<int, S...>,
+                                              double (&w)[RPT][2 * B],
+                                              double (*part)[JW][pow2_at_least(3 * B)],
+                                              double (*Gm)[2 * B + 1], int tid, int lane, int wave,
+                                              double tol, int* rotated) {
+  (jacobi_inner<RPT, B, FULL, S>(w, part, Gm, tid, lane, wave, tol, rotated), ...);
+}
+
+// One launch of a sweep: workgroup p takes blocks (rr_pos(p), rr_pos(nbe-1-p))
+// of round t.  W and J hold vector c at [c*r, c*r + r).
+template <int RPT, int B, bool FULL>
+__global__ void __launch_bounds__(JT) jacobi_round(double* __restrict__ W, double* __restrict__ J,
+                                                   int32_t* __restrict__ ctl, int64_t r, int nbe,
+                                                   int t, int sweep, double tol) {
+  if (ctl[0] != 0) return;  // converged in an earlier sweep
+  constexpr int C2 = 2 * B;
+  constexpr int NV = pow2_at_least(3 * B);
+  __shared__ double part[2][JW][NV];
+  __shared__ double Gm[C2][C2 + 1];
+  __shared__ int rotated;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = blockIdx.x;
+  const int bi = rr_pos(p, t, nbe), bj = rr_pos(nbe - 1 - p, t, nbe);
+  int64_t col[C2];
+#pragma unroll
+  for (int c = 0; c < C2; ++c) col[c] = (c < B) ? (int64_t)bi * B + c : (int64_t)bj * B + (c - B);
+  double w[RPT][C2];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int64_t i = tid + (int64_t)q * JT;
+#pragma unroll
+    for (int c = 0; c < C2; ++c) w[q][c] = (i < r && col[c] < r) ? W[col[c] * r + i] : 0.0;
+  }
+  for (int e = tid; e < C2 * C2; e += JT) Gm[e / C2][e % C2] = (e / C2 == e % C2) ? 1.0 : 0.0;
+  if (tid == 0) rotated = 0;
+  __syncthreads();
+  if (FULL)
+    jacobi_rounds<RPT, B, FULL>(std::make_integer_sequence<int, C2 - 1>{}, w, part, Gm, tid, lane,
+                                wave, tol, &rotated);
+  else
+    jacobi_rounds<RPT, B, FULL>(std::make_integer_sequence<int, B>{}, w, part, Gm, tid, lane, wave,
+                                tol, &rotated);
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int64_t i = tid + (int64_t)q * JT;
+    if (i < r) {
+#pragma unroll
+      for (int c = 0; c < C2; ++c)
+        if (col[c] < r) W[col[c] * r + i] = w[q][c];
+    }
+  }
+  __syncthreads();
+  // J[:, cols] <- J[:, cols] Gm
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int64_t i = tid + (int64_t)q * JT;
+    if (i < r) {
+      double jr[C2];
+#pragma unroll
+      for (int c = 0; c < C2; ++c) jr[c] = (col[c] < r) ? J[col[c] * r + i] : 0.0;
+#pragma unroll
+      for (int c = 0; c < C2; ++c) {
+        double o = 0.0;
+#pragma unroll
+        for (int d = 0; d < C2; ++d) o = fma(jr[d], Gm[d][c], o);
+        if (col[c] < r) J[col[c] * r + i] = o;
+      }
+    }
+  }
+  if (tid == 0 && rotated) atomicAdd(&ctl[2 + sweep], 1);
+}
+
+__global__ void __launch_bounds__(64) jacobi_sweep_end(int32_t* ctl, int sweep) {
+  if (threadIdx.x != 0 || ctl[0] != 0) return;
+  ctl[1] = sweep + 1;
+  if (ctl[2 + sweep] == 0) ctl[0] = 1;
+}
+
+// W = rows of R (vector c = R[c, :], zero below the diagonal), J = I, counters 0.
+__global__ void __launch_bounds__(256) jacobi_init(const double* __restrict__ R, int64_t ldr,
+                                                   int64_t r, double* __restrict__ W,
+                                                   double* __restrict__ J, int32_t* ctl) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < 2 + kMaxSweeps) ctl[e] = 0;
+  if (e >= r * r) return;
+  const int64_t c = e / r, i = e - c * r;
+  W[e] = (i >= c) ? R[c * ldr + i] : 0.0;
+  J[e] = (i == c) ? 1.0 : 0.0;
+}
+
+// sigma[c] = ||W[c*r .. c*r + r)||, one wave per vector, fixed-order sums.
+__global__ void __launch_bounds__(256) vec_norms(const double* __restrict__ W, int64_t r,
+                                                 double* __restrict__ sigma) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= r) return;
+  double s = 0.0;
+  for (int64_t i = lane; i < r; i += 64) {
+    const double x = W[c * r + i];
+    s = fma(x, x, s);
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) sigma[c] = sqrt(s);
+}
+
+// Sort sigma descending (ties by index, NaN first), write perm and the sorted
+// values, the kept rank and the status bits.  lift: perturbation (a) (k = r, bit
+// 16 when something was raised); else the SVD truncation (k = count >= tau, or
+// > 0 when tau <= 0).  Bit 32: Jacobi stopped at the sweep limit.
+__global__ void __launch_bounds__(1024) svd_sort(const double* __restrict__ sigma, int64_t r,
+                                                 double tau, int lift, const int32_t* ctl,
+                                                 int32_t* __restrict__ perm,
+                                                 double* __restrict__ sig_sorted, int32_t* kout,
+                                                 int32_t* status) {
+  __shared__ double key[kSortMax];
+  __shared__ int idx[kSortMax];
+  __shared__ int s_first, s_nf, s_low;
+  const int tid = threadIdx.x;
+  int n = 1;
+  while (n < r) n <<= 1;
+  for (int i = tid; i < n; i += 1024) {
+    double v = (i < r) ? sigma[i] : -INFINITY;
+    if (i < r && isnan(v)) v = INFINITY;
+    key[i] = v;
+    idx[i] = i;
+  }
+  if (tid == 0) {
+    s_first = (int)r;
+    s_nf = 0;
+    s_low = 0;
+  }
+  __syncthreads();
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < n; i += 1024) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool first_before = (key[i] > key[j]) || (key[i] == key[j] && idx[i] < idx[j]);
+          const bool want = (i & size) == 0;  // this run in "comes before" order
+          if (first_before != want) {
+            const double tk = key[i];
+            key[i] = key[j];
+            key[j] = tk;
+            const int ti = idx[i];
+            idx[i] = idx[j];
+            idx[j] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = tid; j < r; j += 1024) {
+    const double v = sigma[idx[j]];
+    perm[j] = idx[j];
+    sig_sorted[j] = v;
+    if (!isfinite(v)) atomicOr(&s_nf, 1);
+    const bool keep = isfinite(v) && ((tau > 0.0) ? (v >= tau) : (v > 0.0));
+    if (!keep) atomicMin(&s_first, j);
+    if (lift && !(v >= tau)) atomicOr(&s_low, 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int k = lift ? (int)r : s_first;
+    *kout = k;
+    *status = (s_nf ? 1 : 0) | (k == 0 ? 2 : 0) | (lift && s_low ? 16 : 0) | (ctl[0] == 0 ? 32 : 0);
+  }
+}
+
+// dst[i*r + j] = src[perm[j]*r + i] (/ sig[j], or 0 when sig[j] == 0, if sig).
+__global__ void __launch_bounds__(256) gather_transpose(const double* __restrict__ src,
+                                                        const int32_t* __restrict__ perm,
+                                                        const double* __restrict__ sig, int64_t r,
+                                                        double* __restrict__ dst) {
+  __shared__ double tile[32][33];
+  const int64_t j0 = (int64_t)blockIdx.x * 32, i0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t j = j0 + y, i = i0 + tx;
+    double v = 0.0;
+    if (j < r && i < r) {
+      v = src[(int64_t)perm[j] * r + i];
+      if (sig) {
+        const double sv = sig[j];
+        v = (sv != 0.0) ? v / sv : 0.0;
+      }
+    }
+    tile[y][tx] = v;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t i = i0 + y, j = j0 + tx;
+    if (i < r && j < r) dst[i * r + j] = tile[tx][y];
+  }
+}
+
+// R2 = diag(sig) (lift: diag(max(sig, tau))), zero elsewhere.
+__global__ void __launch_bounds__(256) diag_matrix(const double* __restrict__ sig, int64_t r,
+                                                   double tau, int lift, double* __restrict__ R2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= r * r) return;
+  const int64_t i = e / r, j = e - i * r;
+  double v = 0.0;
+  if (i == j) {
+    v = sig[i];
+    if (lift && !(v >= tau)) v = tau;
+  }
+  R2[e] = v;
+}
+
+// ---------------------------------------------------------------------------- pivoted QR
+// B = R (vector c = column c of R at B[c*r .. c*r + r)), perm = identity.
+__global__ void __launch_bounds__(256) qrcp_init(const double* __restrict__ R, int64_t ldr,
+                                                 int64_t r, double* __restrict__ Bc,
+                                                 int32_t* __restrict__ perm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < r) perm[e] = (int32_t)e;
+  if (e >= r * r) return;
+  const int64_t c = e / r, i = e - c * r;
+  Bc[e] = R[i * ldr + c];
+}
+
+// Step j: pivot = the largest remaining column norm (lowest index on ties; NaN
+// counts as largest), swapped into position j, then the Householder reflector of
+// column j (rows j..r-1): beta on the diagonal, v (v_j = 1) below it, tau_h.
+__global__ void __launch_bounds__(1024) qrcp_pivot(double* __restrict__ Bc, double* __restrict__ nrm,
+                                                   int32_t* __restrict__ perm,
+                                                   double* __restrict__ tauh, int64_t r, int64_t j) {
+  __shared__ double sv[1024];
+  __shared__ int64_t si[1024];
+  __shared__ double sred[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double best = -1.0;
+  int64_t bi = r;
+  for (int64_t c = j + tid; c < r; c += 1024) {
+    double v = nrm[c];
+    if (isnan(v)) v = INFINITY;
+    if (v > best || (v == best && c < bi)) {
+      best = v;
+      bi = c;
+    }
+  }
+  sv[tid] = best;
+  si[tid] = bi;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (tid < w) {
+      const double v2 = sv[tid + w];
+      const int64_t i2 = si[tid + w];
+      if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) {
+        sv[tid] = v2;
+        si[tid] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t p = si[0];
+  if (p != j && p < r) {
+    for (int64_t i = tid; i < r; i += 1024) {
+      const double a = Bc[j * r + i];
+      Bc[j * r + i] = Bc[p * r + i];
+      Bc[p * r + i] = a;
+    }
+    if (tid == 0) {
+      const double t = nrm[j];
+      nrm[j] = nrm[p];
+      nrm[p] = t;
+      const int32_t q = perm[j];
+      perm[j] = perm[p];
+      perm[p] = q;
+    }
+  }
+  __syncthreads();
+  double s = 0.0;
+  for (int64_t i = j + 1 + tid; i < r; i += 1024) {
+    const double x = Bc[j * r + i];
+    s = fma(x, x, s);
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) sred[wave] = s;
+  __syncthreads();
+  double sigma2 = 0.0;
+  for (int w = 0; w < 16; ++w) sigma2 += sred[w];
+  const double alpha = Bc[j * r + j];
+  if (sigma2 == 0.0) {
+    if (tid == 0) tauh[j] = 0.0;
+    return;
+  }
+  const double beta = -copysign(sqrt(fma(alpha, alpha, sigma2)), alpha);
+  const double scale = 1.0 / (alpha - beta);
+  for (int64_t i = j + 1 + tid; i < r; i += 1024) Bc[j * r + i] *= scale;
+  if (tid == 0) {
+    Bc[j * r + j] = beta;
+    tauh[j] = (beta - alpha) / beta;
+  }
+}
+
+// Step j: trailing columns c > j (one wave each) <- (I - tau_h v v^T) column,
+// then nrm[c] = the norm of rows j+1.. (the next step's candidates).
+__global__ void __launch_bounds__(256) qrcp_update(double* __restrict__ Bc, double* __restrict__ nrm,
+                                                   const double* __restrict__ tauh, int64_t r,
+                                                   int64_t j) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = j + 1 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= r) return;
+  const double th = tauh[j];
+  double* x = Bc + c * r;
+  const double* v = Bc + j * r;
+  if (th != 0.0) {
+    double s = 0.0;
+    for (int64_t i = j + 1 + lane; i < r; i += 64) s = fma(v[i], x[i], s);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    const double tw = th * (x[j] + s);
+    for (int64_t i = j + 1 + lane; i < r; i += 64) x[i] = fma(-tw, v[i], x[i]);
+    if (lane == 0) x[j] -= tw;
+  }
+  double s2 = 0.0;
+  for (int64_t i = j + 1 + lane; i < r; i += 64) s2 = fma(x[i], x[i], s2);
+  for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+  if (lane == 0) nrm[c] = sqrt(s2);
+}
+
+// Z[i*r + c] = R[i*ldr + perm[c]] (R with its columns permuted).
+__global__ void __launch_bounds__(256) gather_cols(const double* __restrict__ R, int64_t ldr,
+                                                   const int32_t* __restrict__ perm, int64_t r,
+                                                   double* __restrict__ Z) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= r * r) return;
+  const int64_t i = e / r, c = e - i * r;
+  Z[e] = R[i * ldr + perm[c]];
+}
+
+__device__ __forceinline__ double lifted(double d, double tau) {
+  return (fabs(d) < tau) ? ((d < 0.0) ? -tau : tau) : d;
+}
+
+// Z2 = (R_p with its small diagonal raised to tau)^T, row-major r x r.
+__global__ void __launch_bounds__(256) lift_transpose(const double* __restrict__ Rp, int64_t r,
+                                                      double tau, double* __restrict__ Z2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= r * r) return;
+  const int64_t i = e / r, j = e - i * r;
+  double v = 0.0;
+  if (i == j)
+    v = lifted(Rp[i * r + i], tau);
+  else if (j < i)
+    v = Rp[j * r + i];
+  Z2[e] = v;
+}
+
+// k = r; status: 1 non-finite diagonal, 16 some |diagonal| < tau.  When
+// in_place, the diagonal is raised to tau in R itself (perturbation (c)).
+__global__ void __launch_bounds__(256) lift_scan(double* __restrict__ R, int64_t ldr, int64_t r,
+                                                 double tau, int in_place, int32_t* kout,
+                                                 int32_t* status) {
+  __shared__ int s_nf, s_low;
+  if (threadIdx.x == 0) {
+    s_nf = 0;
+    s_low = 0;
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < r; i += 256) {
+    const double d = R[i * ldr + i];
+    if (!isfinite(d)) atomicOr(&s_nf, 1);
+    if (fabs(d) < tau) {
+      atomicOr(&s_low, 1);
+      if (in_place) R[i * ldr + i] = lifted(d, tau);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *kout = (int32_t)r;
+    *status = (s_nf ? 1 : 0) | (s_low ? 16 : 0);
+  }
+}
+
+// Q2[perm[j]*r + c] = Q3[j*r + c]  (Q2 = P Q3).
+__global__ void __launch_bounds__(256) scatter_rows(const double* __restrict__ Q3,
+                                                    const int32_t* __restrict__ perm, int64_t r,
+                                                    double* __restrict__ Q2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= r * r) return;
+  const int64_t j = e / r, c = e - j * r;
+  Q2[(int64_t)perm[j] * r + c] = Q3[e];
+}
+
+// ---------------------------------------------------------------------------- power method
+// Rows of V (nv x r): entries at or beyond the kept size zeroed, rows normalized
+// to unit length; est = 0.  One wave per row.
+__global__ void __launch_bounds__(1024) power_prep(double* __restrict__ V, int nv, int64_t r,
+                                                   const int32_t* kdev, double* est) {
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int64_t k = (*kdev < r) ? *kdev : r;
+  if (threadIdx.x == 0) *est = 0.0;
+  if (row >= nv) return;
+  double* v = V + (int64_t)row * r;
+  double s = 0.0;
+  for (int64_t i = lane; i < r; i += 64) {
+    if (i >= k) v[i] = 0.0;
+    const double x = (i < k) ? v[i] : 0.0;
+    s = fma(x, x, s);
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  const double inv = (s > 0.0) ? 1.0 / sqrt(s) : 0.0;
+  for (int64_t i = lane; i < k; i += 64) v[i] *= inv;
+}
+
+// est = max(est, max_row ||row||); normalize: rows scaled to unit length.
+__global__ void __launch_bounds__(1024) power_rows(double* __restrict__ V, int nv, int64_t r,
+                                                   double* est, int normalize) {
+  __shared__ double sn[16];
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  double nr = 0.0;
+  if (row < nv) {
+    double* v = V + (int64_t)row * r;
+    double s = 0.0;
+    for (int64_t i = lane; i < r; i += 64) s = fma(v[i], v[i], s);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    nr = sqrt(s);
+    if (normalize && nr > 0.0) {
+      const double inv = 1.0 / nr;
+      for (int64_t i = lane; i < r; i += 64) v[i] *= inv;
+    }
+  }
+  if (normalize) return;
+  if (lane == 0) sn[row] = nr;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = *est;
+    for (int w = 0; w < nv; ++w) m = fmax(m, sn[w]);
+    *est = m;
+  }
+}
+
+__global__ void __launch_bounds__(64) power_flag(const double* est, double tau_d,
+                                                 int32_t* status, double* est_out) {
+  if (threadIdx.x != 0) return;
+  const double e = *est;
+  if (e * tau_d > 1.0 || isnan(e)) *status |= 8;
+  if (est_out) *est_out = e;
+}
+
+// ---------------------------------------------------------------------------- Jacobi driver
+struct JacobiShape {
+  int rpt, b;
+};
+JacobiShape jacobi_shape(int64_t r) {
+  if (r <= 256) return {1, 8};
+  if (r <= 512) return {2, 8};
+  if (r <= 1024) return {4, 8};
+  if (r <= 2048) return {8, 4};
+  return {16, 2};
+}
+
+template <int RPT, int B>
+gn_status run_jacobi(double* W, double* J, int32_t* ctl, int64_t r, double tol, hipStream_t s) {
+  const int nb = (int)cdiv(r, B);
+  const int nbe = nb + (nb & 1);
+  const dim3 grid((unsigned)(nbe / 2)), block(JT);
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    for (int t = 0; t < nbe - 1; ++t) {
+      if (t == 0)
+        jacobi_round<RPT, B, true><<<grid, block, 0, s>>>(W, J, ctl, r, nbe, t, sweep, tol);
+      else
+        jacobi_round<RPT, B, false><<<grid, block, 0, s>>>(W, J, ctl, r, nbe, t, sweep, tol);
+      GN_LAUNCH_CHECK();
+    }
+    jacobi_sweep_end<<<dim3(1), dim3(64), 0, s>>>(ctl, sweep);
+    GN_LAUNCH_CHECK();
+  }
+  return GN_OK;
+}
+
+struct SvdWs {
+  size_t w, j, sig, sorted, perm, ctl, total;
+};
+SvdWs svd_ws(int64_t r) {
+  SvdWs w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  w.w = take((size_t)r * r * 8);
+  w.j = take((size_t)r * r * 8);
+  w.sig = take((size_t)r * 8);
+  w.sorted = take((size_t)r * 8);
+  w.perm = take((size_t)r * 4);
+  w.ctl = take((size_t)(2 + kMaxSweeps) * 4);
+  w.total = off;
+  return w;
+}
+
+struct RrqrWs {
+  size_t b, nrm, tauh, perm, z, qr, z2, q3, qrws, total;
+};
+RrqrWs rrqr_ws(int64_t r) {
+  RrqrWs w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  w.b = take((size_t)r * r * 8);
+  w.nrm = take((size_t)r * 8);
+  w.tauh = take((size_t)r * 8);
+  w.perm = take((size_t)r * 4);
+  w.z = take((size_t)r * r * 8);
+  w.qr = take((size_t)r * r * 8);
+  w.z2 = take((size_t)r * r * 8);
+  w.q3 = take((size_t)r * r * 8);
+  w.qrws = take(qr_ws_bytes(r, r));
+  w.total = off;
+  return w;
+}
+
+}  // namespace
+
+size_t stabilize_ws_bytes(int32_t method, int64_t r) {
+  if (method == GN_CORE_SVD || method == GN_CORE_LIFT_SVD) return svd_ws(r).total;
+  if (method == GN_CORE_LIFT_RRQR) return rrqr_ws(r).total;
+  return 0;
+}
+
+gn_status launch_svd_core(int64_t r, int64_t rl, const double* R, int64_t ldr, const double* Q1,
+                          double tau, int lift, int32_t* k, int32_t* status, double* Q1_out,
+                          double* Q2, double* R2, void* ws, hipStream_t s) {
+  if (r < 1 || r > kSortMax) return GN_ERR_UNSUPPORTED;
+  const SvdWs L = svd_ws(r);
+  char* base = (char*)ws;
+  double* W = (double*)(base + L.w);
+  double* J = (double*)(base + L.j);
+  double* sig = (double*)(base + L.sig);
+  double* srt = (double*)(base + L.sorted);
+  int32_t* perm = (int32_t*)(base + L.perm);
+  int32_t* ctl = (int32_t*)(base + L.ctl);
+  const int64_t nel = r * r > 2 + kMaxSweeps ? r * r : 2 + kMaxSweeps;
+  jacobi_init<<<dim3((unsigned)cdiv(nel, 256)), dim3(256), 0, s>>>(R, ldr, r, W, J, ctl);
+  GN_LAUNCH_CHECK();
+  const double tol = sqrt((double)r) * 0x1.0p-53;
+  const JacobiShape sh = jacobi_shape(r);
+  if (sh.rpt == 1)
+    GN_TRY((run_jacobi<1, 8>(W, J, ctl, r, tol, s)));
+  else if (sh.rpt == 2)
+    GN_TRY((run_jacobi<2, 8>(W, J, ctl, r, tol, s)));
+  else if (sh.rpt == 4)
+    GN_TRY((run_jacobi<4, 8>(W, J, ctl, r, tol, s)));
+  else if (sh.rpt == 8)
+    GN_TRY((run_jacobi<8, 4>(W, J, ctl, r, tol, s)));
+  else
+    GN_TRY((run_jacobi<16, 2>(W, J, ctl, r, tol, s)));
+  vec_norms<<<dim3((unsigned)cdiv(r, 4)), dim3(256), 0, s>>>(W, r, sig);
+  GN_LAUNCH_CHECK();
+  svd_sort<<<dim3(1), dim3(1024), 0, s>>>(sig, r, tau, lift, ctl, perm, srt, k, status);
+  GN_LAUNCH_CHECK();
+  const dim3 tg((unsigned)cdiv(r, 32), (unsigned)cdiv(r, 32));
+  // Q2 = U' (right singular vectors of C, sorted), then J's columns sorted into W
+  gather_transpose<<<tg, dim3(256), 0, s>>>(W, perm, srt, r, Q2);
+  GN_LAUNCH_CHECK();
+  gather_transpose<<<tg, dim3(256), 0, s>>>(J, perm, nullptr, r, W);
+  GN_LAUNCH_CHECK();
+  diag_matrix<<<dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, s>>>(srt, r, tau, lift, R2);
+  GN_LAUNCH_CHECK();
+  // Q1_out = Q1 J (left singular vectors of C)
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, MatRef{Q1, GN_DT_F64, r, 1}, MatRef{W, GN_DT_F64, r, 1}, 0.0,
+                      Q1_out, r, 1, nullptr, false, s));
+  return GN_OK;
+}
+
+gn_status launch_rrqr_core(int64_t r, int64_t rl, const double* R, int64_t ldr, const double* Q1,
+                           double tau, int32_t* k, int32_t* status, double* Q1_out, double* Rp,
+                           double* Q2, double* R2, void* ws, hipStream_t s) {
+  const RrqrWs L = rrqr_ws(r);
+  char* base = (char*)ws;
+  double* Bc = (double*)(base + L.b);
+  double* nrm = (double*)(base + L.nrm);
+  double* tauh = (double*)(base + L.tauh);
+  int32_t* perm = (int32_t*)(base + L.perm);
+  double* Z = (double*)(base + L.z);
+  double* Qr = (double*)(base + L.qr);
+  double* Z2 = (double*)(base + L.z2);
+  double* Q3 = (double*)(base + L.q3);
+  double* qws = (double*)(base + L.qrws);
+  qrcp_init<<<dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, s>>>(R, ldr, r, Bc, perm);
+  GN_LAUNCH_CHECK();
+  vec_norms<<<dim3((unsigned)cdiv(r, 4)), dim3(256), 0, s>>>(Bc, r, nrm);
+  GN_LAUNCH_CHECK();
+  for (int64_t j = 0; j + 1 < r; ++j) {
+    qrcp_pivot<<<dim3(1), dim3(1024), 0, s>>>(Bc, nrm, perm, tauh, r, j);
+    GN_LAUNCH_CHECK();
+    qrcp_update<<<dim3((unsigned)cdiv(r - j - 1, 4)), dim3(256), 0, s>>>(Bc, nrm, tauh, r, j);
+    GN_LAUNCH_CHECK();
+  }
+  // R P = Q_R R_p by the blocked QR; C P = (Q1 Q_R) R_p
+  gather_cols<<<dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, s>>>(R, ldr, perm, r, Z);
+  GN_LAUNCH_CHECK();
+  GN_TRY(launch_qr(r, r, Z, r, Qr, r, Rp, r, qws, nullptr, s));
+  lift_scan<<<dim3(1), dim3(256), 0, s>>>(Rp, r, r, tau, 0, k, status);
+  GN_LAUNCH_CHECK();
+  lift_transpose<<<dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, s>>>(Rp, r, tau, Z2);
+  GN_LAUNCH_CHECK();
+  GN_TRY(launch_qr(r, r, Z2, r, Q3, r, R2, r, qws, nullptr, s));
+  scatter_rows<<<dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, s>>>(Q3, perm, r, Q2);
+  GN_LAUNCH_CHECK();
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, MatRef{Q1, GN_DT_F64, r, 1}, MatRef{Qr, GN_DT_F64, r, 1}, 0.0,
+                      Q1_out, r, 1, nullptr, false, s));
+  return GN_OK;
+}
+
+gn_status launch_lift_diag(int64_t r, double* R, int64_t ldr, double tau, int32_t* k,
+                           int32_t* status, hipStream_t s) {
+  lift_scan<<<dim3(1), dim3(256), 0, s>>>(R, ldr, r, tau, 1, k, status);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+size_t power_ws_bytes(int64_t r, int32_t nv) { return align_up((size_t)nv * r * 8) + 256; }
+
+gn_status launch_power_check(int64_t r, uint64_t seed, int32_t nv, int32_t iters,
+                             const double* R, const double* R2, const int32_t* k, bool force_trunc,
+                             double tau_d, int32_t* status, double* est_out, void* ws,
+                             hipStream_t s) {
+  double* V = (double*)ws;
+  double* est = (double*)((char*)ws + align_up((size_t)nv * r * 8));
+  GN_TRY(launch_gaussian(seed, 6, 0, 0, nv, r, GN_DT_F64, 0, V, r, s));
+  power_prep<<<dim3(1), dim3(1024), 0, s>>>(V, nv, r, k, est);
+  GN_LAUNCH_CHECK();
+  for (int it = 0; it < iters; ++it) {
+    // y = T^{-T} v: the right-side solve X T = B (T = R, or R_2^T when truncated)
+    GN_TRY(launch_trsm_core(nv, r, R, R2, r, k, V, r, 1, false, true, s, false, force_trunc));
+    power_rows<<<dim3(1), dim3(1024), 0, s>>>(V, nv, r, est, 0);
+    GN_LAUNCH_CHECK();
+    // z = T^{-1} y: the transposed solve
+    GN_TRY(launch_trsm_core(nv, r, R, R2, r, k, V, r, 1, true, true, s, false, force_trunc));
+    power_rows<<<dim3(1), dim3(1024), 0, s>>>(V, nv, r, est, 1);
+    GN_LAUNCH_CHECK();
+  }
+  power_flag<<<dim3(1), dim3(64), 0, s>>>(est, tau_d, status, est_out);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+}  // namespace gn

@@ -27,12 +27,13 @@ __global__ void __launch_bounds__(TB) trsm_diag(int64_t rows, int64_t r, const d
                                                 const double* __restrict__ R2, int64_t ldt,
                                                 const int32_t* __restrict__ kdev, int want_trunc,
                                                 int trans, int r_only, double* __restrict__ X,
-                                                int64_t rsx, int64_t csx, int64_t jb, int w) {
+                                                int64_t rsx, int64_t csx, int64_t jb, int w,
+                                                int force_trunc) {
   const int32_t k = *kdev;
-  const bool trunc = k < r;
+  const bool trunc = force_trunc || k < r;
   if (trunc != (want_trunc != 0)) return;
   const double* S = (trunc && !r_only) ? R2 : R;
-  const int64_t kk = trunc ? k : r;
+  const int64_t kk = (k < r) ? k : r;
   __shared__ __attribute__((aligned(16))) double Tt[TB][TB + 2];
   const int tid = threadIdx.x;
   // consecutive threads read consecutive addresses of T's storage
@@ -80,11 +81,15 @@ __global__ void __launch_bounds__(TB) trsm_diag(int64_t rows, int64_t r, const d
 
 gn_status launch_trsm_core(int64_t rows, int64_t r, const double* R, const double* R2, int64_t ldt,
                            const int32_t* k, double* X, int64_t rsx, int64_t csx, bool left,
-                           bool maybe_trunc, hipStream_t s, bool r_only) {
+                           bool maybe_trunc, hipStream_t s, bool r_only, bool force_trunc) {
   if (rows <= 0) return GN_OK;
   const dim3 grid((unsigned)cdiv(rows, TB)), block(TB);
   const int64_t nblk = cdiv(r, TB);
-  for (int want_trunc = 0; want_trunc <= (maybe_trunc ? 1 : 0); ++want_trunc) {
+  // force_trunc: the core is in the factored pseudoinverse form whatever k is;
+  // the gate of the off-diagonal products then compares k with r + 1.
+  const int64_t gate_n = force_trunc ? r + 1 : r;
+  for (int want_trunc = force_trunc ? 1 : 0; want_trunc <= (maybe_trunc || force_trunc ? 1 : 0);
+       ++want_trunc) {
     const double* S = (want_trunc && !r_only) ? R2 : R;
     const bool trans = r_only ? left : (left ? !want_trunc : (bool)want_trunc);
     const bool upper = !trans;
@@ -100,14 +105,16 @@ gn_status launch_trsm_core(int64_t rows, int64_t r, const double* R, const doubl
         MatRef tm = trans ? MatRef{S + jb * ldt + t0, GN_DT_F64, 1, ldt}
                           : MatRef{S + t0 * ldt + jb, GN_DT_F64, ldt, 1};
         GN_TRY(launch_dgemm(rows, w, t1 - t0, -1.0, xa, tm, 1.0, X + jb * csx, rsx, csx, nullptr,
-                            false, s, k, r, want_trunc != 0));
+                            false, s, k, gate_n, want_trunc != 0));
       }
       if (upper)
         trsm_diag<true><<<grid, block, 0, s>>>(rows, r, R, R2, ldt, k, want_trunc, trans ? 1 : 0,
-                                               r_only ? 1 : 0, X, rsx, csx, jb, w);
+                                               r_only ? 1 : 0, X, rsx, csx, jb, w,
+                                               force_trunc ? 1 : 0);
       else
         trsm_diag<false><<<grid, block, 0, s>>>(rows, r, R, R2, ldt, k, want_trunc, trans ? 1 : 0,
-                                                r_only ? 1 : 0, X, rsx, csx, jb, w);
+                                                r_only ? 1 : 0, X, rsx, csx, jb, w,
+                                                force_trunc ? 1 : 0);
       GN_LAUNCH_CHECK();
     }
   }

@@ -5,6 +5,7 @@ only: every step of the computation runs in the library's HIP kernels.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 from dataclasses import dataclass
 
 import torch
@@ -14,6 +15,8 @@ from ._capi import GNError  # noqa: F401  (re-export)
 
 MODES = {"f64": C.GN_MODE_F64, "f32": C.GN_MODE_F32, "bf16": C.GN_MODE_BF16_BS}
 KINDS = {"gaussian": C.GN_SKETCH_GAUSSIAN, "srht": C.GN_SKETCH_SRHT, "user": C.GN_SKETCH_USER}
+CORE_METHODS = {"qr": C.GN_CORE_QR, "svd": C.GN_CORE_SVD, "lift_svd": C.GN_CORE_LIFT_SVD,
+                "lift_rrqr": C.GN_CORE_LIFT_RRQR, "lift_diag": C.GN_CORE_LIFT_DIAG}
 SKETCH_TORCH = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
 ACCUM_TORCH = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
 DT_OF_TORCH = {torch.float64: C.GN_DT_F64, torch.float32: C.GN_DT_F32, torch.bfloat16: C.GN_DT_BF16}
@@ -34,6 +37,7 @@ class Problem:
     eps: float = 0.0         # absolute; <= 0: plain GN
     nu_x: float = 0.0
     nu_y: float = 0.0
+    core_method: str = "qr"  # Section 5.1.1: qr, svd, lift_svd, lift_rrqr, lift_diag
 
     @property
     def l_eff(self) -> int:
@@ -45,8 +49,8 @@ class Problem:
 
     def c(self) -> C.GnProblem:
         return C.GnProblem(self.m, self.n, self.r, self.l, KINDS[self.kind_x], KINDS[self.kind_y],
-                           self.seed & ((1 << 64) - 1), MODES[self.mode], 0, self.eps, self.nu_x,
-                           self.nu_y)
+                           self.seed & ((1 << 64) - 1), MODES[self.mode],
+                           CORE_METHODS[self.core_method], self.eps, self.nu_x, self.nu_y)
 
 
 def _ptr(t):
@@ -189,6 +193,34 @@ def gn_core(p: Problem, AX: torch.Tensor, Y_user=None, out: CoreResult | None = 
                             Y_user.stride(0) if Y_user is not None else 0, ctypes.byref(oc),
                             _ptr(ws), ws.numel(), _stream()), "gn_core")
     return out
+
+
+def gn_core_check(p: Problem, core: CoreResult, delta: float = 0.0, nv: int = 8, iters: int = 4,
+                  est: torch.Tensor | None = None) -> torch.Tensor:
+    """Section 5.1.2 power-method check of a core: returns the estimate of the
+    2-norm of the inverse triangular factor (device double); sets bit 8 of
+    core.status when estimate * delta * nu_x * nu_y > 1 (delta <= 0: p.eps)."""
+    est = torch.zeros(1, dtype=torch.float64, device=core.R.device) if est is None else est
+    ws = workspace(p, C.GN_OP_CHECK, nv, device=core.R.device)
+    pc, oc = p.c(), core.c()
+    C.check(C.lib().gn_core_check(ctypes.byref(pc), ctypes.byref(oc), float(delta), nv, iters,
+                                  _ptr(est), _ptr(ws), ws.numel(), _stream()), "gn_core_check")
+    return est
+
+
+def gn_core_checked(p: Problem, AX: torch.Tensor, delta: float, nv: int = 8, iters: int = 4,
+                    Y_user=None):
+    """Plain GN's core, checked (Section 5.1.2); when the check flags it, the
+    core is recomputed as SGN with eps = delta.  Synchronizes to read the flag.
+    Returns (problem used, core, estimate, flagged)."""
+    plain = dataclasses.replace(p, eps=0.0, core_method="qr")
+    core = gn_core(plain, AX, Y_user)
+    est = gn_core_check(plain, core, delta, nv, iters)
+    flagged = bool(core.flags() & 8)
+    if not flagged:
+        return plain, core, est, False
+    sgn = dataclasses.replace(p, eps=delta, core_method="qr")
+    return sgn, gn_core(sgn, AX, Y_user), est, True
 
 
 def gn_factors(p: Problem, AX, YtA, core: CoreResult, F=None, G=None):

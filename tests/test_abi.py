@@ -44,7 +44,7 @@ def test_status_strings_and_version(lib):
 
 
 def _prob(**kw):
-    base = dict(m=2000, n=1000, r=50, l=25, kind_x=0, kind_y=0, seed=1, mode=0, reserved=0,
+    base = dict(m=2000, n=1000, r=50, l=25, kind_x=0, kind_y=0, seed=1, mode=0, core_method=0,
                 eps=1e-15, nu_x=0.0, nu_y=0.0)
     base.update(kw)
     return C.GnProblem(**base)
@@ -68,12 +68,25 @@ def test_workspace_sizes(lib):
     code, b = _ws(lib, p, C.GN_OP_MATERIALIZE)
     assert code == 0 and b >= 8 * (2000 * 50 + 50 * 1000)
     assert _ws(lib, p, 99)[0] == C.GN_ERR_ARG
+    # the power-method check: nv start vectors of length r
+    assert _ws(lib, p, C.GN_OP_CHECK, 0)[0] == C.GN_ERR_ARG
+    assert _ws(lib, p, C.GN_OP_CHECK, 17)[0] == C.GN_ERR_ARG
+    code, b = _ws(lib, p, C.GN_OP_CHECK, 8)
+    assert code == 0 and b >= 8 * 8 * 50
+    # the SVD route adds the Jacobi vectors and rotations (two r x r) and Q (r+l) x r
+    qr_bytes = _ws(lib, p, C.GN_OP_CORE)[1]
+    for method in (C.GN_CORE_SVD, C.GN_CORE_LIFT_SVD, C.GN_CORE_LIFT_RRQR):
+        code, b = _ws(lib, _prob(core_method=method), C.GN_OP_CORE)
+        assert code == 0 and b >= qr_bytes + 8 * (2 * 50 * 50 + 75 * 50)
+    assert _ws(lib, _prob(core_method=C.GN_CORE_LIFT_DIAG), C.GN_OP_CORE)[1] == qr_bytes
 
 
 @pytest.mark.parametrize("kw,code", [
     (dict(r=0), C.GN_ERR_SHAPE), (dict(r=1001), C.GN_ERR_SHAPE), (dict(m=0), C.GN_ERR_SHAPE),
     (dict(mode=7), C.GN_ERR_ARG), (dict(kind_x=5), C.GN_ERR_ARG), (dict(kind_y=1), C.GN_ERR_ARG),
-    (dict(eps=float("nan")), C.GN_ERR_ARG), (dict(reserved=1), C.GN_ERR_ARG),
+    (dict(eps=float("nan")), C.GN_ERR_ARG), (dict(core_method=5), C.GN_ERR_ARG),
+    (dict(core_method=-1), C.GN_ERR_ARG), (dict(core_method=2, eps=0.0), C.GN_ERR_ARG),
+    (dict(core_method=4, eps=-1.0), C.GN_ERR_ARG),
     (dict(r=3000, l=2000, m=9000, n=9000), C.GN_ERR_UNSUPPORTED),
     (dict(kind_x=1, n=1 << 18, m=10), C.GN_ERR_SHAPE),
     (dict(kind_x=1, n=1 << 18, m=1 << 18), C.GN_ERR_UNSUPPORTED),
@@ -110,6 +123,16 @@ def test_entry_points_reject_before_enqueue(lib):
     assert lib.gn_apply(ctypes.byref(p), 3, fake, 50, fake, 1000, ctypes.byref(out), fake, 1, 1,
                         fake, 1, fake, 1 << 30, null) == C.GN_ERR_ARG
     good = C.GnCoreOut(1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20)
+    # gn_core_check: every case fails a check before anything is enqueued
+    def chk(prob=p, core=good, delta=0.0, nv=8, iters=4, ws_bytes=1 << 34):
+        return lib.gn_core_check(ctypes.byref(prob), ctypes.byref(core), delta, nv, iters, null,
+                                 fake, ws_bytes, null)
+    assert chk(core=out) == C.GN_ERR_ARG                      # null status
+    assert chk(nv=0) == C.GN_ERR_ARG and chk(nv=17) == C.GN_ERR_ARG
+    assert chk(iters=0) == C.GN_ERR_ARG and chk(iters=65) == C.GN_ERR_ARG
+    assert chk(prob=_prob(eps=0.0)) == C.GN_ERR_ARG            # no threshold at all
+    assert chk(delta=float("inf")) == C.GN_ERR_ARG
+    assert chk(ws_bytes=64) == C.GN_ERR_WORKSPACE
     # side 2 (materialize): ldo < n, then a workspace too small
     assert lib.gn_apply(ctypes.byref(p), 2, fake, 50, fake, 1000, ctypes.byref(good), null, 0, 0,
                         fake, 999, fake, 1 << 30, null) == C.GN_ERR_SHAPE
@@ -122,6 +145,7 @@ def test_entry_points_reject_before_enqueue(lib):
                                ctypes.byref(core), fake, 1000, fake, ws_bytes, null)
     assert back(_prob(kind_x=1)) == C.GN_ERR_UNSUPPORTED
     assert back(_prob(mode=2)) == C.GN_ERR_UNSUPPORTED
+    assert back(_prob(core_method=C.GN_CORE_SVD)) == C.GN_ERR_UNSUPPORTED   # QR cores only
     assert back(p, G=null) == C.GN_ERR_ARG
     assert back(p, A=null, AX=null) == C.GN_ERR_ARG
     nok = C.GnCoreOut(0, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20)   # k pointer null

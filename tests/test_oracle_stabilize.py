@@ -216,6 +216,8 @@ def test_s6_power_method_bound_and_convergence():
     D = np.diag(np.linspace(1.0, 2.0, r))
     D[5, 5] = 1e-3
     assert math.isclose(S.inv_norm_power(D, V0, 4), 1e3, rel_tol=1e-9)
+    # a lower triangular factor: the same norm as its transpose
+    assert math.isclose(S.inv_norm_power(T.T.copy(), V0, 3, lower=True), true, rel_tol=1e-3)
     assert S.power_start(11, 8, r).shape == (8, r)
     assert np.array_equal(S.power_start(11, 8, r), philox.gaussian(11, 6, 8, r))
 
@@ -236,6 +238,10 @@ def test_s7_check_decides_on_both_sides():
     plain = G.gn(Ad, X, Y, 0.0)
     est_d, flag_d = S.check(plain.core, delta, nx, ny, seed=3)
     assert flag_d and est_d * delta * nx * ny > 10
+    # on the truncated core the applied factor R_2^T is bounded: no flag
+    sgn = G.gn(Ad, X, Y, G.threshold(delta, nx, ny))
+    est_t, flag_t = S.check(sgn.core, delta, nx, ny, seed=3)
+    assert sgn.core.k == 20 and not flag_t and est_t * delta * nx * ny < 1
     res_d, _, flagged = S.gn_checked(Ad, X, Y, delta, nx, ny, seed=3)
     assert flagged and res_d.core.k == 20
     assert relerr(res_d.approx, Ad) <= 1e-10
