@@ -13,7 +13,8 @@ pass's algorithmic TFLOP/s.  After timing: the error ||A - A_hat||_F (tile-wise
 on the device), a bounded CPU-oracle baseline, and the BF16-vs-FP32 comparison
 on the 32768^2, r = 2000, l = 1000 shape (same matrix), the reverse mode on the
 8192 x 4096 gradient workload (forward, backward, backward with AX recomputed),
-and the 512-problem batched workload (persistent pass, whole solve, graph replay).
+the 512-problem batched workload (persistent pass, whole solve, graph replay),
+and the core under each Section 5.1.1 stabilization with the Section 5.1.2 check.
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -265,6 +266,55 @@ def batch_bench(gn, W, steps=5, warmup=2, count=512):
     return out
 
 
+def stabilize_bench(gn, run, steps=3, warmup=1):
+    """The core under each Section 5.1.1 stabilization on the main workload's AX
+    (the pass output of the timed steps): truncated QR, the SVD route, the three
+    perturbations, and the Section 5.1.2 power-method check of the plain core.
+    Each core is timed with HIP events on the library's stream; its approximant's
+    error ||A - A_hat||_F / ||A||_F is measured on the device."""
+    import dataclasses
+    import torch
+
+    def timeit(f):
+        for _ in range(warmup):
+            f()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(steps):
+            f()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / steps
+
+    z = torch.zeros(run.w.m, 1, dtype=torch.float64, device="cuda")
+    zg = torch.zeros(1, run.w.n, dtype=torch.float64, device="cuda")
+    na = math.sqrt(float(gn.gn_residual(run.A, z, zg, k=0, scales=run.scales).item()))
+    out = {"workload": run.w.name, "r": run.w.r, "l": run.p.l_eff, "methods": {}}
+    for method in ("qr", "svd", "lift_svd", "lift_rrqr", "lift_diag"):
+        p = dataclasses.replace(run.p, core_method=method)
+        ws = gn.workspace(p, gn.C.GN_OP_CORE)
+        core = gn.new_core(p)
+        ms = timeit(lambda: gn.gn_core(p, run.AX, out=core, ws=ws))
+        F, G = gn.gn_factors(p, run.AX, run.YtA, core)
+        e = math.sqrt(float(gn.gn_residual(run.A, F, G, scales=run.scales).item()))
+        out["methods"][method] = {"core_ms": ms, "kept_rank": core.rank(),
+                                  "status_flags": core.flags(), "rel_err": e / na}
+        log(f"core {method}: {ms:.2f} ms, k={core.rank()}, flags={core.flags()}, err {e / na:.4e}")
+        del F, G, ws, core
+        torch.cuda.empty_cache()
+    plain = dataclasses.replace(run.p, eps=0.0, core_method="qr")
+    core = gn.gn_core(plain, run.AX)
+    est = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ms = timeit(lambda: gn.gn_core_check(plain, core, run.p.eps, 8, 4, est=est))
+    out["check"] = {"ms": ms, "start_vectors": 8, "iterations": 4,
+                    "estimate_inv_norm": float(est.item()), "flagged": bool(core.flags() & 8),
+                    "delta": run.p.eps}
+    log(f"check of the plain core: {ms:.3f} ms, estimate {float(est.item()):.3e}, "
+        f"flagged={bool(core.flags() & 8)}")
+    return out
+
+
 def cpu_baseline(A_dev, w, target_s=12.0):
     """The FP64 oracle's sketch pass on a bounded block of rows of the same A."""
     import numpy as np
@@ -313,6 +363,8 @@ def main():
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the reverse-mode measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
+    ap.add_argument("--no-stab", action="store_true",
+                    help="skip the timing of the other core stabilizations and the check")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--host-factors", action="store_true",
@@ -387,6 +439,10 @@ def main():
                         "optimum_estimate": optimum_estimate(w),
                         "ratio_to_optimum": e / optimum_estimate(w)}
         log(f"error {e / na:.4e} (abs {e:.4e}, k={k})")
+
+    if not args.no_stab:
+        log("core stabilizations and the plain-GN check")
+        res["stabilizations"] = stabilize_bench(gn, run)
 
     if not args.no_compare and w.m == 32768 and w.n == 32768:
         cmp = {}
