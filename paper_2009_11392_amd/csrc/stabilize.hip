@@ -222,6 +222,192 @@ __global__ void __launch_bounds__(JT) jacobi_round(double* __restrict__ W, doubl
   if (tid == 0 && rotated) atomicAdd(&ctl[2 + sweep], 1);
 }
 
+// The same launch with one wave per pair: B waves, wave p holding element l +
+// 64 q (q < E) of block I's vector p (wa) and of one block-J vector (wb).  In
+// cross round s wave p pairs I_p with J_{(p+s) mod B}; after the round every
+// wave passes its J vector to wave p - 1 through a double-buffered LDS ring, so
+// a round needs one barrier and no workgroup reduction (the three dots are
+// reduced inside the wave).  A FULL launch first runs the circle method inside
+// each block with the 2B vectors in LDS (waves 0 .. B/2-1 on block I, the rest
+// on block J).
+// A 64-bit value moved between lanes of a 16-lane row by a DPP pattern.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes, the same value in every lane: within each 16-lane row
+// by lane swaps (xor 1, xor 2, then the 8- and 16-lane mirrors, each pairing
+// lanes that hold disjoint partial sums), then the four row sums in a fixed order.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+template <int E>
+__device__ __forceinline__ void wave_dots(const double (&a)[E], const double (&b)[E], int lane,
+                                          double& alpha, double& beta, double& gamma) {
+  (void)lane;
+  double s[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};  // two chains per dot
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    s[0][q & 1] = fma(a[q], a[q], s[0][q & 1]);
+    s[1][q & 1] = fma(b[q], b[q], s[1][q & 1]);
+    s[2][q & 1] = fma(a[q], b[q], s[2][q & 1]);
+  }
+  alpha = wave_sum_dpp(s[0][0] + s[0][1]);
+  beta = wave_sum_dpp(s[1][0] + s[1][1]);
+  gamma = wave_sum_dpp(s[2][0] + s[2][1]);
+}
+
+template <int E>
+__device__ __forceinline__ void rotate_pair(double (&a)[E], double (&b)[E], double c, double s) {
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const double x = a[q], y = b[q];
+    a[q] = fma(c, x, -s * y);
+    b[q] = fma(s, x, c * y);
+  }
+}
+
+template <int E, int B, bool FULL>
+__global__ void __launch_bounds__(64 * B) jacobi_ring(double* __restrict__ W, double* __restrict__ J,
+                                                      int32_t* __restrict__ ctl, int64_t r, int nbe,
+                                                      int t, int sweep, double tol) {
+  if (ctl[0] != 0) return;  // converged in an earlier sweep
+  constexpr int C2 = 2 * B;
+  __shared__ double ring[2][B][E * 64];
+  __shared__ double Gm[C2][C2 + 1];
+  __shared__ int rotated;
+  const int tid = threadIdx.x, lane = tid & 63, p = tid >> 6;
+  const int bi = rr_pos(blockIdx.x, t, nbe), bj = rr_pos(nbe - 1 - blockIdx.x, t, nbe);
+  const int64_t colI = (int64_t)bi * B + p;
+  double wa[E], wb[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int64_t i = lane + 64 * q;
+    wa[q] = (i < r && colI < r) ? W[colI * r + i] : 0.0;
+    const int64_t cj = (int64_t)bj * B + p;
+    wb[q] = (i < r && cj < r) ? W[cj * r + i] : 0.0;
+  }
+  for (int e = tid; e < C2 * C2; e += 64 * B) Gm[e / C2][e % C2] = (e / C2 == e % C2) ? 1.0 : 0.0;
+  if (tid == 0) rotated = 0;
+  int rot_any = 0;
+  if (FULL) {
+    // pairs inside each block: ring[0] holds block I, ring[1] block J
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      ring[0][p][lane + 64 * q] = wa[q];
+      ring[1][p][lane + 64 * q] = wb[q];
+    }
+    __syncthreads();
+    const int half = B / 2;
+    const int blk = (p < half) ? 0 : 1, pq = p % half;
+    for (int s2 = 0; s2 < B - 1; ++s2) {
+      const int a = rr_pos(pq, s2, B), b = rr_pos(B - 1 - pq, s2, B);
+      double xa[E], xb[E];
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        xa[q] = ring[blk][a][lane + 64 * q];
+        xb[q] = ring[blk][b][lane + 64 * q];
+      }
+      double al, be, ga, c, sn;
+      int rot;
+      wave_dots<E>(xa, xb, lane, al, be, ga);
+      jacobi_rotation(al, be, ga, tol, c, sn, rot);
+      rot_any |= rot;
+      rotate_pair<E>(xa, xb, c, sn);
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        ring[blk][a][lane + 64 * q] = xa[q];
+        ring[blk][b][lane + 64 * q] = xb[q];
+      }
+      if (lane < C2) {
+        const int ga_ = blk * B + a, gb_ = blk * B + b;
+        const double g1 = Gm[lane][ga_], g2 = Gm[lane][gb_];
+        Gm[lane][ga_] = fma(c, g1, -sn * g2);
+        Gm[lane][gb_] = fma(sn, g1, c * g2);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      wa[q] = ring[0][p][lane + 64 * q];
+      wb[q] = ring[1][p][lane + 64 * q];
+    }
+    __syncthreads();
+  }
+  // cross rounds: wave p pairs I_p with J_{(p+s) mod B}
+  for (int s2 = 0; s2 < B; ++s2) {
+    const int jb = (p + s2) % B;
+    double al, be, ga, c, sn;
+    int rot;
+    wave_dots<E>(wa, wb, lane, al, be, ga);
+    jacobi_rotation(al, be, ga, tol, c, sn, rot);
+    rot_any |= rot;
+    rotate_pair<E>(wa, wb, c, sn);
+    if (lane < C2) {
+      const double g1 = Gm[lane][p], g2 = Gm[lane][B + jb];
+      Gm[lane][p] = fma(c, g1, -sn * g2);
+      Gm[lane][B + jb] = fma(sn, g1, c * g2);
+    }
+    if (s2 + 1 < B) {
+      const int buf = s2 & 1;
+#pragma unroll
+      for (int q = 0; q < E; ++q) ring[buf][p][lane + 64 * q] = wb[q];
+      __syncthreads();
+      const int from = (p + 1) % B;
+#pragma unroll
+      for (int q = 0; q < E; ++q) wb[q] = ring[buf][from][lane + 64 * q];
+    }
+  }
+  const int64_t cjf = (int64_t)bj * B + (p + B - 1) % B;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int64_t i = lane + 64 * q;
+    if (i < r) {
+      if (colI < r) W[colI * r + i] = wa[q];
+      if (cjf < r) W[cjf * r + i] = wb[q];
+    }
+  }
+  if (rot_any && lane == 0) rotated = 1;
+  __syncthreads();
+  // J[:, cols] <- J[:, cols] Gm, cols = block I then block J; each thread keeps
+  // its rows of the 2B columns in registers and takes Gm one column at a time
+  constexpr int JR = (E + B - 1) / B;  // rows per thread (r <= 64 E)
+  int64_t col[C2];
+#pragma unroll
+  for (int c = 0; c < C2; ++c) col[c] = (c < B) ? (int64_t)bi * B + c : (int64_t)bj * B + (c - B);
+  double jr[JR][C2];
+#pragma unroll
+  for (int q = 0; q < JR; ++q) {
+    const int64_t i = tid + (int64_t)q * 64 * B;
+#pragma unroll
+    for (int c = 0; c < C2; ++c) jr[q][c] = (i < r && col[c] < r) ? J[col[c] * r + i] : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < C2; ++c) {
+    double g[C2];
+#pragma unroll
+    for (int d = 0; d < C2; ++d) g[d] = Gm[d][c];
+#pragma unroll
+    for (int q = 0; q < JR; ++q) {
+      const int64_t i = tid + (int64_t)q * 64 * B;
+      double o = 0.0;
+#pragma unroll
+      for (int d = 0; d < C2; ++d) o = fma(jr[q][d], g[d], o);
+      if (i < r && col[c] < r) J[col[c] * r + i] = o;
+    }
+  }
+  if (tid == 0 && rotated) atomicAdd(&ctl[2 + sweep], 1);
+}
+
 __global__ void __launch_bounds__(64) jacobi_sweep_end(int32_t* ctl, int sweep) {
   if (threadIdx.x != 0 || ctl[0] != 0) return;
   ctl[1] = sweep + 1;
@@ -592,6 +778,212 @@ __global__ void __launch_bounds__(64) power_flag(const double* est, double tau_d
   if (est_out) *est_out = e;
 }
 
+// The check's solves in one workgroup.  U is the upper triangular factor the
+// check solves with: R for a plain core, R2 for a truncated or factored one
+// (k x k, ld r).  Its 64 x 64 diagonal blocks are inverted once (one thread per
+// column, back substitution in LDS), U^T is copied once, and then a single
+// launch runs every power step with the nv right-hand sides in LDS: a block of
+// unknowns is the inverted diagonal block times its right-hand sides, then the
+// later (forward) or earlier (backward) right-hand sides take the block's
+// contribution, reading U's rows (forward) or U^T's rows (backward) coalesced.
+constexpr int PB = 64;
+constexpr int kPowerLds = 16384;  // doubles of right-hand sides held in LDS
+constexpr int kPowerThreads = 512;
+
+__device__ __forceinline__ const double* power_factor(const double* R, const double* R2,
+                                                      int64_t r, const int32_t* kdev, int force,
+                                                      int64_t& k, bool& use2) {
+  k = (*kdev < r) ? *kdev : r;
+  use2 = force || *kdev < r;
+  return use2 ? R2 : R;
+}
+
+__global__ void __launch_bounds__(PB) power_block_inverse(const double* __restrict__ R,
+                                                          const double* __restrict__ R2, int64_t r,
+                                                          const int32_t* kdev, int force,
+                                                          double* __restrict__ Dinv) {
+  int64_t k;
+  bool use2;
+  const double* U = power_factor(R, R2, r, kdev, force, k, use2);
+  const int64_t j0 = (int64_t)blockIdx.x * PB;
+  if (j0 >= k) return;
+  __shared__ double Bs[PB][PB + 1];
+  __shared__ double Xs[PB][PB + 1];
+  const int t = threadIdx.x;
+  for (int i = 0; i < PB; ++i) {
+    double v = (i == t) ? 1.0 : 0.0;  // identity beyond the kept size
+    if (j0 + i < k && j0 + t < k) v = (t >= i) ? U[(j0 + i) * r + j0 + t] : 0.0;
+    Bs[i][t] = v;
+    Xs[i][t] = 0.0;
+  }
+  __syncthreads();
+  // column t of the inverse: B x = e_t by back substitution (x_i = 0 for i > t)
+  for (int i = t; i >= 0; --i) {
+    double acc = (i == t) ? 1.0 : 0.0;
+    for (int l = i + 1; l <= t; ++l) acc = fma(-Bs[i][l], Xs[l][t], acc);
+    Xs[i][t] = acc / Bs[i][i];
+  }
+  for (int i = 0; i < PB; ++i) Dinv[(int64_t)blockIdx.x * PB * PB + i * PB + t] = Xs[i][t];
+}
+
+// Ut[i*r + j] = U[j*r + i] over the k x k block.
+__global__ void __launch_bounds__(256) power_transpose(const double* __restrict__ R,
+                                                       const double* __restrict__ R2, int64_t r,
+                                                       const int32_t* kdev, int force,
+                                                       double* __restrict__ Ut) {
+  int64_t k;
+  bool use2;
+  const double* U = power_factor(R, R2, r, kdev, force, k, use2);
+  __shared__ double tile[32][33];
+  const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t i = r0 + y, j = c0 + tx;
+    tile[y][tx] = (i < k && j < k) ? U[i * r + j] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t i = c0 + y, j = r0 + tx;  // Ut row i = U column i
+    if (i < k && j < k) Ut[i * r + j] = tile[tx][y];
+  }
+}
+
+// Row norms of X (nv x k in LDS, row v at v*kp, kp = k rounded up to a multiple
+// of 64, the padding zero): one wave per row; optionally
+// scales the rows to unit length; returns the largest norm (valid in thread 0
+// after the call; every thread passes the barriers).
+__device__ double power_norms(double* X, int nv, int64_t k, bool normalize, double* sn) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t kp = cdiv_d(k, PB) * PB;
+  for (int v = wave; v < nv; v += kPowerThreads / 64) {
+    double s = 0.0;
+    for (int64_t i = lane; i < k; i += 64) s = fma(X[v * kp + i], X[v * kp + i], s);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    const double nr = sqrt(s);
+    if (normalize && nr > 0.0) {
+      const double inv = 1.0 / nr;
+      for (int64_t i = lane; i < k; i += 64) X[v * kp + i] *= inv;
+    }
+    if (lane == 0) sn[v] = nr;
+  }
+  __syncthreads();
+  double m = 0.0;
+  if (threadIdx.x == 0)
+    for (int v = 0; v < nv; ++v) m = fmax(m, sn[v]);
+  return m;
+}
+
+// U^T x = b (forward) or U x = b (backward) for the nv rows of X in place.
+template <bool FORWARD>
+__device__ void power_solve(double* X, double* xtmp, int nv, int64_t k, int64_t r,
+                            const double* U, const double* Ut, const double* Dinv) {
+  const int tid = threadIdx.x;
+  const int64_t kp = cdiv_d(k, PB) * PB;  // row stride of X
+  const int nblk = (int)cdiv_d(k, PB);
+  for (int s = 0; s < nblk; ++s) {
+    const int b = FORWARD ? s : nblk - 1 - s;
+    const int64_t j0 = (int64_t)b * PB;
+    const int w = (int)((k - j0 < PB) ? (k - j0) : PB);
+    const double* D = Dinv + (int64_t)b * PB * PB;
+    // unknowns of the block: x = D^T b_blk (forward) or D b_blk (backward); D is
+    // zero outside its upper triangle, so the sums run over the whole block with
+    // the loads issued several at a time
+    constexpr int VS = kPowerThreads / PB;  // vectors per pass over the block
+    const int j = tid % PB;
+#pragma unroll 1
+    for (int v = tid / PB; v < nv; v += VS) {
+      double acc = 0.0;
+      if (j < w) {
+        // rows of X are padded to a multiple of 64 with zeros, and D's entries
+        // that pair with rows beyond the kept size are zero
+        const double* xb = X + v * kp + j0;
+#pragma unroll 1
+        for (int u0 = 0; u0 < PB; u0 += 32) {
+          double d[32];
+#pragma unroll
+          for (int u = 0; u < 32; ++u)
+            d[u] = FORWARD ? D[(u0 + u) * PB + j] : D[j * PB + u0 + u];
+#pragma unroll
+          for (int u = 0; u < 32; ++u) acc = fma(d[u], xb[u0 + u], acc);
+        }
+      }
+      xtmp[v * PB + j] = acc;
+    }
+    __syncthreads();
+    for (int v = tid / PB; v < nv; v += VS)
+      if (j < w) X[v * kp + j0 + j] = xtmp[v * PB + j];
+    __syncthreads();
+    // the other right-hand sides take the block's contribution
+    const int64_t c_lo = FORWARD ? j0 + w : 0, c_hi = FORWARD ? k : j0;
+    const double* Ub = FORWARD ? U : Ut;
+    for (int64_t c = c_lo + tid; c < c_hi; c += kPowerThreads) {
+      // half of the block's column strip of U in flight at a time (zero beyond w)
+#pragma unroll 1
+      for (int t0 = 0; t0 < PB; t0 += 32) {
+        double u[32];
+#pragma unroll
+        for (int t = 0; t < 32; ++t) u[t] = (t0 + t < w) ? Ub[(j0 + t0 + t) * r + c] : 0.0;
+#pragma unroll 1
+        for (int q = 0; q < nv; ++q) {
+          const double* xq = X + q * kp + j0 + t0;
+          double a = 0.0;
+#pragma unroll
+          for (int t = 0; t < 32; ++t) a = fma(u[t], xq[t], a);
+          X[q * kp + c] -= a;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Every power step in one workgroup: v <- v / ||v||; y = T^{-T} v; est = max
+// ||y||; z = T^{-1} y; v <- z / ||z||.  T = R (plain core): forward then
+// backward; T = R2^T (truncated or factored core): backward then forward.
+__global__ void __launch_bounds__(kPowerThreads) power_iterate(const double* __restrict__ R,
+                                                      const double* __restrict__ R2, int64_t r,
+                                                      const int32_t* kdev, int force,
+                                                      const double* __restrict__ Dinv,
+                                                      const double* __restrict__ Ut,
+                                                      double* __restrict__ V, int nv, int iters,
+                                                      double* est) {
+  __shared__ double X[kPowerLds];
+  __shared__ double xtmp[16 * PB];
+  __shared__ double sn[16];
+  int64_t k;
+  bool use2;
+  const double* U = power_factor(R, R2, r, kdev, force, k, use2);
+  const int64_t kp = cdiv_d(k, PB) * PB;
+  for (int64_t e = threadIdx.x; e < (int64_t)nv * kp; e += kPowerThreads) {
+    const int64_t v = e / kp, i = e - v * kp;
+    X[e] = (i < k) ? V[v * r + i] : 0.0;
+  }
+  __syncthreads();
+  double best = 0.0;
+  if (k > 0) {
+    power_norms(X, nv, k, true, sn);
+    for (int it = 0; it < iters; ++it) {
+      if (use2)
+        power_solve<false>(X, xtmp, nv, k, r, U, Ut, Dinv);
+      else
+        power_solve<true>(X, xtmp, nv, k, r, U, Ut, Dinv);
+      best = fmax(best, power_norms(X, nv, k, false, sn));
+      __syncthreads();
+      if (use2)
+        power_solve<true>(X, xtmp, nv, k, r, U, Ut, Dinv);
+      else
+        power_solve<false>(X, xtmp, nv, k, r, U, Ut, Dinv);
+      power_norms(X, nv, k, true, sn);
+      __syncthreads();
+    }
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)nv * kp; e += kPowerThreads) {
+    const int64_t v = e / kp, i = e - v * kp;
+    if (i < k) V[v * r + i] = X[e];
+  }
+  if (threadIdx.x == 0) *est = best;
+}
+
 // ---------------------------------------------------------------------------- Jacobi driver
 struct JacobiShape {
   int rpt, b;
@@ -602,6 +994,26 @@ JacobiShape jacobi_shape(int64_t r) {
   if (r <= 1024) return {4, 8};
   if (r <= 2048) return {8, 4};
   return {16, 2};
+}
+
+template <int E, int B>
+gn_status run_jacobi_ring(double* W, double* J, int32_t* ctl, int64_t r, double tol,
+                          hipStream_t s) {
+  const int nb = (int)cdiv(r, B);
+  const int nbe = nb + (nb & 1);
+  const dim3 grid((unsigned)(nbe / 2)), block(64 * B);
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    for (int t = 0; t < nbe - 1; ++t) {
+      if (t == 0)
+        jacobi_ring<E, B, true><<<grid, block, 0, s>>>(W, J, ctl, r, nbe, t, sweep, tol);
+      else
+        jacobi_ring<E, B, false><<<grid, block, 0, s>>>(W, J, ctl, r, nbe, t, sweep, tol);
+      GN_LAUNCH_CHECK();
+    }
+    jacobi_sweep_end<<<dim3(1), dim3(64), 0, s>>>(ctl, sweep);
+    GN_LAUNCH_CHECK();
+  }
+  return GN_OK;
 }
 
 template <int RPT, int B>
@@ -692,15 +1104,14 @@ gn_status launch_svd_core(int64_t r, int64_t rl, const double* R, int64_t ldr, c
   jacobi_init<<<dim3((unsigned)cdiv(nel, 256)), dim3(256), 0, s>>>(R, ldr, r, W, J, ctl);
   GN_LAUNCH_CHECK();
   const double tol = sqrt((double)r) * 0x1.0p-53;
-  const JacobiShape sh = jacobi_shape(r);
-  if (sh.rpt == 1)
-    GN_TRY((run_jacobi<1, 8>(W, J, ctl, r, tol, s)));
-  else if (sh.rpt == 2)
-    GN_TRY((run_jacobi<2, 8>(W, J, ctl, r, tol, s)));
-  else if (sh.rpt == 4)
-    GN_TRY((run_jacobi<4, 8>(W, J, ctl, r, tol, s)));
-  else if (sh.rpt == 8)
-    GN_TRY((run_jacobi<8, 4>(W, J, ctl, r, tol, s)));
+  if (r <= 256)
+    GN_TRY((run_jacobi_ring<4, 8>(W, J, ctl, r, tol, s)));
+  else if (r <= 512)
+    GN_TRY((run_jacobi_ring<8, 8>(W, J, ctl, r, tol, s)));
+  else if (r <= 1024)
+    GN_TRY((run_jacobi_ring<16, 8>(W, J, ctl, r, tol, s)));
+  else if (r <= 2048)
+    GN_TRY((run_jacobi_ring<32, 4>(W, J, ctl, r, tol, s)));
   else
     GN_TRY((run_jacobi<16, 2>(W, J, ctl, r, tol, s)));
   vec_norms<<<dim3((unsigned)cdiv(r, 4)), dim3(256), 0, s>>>(W, r, sig);
@@ -768,26 +1179,44 @@ gn_status launch_lift_diag(int64_t r, double* R, int64_t ldr, double tau, int32_
   return GN_OK;
 }
 
-size_t power_ws_bytes(int64_t r, int32_t nv) { return align_up((size_t)nv * r * 8) + 256; }
+size_t power_ws_bytes(int64_t r, int32_t nv) {
+  return align_up((size_t)nv * r * 8) + 256 + align_up((size_t)cdiv(r, PB) * PB * PB * 8) +
+         align_up((size_t)r * r * 8);
+}
 
 gn_status launch_power_check(int64_t r, uint64_t seed, int32_t nv, int32_t iters,
                              const double* R, const double* R2, const int32_t* k, bool force_trunc,
                              double tau_d, int32_t* status, double* est_out, void* ws,
                              hipStream_t s) {
-  double* V = (double*)ws;
-  double* est = (double*)((char*)ws + align_up((size_t)nv * r * 8));
+  char* base = (char*)ws;
+  double* V = (double*)base;
+  double* est = (double*)(base + align_up((size_t)nv * r * 8));
+  double* Dinv = (double*)(base + align_up((size_t)nv * r * 8) + 256);
+  double* Ut = (double*)((char*)Dinv + align_up((size_t)cdiv(r, PB) * PB * PB * 8));
   GN_TRY(launch_gaussian(seed, 6, 0, 0, nv, r, GN_DT_F64, 0, V, r, s));
   power_prep<<<dim3(1), dim3(1024), 0, s>>>(V, nv, r, k, est);
   GN_LAUNCH_CHECK();
-  for (int it = 0; it < iters; ++it) {
-    // y = T^{-T} v: the right-side solve X T = B (T = R, or R_2^T when truncated)
-    GN_TRY(launch_trsm_core(nv, r, R, R2, r, k, V, r, 1, false, true, s, false, force_trunc));
-    power_rows<<<dim3(1), dim3(1024), 0, s>>>(V, nv, r, est, 0);
+  if ((int64_t)nv * cdiv(r, PB) * PB <= kPowerLds) {
+    const int f = force_trunc ? 1 : 0;
+    power_block_inverse<<<dim3((unsigned)cdiv(r, PB)), dim3(PB), 0, s>>>(R, R2, r, k, f, Dinv);
     GN_LAUNCH_CHECK();
-    // z = T^{-1} y: the transposed solve
-    GN_TRY(launch_trsm_core(nv, r, R, R2, r, k, V, r, 1, true, true, s, false, force_trunc));
-    power_rows<<<dim3(1), dim3(1024), 0, s>>>(V, nv, r, est, 1);
+    power_transpose<<<dim3((unsigned)cdiv(r, 32), (unsigned)cdiv(r, 32)), dim3(256), 0, s>>>(
+        R, R2, r, k, f, Ut);
     GN_LAUNCH_CHECK();
+    power_iterate<<<dim3(1), dim3(kPowerThreads), 0, s>>>(R, R2, r, k, f, Dinv, Ut, V, nv, iters,
+                                                          est);
+    GN_LAUNCH_CHECK();
+  } else {
+    for (int it = 0; it < iters; ++it) {
+      // y = T^{-T} v: the right-side solve X T = B (T = R, or R_2^T when truncated)
+      GN_TRY(launch_trsm_core(nv, r, R, R2, r, k, V, r, 1, false, true, s, false, force_trunc));
+      power_rows<<<dim3(1), dim3(1024), 0, s>>>(V, nv, r, est, 0);
+      GN_LAUNCH_CHECK();
+      // z = T^{-1} y: the transposed solve
+      GN_TRY(launch_trsm_core(nv, r, R, R2, r, k, V, r, 1, true, true, s, false, force_trunc));
+      power_rows<<<dim3(1), dim3(1024), 0, s>>>(V, nv, r, est, 1);
+      GN_LAUNCH_CHECK();
+    }
   }
   power_flag<<<dim3(1), dim3(64), 0, s>>>(est, tau_d, status, est_out);
   GN_LAUNCH_CHECK();
