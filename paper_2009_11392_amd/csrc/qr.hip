@@ -23,6 +23,7 @@
 #include "wave_ops.h"
 
 #include <utility>
+#include <vector>
 
 namespace gn {
 namespace {
@@ -492,6 +493,82 @@ __global__ void __launch_bounds__(256) build_z_b(const TruncJob* __restrict__ jo
   build_z_body(J.r, J.R, J.ldr, J.k, J.Z, J.ldz);
 }
 
+// ---------------------------------------------------------------------------- outer blocks
+// Panels are grouped into outer blocks of QR_OB columns: inside a block the
+// panel updates touch only the block's columns; the block's reflectors are then
+// applied to the trailing columns (and, walking back, to Q) as one block
+// reflector I - V T V^T by three FP64 MFMA products.
+constexpr int QR_OB = 64;
+
+// Vb ((M - J0) x w, ld QR_OB): the block's unit lower trapezoidal reflectors.
+__global__ void __launch_bounds__(256) qr_build_v(const double* __restrict__ C, int64_t ldc,
+                                                  int64_t M, int64_t J0, int w,
+                                                  double* __restrict__ Vb, const int32_t* gate,
+                                                  int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t Mp = M - J0;
+  if (e >= Mp * QR_OB) return;
+  const int64_t i = e / QR_OB;
+  const int c = (int)(e - i * QR_OB);
+  double v = 0.0;
+  if (c < w) v = (i < c) ? 0.0 : (i == c ? 1.0 : C[(J0 + i) * ldc + J0 + c]);
+  Vb[e] = v;
+}
+
+// The panels of one outer block (at most QR_OB / 8 of them).
+struct OuterPanels {
+  int count;
+  int off[QR_OB / 8];    // first column within the block
+  int width[QR_OB / 8];
+  int tidx[QR_OB / 8];   // index of the panel's T in the T array
+};
+
+// T of the whole block (w x w, ld QR_OB, upper triangular) from the panels' T
+// and G = Vb^T Vb, merging left to right: with T_a the block so far (columns
+// 0..s) and T_b the next panel's, T = [T_a, -T_a G[0:s, b] T_b; 0, T_b]
+// (the product of the two block reflectors).
+__global__ void __launch_bounds__(256) qr_merge_t(const double* __restrict__ G,
+                                                  const double* __restrict__ Tpanels,
+                                                  OuterPanels op, int w,
+                                                  double* __restrict__ Tout, const int32_t* gate,
+                                                  int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  __shared__ double T[QR_OB][QR_OB + 1];
+  __shared__ double Y[QR_OB][QR_NB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < QR_OB * QR_OB; e += 256) T[e / QR_OB][e % QR_OB] = 0.0;
+  __syncthreads();
+  for (int b = 0; b < op.count; ++b) {
+    const int o = op.off[b], wb = op.width[b];
+    const double* Tb = Tpanels + (size_t)op.tidx[b] * QR_NB * QR_NB;
+    for (int e = tid; e < wb * wb; e += 256) T[o + e / wb][o + e % wb] = Tb[(e / wb) * QR_NB + e % wb];
+    __syncthreads();
+    if (o > 0) {
+      // Y = T_a G[0:o, o:o+wb]   (o x wb)
+      for (int e = tid; e < o * wb; e += 256) {
+        const int i = e / wb, j = e % wb;
+        double acc = 0.0;
+        for (int l = i; l < o; ++l) acc = fma(T[i][l], G[l * QR_OB + o + j], acc);
+        Y[i][j] = acc;
+      }
+      __syncthreads();
+      // T[0:o, o:o+wb] = -Y T_b
+      for (int e = tid; e < o * wb; e += 256) {
+        const int i = e / wb, j = e % wb;
+        double acc = 0.0;
+        for (int l = 0; l <= j; ++l) acc = fma(Y[i][l], T[o + l][o + j], acc);
+        T[i][o + j] = -acc;
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = tid; e < QR_OB * QR_OB; e += 256) {
+    const int i = e / QR_OB, j = e % QR_OB;
+    Tout[e] = (i < w && j < w) ? T[i][j] : 0.0;
+  }
+}
+
 // Panel width and rows per thread for the panel starting at j0 (Mp rows).
 struct PanelShape {
   int nb, rpt;
@@ -543,42 +620,118 @@ gn_status run_update(const double* Cp, int64_t ldc, int64_t M, int64_t j0, int n
 static size_t qr_t_bytes(int64_t N) {
   return align_up((size_t)(cdiv(N, 8) + 1) * QR_NB * QR_NB * sizeof(double));
 }
-size_t qr_ws_bytes(int64_t M, int64_t N) {
-  return qr_t_bytes(N) + align_up((size_t)cdiv(M, QU_CH) * QR_NB * N * sizeof(double));
+struct QrWs {
+  size_t tin, wp, vb, g, w, w2, tout, split, split_bytes, total;
+};
+static QrWs qr_ws_layout(int64_t M, int64_t N) {
+  QrWs q{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  q.tin = take(qr_t_bytes(N));
+  q.wp = take((size_t)cdiv(M, QU_CH) * QR_NB * QR_OB * sizeof(double));  // inner updates only
+  q.vb = take((size_t)M * QR_OB * sizeof(double));
+  q.g = take((size_t)QR_OB * QR_OB * sizeof(double));
+  q.w = take((size_t)QR_OB * N * sizeof(double));
+  q.w2 = take((size_t)QR_OB * N * sizeof(double));
+  q.tout = take((size_t)cdiv(N, QR_OB) * QR_OB * QR_OB * sizeof(double));
+  // K-split partials of V^T D (QR_OB x up to N, at most 32 slices)
+  q.split_bytes = (size_t)32 * QR_OB * N * sizeof(double);
+  q.split = take(q.split_bytes);
+  q.total = off;
+  return q;
 }
 
+size_t qr_ws_bytes(int64_t M, int64_t N) { return qr_ws_layout(M, N).total; }
+
+// Two-level blocked Householder QR: panels (register kernel) inside outer blocks
+// of QR_OB columns, panel updates restricted to the block, then one block
+// reflector per outer block applied by FP64 MFMA products to the trailing
+// columns; Q formed from [I; 0] by the outer blocks right to left.
 gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int64_t ldq, double* R,
                     int64_t ldr, double* ws, const int32_t* gate_k, hipStream_t s) {
   if (M < N || M > QR_MAXROWS || N < 1) return GN_ERR_UNSUPPORTED;
   const int64_t gate_n = N;
-  double* Wp = ws + qr_t_bytes(N) / sizeof(double);
-  int64_t starts[QR_MAXROWS];
-  int widths[QR_MAXROWS];
-  int np = 0;
-  for (int64_t jj = 0; jj < N;) {
-    const int nb = panel_shape(M - jj).nb;
-    const int w = (int)((N - jj < nb) ? (N - jj) : nb);
-    starts[np] = jj;
-    widths[np] = w;
-    ++np;
-    jj += w;
+  const QrWs L = qr_ws_layout(M, N);
+  char* base = (char*)ws;
+  double* Tin = (double*)(base + L.tin);
+  double* Wp = (double*)(base + L.wp);
+  double* Vb = (double*)(base + L.vb);
+  double* G = (double*)(base + L.g);
+  double* W = (double*)(base + L.w);
+  double* W2 = (double*)(base + L.w2);
+  double* Tout = (double*)(base + L.tout);
+  double* sp = (double*)(base + L.split);
+  const int64_t nob = cdiv(N, QR_OB);
+  std::vector<OuterPanels> ops((size_t)nob);
+  int pi = 0;
+  // factor: outer blocks left to right
+  for (int64_t ob = 0; ob < nob; ++ob) {
+    const int64_t J0 = ob * QR_OB, J1 = (J0 + QR_OB < N) ? J0 + QR_OB : N;
+    const int w = (int)(J1 - J0);
+    OuterPanels& op = ops[(size_t)ob];
+    op.count = 0;
+    for (int64_t j0 = J0; j0 < J1;) {
+      const int nb = panel_shape(M - j0).nb;
+      const int nbw = (int)((J1 - j0 < nb) ? (J1 - j0) : nb);
+      double* Tp = Tin + (size_t)pi * QR_NB * QR_NB;
+      GN_TRY(run_panel(C, ldc, M, j0, nbw, Tp, gate_k, gate_n, s));
+      GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, j0 + nbw, J1 - j0 - nbw, Tp, 1, Wp, gate_k,
+                        gate_n, s));
+      op.off[op.count] = (int)(j0 - J0);
+      op.width[op.count] = nbw;
+      op.tidx[op.count] = pi;
+      ++op.count;
+      ++pi;
+      j0 += nbw;
+    }
+    const int64_t Mp = M - J0;
+    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w, Vb,
+                                                                         gate_k, gate_n);
+    GN_LAUNCH_CHECK();
+    const MatRef vt{Vb, GN_DT_F64, 1, QR_OB}, vv{Vb, GN_DT_F64, QR_OB, 1};
+    GN_TRY(launch_dgemm(w, w, Mp, 1.0, vt, vv, 0.0, G, QR_OB, 1, nullptr, false, s, gate_k, gate_n,
+                        true, sp, L.split_bytes));
+    double* Tb = Tout + (size_t)ob * QR_OB * QR_OB;
+    qr_merge_t<<<dim3(1), dim3(256), 0, s>>>(G, Tin, op, w, Tb, gate_k, gate_n);
+    GN_LAUNCH_CHECK();
+    const int64_t nt = N - J1;
+    if (nt > 0) {
+      // C2 <- (I - V T^T V^T) C2 = C2 - V (T^T (V^T C2))
+      const MatRef c2{C + J0 * ldc + J1, GN_DT_F64, ldc, 1};
+      GN_TRY(launch_dgemm(w, nt, Mp, 1.0, vt, c2, 0.0, W, nt, 1, nullptr, false, s, gate_k,
+                          gate_n, true, sp, L.split_bytes));
+      GN_TRY(launch_dgemm(w, nt, w, 1.0, MatRef{Tb, GN_DT_F64, 1, QR_OB},
+                          MatRef{W, GN_DT_F64, nt, 1}, 0.0, W2, nt, 1, nullptr, false, s, gate_k,
+                          gate_n, true));
+      GN_TRY(launch_dgemm(Mp, nt, w, -1.0, vv, MatRef{W2, GN_DT_F64, nt, 1}, 1.0,
+                          C + J0 * ldc + J1, ldc, 1, nullptr, false, s, gate_k, gate_n, true));
+    }
   }
-  // factor: panels left to right, each followed by the trailing update
-  for (int pi = 0; pi < np; ++pi) {
-    const int64_t j0 = starts[pi];
-    const int nbw = widths[pi];
-    double* Tp = ws + (size_t)pi * QR_NB * QR_NB;
-    GN_TRY(run_panel(C, ldc, M, j0, nbw, Tp, gate_k, gate_n, s));
-    const int64_t c0 = j0 + nbw, nt = N - c0;
-    GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, c0, nt, Tp, 1, Wp, gate_k, gate_n, s));
-  }
-  // explicit Q: start from [I; 0] and apply the block reflectors right to left
+  // explicit Q: start from [I; 0] and apply the outer blocks right to left,
+  // Q2 <- (I - V T V^T) Q2 on rows and columns J0..
   qr_init_q<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(Q, ldq, M, N, gate_k, gate_n);
   GN_LAUNCH_CHECK();
-  for (int pi = np - 1; pi >= 0; --pi) {
-    const int64_t j0 = starts[pi];
-    const double* Tp = ws + (size_t)pi * QR_NB * QR_NB;
-    GN_TRY(run_update(C, ldc, M, j0, widths[pi], Q, ldq, j0, N - j0, Tp, 0, Wp, gate_k, gate_n, s));
+  for (int64_t ob = nob - 1; ob >= 0; --ob) {
+    const int64_t J0 = ob * QR_OB, J1 = (J0 + QR_OB < N) ? J0 + QR_OB : N;
+    const int w = (int)(J1 - J0);
+    const int64_t Mp = M - J0, nq = N - J0;
+    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w, Vb,
+                                                                         gate_k, gate_n);
+    GN_LAUNCH_CHECK();
+    const MatRef vt{Vb, GN_DT_F64, 1, QR_OB}, vv{Vb, GN_DT_F64, QR_OB, 1};
+    const double* Tb = Tout + (size_t)ob * QR_OB * QR_OB;
+    const MatRef q2{Q + J0 * ldq + J0, GN_DT_F64, ldq, 1};
+    GN_TRY(launch_dgemm(w, nq, Mp, 1.0, vt, q2, 0.0, W, nq, 1, nullptr, false, s, gate_k, gate_n,
+                        true, sp, L.split_bytes));
+    GN_TRY(launch_dgemm(w, nq, w, 1.0, MatRef{Tb, GN_DT_F64, QR_OB, 1},
+                        MatRef{W, GN_DT_F64, nq, 1}, 0.0, W2, nq, 1, nullptr, false, s, gate_k,
+                        gate_n, true));
+    GN_TRY(launch_dgemm(Mp, nq, w, -1.0, vv, MatRef{W2, GN_DT_F64, nq, 1}, 1.0,
+                        Q + J0 * ldq + J0, ldq, 1, nullptr, false, s, gate_k, gate_n, true));
   }
   qr_signfix<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(C, ldc, Q, ldq, R, ldr, M, N,
                                                                    gate_k, gate_n);
