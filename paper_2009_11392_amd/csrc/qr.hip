@@ -575,7 +575,7 @@ struct PanelShape {
 };
 inline PanelShape panel_shape(int64_t Mp) {
   const int rpt = (int)cdiv(Mp, QP_T);
-  return PanelShape{rpt <= 3 ? 16 : 8, rpt};  // 4 x 16 doubles per thread would spill
+  return PanelShape{rpt <= 5 ? 16 : 8, rpt};  // 6 x 16 doubles per thread would spill
 }
 
 gn_status run_panel(double* C, int64_t ldc, int64_t M, int64_t j0, int nbw, double* Tp,
@@ -587,8 +587,8 @@ gn_status run_panel(double* C, int64_t ldc, int64_t M, int64_t j0, int nbw, doub
     case 1: GN_PANEL(1, 16); break;
     case 2: GN_PANEL(2, 16); break;
     case 3: GN_PANEL(3, 16); break;
-    case 4: GN_PANEL(4, 8); break;
-    case 5: GN_PANEL(5, 8); break;
+    case 4: GN_PANEL(4, 16); break;
+    case 5: GN_PANEL(5, 16); break;
     case 6: GN_PANEL(6, 8); break;
     case 7: GN_PANEL(7, 8); break;
     case 8: GN_PANEL(8, 8); break;
