@@ -241,10 +241,23 @@ __device__ void f32_tile_cfg(const GemmF32& g, int64_t local, char* smem) {
 using F32Pass = F32Cfg<256, 256, 32, 4, 4, 32>;
 
 // ------------------------------------------------------------------ BF16 with block scales
-// A(i,k) = PA[i*lda + k] (k-contiguous; the matrix A when A_IS_MAT, then scaled);
-// B(k,j) = PB[j*ldb + k] when B_KC, else PB[k*ldb + j] (the matrix A, scaled).
-// LDS holds both operands k-contiguous, S[row][k] (row stride BK + 8 bf16), the
-// layout the bf16 MFMA fragments read with one 16-byte load per lane.
+// A(i,k) = PA[i*lda + k] (k-contiguous; the matrix A when A_IS_MAT);
+// B(k,j) = PB[j*ldb + k] when B_KC, else PB[k*ldb + j] (the matrix A).
+// The matrix operand is stored as bfloat16 values in [-1, 1] with one
+// power-of-two scale per 128 x 128 block.  Tiles copy the stored values into LDS
+// unchanged; the scale is applied to the accumulators instead: each wave's 64
+// output rows (AX) or columns (Y^T A) lie in one scale block, so along K the
+// accumulators are kept in units of the current K block's scale and multiplied
+// by the ratio of consecutive scales at each 128-deep K block boundary, and by
+// the last scale at the end.  Scaling by powers of two is exact, so the result
+// equals the product of the scaled values.
+// k-contiguous operands live in LDS as S[row][k] (row stride BK + 8), read with
+// one 16-byte load per lane per MFMA fragment; the n-contiguous matrix operand
+// of Y^T A lives as S[k][j] (row stride BN + 16), copied 16 bytes at a time and
+// read with the transposing LDS load (ds_read_b64_tr_b16): in each group of 16
+// lanes, lane 4a + b reads the 4 values at row k0 + a, columns c0 + 4b .. + 3,
+// and lane i receives column c0 + i at rows k0 .. k0 + 3, which is the layout
+// of the MFMA B fragment.
 struct GemmBF16 {
   int64_t M, N, K;
   const uint16_t* A;
@@ -266,144 +279,78 @@ struct BF16Cfg {
   static constexpr int TM = BM / WM, TN = BN / WN;
   static constexpr int FM = TM / 32, FN = TN / 32;
   static constexpr int LDK = BK + 8;
-  static constexpr size_t smem() { return 2 * (size_t)(BM + BN) * LDK * sizeof(uint16_t); }
+  static constexpr int LDN = BN + 16;
+  static_assert(TM % 32 == 0 && TN % 32 == 0 && 128 % TM == 0 && 128 % TN == 0 && 128 % BK == 0,
+                "a wave's rows and columns must lie in one 128 x 128 scale block");
+  static constexpr size_t smem() {
+    const size_t kc = 2 * (size_t)(BM + BN) * LDK;
+    const size_t nc = 2 * (size_t)BM * LDK + 2 * (size_t)BK * LDN;
+    return (kc > nc ? kc : nc) * sizeof(uint16_t);
+  }
 };
 
-// Multiply two packed bfloat16 values by a power of two (exact).
-__device__ __forceinline__ uint32_t scale_bf16x2(uint32_t w, float s) {
-  const float lo = __uint_as_float(w << 16) * s;
-  const float hi = __uint_as_float(w & 0xffff0000u) * s;
-  return (__float_as_uint(lo) >> 16) | (__float_as_uint(hi) & 0xffff0000u);
-}
-
-// k-contiguous operand tile (ROWS x BK): 16-byte chunks straight into S[row][k].
-// load() only issues the global loads (the prefetch of the next K slab); the
-// block scale is applied in store(), after the current slab's MFMAs.
-template <int ROWS, int BK, int T, bool SCALED>
-struct BFStageKC {
-  static constexpr int NV = ROWS * BK / 8 / T;
-  static_assert(NV * 8 * T == ROWS * BK, "tile not divisible");
+// 16-byte chunks of a row-major operand slab: ROWS rows of WIDTH elements
+// starting at (r0, c0) of P, copied into S[row][c] (row stride LDS_).
+template <int ROWS, int WIDTH, int T, int LDS_>
+struct BFStage {
+  static constexpr int NV = ROWS * WIDTH / 8 / T;
+  static_assert(NV >= 1 && NV * 8 * T == ROWS * WIDTH, "tile not divisible");
   u32x4 v[NV];
-  float sc[SCALED ? NV : 1];
   __device__ __forceinline__ void load(const uint16_t* __restrict__ P, int64_t ld, int64_t rows,
-                                       int64_t K, int64_t r0, int64_t k0,
-                                       const float* __restrict__ scales, int64_t nsb, bool vec) {
+                                       int64_t cols, int64_t r0, int64_t c0, bool vec) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       const int e = threadIdx.x + T * q;
-      const int64_t row = r0 + e / (BK / 8), k = k0 + 8 * (e % (BK / 8));
+      const int64_t row = r0 + e / (WIDTH / 8), c = c0 + 8 * (e % (WIDTH / 8));
       u32x4 x = {0u, 0u, 0u, 0u};
-      float s = 0.f;
-      if (row < rows && k < K) {
-        const uint16_t* src = P + row * ld + k;
-        if (vec && k + 7 < K) {
+      if (row < rows && c < cols) {
+        const uint16_t* src = P + row * ld + c;
+        if (vec && c + 7 < cols) {
           x = *reinterpret_cast<const u32x4*>(src);
         } else {
 #pragma unroll
           for (int t = 0; t < 8; ++t) {
-            const uint32_t b = (k + t < K) ? src[t] : 0u;
+            const uint32_t b = (c + t < cols) ? src[t] : 0u;
             x[t >> 1] |= b << (16 * (t & 1));
           }
         }
-        if (SCALED) s = scales[(row >> 7) * nsb + (k >> 7)];
       }
       v[q] = x;
-      if (SCALED) sc[q] = s;
     }
   }
   __device__ __forceinline__ void store(uint16_t* S) const {
-    constexpr int LDK = BK + 8;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       const int e = threadIdx.x + T * q;
-      const int row = e / (BK / 8), kc = 8 * (e % (BK / 8));
-      u32x4 x = v[q];
-      if (SCALED) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) x[t] = scale_bf16x2(x[t], sc[q]);
-      }
-      *reinterpret_cast<u32x4*>(S + row * LDK + kc) = x;
+      const int row = e / (WIDTH / 8), c = 8 * (e % (WIDTH / 8));
+      *reinterpret_cast<u32x4*>(S + row * LDS_ + c) = v[q];
     }
   }
 };
 
-// n-contiguous matrix operand (BK x COLS, scaled) transposed into S[j][k]: a task
-// reads rows k, k+1 at 8 consecutive j and writes eight (k, k+1) pairs.  As in
-// BFStageKC, scaling happens in store().
-template <int COLS, int BK, int T>
-struct BFStageNC {
-  static constexpr int TASKS = (BK / 2) * (COLS / 8);
-  static constexpr int NT = (TASKS + T - 1) / T;
-  u32x4 v0[NT], v1[NT];
-  float sc[NT];
-  __device__ __forceinline__ void load(const uint16_t* __restrict__ P, int64_t ld, int64_t cols,
-                                       int64_t K, int64_t j0, int64_t k0,
-                                       const float* __restrict__ scales, int64_t nsb, bool vec) {
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      const int task = threadIdx.x + T * q;
-      v0[q] = u32x4{0u, 0u, 0u, 0u};
-      v1[q] = u32x4{0u, 0u, 0u, 0u};
-      sc[q] = 0.f;
-      if (task >= TASKS) continue;
-      // consecutive lanes take consecutive k-pairs: their (k, k+1) words land in
-      // consecutive LDS banks in store() (a j-major order would put all lanes of
-      // a wave in one bank, the row stride of 8 columns being a multiple of 128 B)
-      const int kp = task % (BK / 2), jc = task / (BK / 2);
-      const int64_t k = k0 + 2 * kp, j = j0 + 8 * jc;
-      if (j >= cols || k >= K) continue;
-      // k is even, so rows k and k+1 share one 128-row scale block
-      sc[q] = scales[(k >> 7) * nsb + (j >> 7)];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int64_t kk = k + h;
-        if (kk >= K) continue;
-        const uint16_t* src = P + kk * ld + j;
-        u32x4 x = {0u, 0u, 0u, 0u};
-        if (vec && j + 7 < cols) {
-          x = *reinterpret_cast<const u32x4*>(src);
-        } else {
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const uint32_t b = (j + t < cols) ? src[t] : 0u;
-            x[t >> 1] |= b << (16 * (t & 1));
-          }
-        }
-        if (h == 0)
-          v0[q] = x;
-        else
-          v1[q] = x;
-      }
-    }
-  }
-  __device__ __forceinline__ void store(uint16_t* S) const {
-    constexpr int LDK = BK + 8;
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      const int task = threadIdx.x + T * q;
-      if (task >= TASKS) continue;
-      const int kp = task % (BK / 2), jc = task / (BK / 2);
-      u32x4 a4 = v0[q], b4 = v1[q];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        a4[t] = scale_bf16x2(a4[t], sc[q]);
-        b4[t] = scale_bf16x2(b4[t], sc[q]);
-      }
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const uint32_t a = (a4[t >> 1] >> (16 * (t & 1))) & 0xffffu;
-        const uint32_t b = (b4[t >> 1] >> (16 * (t & 1))) & 0xffffu;
-        *reinterpret_cast<uint32_t*>(S + (8 * jc + t) * LDK + 2 * kp) = a | (b << 16);
-      }
-    }
-  }
-};
+typedef short bf16x4_bits __attribute__((ext_vector_type(4)));
+
+// Eight k-consecutive bfloat16 values of column `col` for the MFMA B fragment
+// from S[k][j] (row stride LDN): two transposing loads of four rows each.
+template <int LDN>
+__device__ __forceinline__ bf16x8 bf16_frag_tr(const uint16_t* S, int k0, int c0, int lane) {
+  const int g = lane >> 4, p = lane & 15, a = p >> 2, b = p & 3;
+  const int row = k0 + 8 * (g >> 1) + a, col = c0 + 16 * (g & 1) + 4 * b;
+  typedef __attribute__((address_space(3))) bf16x4_bits lds_v4;
+  const bf16x4_bits h0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4*)(S + row * LDN + col));
+  const bf16x4_bits h1 =
+      __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4*)(S + (row + 4) * LDN + col));
+  typedef short s8 __attribute__((ext_vector_type(8)));
+  const s8 v = {h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+  return __builtin_bit_cast(bf16x8, v);
+}
 
 template <class CF, bool A_IS_MAT, bool B_KC>
 __device__ void bf16_tile_cfg(const GemmBF16& g, int64_t local, char* smem) {
-  constexpr int BM = CF::BM, BN = CF::BN, BK = CF::BK, LDK = CF::LDK;
+  constexpr int BM = CF::BM, BN = CF::BN, BK = CF::BK, LDK = CF::LDK, LDN = CF::LDN;
+  constexpr int SB = B_KC ? BN * LDK : BK * LDN;     // one B buffer
   uint16_t* sA = reinterpret_cast<uint16_t*>(smem);  // [2][BM * LDK]
-  uint16_t* sB = sA + 2 * BM * LDK;                  // [2][BN * LDK]
+  uint16_t* sB = sA + 2 * BM * LDK;                  // [2][SB]
   const int64_t tm_n = cdiv_d(g.M, BM), tn_n = cdiv_d(g.N, BN);
   int64_t tm, tn;
   if (g.inner_is_m) {
@@ -423,25 +370,56 @@ __device__ void bf16_tile_cfg(const GemmBF16& g, int64_t local, char* smem) {
     for (int y = 0; y < CF::FN; ++y)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.f;
+  // the scale block of this wave's rows (AX) or columns (Y^T A), clamped at the edge
+  const int64_t nkb = cdiv_d(g.K, 128);
+  const int64_t obl = A_IS_MAT ? (i0 + wm * CF::TM) >> 7 : (j0 + wn * CF::TN) >> 7;
+  const int64_t omax = A_IS_MAT ? cdiv_d(g.M, 128) - 1 : g.nsb - 1;
+  const int64_t ob = obl < omax ? obl : omax;
+  auto scale_of = [&](int64_t kb) -> float {
+    return A_IS_MAT ? g.scales[ob * g.nsb + kb] : g.scales[kb * g.nsb + ob];
+  };
+  int64_t kb_cur = 0;
+  float s_cur = scale_of(0);
 
-  BFStageKC<BM, BK, CF::T, A_IS_MAT> sa;
-  typedef typename std::conditional<B_KC, BFStageKC<BN, BK, CF::T, false>,
-                                    BFStageNC<BN, BK, CF::T>>::type StageB;
+  BFStage<BM, BK, CF::T, LDK> sa;
+  typedef typename std::conditional<B_KC, BFStage<BN, BK, CF::T, LDK>,
+                                    BFStage<BK, BN, CF::T, LDN>>::type StageB;
   StageB sb;
   const int64_t nk = cdiv_d(g.K, BK);
-  sa.load(g.A, g.lda, g.M, g.K, i0, 0, g.scales, g.nsb, vec);
-  sb.load(g.B, g.ldb, g.N, g.K, j0, 0, g.scales, g.nsb, vec);
+  // A: rows i0.., k 0..; B: rows j0.., k 0.. (k-contiguous) or rows k 0.., columns j0..
+  sa.load(g.A, g.lda, g.M, g.K, i0, 0, vec);
+  if (B_KC)
+    sb.load(g.B, g.ldb, g.N, g.K, j0, 0, vec);
+  else
+    sb.load(g.B, g.ldb, g.K, g.N, 0, j0, vec);
   sa.store(sA);
   sb.store(sB);
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      sa.load(g.A, g.lda, g.M, g.K, i0, (kt + 1) * BK, g.scales, g.nsb, vec);
-      sb.load(g.B, g.ldb, g.N, g.K, j0, (kt + 1) * BK, g.scales, g.nsb, vec);
+      const int64_t kn = (kt + 1) * BK;
+      sa.load(g.A, g.lda, g.M, g.K, i0, kn, vec);
+      if (B_KC)
+        sb.load(g.B, g.ldb, g.N, g.K, j0, kn, vec);
+      else
+        sb.load(g.B, g.ldb, g.K, g.N, kn, j0, vec);
+    }
+    {
+      const int64_t kb = (kt * BK) >> 7;
+      if (kb != kb_cur) {
+        const float s_new = scale_of(kb);
+        const float ratio = s_cur / s_new;  // a power of two: exact
+#pragma unroll
+        for (int x = 0; x < CF::FM; ++x)
+#pragma unroll
+          for (int y = 0; y < CF::FN; ++y) acc[x][y] *= ratio;
+        s_cur = s_new;
+        kb_cur = kb;
+      }
     }
     const uint16_t* a_s = sA + cur * BM * LDK + (wm * CF::TM + li) * LDK + 8 * lk;
-    const uint16_t* b_s = sB + cur * BN * LDK + (wn * CF::TN + li) * LDK + 8 * lk;
+    const uint16_t* b_base = sB + cur * SB;
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
       bf16x8 af[CF::FM], bfr[CF::FN];
@@ -449,8 +427,14 @@ __device__ void bf16_tile_cfg(const GemmBF16& g, int64_t local, char* smem) {
       for (int x = 0; x < CF::FM; ++x)
         af[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(a_s + x * 32 * LDK + ks));
 #pragma unroll
-      for (int y = 0; y < CF::FN; ++y)
-        bfr[y] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(b_s + y * 32 * LDK + ks));
+      for (int y = 0; y < CF::FN; ++y) {
+        if (B_KC)
+          bfr[y] = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const u32x4*>(b_base + (wn * CF::TN + y * 32 + li) * LDK +
+                                                      8 * lk + ks));
+        else
+          bfr[y] = bf16_frag_tr<LDN>(b_base, ks, wn * CF::TN + y * 32, lane);
+      }
 #pragma unroll
       for (int x = 0; x < CF::FM; ++x)
 #pragma unroll
@@ -459,10 +443,11 @@ __device__ void bf16_tile_cfg(const GemmBF16& g, int64_t local, char* smem) {
     }
     if (kt + 1 < nk) {
       sa.store(sA + (cur ^ 1) * BM * LDK);
-      sb.store(sB + (cur ^ 1) * BN * LDK);
+      sb.store(sB + (cur ^ 1) * SB);
     }
     __syncthreads();
   }
+  (void)nkb;
   // 32x32 accumulator: register v of lane l holds row 8(v/4) + 4(l/32) + v%4, column l%32.
 #pragma unroll
   for (int x = 0; x < CF::FM; ++x)
@@ -472,12 +457,14 @@ __device__ void bf16_tile_cfg(const GemmBF16& g, int64_t local, char* smem) {
       for (int v = 0; v < 16; ++v) {
         const int64_t row = i0 + wm * CF::TM + x * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
         const int64_t col = j0 + wn * CF::TN + y * 32 + li;
-        if (row < g.M && col < g.N) g.D[row * g.ldd + col] = acc[x][y][v];
+        if (row < g.M && col < g.N) g.D[row * g.ldd + col] = acc[x][y][v] * s_cur;
       }
 }
 
-// The production BF16 configuration: 256 x 256 tiles, 16 waves of 64 x 64.
-using BF16Pass = BF16Cfg<256, 256, 32, 4, 4>;
+// The production BF16 configuration: 256 x 256 tiles, 16 waves of 64 x 64, K
+// staged 64 deep (a 32-deep slab leaves too little MFMA work per wave to cover
+// the next slab's global loads).
+using BF16Pass = BF16Cfg<256, 256, 64, 4, 4>;
 
 }  // namespace tiles
 }  // namespace gn
