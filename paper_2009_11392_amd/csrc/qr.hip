@@ -14,11 +14,15 @@
 // (the y of the compact-WY recurrence for T, H_1 ... H_nb = I - V T V^T).
 // Reductions are in a fixed order, so results do not depend on scheduling.
 //
-// The block reflector is applied to the trailing columns, C2 <- (I - V T^T V^T) C2,
-// and, walking the panels backwards from [I; 0], to the explicit Q with
-// Q2 <- (I - V T V^T) Q2, by two kernels over (128-row chunk) x (64-column group)
-// tiles: partial W = V^T D per chunk, then W summed over chunks in chunk order,
-// multiplied by T^T (or T) and subtracted, D -= V W.
+// A panel's block reflector is applied to the columns left in its outer block of
+// QR_OB columns, C2 <- (I - V T^T V^T) C2, by one kernel per panel that sums
+// W = V^T C2 on chip; each outer block's panels are merged into one block
+// reflector (T from the panels' T's and V^T V), which FP64 matrix products apply
+// to the trailing columns and, walking the outer blocks backwards from [I; 0], to
+// the explicit Q with Q2 <- (I - V T V^T) Q2.  The batched form (many small
+// problems, one panel width at a time) updates with two kernels over
+// (128-row chunk) x (64-column group) tiles: partial W = V^T D per chunk, then W
+// summed over chunks in chunk order, multiplied by T^T (or T) and subtracted.
 #include "gn_internal.h"
 #include "wave_ops.h"
 
@@ -28,17 +32,16 @@
 namespace gn {
 namespace {
 
-constexpr int QP_T = 512;
-constexpr int QP_WAVES = QP_T / 64;
+constexpr int QP_T = 512;  // largest panel workgroup (and the batched panel's)
 constexpr int QR_MAXROWS = 4096;
 constexpr int QR_NB = 16;  // largest panel width
 
 // One column step of the panel, c a compile-time column index: every register
 // array is indexed by constants, and only row c's thread and the rows above the
 // pivot (all in the first register row, c < NB) need run-time predicates.
-template <int RPT, int NB, int c>
+template <int RPT, int NB, int NT, int c>
 __device__ __forceinline__ void qr_column(double (&p)[RPT][NB], int t, int lane, int wave,
-                                          double (*part)[QP_WAVES][NB], double (*prow)[NB],
+                                          double (*part)[NT / 64][NB], double (*prow)[NB],
                                           double (*T)[NB + 1]) {
   constexpr int buf = c & 1;
   constexpr int kLowBits = 64 / NB;  // lanes sharing a reduction slot
@@ -46,7 +49,7 @@ __device__ __forceinline__ void qr_column(double (&p)[RPT][NB], int t, int lane,
 #pragma unroll
   for (int q = 0; q < RPT; ++q) x[q] = p[q][c];
   // slot cc: x . p_cc over rows >= c; slot c: |x|^2 over rows > c.  Rows of
-  // register row q >= 1 are >= 512 > c.
+  // register row q >= 1 are >= NT > c.
   const double x_ge = (t >= c) ? x[0] : 0.0;
   const double x_gt = (t > c) ? x[0] : 0.0;
   double acc[NB];
@@ -65,20 +68,14 @@ __device__ __forceinline__ void qr_column(double (&p)[RPT][NB], int t, int lane,
   const double ws = wave_transpose_sum<NB>(acc, lane, &slot);
   if ((lane & (kLowBits - 1)) == 0) part[buf][wave][slot] = ws;
   __syncthreads();
-  // totals, summed over waves in a fixed order, made uniform via readlane
-  double tot_l = 0.0;
-  {
-    const int sl = lane % NB;
+  // lane l holds the total of slot l % NB (summed over waves in a fixed order)
+  // and the pivot row's entry P_l; sigma and alpha are made uniform
+  const int sl = lane % NB;
+  double tot = 0.0;
 #pragma unroll
-    for (int w = 0; w < QP_WAVES; ++w) tot_l += part[buf][w][sl];
-  }
-  double D[NB], P[NB];
-#pragma unroll
-  for (int cc = 0; cc < NB; ++cc) {
-    D[cc] = readlane_f64(tot_l, cc);  // lane cc holds slot cc
-    P[cc] = prow[buf][cc];
-  }
-  const double sigma = D[c], alpha = P[c];
+  for (int w = 0; w < NT / 64; ++w) tot += part[buf][w][sl];
+  const double Pl = prow[buf][sl];
+  const double sigma = readlane_f64(tot, c), alpha = prow[buf][c];
   double beta = alpha, tau = 0.0, scale = 0.0;
   if (sigma != 0.0) {
     const double nrm = sqrt(fma(alpha, alpha, sigma));
@@ -86,17 +83,20 @@ __device__ __forceinline__ void qr_column(double (&p)[RPT][NB], int t, int lane,
     tau = (beta - alpha) / beta;
     scale = 1.0 / (alpha - beta);
   }
-  // w_j = v^T p_j for every j != c (earlier reflectors: y of the T recurrence)
-  double w[NB];
+  // tw_j = -tau v^T p_j with v^T p_j = (x.p_j - beta p_j[c]) / (alpha - beta), one
+  // j per lane, then made uniform: the update of the columns right of c and, for
+  // j < c, the y of the T recurrence
+  const double twl = (tau != 0.0) ? -tau * (scale * fma(-beta, Pl, tot)) : 0.0;
+  double tw[NB];
 #pragma unroll
-  for (int cc = 0; cc < NB; ++cc) w[cc] = (tau != 0.0) ? scale * fma(-beta, P[cc], D[cc]) : P[cc];
+  for (int cc = 0; cc < NB; ++cc) tw[cc] = readlane_f64(twl, cc);
   // apply H_c to the columns right of c; store v and R_cc = beta in column c
   const double v0 = (t > c) ? x[0] * scale : (t == c ? 1.0 : 0.0);
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const double v = (q == 0) ? v0 : x[q] * scale;
 #pragma unroll
-    for (int cc = c + 1; cc < NB; ++cc) p[q][cc] = fma(-tau * w[cc], v, p[q][cc]);
+    for (int cc = c + 1; cc < NB; ++cc) p[q][cc] = fma(tw[cc], v, p[q][cc]);
   }
   if (tau != 0.0) {
     p[0][c] = (t > c) ? v0 : (t == c ? beta : p[0][c]);
@@ -108,25 +108,25 @@ __device__ __forceinline__ void qr_column(double (&p)[RPT][NB], int t, int lane,
   if (t < c) {
     double s = 0.0;
 #pragma unroll
-    for (int l = 0; l < c; ++l) s = fma(T[t][l], w[l], s);
-    T[t][c] = -tau * s;
+    for (int l = 0; l < c; ++l) s = fma(T[t][l], tw[l], s);
+    T[t][c] = s;
   }
   if (t == c) T[c][c] = tau;
 }
 
-template <int RPT, int NB, int... Cs>
+template <int RPT, int NB, int NT, int... Cs>
 __device__ __forceinline__ void qr_columns(std::integer_sequence<int, Cs...>, int nbw,
                                            double (&p)[RPT][NB], int t, int lane, int wave,
-                                           double (*part)[QP_WAVES][NB], double (*prow)[NB],
+                                           double (*part)[NT / 64][NB], double (*prow)[NB],
                                            double (*T)[NB + 1]) {
   // nbw is uniform: columns past the panel width are skipped by a scalar branch
-  ((Cs < nbw ? (qr_column<RPT, NB, Cs>(p, t, lane, wave, part, prow, T), 0) : 0), ...);
+  ((Cs < nbw ? (qr_column<RPT, NB, NT, Cs>(p, t, lane, wave, part, prow, T), 0) : 0), ...);
 }
 
-template <int RPT, int NB>
+template <int RPT, int NB, int NT>
 __device__ __forceinline__ void qr_panel_body(double* __restrict__ C, int64_t ldc, int64_t M,
                                               int64_t j0, int nbw, double* __restrict__ Tout) {
-  __shared__ double part[2][QP_WAVES][NB];
+  __shared__ double part[2][NT / 64][NB];
   __shared__ double prow[2][NB];
   __shared__ double T[NB][NB + 1];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -134,7 +134,7 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ C, int64_t ld
   double p[RPT][NB];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t row = t + (int64_t)QP_T * q;
+    const int64_t row = t + (int64_t)NT * q;
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       p[q][c] = (row < Mp && c < nbw) ? C[(j0 + row) * ldc + j0 + c] : 0.0;
@@ -142,25 +142,26 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ C, int64_t ld
   if (t < NB) {
     for (int l = 0; l < NB; ++l) T[t][l] = 0.0;  // row t of T is only touched by thread t
   }
-  qr_columns<RPT, NB>(std::make_integer_sequence<int, NB>{}, nbw, p, t, lane, wave, part, prow, T);
+  qr_columns<RPT, NB, NT>(std::make_integer_sequence<int, NB>{}, nbw, p, t, lane, wave, part, prow,
+                          T);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t row = t + (int64_t)QP_T * q;
+    const int64_t row = t + (int64_t)NT * q;
     if (row >= Mp) continue;
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       if (c < nbw) C[(j0 + row) * ldc + j0 + c] = p[q][c];
   }
-  if (t < NB * NB) Tout[(t / NB) * QR_NB + (t % NB)] = T[t / NB][t % NB];  // stride QR_NB
+  for (int e = t; e < NB * NB; e += NT) Tout[(e / NB) * QR_NB + (e % NB)] = T[e / NB][e % NB];  // stride QR_NB
 }
 
-template <int RPT, int NB>
-__global__ void __launch_bounds__(QP_T) qr_panel(double* __restrict__ C, int64_t ldc, int64_t M,
+template <int RPT, int NB, int NT>
+__global__ void __launch_bounds__(NT) qr_panel(double* __restrict__ C, int64_t ldc, int64_t M,
                                                  int64_t j0, int nbw, double* __restrict__ Tout,
                                                  const int32_t* gate, int64_t gate_n) {
   if (gate && *gate >= gate_n) return;
-  qr_panel_body<RPT, NB>(C, ldc, M, j0, nbw, Tout);
+  qr_panel_body<RPT, NB, NT>(C, ldc, M, j0, nbw, Tout);
 }
 
 // Batched: job blockIdx.z, panel of width 16 at column j0 (every job has at most
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__(QP_T) qr_panel_b(const QrJob* __restrict__ job
   if (J.gate && *J.gate >= J.gate_n) return;
   if (j0 >= J.N) return;
   const int nbw = (int)((J.N - j0 < QR_NB) ? (J.N - j0) : QR_NB);
-  qr_panel_body<1, QR_NB>(J.C, J.ldc, J.M, j0, nbw, J.T + (j0 / QR_NB) * QR_NB * QR_NB);
+  qr_panel_body<1, QR_NB, QP_T>(J.C, J.ldc, J.M, j0, nbw, J.T + (j0 / QR_NB) * QR_NB * QR_NB);
 }
 
 // Block-reflector update of D[j0 + i, col0 + j] (0 <= i < M - j0, 0 <= j < ncols)
@@ -230,13 +231,104 @@ __device__ __forceinline__ void qr_upd_w_body(const double* __restrict__ Cp, int
   }
 }
 
-__global__ void __launch_bounds__(256) qr_upd_w(const double* __restrict__ Cp, int64_t ldc,
-                                                int64_t M, int64_t j0, int nbw,
-                                                const double* __restrict__ D, int64_t ldd,
-                                                int64_t col0, int64_t ncols, double* __restrict__ Wp,
-                                                const int32_t* gate, int64_t gate_n) {
+
+// Single-launch update of a narrow target (the columns left in the outer block):
+// one workgroup per QF_CPW target columns walks the whole panel height (row
+// t + 256 q in thread t, the d values kept in registers), so W = V^T D is summed
+// on chip and no second launch is needed: W by a transposing wave sum and the
+// waves' partials in a fixed order, W <- Top W (Top = T^T when trans, else T),
+// then D -= V W with V's rows read again.
+constexpr int QF_T = 256;
+constexpr int QF_CPW = 2;                   // target columns per workgroup
+constexpr int QF_RPT = QR_MAXROWS / QF_T;   // rows per thread at the largest height
+
+__device__ __forceinline__ void qr_load_vrow(double (&v)[QR_NB], const double* __restrict__ Cp,
+                                             int64_t ldc, int64_t j0, int64_t row, int nbw) {
+  const double* vr = Cp + (j0 + row) * ldc + j0;
+#pragma unroll
+  for (int a = 0; a < QR_NB; ++a)
+    v[a] = (a < nbw && row >= a) ? (row == a ? 1.0 : vr[a]) : 0.0;
+}
+
+__global__ void __launch_bounds__(QF_T) qr_upd_fused(const double* __restrict__ Cp, int64_t ldc,
+                                                     int64_t M, int64_t j0, int nbw,
+                                                     double* __restrict__ D, int64_t ldd,
+                                                     int64_t col0, int64_t ncols,
+                                                     const double* __restrict__ T, int trans,
+                                                     const int32_t* gate, int64_t gate_n) {
   if (gate && *gate >= gate_n) return;
-  qr_upd_w_body(Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Wp, blockIdx.x, blockIdx.y);
+  constexpr int NW = QR_NB * QF_CPW;  // W entries, a + 16 b
+  __shared__ double part[QF_T / 64][NW];
+  __shared__ double sT[QR_NB][QR_NB + 1];
+  __shared__ double Ws[NW];
+  __shared__ double W2s[NW];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t Mp = M - j0;
+  const int64_t c0 = (int64_t)blockIdx.x * QF_CPW;
+  {
+    const int a = t / QR_NB, l = t % QR_NB;  // 256 = 16 x 16
+    const double v = trans ? T[l * QR_NB + a] : T[a * QR_NB + l];
+    sT[a][l] = (a < nbw && l < nbw) ? v : 0.0;
+  }
+  double d[QF_RPT][QF_CPW];
+  double acc[NW];
+#pragma unroll
+  for (int i = 0; i < NW; ++i) acc[i] = 0.0;
+#pragma unroll
+  for (int q = 0; q < QF_RPT; ++q) {
+    const int64_t row = t + (int64_t)QF_T * q;
+    const bool in = row < Mp;
+#pragma unroll
+    for (int b = 0; b < QF_CPW; ++b)
+      d[q][b] = (in && c0 + b < ncols) ? D[(j0 + row) * ldd + col0 + c0 + b] : 0.0;
+    if (in) {
+      double v[QR_NB];
+      qr_load_vrow(v, Cp, ldc, j0, row, nbw);
+#pragma unroll
+      for (int b = 0; b < QF_CPW; ++b)
+#pragma unroll
+        for (int a = 0; a < QR_NB; ++a) acc[a + QR_NB * b] = fma(v[a], d[q][b], acc[a + QR_NB * b]);
+    }
+  }
+  int slot;
+  const double ws = wave_transpose_sum<NW>(acc, lane, &slot);
+  if ((lane & (64 / NW - 1)) == 0) part[wave][slot] = ws;
+  __syncthreads();
+  if (t < NW) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < QF_T / 64; ++w) s += part[w][t];
+    Ws[t] = s;
+  }
+  __syncthreads();
+  if (t < NW) {
+    const int a = t % QR_NB, b = t / QR_NB;
+    double s = 0.0;
+#pragma unroll
+    for (int l = 0; l < QR_NB; ++l) s = fma(sT[a][l], Ws[l + QR_NB * b], s);
+    W2s[t] = s;
+  }
+  __syncthreads();
+  double w2[QF_CPW][QR_NB];
+#pragma unroll
+  for (int b = 0; b < QF_CPW; ++b)
+#pragma unroll
+    for (int a = 0; a < QR_NB; ++a) w2[b][a] = W2s[a + QR_NB * b];
+#pragma unroll
+  for (int q = 0; q < QF_RPT; ++q) {
+    const int64_t row = t + (int64_t)QF_T * q;
+    if (row < Mp) {
+      double v[QR_NB];
+      qr_load_vrow(v, Cp, ldc, j0, row, nbw);
+#pragma unroll
+      for (int b = 0; b < QF_CPW; ++b) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < QR_NB; ++a) s = fma(v[a], w2[b][a], s);
+        if (c0 + b < ncols) D[(j0 + row) * ldd + col0 + c0 + b] = d[q][b] - s;
+      }
+    }
+  }
 }
 
 // Batched update target of job J for the panel at j0: the trailing columns of C
@@ -342,17 +434,6 @@ __device__ __forceinline__ void qr_upd_apply_body(const double* __restrict__ Cp,
   }
 }
 
-__global__ void __launch_bounds__(256) qr_upd_apply(const double* __restrict__ Cp, int64_t ldc,
-                                                    int64_t M, int64_t j0, int nbw,
-                                                    double* __restrict__ D, int64_t ldd,
-                                                    int64_t col0, int64_t ncols,
-                                                    const double* __restrict__ Wp, int nchunks,
-                                                    const double* __restrict__ T, int trans,
-                                                    const int32_t* gate, int64_t gate_n) {
-  if (gate && *gate >= gate_n) return;
-  qr_upd_apply_body(Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Wp, nchunks, T, trans, blockIdx.x,
-                    blockIdx.y);
-}
 
 __global__ void __launch_bounds__(256) qr_upd_apply_b(const QrJob* __restrict__ jobs, int64_t j0,
                                                       int phase) {
@@ -535,9 +616,13 @@ __global__ void __launch_bounds__(256) qr_merge_t(const double* __restrict__ G,
                                                   int64_t gate_n) {
   if (gate && *gate >= gate_n) return;
   __shared__ double T[QR_OB][QR_OB + 1];
+  __shared__ double Gs[QR_OB][QR_OB + 1];
   __shared__ double Y[QR_OB][QR_NB + 1];
   const int tid = threadIdx.x;
-  for (int e = tid; e < QR_OB * QR_OB; e += 256) T[e / QR_OB][e % QR_OB] = 0.0;
+  for (int e = tid; e < QR_OB * QR_OB; e += 256) {
+    T[e / QR_OB][e % QR_OB] = 0.0;
+    Gs[e / QR_OB][e % QR_OB] = G[e];
+  }
   __syncthreads();
   for (int b = 0; b < op.count; ++b) {
     const int o = op.off[b], wb = op.width[b];
@@ -549,7 +634,7 @@ __global__ void __launch_bounds__(256) qr_merge_t(const double* __restrict__ G,
       for (int e = tid; e < o * wb; e += 256) {
         const int i = e / wb, j = e % wb;
         double acc = 0.0;
-        for (int l = i; l < o; ++l) acc = fma(T[i][l], G[l * QR_OB + o + j], acc);
+        for (int l = i; l < o; ++l) acc = fma(T[i][l], Gs[l][o + j], acc);
         Y[i][j] = acc;
       }
       __syncthreads();
@@ -582,7 +667,7 @@ gn_status run_panel(double* C, int64_t ldc, int64_t M, int64_t j0, int nbw, doub
                     const int32_t* gate, int64_t gate_n, hipStream_t s) {
   const PanelShape ps = panel_shape(M - j0);
   const dim3 g(1), b(QP_T);
-#define GN_PANEL(R, NBV) qr_panel<R, NBV><<<g, b, 0, s>>>(C, ldc, M, j0, nbw, Tp, gate, gate_n)
+#define GN_PANEL(R, NBV) qr_panel<R, NBV, QP_T><<<g, b, 0, s>>>(C, ldc, M, j0, nbw, Tp, gate, gate_n)
   switch (ps.rpt) {
     case 1: GN_PANEL(1, 16); break;
     case 2: GN_PANEL(2, 16); break;
@@ -600,28 +685,24 @@ gn_status run_panel(double* C, int64_t ldc, int64_t M, int64_t j0, int nbw, doub
 }
 
 gn_status run_update(const double* Cp, int64_t ldc, int64_t M, int64_t j0, int nbw, double* D,
-                     int64_t ldd, int64_t col0, int64_t ncols, const double* Tp, int trans,
-                     double* Wp, const int32_t* gate, int64_t gate_n, hipStream_t s) {
+                    int64_t ldd, int64_t col0, int64_t ncols, const double* Tp, int trans,
+                    const int32_t* gate, int64_t gate_n, hipStream_t s) {
   if (ncols <= 0) return GN_OK;
-  const int nch = (int)cdiv(M - j0, QU_CH);
-  const dim3 g((unsigned)nch, (unsigned)cdiv(ncols, QU_CG)), b(256);
-  qr_upd_w<<<g, b, 0, s>>>(Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Wp, gate, gate_n);
-  GN_LAUNCH_CHECK();
-  qr_upd_apply<<<g, b, 0, s>>>(Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Wp, nch, Tp, trans, gate,
-                               gate_n);
+  if (M - j0 > QR_MAXROWS) return GN_ERR_UNSUPPORTED;
+  qr_upd_fused<<<dim3((unsigned)cdiv(ncols, QF_CPW)), dim3(QF_T), 0, s>>>(
+      Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Tp, trans, gate, gate_n);
   GN_LAUNCH_CHECK();
   return GN_OK;
 }
 
 }  // namespace
 
-// one nb x nb T per panel (panels are at least 8 wide), then the per-chunk
-// partial products of the block update
+// one nb x nb T per panel (panels are at least 8 wide)
 static size_t qr_t_bytes(int64_t N) {
   return align_up((size_t)(cdiv(N, 8) + 1) * QR_NB * QR_NB * sizeof(double));
 }
 struct QrWs {
-  size_t tin, wp, vb, g, w, w2, tout, split, split_bytes, total;
+  size_t tin, vb, g, w, w2, tout, split, split_bytes, total;
 };
 static QrWs qr_ws_layout(int64_t M, int64_t N) {
   QrWs q{};
@@ -632,7 +713,6 @@ static QrWs qr_ws_layout(int64_t M, int64_t N) {
     return o;
   };
   q.tin = take(qr_t_bytes(N));
-  q.wp = take((size_t)cdiv(M, QU_CH) * QR_NB * QR_OB * sizeof(double));  // inner updates only
   q.vb = take((size_t)M * QR_OB * sizeof(double));
   q.g = take((size_t)QR_OB * QR_OB * sizeof(double));
   q.w = take((size_t)QR_OB * N * sizeof(double));
@@ -658,7 +738,6 @@ gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int
   const QrWs L = qr_ws_layout(M, N);
   char* base = (char*)ws;
   double* Tin = (double*)(base + L.tin);
-  double* Wp = (double*)(base + L.wp);
   double* Vb = (double*)(base + L.vb);
   double* G = (double*)(base + L.g);
   double* W = (double*)(base + L.w);
@@ -679,8 +758,8 @@ gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int
       const int nbw = (int)((J1 - j0 < nb) ? (J1 - j0) : nb);
       double* Tp = Tin + (size_t)pi * QR_NB * QR_NB;
       GN_TRY(run_panel(C, ldc, M, j0, nbw, Tp, gate_k, gate_n, s));
-      GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, j0 + nbw, J1 - j0 - nbw, Tp, 1, Wp, gate_k,
-                        gate_n, s));
+      GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, j0 + nbw, J1 - j0 - nbw, Tp, 1, gate_k, gate_n,
+                        s));
       op.off[op.count] = (int)(j0 - J0);
       op.width[op.count] = nbw;
       op.tidx[op.count] = pi;

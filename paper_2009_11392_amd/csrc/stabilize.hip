@@ -230,15 +230,6 @@ __global__ void __launch_bounds__(JT) jacobi_round(double* __restrict__ W, doubl
 // reduced inside the wave).  A FULL launch first runs the circle method inside
 // each block with the 2B vectors in LDS (waves 0 .. B/2-1 on block I, the rest
 // on block J).
-// A 64-bit value moved between lanes of a 16-lane row by a DPP pattern.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
 // Sum over the 64 lanes, the same value in every lane: within each 16-lane row
 // by lane swaps (xor 1, xor 2, then the 8- and 16-lane mirrors, each pairing
 // lanes that hold disjoint partial sums), then the four row sums in a fixed order.
@@ -558,30 +549,42 @@ __global__ void __launch_bounds__(256) qrcp_init(const double* __restrict__ R, i
   Bc[e] = R[i * ldr + c];
 }
 
-// Step j: pivot = the largest remaining column norm (lowest index on ties; NaN
-// counts as largest), swapped into position j, then the Householder reflector of
-// column j (rows j..r-1): beta on the diagonal, v (v_j = 1) below it, tau_h.
-__global__ void __launch_bounds__(1024) qrcp_pivot(double* __restrict__ Bc, double* __restrict__ nrm,
-                                                   int32_t* __restrict__ perm,
-                                                   double* __restrict__ tauh, int64_t r, int64_t j) {
-  __shared__ double sv[1024];
-  __shared__ int64_t si[1024];
-  __shared__ double sred[16];
+// One pivoting step in one launch.  Every workgroup finds the pivot p of step j
+// (the largest norm among columns not pivoted before step j, lowest index on
+// ties, NaN first), forms the Householder vector of column p (rows j..r-1) in
+// LDS, and applies it to its own columns (one wave per column), writing their
+// new trailing norms to nrm_out.  Column p itself is never written again (only
+// the permutation is needed), and the pivot record is stamped with the step, so
+// the launch has no write a concurrent workgroup reads.  Workgroup 0 records p.
+constexpr int QCP_T = 256;
+constexpr int QCP_COLS = 16;  // columns per workgroup (four per wave)
+
+__global__ void __launch_bounds__(QCP_T) qrcp_step(double* __restrict__ Bc,
+                                                   const double* __restrict__ nrm_in,
+                                                   double* __restrict__ nrm_out,
+                                                   int32_t* __restrict__ stamp,
+                                                   int32_t* __restrict__ perm, int64_t r,
+                                                   int64_t j) {
+  __shared__ double sv[QCP_T];
+  __shared__ int64_t si[QCP_T];
+  __shared__ double sred[QCP_T / 64];
+  __shared__ double v[4096];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double best = -1.0;
   int64_t bi = r;
-  for (int64_t c = j + tid; c < r; c += 1024) {
-    double v = nrm[c];
-    if (isnan(v)) v = INFINITY;
-    if (v > best || (v == best && c < bi)) {
-      best = v;
+  for (int64_t c = tid; c < r; c += QCP_T) {
+    if (stamp[c] < j) continue;  // pivoted at an earlier step
+    double x = nrm_in[c];
+    if (isnan(x)) x = INFINITY;
+    if (x > best || (x == best && c < bi)) {
+      best = x;
       bi = c;
     }
   }
   sv[tid] = best;
   si[tid] = bi;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
+  for (int w = QCP_T / 2; w > 0; w >>= 1) {
     if (tid < w) {
       const double v2 = sv[tid + w];
       const int64_t i2 = si[tid + w];
@@ -593,69 +596,58 @@ __global__ void __launch_bounds__(1024) qrcp_pivot(double* __restrict__ Bc, doub
     __syncthreads();
   }
   const int64_t p = si[0];
-  if (p != j && p < r) {
-    for (int64_t i = tid; i < r; i += 1024) {
-      const double a = Bc[j * r + i];
-      Bc[j * r + i] = Bc[p * r + i];
-      Bc[p * r + i] = a;
-    }
-    if (tid == 0) {
-      const double t = nrm[j];
-      nrm[j] = nrm[p];
-      nrm[p] = t;
-      const int32_t q = perm[j];
-      perm[j] = perm[p];
-      perm[p] = q;
-    }
+  if (blockIdx.x == 0 && tid == 0) {
+    stamp[p] = (int32_t)j;
+    perm[j] = (int32_t)p;
   }
-  __syncthreads();
-  double s = 0.0;
-  for (int64_t i = j + 1 + tid; i < r; i += 1024) {
-    const double x = Bc[j * r + i];
-    s = fma(x, x, s);
-  }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) sred[wave] = s;
+  // Householder vector of column p over rows j..r-1: v_j = 1, v_i = x_i / (alpha - beta)
+  const double* xp = Bc + p * r;
+  double s2 = 0.0;
+  for (int64_t i = j + 1 + tid; i < r; i += QCP_T) s2 = fma(xp[i], xp[i], s2);
+  for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+  if (lane == 0) sred[wave] = s2;
   __syncthreads();
   double sigma2 = 0.0;
-  for (int w = 0; w < 16; ++w) sigma2 += sred[w];
-  const double alpha = Bc[j * r + j];
-  if (sigma2 == 0.0) {
-    if (tid == 0) tauh[j] = 0.0;
-    return;
+  for (int w = 0; w < QCP_T / 64; ++w) sigma2 += sred[w];
+  const double alpha = xp[j];
+  double th = 0.0, scale = 0.0;
+  if (sigma2 != 0.0) {
+    const double beta = -copysign(sqrt(fma(alpha, alpha, sigma2)), alpha);
+    th = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
   }
-  const double beta = -copysign(sqrt(fma(alpha, alpha, sigma2)), alpha);
-  const double scale = 1.0 / (alpha - beta);
-  for (int64_t i = j + 1 + tid; i < r; i += 1024) Bc[j * r + i] *= scale;
-  if (tid == 0) {
-    Bc[j * r + j] = beta;
-    tauh[j] = (beta - alpha) / beta;
+  for (int64_t i = j + 1 + tid; i < r; i += QCP_T) v[i - j] = xp[i] * scale;
+  if (tid == 0) v[0] = 1.0;
+  __syncthreads();
+  // this workgroup's columns, one wave per column
+  for (int q = wave; q < QCP_COLS; q += QCP_T / 64) {
+    const int64_t c = (int64_t)blockIdx.x * QCP_COLS + q;
+    if (c >= r || c == p || stamp[c] < j) continue;
+    double* x = Bc + c * r;
+    if (th != 0.0) {
+      double s = 0.0;
+      for (int64_t i = j + lane; i < r; i += 64) s = fma(v[i - j], x[i], s);
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      const double tw = th * s;
+      for (int64_t i = j + lane; i < r; i += 64) x[i] = fma(-tw, v[i - j], x[i]);
+    }
+    double n2 = 0.0;
+    for (int64_t i = j + 1 + lane; i < r; i += 64) n2 = fma(x[i], x[i], n2);
+    for (int off = 32; off > 0; off >>= 1) n2 += __shfl_xor(n2, off, 64);
+    if (lane == 0) nrm_out[c] = sqrt(n2);
   }
 }
 
-// Step j: trailing columns c > j (one wave each) <- (I - tau_h v v^T) column,
-// then nrm[c] = the norm of rows j+1.. (the next step's candidates).
-__global__ void __launch_bounds__(256) qrcp_update(double* __restrict__ Bc, double* __restrict__ nrm,
-                                                   const double* __restrict__ tauh, int64_t r,
-                                                   int64_t j) {
-  const int lane = threadIdx.x & 63;
-  const int64_t c = j + 1 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= r) return;
-  const double th = tauh[j];
-  double* x = Bc + c * r;
-  const double* v = Bc + j * r;
-  if (th != 0.0) {
-    double s = 0.0;
-    for (int64_t i = j + 1 + lane; i < r; i += 64) s = fma(v[i], x[i], s);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    const double tw = th * (x[j] + s);
-    for (int64_t i = j + 1 + lane; i < r; i += 64) x[i] = fma(-tw, v[i], x[i]);
-    if (lane == 0) x[j] -= tw;
-  }
-  double s2 = 0.0;
-  for (int64_t i = j + 1 + lane; i < r; i += 64) s2 = fma(x[i], x[i], s2);
-  for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
-  if (lane == 0) nrm[c] = sqrt(s2);
+// The last column is the one never pivoted.
+__global__ void __launch_bounds__(256) qrcp_last(const int32_t* __restrict__ stamp,
+                                                 int32_t* __restrict__ perm, int64_t r) {
+  for (int64_t c = threadIdx.x; c < r; c += 256)
+    if (stamp[c] >= r - 1) perm[r - 1] = (int32_t)c;
+}
+
+__global__ void __launch_bounds__(256) qrcp_stamp_init(int32_t* stamp, int64_t r) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < r) stamp[e] = (int32_t)r;
 }
 
 // Z[i*r + c] = R[i*ldr + perm[c]] (R with its columns permuted).
@@ -1057,7 +1049,7 @@ SvdWs svd_ws(int64_t r) {
 }
 
 struct RrqrWs {
-  size_t b, nrm, tauh, perm, z, qr, z2, q3, qrws, total;
+  size_t b, nrm, nrm2, stamp, perm, z, qr, z2, q3, qrws, total;
 };
 RrqrWs rrqr_ws(int64_t r) {
   RrqrWs w{};
@@ -1069,7 +1061,8 @@ RrqrWs rrqr_ws(int64_t r) {
   };
   w.b = take((size_t)r * r * 8);
   w.nrm = take((size_t)r * 8);
-  w.tauh = take((size_t)r * 8);
+  w.nrm2 = take((size_t)r * 8);
+  w.stamp = take((size_t)r * 4);
   w.perm = take((size_t)r * 4);
   w.z = take((size_t)r * r * 8);
   w.qr = take((size_t)r * r * 8);
@@ -1139,23 +1132,29 @@ gn_status launch_rrqr_core(int64_t r, int64_t rl, const double* R, int64_t ldr, 
   char* base = (char*)ws;
   double* Bc = (double*)(base + L.b);
   double* nrm = (double*)(base + L.nrm);
-  double* tauh = (double*)(base + L.tauh);
   int32_t* perm = (int32_t*)(base + L.perm);
   double* Z = (double*)(base + L.z);
   double* Qr = (double*)(base + L.qr);
   double* Z2 = (double*)(base + L.z2);
   double* Q3 = (double*)(base + L.q3);
   double* qws = (double*)(base + L.qrws);
+  double* nrm2 = (double*)(base + L.nrm2);
+  int32_t* stamp = (int32_t*)(base + L.stamp);
   qrcp_init<<<dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, s>>>(R, ldr, r, Bc, perm);
+  GN_LAUNCH_CHECK();
+  qrcp_stamp_init<<<dim3((unsigned)cdiv(r, 256)), dim3(256), 0, s>>>(stamp, r);
   GN_LAUNCH_CHECK();
   vec_norms<<<dim3((unsigned)cdiv(r, 4)), dim3(256), 0, s>>>(Bc, r, nrm);
   GN_LAUNCH_CHECK();
   for (int64_t j = 0; j + 1 < r; ++j) {
-    qrcp_pivot<<<dim3(1), dim3(1024), 0, s>>>(Bc, nrm, perm, tauh, r, j);
-    GN_LAUNCH_CHECK();
-    qrcp_update<<<dim3((unsigned)cdiv(r - j - 1, 4)), dim3(256), 0, s>>>(Bc, nrm, tauh, r, j);
+    const double* nin = (j & 1) ? nrm2 : nrm;
+    double* nout = (j & 1) ? nrm : nrm2;
+    qrcp_step<<<dim3((unsigned)cdiv(r, QCP_COLS)), dim3(QCP_T), 0, s>>>(Bc, nin, nout, stamp, perm,
+                                                                        r, j);
     GN_LAUNCH_CHECK();
   }
+  qrcp_last<<<dim3(1), dim3(256), 0, s>>>(stamp, perm, r);
+  GN_LAUNCH_CHECK();
   // R P = Q_R R_p by the blocked QR; C P = (Q1 Q_R) R_p
   gather_cols<<<dim3((unsigned)cdiv(r * r, 256)), dim3(256), 0, s>>>(R, ldr, perm, r, Z);
   GN_LAUNCH_CHECK();
