@@ -26,6 +26,7 @@
 #include "gn_internal.h"
 #include "wave_ops.h"
 
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -584,20 +585,223 @@ constexpr int QR_OB = 64;
 // Vb ((M - J0) x w, ld QR_OB): the block's unit lower trapezoidal reflectors.
 __global__ void __launch_bounds__(256) qr_build_v(const double* __restrict__ C, int64_t ldc,
                                                   int64_t M, int64_t J0, int w,
-                                                  double* __restrict__ Vb, const int32_t* gate,
-                                                  int64_t gate_n) {
+                                                  double* __restrict__ Vb, double* __restrict__ Vt,
+                                                  const int32_t* gate, int64_t gate_n) {
   if (gate && *gate >= gate_n) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t Mp = M - J0;
   if (e >= Mp * QR_OB) return;
-  const int64_t i = e / QR_OB;
-  const int c = (int)(e - i * QR_OB);
-  double v = 0.0;
-  if (c < w) v = (i < c) ? 0.0 : (i == c ? 1.0 : C[(J0 + i) * ldc + J0 + c]);
-  Vb[e] = v;
+  {  // Vb: Mp x QR_OB, row-major
+    const int64_t i = e / QR_OB;
+    const int c = (int)(e - i * QR_OB);
+    double v = 0.0;
+    if (c < w) v = (i < c) ? 0.0 : (i == c ? 1.0 : C[(J0 + i) * ldc + J0 + c]);
+    Vb[e] = v;
+  }
+  {  // Vt: QR_OB x Mp, row-major (V by columns)
+    const int c = (int)(e / Mp);
+    const int64_t i = e - (int64_t)c * Mp;
+    double v = 0.0;
+    if (c < w) v = (i < c) ? 0.0 : (i == c ? 1.0 : C[(J0 + i) * ldc + J0 + c]);
+    Vt[e] = v;
+  }
 }
 
 // The panels of one outer block (at most QR_OB / 8 of them).
+// Outer-block reflector H = I - V T' V^T (V: Mp x QR_OB unit-lower, zero past the
+// block width; T' = T^T when trans, else T) applied to an Mp x ncols target D,
+// D <- D - V (T' (V^T D)), in three launches with FP64 MFMA
+// (v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// register v of its result holds row l / 16 + 4 v, column l % 16):
+//   qr_oupd_w     partial W_c = V_c^T D_c per QO_CH-row chunk c and QO_CG-column
+//                 strip, the four waves each owning a 32 x 32 quarter;
+//   qr_oupd_w2    per QO_CW columns, W = sum of the partials in chunk order (all
+//                 loads issued first), W2 = T' W;
+//   qr_oupd_apply per QO_CA-row chunk and strip, D_c -= V_c W2 with W2 staged in
+//                 LDS, V read by columns (Vt) so that the operand loads are
+//                 contiguous, and V and D loaded before the products.
+typedef double qr_f64x4 __attribute__((ext_vector_type(4)));
+constexpr int QO_CH = 128;  // rows per partial (at most QR_MAXROWS / QO_CH = 32 partials)
+constexpr int QO_CG = 64;   // target columns per strip
+constexpr int QO_CW = 16;   // target columns per W2 workgroup
+constexpr int QO_CA = 128;  // rows per apply tile
+
+__device__ __forceinline__ qr_f64x4 qr_mfma(double a, double b, qr_f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__global__ void __launch_bounds__(256) qr_oupd_w(const double* __restrict__ Vb, int64_t Mp,
+                                                 const double* __restrict__ D, int64_t ldd,
+                                                 int64_t ncols, double* __restrict__ Wp,
+                                                 const int32_t* gate, int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * QO_CH;
+  const int64_t c0 = (int64_t)blockIdx.y * QO_CG;
+  qr_f64x4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = qr_f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int kb = 0; kb < QO_CH; kb += 16) {
+    double a[4][2], b[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = r0 + kb + 4 * u + lk;
+      const bool rin = row < Mp;
+#pragma unroll
+      for (int x = 0; x < 2; ++x) a[u][x] = rin ? Vb[row * QR_OB + wm * 32 + x * 16 + li] : 0.0;
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int64_t col = c0 + wn * 32 + y * 16 + li;
+        b[u][y] = (rin && col < ncols) ? D[row * ldd + col] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = qr_mfma(a[u][x], b[u][y], acc[x][y]);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = wm * 32 + x * 16 + lk + 4 * v;
+        const int64_t col = c0 + wn * 32 + y * 16 + li;
+        if (col < ncols) Wp[((int64_t)blockIdx.x * QR_OB + a) * ncols + col] = acc[x][y][v];
+      }
+}
+
+__global__ void __launch_bounds__(256) qr_oupd_w2(const double* __restrict__ Wp, int nch,
+                                                  int64_t ncols, const double* __restrict__ T,
+                                                  int trans, double* __restrict__ W2,
+                                                  const int32_t* gate, int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  constexpr int kMaxCh = QR_MAXROWS / QO_CH;
+  __shared__ double sT[QR_OB][QR_OB + 1];
+  __shared__ double sW[QR_OB][QO_CW + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t c0 = (int64_t)blockIdx.x * QO_CW;
+  // W (QR_OB x QO_CW) = sum of the partials in chunk order, every load issued first
+#pragma unroll
+  for (int q = 0; q < QR_OB * QO_CW / 256; ++q) {
+    const int e = tid + 256 * q;
+    const int a = e / QO_CW, b = e % QO_CW;
+    const int64_t col = c0 + b;
+    double v[kMaxCh];
+#pragma unroll
+    for (int c = 0; c < kMaxCh; ++c)
+      v[c] = (c < nch && col < ncols) ? Wp[((int64_t)c * QR_OB + a) * ncols + col] : 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMaxCh; ++c) acc += v[c];
+    sW[a][b] = acc;
+  }
+  for (int e = tid; e < QR_OB * QR_OB; e += 256) {
+    const int a = e / QR_OB, l = e % QR_OB;
+    sT[a][l] = trans ? T[l * QR_OB + a] : T[a * QR_OB + l];
+  }
+  __syncthreads();
+  // wave w: rows 16 w .. 16 w + 15 of W2 = T' W
+  qr_f64x4 acc = qr_f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < QR_OB; k0 += 4)
+    acc = qr_mfma(sT[16 * wave + li][k0 + lk], sW[k0 + lk][li], acc);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = 16 * wave + lk + 4 * v;
+    const int64_t col = c0 + li;
+    if (col < ncols) W2[(int64_t)a * ncols + col] = acc[v];
+  }
+}
+
+__global__ void __launch_bounds__(256) qr_oupd_apply(const double* __restrict__ Vt, int64_t Mp,
+                                                     double* __restrict__ D, int64_t ldd,
+                                                     int64_t ncols, const double* __restrict__ W2,
+                                                     const int32_t* gate, int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  __shared__ double sW[QR_OB][QO_CG + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * QO_CA + wave * (QO_CA / 4);  // 32 rows per wave
+  const int64_t c0 = (int64_t)blockIdx.y * QO_CG;
+  for (int e = tid; e < QR_OB * QO_CG; e += 256) {
+    const int k = e / QO_CG, b = e % QO_CG;
+    const int64_t col = c0 + b;
+    sW[k][b] = (col < ncols) ? W2[(int64_t)k * ncols + col] : 0.0;
+  }
+  // this wave's V rows (all QR_OB columns) and its part of D, loaded before any use
+  double a[QR_OB / 4][2];
+#pragma unroll
+  for (int ks = 0; ks < QR_OB / 4; ++ks)
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const int64_t row = r0 + x * 16 + li;
+      a[ks][x] = (row < Mp) ? Vt[(int64_t)(4 * ks + lk) * Mp + row] : 0.0;
+    }
+  double d[2][4][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + x * 16 + lk + 4 * v;
+        const int64_t col = c0 + y * 16 + li;
+        d[x][y][v] = (row < Mp && col < ncols) ? D[row * ldd + col] : 0.0;
+      }
+  __syncthreads();
+  qr_f64x4 acc[2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = qr_f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < QR_OB / 4; ++ks) {
+    double b[4];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) b[y] = sW[4 * ks + lk][y * 16 + li];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = qr_mfma(a[ks][x], b[y], acc[x][y]);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + x * 16 + lk + 4 * v;
+        const int64_t col = c0 + y * 16 + li;
+        if (row < Mp && col < ncols) D[row * ldd + col] = d[x][y][v] - acc[x][y][v];
+      }
+}
+
+// G = V^T V from its chunk partials, summed in chunk order (one entry per thread,
+// every load issued first).
+__global__ void __launch_bounds__(256) qr_sum_g(const double* __restrict__ Gp, int nch,
+                                                double* __restrict__ G, const int32_t* gate,
+                                                int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  constexpr int kMaxCh = QR_MAXROWS / QO_CH;
+  const int e = blockIdx.x * 256 + threadIdx.x;  // < QR_OB * QR_OB
+  double v[kMaxCh];
+#pragma unroll
+  for (int c = 0; c < kMaxCh; ++c) v[c] = (c < nch) ? Gp[(int64_t)c * QR_OB * QR_OB + e] : 0.0;
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kMaxCh; ++c) acc += v[c];
+  G[e] = acc;
+}
+
 struct OuterPanels {
   int count;
   int off[QR_OB / 8];    // first column within the block
@@ -701,8 +905,11 @@ gn_status run_update(const double* Cp, int64_t ldc, int64_t M, int64_t j0, int n
 static size_t qr_t_bytes(int64_t N) {
   return align_up((size_t)(cdiv(N, 8) + 1) * QR_NB * QR_NB * sizeof(double));
 }
+// Two sets of V (by rows and by columns), partial products and W2: the outer
+// block being factored on the caller's stream and the trailing update of the
+// previous block on the side stream use one set each.
 struct QrWs {
-  size_t tin, vb, g, w, w2, tout, split, split_bytes, total;
+  size_t tin, vb[2], vt[2], w2[2], part[2], g, tout, total;
 };
 static QrWs qr_ws_layout(int64_t M, int64_t N) {
   QrWs q{};
@@ -712,17 +919,46 @@ static QrWs qr_ws_layout(int64_t M, int64_t N) {
     off += align_up(bytes);
     return o;
   };
+  const int64_t nw = N > QR_OB ? N : QR_OB;  // widest target (the trailing columns, or V itself)
   q.tin = take(qr_t_bytes(N));
-  q.vb = take((size_t)M * QR_OB * sizeof(double));
+  for (int k = 0; k < 2; ++k) {
+    q.vb[k] = take((size_t)M * QR_OB * sizeof(double));
+    q.vt[k] = take((size_t)M * QR_OB * sizeof(double));
+    q.w2[k] = take((size_t)QR_OB * nw * sizeof(double));
+    // partial products V_c^T D_c, one per QO_CH-row chunk
+    q.part[k] = take((size_t)cdiv(M, QO_CH) * QR_OB * nw * sizeof(double));
+  }
   q.g = take((size_t)QR_OB * QR_OB * sizeof(double));
-  q.w = take((size_t)QR_OB * N * sizeof(double));
-  q.w2 = take((size_t)QR_OB * N * sizeof(double));
   q.tout = take((size_t)cdiv(N, QR_OB) * QR_OB * QR_OB * sizeof(double));
-  // K-split partials of V^T D (QR_OB x up to N, at most 32 slices)
-  q.split_bytes = (size_t)32 * QR_OB * N * sizeof(double);
-  q.split = take(q.split_bytes);
   q.total = off;
   return q;
+}
+
+// The side stream of the look-ahead and its events, one set per device, created
+// on first use and kept for the life of the process (default priority).  Calls
+// enqueue under one lock, so concurrent callers share the side stream in turn.
+struct QrSide {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, a[4] = {}, b[4] = {};
+  bool ready = false;
+};
+std::mutex g_qr_side_mu;
+QrSide g_qr_side[64];
+
+gn_status qr_side(QrSide*& out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return GN_ERR_HIP;
+  QrSide& q = g_qr_side[dev];
+  if (!q.ready) {
+    if (hipStreamCreateWithFlags(&q.s, hipStreamNonBlocking) != hipSuccess) return GN_ERR_HIP;
+    hipEvent_t* evs[10] = {&q.fork, &q.join, &q.a[0], &q.a[1], &q.a[2],
+                           &q.a[3], &q.b[0], &q.b[1], &q.b[2], &q.b[3]};
+    for (hipEvent_t* e : evs)
+      if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return GN_ERR_HIP;
+    q.ready = true;
+  }
+  out = &q;
+  return GN_OK;
 }
 
 size_t qr_ws_bytes(int64_t M, int64_t N) { return qr_ws_layout(M, N).total; }
@@ -734,62 +970,107 @@ size_t qr_ws_bytes(int64_t M, int64_t N) { return qr_ws_layout(M, N).total; }
 gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int64_t ldq, double* R,
                     int64_t ldr, double* ws, const int32_t* gate_k, hipStream_t s) {
   if (M < N || M > QR_MAXROWS || N < 1) return GN_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_qr_side_mu);
+  QrSide* side = nullptr;
+  GN_TRY(qr_side(side));
   const int64_t gate_n = N;
   const QrWs L = qr_ws_layout(M, N);
   char* base = (char*)ws;
   double* Tin = (double*)(base + L.tin);
-  double* Vb = (double*)(base + L.vb);
   double* G = (double*)(base + L.g);
-  double* W = (double*)(base + L.w);
-  double* W2 = (double*)(base + L.w2);
   double* Tout = (double*)(base + L.tout);
-  double* sp = (double*)(base + L.split);
+  double *Vb[2], *Vt[2], *W2[2], *part[2];
+  for (int k = 0; k < 2; ++k) {
+    Vb[k] = (double*)(base + L.vb[k]);
+    Vt[k] = (double*)(base + L.vt[k]);
+    W2[k] = (double*)(base + L.w2[k]);
+    part[k] = (double*)(base + L.part[k]);
+  }
+  // D <- (I - V T' V^T) D on stream st with V set vs and scratch set ps: the outer
+  // block's Mp rows, D with ncols columns
+  auto apply_block = [&](int64_t Mp, double* D, int64_t ldd, int64_t ncols, const double* Tb,
+                         int trans, int vs, int ps, hipStream_t st) -> gn_status {
+    if (ncols <= 0) return GN_OK;
+    const unsigned nch = (unsigned)cdiv(Mp, QO_CH), nst = (unsigned)cdiv(ncols, QO_CG);
+    qr_oupd_w<<<dim3(nch, nst), dim3(256), 0, st>>>(Vb[vs], Mp, D, ldd, ncols, part[ps], gate_k,
+                                                    gate_n);
+    GN_LAUNCH_CHECK();
+    qr_oupd_w2<<<dim3((unsigned)cdiv(ncols, QO_CW)), dim3(256), 0, st>>>(
+        part[ps], (int)nch, ncols, Tb, trans, W2[ps], gate_k, gate_n);
+    GN_LAUNCH_CHECK();
+    qr_oupd_apply<<<dim3((unsigned)cdiv(Mp, QO_CA), nst), dim3(256), 0, st>>>(
+        Vt[vs], Mp, D, ldd, ncols, W2[ps], gate_k, gate_n);
+    GN_LAUNCH_CHECK();
+    return GN_OK;
+  };
   const int64_t nob = cdiv(N, QR_OB);
   std::vector<OuterPanels> ops((size_t)nob);
-  int pi = 0;
-  // factor: outer blocks left to right
-  for (int64_t ob = 0; ob < nob; ++ob) {
-    const int64_t J0 = ob * QR_OB, J1 = (J0 + QR_OB < N) ? J0 + QR_OB : N;
-    const int w = (int)(J1 - J0);
-    OuterPanels& op = ops[(size_t)ob];
-    op.count = 0;
-    for (int64_t j0 = J0; j0 < J1;) {
-      const int nb = panel_shape(M - j0).nb;
-      const int nbw = (int)((J1 - j0 < nb) ? (J1 - j0) : nb);
-      double* Tp = Tin + (size_t)pi * QR_NB * QR_NB;
-      GN_TRY(run_panel(C, ldc, M, j0, nbw, Tp, gate_k, gate_n, s));
-      GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, j0 + nbw, J1 - j0 - nbw, Tp, 1, gate_k, gate_n,
-                        s));
-      op.off[op.count] = (int)(j0 - J0);
-      op.width[op.count] = nbw;
-      op.tidx[op.count] = pi;
-      ++op.count;
-      ++pi;
-      j0 += nbw;
+  // Factor with a look-ahead of one outer block: on the caller's stream, block
+  // ob's columns get the previous block's reflector, then its panels, V and
+  // merged T; the side stream then applies block ob's reflector to the columns
+  // past block ob + 1 while the caller's stream moves on.  Block ob + 1's update
+  // by block ob - 1's reflector (side stream) precedes block ob's (caller), and
+  // a V set is rebuilt only after the side stream's use of it has ended.
+  auto factor = [&]() -> gn_status {
+    int pi = 0;
+    for (int64_t ob = 0; ob < nob; ++ob) {
+      const int64_t J0 = ob * QR_OB, J1 = (J0 + QR_OB < N) ? J0 + QR_OB : N;
+      const int w = (int)(J1 - J0);
+      const int vs = (int)(ob & 1);
+      if (ob > 0) {
+        if (ob >= 2) {
+          if (hipStreamWaitEvent(s, side->b[(ob - 2) & 3], 0) != hipSuccess) return GN_ERR_HIP;
+        }
+        const int64_t P0 = J0 - QR_OB;
+        GN_TRY(apply_block(M - P0, C + P0 * ldc + J0, ldc, w, Tout + (size_t)(ob - 1) * QR_OB * QR_OB,
+                           1, vs ^ 1, 0, s));
+      }
+      OuterPanels& op = ops[(size_t)ob];
+      op.count = 0;
+      for (int64_t j0 = J0; j0 < J1;) {
+        const int nb = panel_shape(M - j0).nb;
+        const int nbw = (int)((J1 - j0 < nb) ? (J1 - j0) : nb);
+        double* Tp = Tin + (size_t)pi * QR_NB * QR_NB;
+        GN_TRY(run_panel(C, ldc, M, j0, nbw, Tp, gate_k, gate_n, s));
+        GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, j0 + nbw, J1 - j0 - nbw, Tp, 1, gate_k,
+                          gate_n, s));
+        op.off[op.count] = (int)(j0 - J0);
+        op.width[op.count] = nbw;
+        op.tidx[op.count] = pi;
+        ++op.count;
+        ++pi;
+        j0 += nbw;
+      }
+      const int64_t Mp = M - J0;
+      qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w,
+                                                                           Vb[vs], Vt[vs], gate_k,
+                                                                           gate_n);
+      GN_LAUNCH_CHECK();
+      const unsigned nchg = (unsigned)cdiv(Mp, QO_CH);  // G = V^T V
+      qr_oupd_w<<<dim3(nchg, 1), dim3(256), 0, s>>>(Vb[vs], Mp, Vb[vs], QR_OB, QR_OB, part[0],
+                                                    gate_k, gate_n);
+      GN_LAUNCH_CHECK();
+      qr_sum_g<<<dim3(QR_OB * QR_OB / 256), dim3(256), 0, s>>>(part[0], (int)nchg, G, gate_k,
+                                                               gate_n);
+      GN_LAUNCH_CHECK();
+      double* Tb = Tout + (size_t)ob * QR_OB * QR_OB;
+      qr_merge_t<<<dim3(1), dim3(256), 0, s>>>(G, Tin, op, w, Tb, gate_k, gate_n);
+      GN_LAUNCH_CHECK();
+      if (hipEventRecord(side->a[ob & 3], s) != hipSuccess) return GN_ERR_HIP;
+      if (hipStreamWaitEvent(side->s, side->a[ob & 3], 0) != hipSuccess) return GN_ERR_HIP;
+      const int64_t K1 = (J1 + QR_OB < N) ? J1 + QR_OB : N;  // past block ob + 1
+      GN_TRY(apply_block(Mp, C + J0 * ldc + K1, ldc, N - K1, Tb, 1, vs, 1, side->s));
+      if (hipEventRecord(side->b[ob & 3], side->s) != hipSuccess) return GN_ERR_HIP;
     }
-    const int64_t Mp = M - J0;
-    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w, Vb,
-                                                                         gate_k, gate_n);
-    GN_LAUNCH_CHECK();
-    const MatRef vt{Vb, GN_DT_F64, 1, QR_OB}, vv{Vb, GN_DT_F64, QR_OB, 1};
-    GN_TRY(launch_dgemm(w, w, Mp, 1.0, vt, vv, 0.0, G, QR_OB, 1, nullptr, false, s, gate_k, gate_n,
-                        true, sp, L.split_bytes));
-    double* Tb = Tout + (size_t)ob * QR_OB * QR_OB;
-    qr_merge_t<<<dim3(1), dim3(256), 0, s>>>(G, Tin, op, w, Tb, gate_k, gate_n);
-    GN_LAUNCH_CHECK();
-    const int64_t nt = N - J1;
-    if (nt > 0) {
-      // C2 <- (I - V T^T V^T) C2 = C2 - V (T^T (V^T C2))
-      const MatRef c2{C + J0 * ldc + J1, GN_DT_F64, ldc, 1};
-      GN_TRY(launch_dgemm(w, nt, Mp, 1.0, vt, c2, 0.0, W, nt, 1, nullptr, false, s, gate_k,
-                          gate_n, true, sp, L.split_bytes));
-      GN_TRY(launch_dgemm(w, nt, w, 1.0, MatRef{Tb, GN_DT_F64, 1, QR_OB},
-                          MatRef{W, GN_DT_F64, nt, 1}, 0.0, W2, nt, 1, nullptr, false, s, gate_k,
-                          gate_n, true));
-      GN_TRY(launch_dgemm(Mp, nt, w, -1.0, vv, MatRef{W2, GN_DT_F64, nt, 1}, 1.0,
-                          C + J0 * ldc + J1, ldc, 1, nullptr, false, s, gate_k, gate_n, true));
-    }
-  }
+    return GN_OK;
+  };
+  if (hipEventRecord(side->fork, s) != hipSuccess) return GN_ERR_HIP;
+  if (hipStreamWaitEvent(side->s, side->fork, 0) != hipSuccess) return GN_ERR_HIP;
+  const gn_status st = factor();
+  // join: the caller's stream continues only after the side stream's last update
+  if (hipEventRecord(side->join, side->s) != hipSuccess) return GN_ERR_HIP;
+  if (hipStreamWaitEvent(s, side->join, 0) != hipSuccess) return GN_ERR_HIP;
+  GN_TRY(st);
   // explicit Q: start from [I; 0] and apply the outer blocks right to left,
   // Q2 <- (I - V T V^T) Q2 on rows and columns J0..
   qr_init_q<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(Q, ldq, M, N, gate_k, gate_n);
@@ -798,19 +1079,11 @@ gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int
     const int64_t J0 = ob * QR_OB, J1 = (J0 + QR_OB < N) ? J0 + QR_OB : N;
     const int w = (int)(J1 - J0);
     const int64_t Mp = M - J0, nq = N - J0;
-    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w, Vb,
-                                                                         gate_k, gate_n);
+    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w, Vb[0],
+                                                                         Vt[0], gate_k, gate_n);
     GN_LAUNCH_CHECK();
-    const MatRef vt{Vb, GN_DT_F64, 1, QR_OB}, vv{Vb, GN_DT_F64, QR_OB, 1};
-    const double* Tb = Tout + (size_t)ob * QR_OB * QR_OB;
-    const MatRef q2{Q + J0 * ldq + J0, GN_DT_F64, ldq, 1};
-    GN_TRY(launch_dgemm(w, nq, Mp, 1.0, vt, q2, 0.0, W, nq, 1, nullptr, false, s, gate_k, gate_n,
-                        true, sp, L.split_bytes));
-    GN_TRY(launch_dgemm(w, nq, w, 1.0, MatRef{Tb, GN_DT_F64, QR_OB, 1},
-                        MatRef{W, GN_DT_F64, nq, 1}, 0.0, W2, nq, 1, nullptr, false, s, gate_k,
-                        gate_n, true));
-    GN_TRY(launch_dgemm(Mp, nq, w, -1.0, vv, MatRef{W2, GN_DT_F64, nq, 1}, 1.0,
-                        Q + J0 * ldq + J0, ldq, 1, nullptr, false, s, gate_k, gate_n, true));
+    GN_TRY(apply_block(Mp, Q + J0 * ldq + J0, ldq, nq, Tout + (size_t)ob * QR_OB * QR_OB, 0, 0, 0,
+                       s));
   }
   qr_signfix<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(C, ldc, Q, ldq, R, ldr, M, N,
                                                                    gate_k, gate_n);

@@ -551,91 +551,119 @@ __global__ void __launch_bounds__(256) qrcp_init(const double* __restrict__ R, i
 
 // One pivoting step in one launch.  Every workgroup finds the pivot p of step j
 // (the largest norm among columns not pivoted before step j, lowest index on
-// ties, NaN first), forms the Householder vector of column p (rows j..r-1) in
-// LDS, and applies it to its own columns (one wave per column), writing their
-// new trailing norms to nrm_out.  Column p itself is never written again (only
-// the permutation is needed), and the pivot record is stamped with the step, so
-// the launch has no write a concurrent workgroup reads.  Workgroup 0 records p.
+// ties, NaN first), stages column p (rows j..r-1) in LDS with its squared norm
+// below row j, and applies the reflector of column p to its own columns, one
+// wave per column, writing their new trailing norms to nrm_out.  A wave loads its
+// column (rows j..r-1, 64 per lane at most) into registers before the pivot is
+// known, so the update and the recomputed norm take one pass.  The reflector is
+// v = [1; x_p(j+1:) / (alpha - beta)], tau_h = (beta - alpha) / beta, and the
+// scale is applied on the fly.  Column p itself is never written again (only the
+// permutation is needed), and the pivot record is stamped with the step, so the
+// launch has no write a concurrent workgroup reads.  Workgroup 0 records p.
 constexpr int QCP_T = 256;
-constexpr int QCP_COLS = 16;  // columns per workgroup (four per wave)
+constexpr int QCP_COLS = QCP_T / 64;  // columns per workgroup, one per wave
 
+__device__ __forceinline__ void argmax_take(double& v, int& i, double v2, int i2) {
+  if (v2 > v || (v2 == v && i2 < i)) {
+    v = v2;
+    i = i2;
+  }
+}
+
+template <int RPL>  // rows per lane: r <= 64 RPL
 __global__ void __launch_bounds__(QCP_T) qrcp_step(double* __restrict__ Bc,
                                                    const double* __restrict__ nrm_in,
                                                    double* __restrict__ nrm_out,
                                                    int32_t* __restrict__ stamp,
                                                    int32_t* __restrict__ perm, int64_t r,
                                                    int64_t j) {
-  __shared__ double sv[QCP_T];
-  __shared__ int64_t si[QCP_T];
+  __shared__ double sv[QCP_T / 64];
+  __shared__ int si[QCP_T / 64];
   __shared__ double sred[QCP_T / 64];
-  __shared__ double v[4096];
+  __shared__ double xp[4096];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // this wave's column, rows j..r-1, loaded first
+  const int64_t c = (int64_t)blockIdx.x * QCP_COLS + wave;
+  const bool live = c < r && stamp[c] >= j;
+  double x[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int64_t i = lane + 64 * q;
+    x[q] = (live && i >= j && i < r) ? Bc[c * r + i] : 0.0;
+  }
+  // pivot: per-thread scan, wave argmax by shuffles, then the waves' results
   double best = -1.0;
-  int64_t bi = r;
-  for (int64_t c = tid; c < r; c += QCP_T) {
-    if (stamp[c] < j) continue;  // pivoted at an earlier step
-    double x = nrm_in[c];
-    if (isnan(x)) x = INFINITY;
-    if (x > best || (x == best && c < bi)) {
-      best = x;
-      bi = c;
-    }
+  int bi = (int)r;
+  for (int64_t cc = tid; cc < r; cc += QCP_T) {
+    if (stamp[cc] < j) continue;  // pivoted at an earlier step
+    double val = nrm_in[cc];
+    if (isnan(val)) val = INFINITY;
+    argmax_take(best, bi, val, (int)cc);
   }
-  sv[tid] = best;
-  si[tid] = bi;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double v2 = __shfl_xor(best, off, 64);
+    const int i2 = __shfl_xor(bi, off, 64);
+    argmax_take(best, bi, v2, i2);
+  }
+  if (lane == 0) {
+    sv[wave] = best;
+    si[wave] = bi;
+  }
   __syncthreads();
-  for (int w = QCP_T / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-      const double v2 = sv[tid + w];
-      const int64_t i2 = si[tid + w];
-      if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) {
-        sv[tid] = v2;
-        si[tid] = i2;
-      }
-    }
-    __syncthreads();
-  }
-  const int64_t p = si[0];
+  best = sv[0];
+  bi = si[0];
+#pragma unroll
+  for (int w = 1; w < QCP_T / 64; ++w) argmax_take(best, bi, sv[w], si[w]);
+  const int64_t p = bi;
   if (blockIdx.x == 0 && tid == 0) {
     stamp[p] = (int32_t)j;
     perm[j] = (int32_t)p;
   }
-  // Householder vector of column p over rows j..r-1: v_j = 1, v_i = x_i / (alpha - beta)
-  const double* xp = Bc + p * r;
+  // column p, rows j..r-1, into LDS; its squared norm below row j
   double s2 = 0.0;
-  for (int64_t i = j + 1 + tid; i < r; i += QCP_T) s2 = fma(xp[i], xp[i], s2);
-  for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+  for (int64_t i = j + tid; i < r; i += QCP_T) {
+    const double e = Bc[p * r + i];
+    xp[i - j] = e;
+    if (i > j) s2 = fma(e, e, s2);
+  }
+  s2 = wave_sum_dpp(s2);
   if (lane == 0) sred[wave] = s2;
   __syncthreads();
   double sigma2 = 0.0;
+#pragma unroll
   for (int w = 0; w < QCP_T / 64; ++w) sigma2 += sred[w];
-  const double alpha = xp[j];
+  const double alpha = xp[0];
   double th = 0.0, scale = 0.0;
   if (sigma2 != 0.0) {
     const double beta = -copysign(sqrt(fma(alpha, alpha, sigma2)), alpha);
     th = (beta - alpha) / beta;
     scale = 1.0 / (alpha - beta);
   }
-  for (int64_t i = j + 1 + tid; i < r; i += QCP_T) v[i - j] = xp[i] * scale;
-  if (tid == 0) v[0] = 1.0;
-  __syncthreads();
-  // this workgroup's columns, one wave per column
-  for (int q = wave; q < QCP_COLS; q += QCP_T / 64) {
-    const int64_t c = (int64_t)blockIdx.x * QCP_COLS + q;
-    if (c >= r || c == p || stamp[c] < j) continue;
-    double* x = Bc + c * r;
-    if (th != 0.0) {
-      double s = 0.0;
-      for (int64_t i = j + lane; i < r; i += 64) s = fma(v[i - j], x[i], s);
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-      const double tw = th * s;
-      for (int64_t i = j + lane; i < r; i += 64) x[i] = fma(-tw, v[i - j], x[i]);
-    }
-    double n2 = 0.0;
-    for (int64_t i = j + 1 + lane; i < r; i += 64) n2 = fma(x[i], x[i], n2);
-    for (int off = 32; off > 0; off >>= 1) n2 += __shfl_xor(n2, off, 64);
-    if (lane == 0) nrm_out[c] = sqrt(n2);
+  if (!live || c == p) return;  // wave-uniform: no barrier follows
+  // v^T x = x_j + scale * sum_{i > j} x_p[i] x[i]
+  double dot = 0.0, xj = 0.0;
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int64_t i = lane + 64 * q;
+    if (i > j && i < r) dot = fma(xp[i - j], x[q], dot);
+    if (i == j) xj = x[q];
   }
+  dot = wave_sum_dpp(dot);
+  xj = wave_sum_dpp(xj);  // the one lane holding row j
+  const double tws = th * (xj + scale * dot) * scale;  // tau_h (v^T x) times the scale of v
+  double n2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int64_t i = lane + 64 * q;
+    if (i > j && i < r) {
+      const double e = fma(-tws, xp[i - j], x[q]);
+      Bc[c * r + i] = e;
+      n2 = fma(e, e, n2);
+    }
+  }
+  n2 = wave_sum_dpp(n2);
+  if (lane == 0) nrm_out[c] = sqrt(n2);
 }
 
 // The last column is the one never pivoted.
@@ -1128,6 +1156,7 @@ gn_status launch_svd_core(int64_t r, int64_t rl, const double* R, int64_t ldr, c
 gn_status launch_rrqr_core(int64_t r, int64_t rl, const double* R, int64_t ldr, const double* Q1,
                            double tau, int32_t* k, int32_t* status, double* Q1_out, double* Rp,
                            double* Q2, double* R2, void* ws, hipStream_t s) {
+  if (r > 4096) return GN_ERR_UNSUPPORTED;  // a column per wave in registers, column p in LDS
   const RrqrWs L = rrqr_ws(r);
   char* base = (char*)ws;
   double* Bc = (double*)(base + L.b);
@@ -1149,8 +1178,13 @@ gn_status launch_rrqr_core(int64_t r, int64_t rl, const double* R, int64_t ldr, 
   for (int64_t j = 0; j + 1 < r; ++j) {
     const double* nin = (j & 1) ? nrm2 : nrm;
     double* nout = (j & 1) ? nrm : nrm2;
-    qrcp_step<<<dim3((unsigned)cdiv(r, QCP_COLS)), dim3(QCP_T), 0, s>>>(Bc, nin, nout, stamp, perm,
-                                                                        r, j);
+    const dim3 g((unsigned)cdiv(r, QCP_COLS)), b(QCP_T);
+    if (r <= 1024)
+      qrcp_step<16><<<g, b, 0, s>>>(Bc, nin, nout, stamp, perm, r, j);
+    else if (r <= 2048)
+      qrcp_step<32><<<g, b, 0, s>>>(Bc, nin, nout, stamp, perm, r, j);
+    else
+      qrcp_step<64><<<g, b, 0, s>>>(Bc, nin, nout, stamp, perm, r, j);
     GN_LAUNCH_CHECK();
   }
   qrcp_last<<<dim3(1), dim3(256), 0, s>>>(stamp, perm, r);
