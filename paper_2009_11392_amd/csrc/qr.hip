@@ -26,7 +26,6 @@
 #include "gn_internal.h"
 #include "wave_ops.h"
 
-#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -579,10 +578,11 @@ __global__ void __launch_bounds__(256) build_z_b(const TruncJob* __restrict__ jo
 // Panels are grouped into outer blocks of QR_OB columns: inside a block the
 // panel updates touch only the block's columns; the block's reflectors are then
 // applied to the trailing columns (and, walking back, to Q) as one block
-// reflector I - V T V^T by three FP64 MFMA products.
+// reflector I - V T V^T by the FP64 MFMA kernels below.
 constexpr int QR_OB = 64;
 
-// Vb ((M - J0) x w, ld QR_OB): the block's unit lower trapezoidal reflectors.
+// Vb ((M - J0) x QR_OB, row-major) and Vt (its transpose, ld M - J0): the block's
+// unit lower trapezoidal reflectors, zero past the block width w.
 __global__ void __launch_bounds__(256) qr_build_v(const double* __restrict__ C, int64_t ldc,
                                                   int64_t M, int64_t J0, int w,
                                                   double* __restrict__ Vb, double* __restrict__ Vt,
@@ -905,11 +905,8 @@ gn_status run_update(const double* Cp, int64_t ldc, int64_t M, int64_t j0, int n
 static size_t qr_t_bytes(int64_t N) {
   return align_up((size_t)(cdiv(N, 8) + 1) * QR_NB * QR_NB * sizeof(double));
 }
-// Two sets of V (by rows and by columns), partial products and W2: the outer
-// block being factored on the caller's stream and the trailing update of the
-// previous block on the side stream use one set each.
 struct QrWs {
-  size_t tin, vb[2], vt[2], w2[2], part[2], g, tout, total;
+  size_t tin, vb, vt, w2, part, g, tout, total;
 };
 static QrWs qr_ws_layout(int64_t M, int64_t N) {
   QrWs q{};
@@ -921,44 +918,15 @@ static QrWs qr_ws_layout(int64_t M, int64_t N) {
   };
   const int64_t nw = N > QR_OB ? N : QR_OB;  // widest target (the trailing columns, or V itself)
   q.tin = take(qr_t_bytes(N));
-  for (int k = 0; k < 2; ++k) {
-    q.vb[k] = take((size_t)M * QR_OB * sizeof(double));
-    q.vt[k] = take((size_t)M * QR_OB * sizeof(double));
-    q.w2[k] = take((size_t)QR_OB * nw * sizeof(double));
-    // partial products V_c^T D_c, one per QO_CH-row chunk
-    q.part[k] = take((size_t)cdiv(M, QO_CH) * QR_OB * nw * sizeof(double));
-  }
+  q.vb = take((size_t)M * QR_OB * sizeof(double));
+  q.vt = take((size_t)M * QR_OB * sizeof(double));
+  q.w2 = take((size_t)QR_OB * nw * sizeof(double));
+  // partial products V_c^T D_c, one per QO_CH-row chunk
+  q.part = take((size_t)cdiv(M, QO_CH) * QR_OB * nw * sizeof(double));
   q.g = take((size_t)QR_OB * QR_OB * sizeof(double));
   q.tout = take((size_t)cdiv(N, QR_OB) * QR_OB * QR_OB * sizeof(double));
   q.total = off;
   return q;
-}
-
-// The side stream of the look-ahead and its events, one set per device, created
-// on first use and kept for the life of the process (default priority).  Calls
-// enqueue under one lock, so concurrent callers share the side stream in turn.
-struct QrSide {
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr, a[4] = {}, b[4] = {};
-  bool ready = false;
-};
-std::mutex g_qr_side_mu;
-QrSide g_qr_side[64];
-
-gn_status qr_side(QrSide*& out) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return GN_ERR_HIP;
-  QrSide& q = g_qr_side[dev];
-  if (!q.ready) {
-    if (hipStreamCreateWithFlags(&q.s, hipStreamNonBlocking) != hipSuccess) return GN_ERR_HIP;
-    hipEvent_t* evs[10] = {&q.fork, &q.join, &q.a[0], &q.a[1], &q.a[2],
-                           &q.a[3], &q.b[0], &q.b[1], &q.b[2], &q.b[3]};
-    for (hipEvent_t* e : evs)
-      if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return GN_ERR_HIP;
-    q.ready = true;
-  }
-  out = &q;
-  return GN_OK;
 }
 
 size_t qr_ws_bytes(int64_t M, int64_t N) { return qr_ws_layout(M, N).total; }
@@ -970,107 +938,69 @@ size_t qr_ws_bytes(int64_t M, int64_t N) { return qr_ws_layout(M, N).total; }
 gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int64_t ldq, double* R,
                     int64_t ldr, double* ws, const int32_t* gate_k, hipStream_t s) {
   if (M < N || M > QR_MAXROWS || N < 1) return GN_ERR_UNSUPPORTED;
-  std::lock_guard<std::mutex> lock(g_qr_side_mu);
-  QrSide* side = nullptr;
-  GN_TRY(qr_side(side));
   const int64_t gate_n = N;
   const QrWs L = qr_ws_layout(M, N);
   char* base = (char*)ws;
   double* Tin = (double*)(base + L.tin);
+  double* Vb = (double*)(base + L.vb);
+  double* Vt = (double*)(base + L.vt);
+  double* W2 = (double*)(base + L.w2);
+  double* part = (double*)(base + L.part);
   double* G = (double*)(base + L.g);
   double* Tout = (double*)(base + L.tout);
-  double *Vb[2], *Vt[2], *W2[2], *part[2];
-  for (int k = 0; k < 2; ++k) {
-    Vb[k] = (double*)(base + L.vb[k]);
-    Vt[k] = (double*)(base + L.vt[k]);
-    W2[k] = (double*)(base + L.w2[k]);
-    part[k] = (double*)(base + L.part[k]);
-  }
-  // D <- (I - V T' V^T) D on stream st with V set vs and scratch set ps: the outer
-  // block's Mp rows, D with ncols columns
+  // D <- (I - V T' V^T) D for the outer block at J0 (Mp rows), D with ncols columns
   auto apply_block = [&](int64_t Mp, double* D, int64_t ldd, int64_t ncols, const double* Tb,
-                         int trans, int vs, int ps, hipStream_t st) -> gn_status {
+                         int trans) -> gn_status {
     if (ncols <= 0) return GN_OK;
     const unsigned nch = (unsigned)cdiv(Mp, QO_CH), nst = (unsigned)cdiv(ncols, QO_CG);
-    qr_oupd_w<<<dim3(nch, nst), dim3(256), 0, st>>>(Vb[vs], Mp, D, ldd, ncols, part[ps], gate_k,
-                                                    gate_n);
+    qr_oupd_w<<<dim3(nch, nst), dim3(256), 0, s>>>(Vb, Mp, D, ldd, ncols, part, gate_k, gate_n);
     GN_LAUNCH_CHECK();
-    qr_oupd_w2<<<dim3((unsigned)cdiv(ncols, QO_CW)), dim3(256), 0, st>>>(
-        part[ps], (int)nch, ncols, Tb, trans, W2[ps], gate_k, gate_n);
+    qr_oupd_w2<<<dim3((unsigned)cdiv(ncols, QO_CW)), dim3(256), 0, s>>>(part, (int)nch, ncols, Tb,
+                                                                         trans, W2, gate_k, gate_n);
     GN_LAUNCH_CHECK();
-    qr_oupd_apply<<<dim3((unsigned)cdiv(Mp, QO_CA), nst), dim3(256), 0, st>>>(
-        Vt[vs], Mp, D, ldd, ncols, W2[ps], gate_k, gate_n);
+    qr_oupd_apply<<<dim3((unsigned)cdiv(Mp, QO_CA), nst), dim3(256), 0, s>>>(Vt, Mp, D, ldd, ncols,
+                                                                            W2, gate_k, gate_n);
     GN_LAUNCH_CHECK();
     return GN_OK;
   };
   const int64_t nob = cdiv(N, QR_OB);
   std::vector<OuterPanels> ops((size_t)nob);
-  // Factor with a look-ahead of one outer block: on the caller's stream, block
-  // ob's columns get the previous block's reflector, then its panels, V and
-  // merged T; the side stream then applies block ob's reflector to the columns
-  // past block ob + 1 while the caller's stream moves on.  Block ob + 1's update
-  // by block ob - 1's reflector (side stream) precedes block ob's (caller), and
-  // a V set is rebuilt only after the side stream's use of it has ended.
-  auto factor = [&]() -> gn_status {
-    int pi = 0;
-    for (int64_t ob = 0; ob < nob; ++ob) {
-      const int64_t J0 = ob * QR_OB, J1 = (J0 + QR_OB < N) ? J0 + QR_OB : N;
-      const int w = (int)(J1 - J0);
-      const int vs = (int)(ob & 1);
-      if (ob > 0) {
-        if (ob >= 2) {
-          if (hipStreamWaitEvent(s, side->b[(ob - 2) & 3], 0) != hipSuccess) return GN_ERR_HIP;
-        }
-        const int64_t P0 = J0 - QR_OB;
-        GN_TRY(apply_block(M - P0, C + P0 * ldc + J0, ldc, w, Tout + (size_t)(ob - 1) * QR_OB * QR_OB,
-                           1, vs ^ 1, 0, s));
-      }
-      OuterPanels& op = ops[(size_t)ob];
-      op.count = 0;
-      for (int64_t j0 = J0; j0 < J1;) {
-        const int nb = panel_shape(M - j0).nb;
-        const int nbw = (int)((J1 - j0 < nb) ? (J1 - j0) : nb);
-        double* Tp = Tin + (size_t)pi * QR_NB * QR_NB;
-        GN_TRY(run_panel(C, ldc, M, j0, nbw, Tp, gate_k, gate_n, s));
-        GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, j0 + nbw, J1 - j0 - nbw, Tp, 1, gate_k,
-                          gate_n, s));
-        op.off[op.count] = (int)(j0 - J0);
-        op.width[op.count] = nbw;
-        op.tidx[op.count] = pi;
-        ++op.count;
-        ++pi;
-        j0 += nbw;
-      }
-      const int64_t Mp = M - J0;
-      qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w,
-                                                                           Vb[vs], Vt[vs], gate_k,
-                                                                           gate_n);
-      GN_LAUNCH_CHECK();
-      const unsigned nchg = (unsigned)cdiv(Mp, QO_CH);  // G = V^T V
-      qr_oupd_w<<<dim3(nchg, 1), dim3(256), 0, s>>>(Vb[vs], Mp, Vb[vs], QR_OB, QR_OB, part[0],
-                                                    gate_k, gate_n);
-      GN_LAUNCH_CHECK();
-      qr_sum_g<<<dim3(QR_OB * QR_OB / 256), dim3(256), 0, s>>>(part[0], (int)nchg, G, gate_k,
-                                                               gate_n);
-      GN_LAUNCH_CHECK();
-      double* Tb = Tout + (size_t)ob * QR_OB * QR_OB;
-      qr_merge_t<<<dim3(1), dim3(256), 0, s>>>(G, Tin, op, w, Tb, gate_k, gate_n);
-      GN_LAUNCH_CHECK();
-      if (hipEventRecord(side->a[ob & 3], s) != hipSuccess) return GN_ERR_HIP;
-      if (hipStreamWaitEvent(side->s, side->a[ob & 3], 0) != hipSuccess) return GN_ERR_HIP;
-      const int64_t K1 = (J1 + QR_OB < N) ? J1 + QR_OB : N;  // past block ob + 1
-      GN_TRY(apply_block(Mp, C + J0 * ldc + K1, ldc, N - K1, Tb, 1, vs, 1, side->s));
-      if (hipEventRecord(side->b[ob & 3], side->s) != hipSuccess) return GN_ERR_HIP;
+  int pi = 0;
+  // factor: outer blocks left to right
+  for (int64_t ob = 0; ob < nob; ++ob) {
+    const int64_t J0 = ob * QR_OB, J1 = (J0 + QR_OB < N) ? J0 + QR_OB : N;
+    const int w = (int)(J1 - J0);
+    OuterPanels& op = ops[(size_t)ob];
+    op.count = 0;
+    for (int64_t j0 = J0; j0 < J1;) {
+      const int nb = panel_shape(M - j0).nb;
+      const int nbw = (int)((J1 - j0 < nb) ? (J1 - j0) : nb);
+      double* Tp = Tin + (size_t)pi * QR_NB * QR_NB;
+      GN_TRY(run_panel(C, ldc, M, j0, nbw, Tp, gate_k, gate_n, s));
+      GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, j0 + nbw, J1 - j0 - nbw, Tp, 1, gate_k, gate_n,
+                        s));
+      op.off[op.count] = (int)(j0 - J0);
+      op.width[op.count] = nbw;
+      op.tidx[op.count] = pi;
+      ++op.count;
+      ++pi;
+      j0 += nbw;
     }
-    return GN_OK;
-  };
-  if (hipEventRecord(side->fork, s) != hipSuccess) return GN_ERR_HIP;
-  if (hipStreamWaitEvent(side->s, side->fork, 0) != hipSuccess) return GN_ERR_HIP;
-  const gn_status st = factor();
-  // join: the caller's stream continues only after the side stream's last update
-  if (hipEventRecord(side->join, side->s) != hipSuccess) return GN_ERR_HIP;
-  if (hipStreamWaitEvent(s, side->join, 0) != hipSuccess) return GN_ERR_HIP;
-  GN_TRY(st);
+    const int64_t Mp = M - J0;
+    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w, Vb, Vt,
+                                                                         gate_k, gate_n);
+    GN_LAUNCH_CHECK();
+    const unsigned nchg = (unsigned)cdiv(Mp, QO_CH);  // G = V^T V
+    qr_oupd_w<<<dim3(nchg, 1), dim3(256), 0, s>>>(Vb, Mp, Vb, QR_OB, QR_OB, part, gate_k, gate_n);
+    GN_LAUNCH_CHECK();
+    qr_sum_g<<<dim3(QR_OB * QR_OB / 256), dim3(256), 0, s>>>(part, (int)nchg, G, gate_k, gate_n);
+    GN_LAUNCH_CHECK();
+    double* Tb = Tout + (size_t)ob * QR_OB * QR_OB;
+    qr_merge_t<<<dim3(1), dim3(256), 0, s>>>(G, Tin, op, w, Tb, gate_k, gate_n);
+    GN_LAUNCH_CHECK();
+    // C2 <- (I - V T^T V^T) C2 on the columns past the block
+    GN_TRY(apply_block(Mp, C + J0 * ldc + J1, ldc, N - J1, Tb, 1));
+  }
   // explicit Q: start from [I; 0] and apply the outer blocks right to left,
   // Q2 <- (I - V T V^T) Q2 on rows and columns J0..
   qr_init_q<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(Q, ldq, M, N, gate_k, gate_n);
@@ -1079,11 +1009,10 @@ gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int
     const int64_t J0 = ob * QR_OB, J1 = (J0 + QR_OB < N) ? J0 + QR_OB : N;
     const int w = (int)(J1 - J0);
     const int64_t Mp = M - J0, nq = N - J0;
-    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w, Vb[0],
-                                                                         Vt[0], gate_k, gate_n);
+    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w, Vb, Vt,
+                                                                         gate_k, gate_n);
     GN_LAUNCH_CHECK();
-    GN_TRY(apply_block(Mp, Q + J0 * ldq + J0, ldq, nq, Tout + (size_t)ob * QR_OB * QR_OB, 0, 0, 0,
-                       s));
+    GN_TRY(apply_block(Mp, Q + J0 * ldq + J0, ldq, nq, Tout + (size_t)ob * QR_OB * QR_OB, 0));
   }
   qr_signfix<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(C, ldc, Q, ldq, R, ldr, M, N,
                                                                    gate_k, gate_n);
