@@ -232,102 +232,121 @@ __device__ __forceinline__ void qr_upd_w_body(const double* __restrict__ Cp, int
 }
 
 
-// Single-launch update of a narrow target (the columns left in the outer block):
-// one workgroup per QF_CPW target columns walks the whole panel height (row
-// t + 256 q in thread t, the d values kept in registers), so W = V^T D is summed
-// on chip and no second launch is needed: W by a transposing wave sum and the
-// waves' partials in a fixed order, W <- Top W (Top = T^T when trans, else T),
-// then D -= V W with V's rows read again.
-constexpr int QF_T = 256;
-constexpr int QF_CPW = 2;                   // target columns per workgroup
-constexpr int QF_RPT = QR_MAXROWS / QF_T;   // rows per thread at the largest height
+// Update of the columns left in the outer block (at most QR_OB - 16) by a panel,
+// in two launches over (QI_CH-row chunk) x (16-column group) tiles: the chunk's
+// V (QI_CH x 16) is staged in LDS once and D kept in registers (a thread owns one
+// column and rows wq + 16 q), W_c = V_c^T D_c is summed over the 16 row groups in
+// LDS in a fixed order; then every tile sums its group's partials in chunk order
+// (all loads issued first), forms W2 = Top W (Top = T^T when trans, else T) and
+// subtracts V_c W2 from its chunk.
+constexpr int QI_CH = 128;                    // rows per chunk
+constexpr int QI_RG = 16;                     // row groups: threads per column
+constexpr int QI_RPT = QI_CH / QI_RG;         // rows per thread
+constexpr int QI_MAXCH = QR_MAXROWS / QI_CH;  // chunks at the largest height
 
-__device__ __forceinline__ void qr_load_vrow(double (&v)[QR_NB], const double* __restrict__ Cp,
-                                             int64_t ldc, int64_t j0, int64_t row, int nbw) {
-  const double* vr = Cp + (j0 + row) * ldc + j0;
-#pragma unroll
-  for (int a = 0; a < QR_NB; ++a)
-    v[a] = (a < nbw && row >= a) ? (row == a ? 1.0 : vr[a]) : 0.0;
+__device__ __forceinline__ void qi_stage_v(double (*sV)[QR_NB + 1], const double* __restrict__ Cp,
+                                           int64_t ldc, int64_t j0, int nbw, int64_t Mp,
+                                           int64_t r0) {
+  for (int e = threadIdx.x; e < QI_CH * QR_NB; e += 256) {
+    const int rr = e / QR_NB, c = e % QR_NB;
+    const int64_t row = r0 + rr;
+    double v = 0.0;
+    if (row < Mp && c < nbw) v = (row < c) ? 0.0 : (row == c ? 1.0 : Cp[(j0 + row) * ldc + j0 + c]);
+    sV[rr][c] = v;
+  }
 }
 
-__global__ void __launch_bounds__(QF_T) qr_upd_fused(const double* __restrict__ Cp, int64_t ldc,
+__global__ void __launch_bounds__(256) qr_iupd_w(const double* __restrict__ Cp, int64_t ldc,
+                                                 int64_t M, int64_t j0, int nbw,
+                                                 const double* __restrict__ D, int64_t ldd,
+                                                 int64_t col0, int64_t ncols,
+                                                 double* __restrict__ Wp, const int32_t* gate,
+                                                 int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  __shared__ double sV[QI_CH][QR_NB + 1];
+  __shared__ double red[QI_RG][QR_NB][QR_NB + 1];
+  const int tid = threadIdx.x, j = tid & 15, wq = tid >> 4;
+  const int64_t Mp = M - j0, r0 = (int64_t)blockIdx.x * QI_CH;
+  const int64_t jg = (int64_t)blockIdx.y * QR_NB + j;
+  const bool jok = jg < ncols;
+  double d[QI_RPT];
+#pragma unroll
+  for (int q = 0; q < QI_RPT; ++q) {
+    const int64_t row = r0 + wq + QI_RG * q;
+    d[q] = (jok && row < Mp) ? D[(j0 + row) * ldd + col0 + jg] : 0.0;
+  }
+  qi_stage_v(sV, Cp, ldc, j0, nbw, Mp, r0);
+  __syncthreads();
+  double acc[QR_NB];
+#pragma unroll
+  for (int a = 0; a < QR_NB; ++a) acc[a] = 0.0;
+#pragma unroll
+  for (int q = 0; q < QI_RPT; ++q)
+#pragma unroll
+    for (int a = 0; a < QR_NB; ++a) acc[a] = fma(sV[wq + QI_RG * q][a], d[q], acc[a]);
+#pragma unroll
+  for (int a = 0; a < QR_NB; ++a) red[wq][a][j] = acc[a];
+  __syncthreads();
+  const int a = tid >> 4, jj = tid & 15;
+  double sum = 0.0;
+#pragma unroll
+  for (int w = 0; w < QI_RG; ++w) sum += red[w][a][jj];
+  const int64_t col = (int64_t)blockIdx.y * QR_NB + jj;
+  if (col < ncols) Wp[((int64_t)blockIdx.x * QR_NB + a) * ncols + col] = sum;
+}
+
+__global__ void __launch_bounds__(256) qr_iupd_apply(const double* __restrict__ Cp, int64_t ldc,
                                                      int64_t M, int64_t j0, int nbw,
                                                      double* __restrict__ D, int64_t ldd,
                                                      int64_t col0, int64_t ncols,
+                                                     const double* __restrict__ Wp, int nch,
                                                      const double* __restrict__ T, int trans,
                                                      const int32_t* gate, int64_t gate_n) {
   if (gate && *gate >= gate_n) return;
-  constexpr int NW = QR_NB * QF_CPW;  // W entries, a + 16 b
-  __shared__ double part[QF_T / 64][NW];
+  __shared__ double sV[QI_CH][QR_NB + 1];
+  __shared__ double sW[QR_NB][QR_NB + 1];
+  __shared__ double sW2[QR_NB][QR_NB + 1];
   __shared__ double sT[QR_NB][QR_NB + 1];
-  __shared__ double Ws[NW];
-  __shared__ double W2s[NW];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int64_t Mp = M - j0;
-  const int64_t c0 = (int64_t)blockIdx.x * QF_CPW;
+  const int tid = threadIdx.x, j = tid & 15, wq = tid >> 4;
+  const int64_t Mp = M - j0, r0 = (int64_t)blockIdx.x * QI_CH;
+  const int64_t jg = (int64_t)blockIdx.y * QR_NB + j;
+  const bool jok = jg < ncols;
+  const int a = tid >> 4, jj = tid & 15;
+  {  // W = sum of the group's partials in chunk order
+    const int64_t col = (int64_t)blockIdx.y * QR_NB + jj;
+    double v[QI_MAXCH];
+#pragma unroll
+    for (int c = 0; c < QI_MAXCH; ++c)
+      v[c] = (c < nch && col < ncols) ? Wp[((int64_t)c * QR_NB + a) * ncols + col] : 0.0;
+    double sum = 0.0;
+#pragma unroll
+    for (int c = 0; c < QI_MAXCH; ++c) sum += v[c];
+    sW[a][jj] = sum;
+    const double t = trans ? T[jj * QR_NB + a] : T[a * QR_NB + jj];
+    sT[a][jj] = (a < nbw && jj < nbw) ? t : 0.0;
+  }
+  double d[QI_RPT];
+#pragma unroll
+  for (int q = 0; q < QI_RPT; ++q) {
+    const int64_t row = r0 + wq + QI_RG * q;
+    d[q] = (jok && row < Mp) ? D[(j0 + row) * ldd + col0 + jg] : 0.0;
+  }
+  qi_stage_v(sV, Cp, ldc, j0, nbw, Mp, r0);
+  __syncthreads();
   {
-    const int a = t / QR_NB, l = t % QR_NB;  // 256 = 16 x 16
-    const double v = trans ? T[l * QR_NB + a] : T[a * QR_NB + l];
-    sT[a][l] = (a < nbw && l < nbw) ? v : 0.0;
-  }
-  double d[QF_RPT][QF_CPW];
-  double acc[NW];
+    double sum = 0.0;
 #pragma unroll
-  for (int i = 0; i < NW; ++i) acc[i] = 0.0;
-#pragma unroll
-  for (int q = 0; q < QF_RPT; ++q) {
-    const int64_t row = t + (int64_t)QF_T * q;
-    const bool in = row < Mp;
-#pragma unroll
-    for (int b = 0; b < QF_CPW; ++b)
-      d[q][b] = (in && c0 + b < ncols) ? D[(j0 + row) * ldd + col0 + c0 + b] : 0.0;
-    if (in) {
-      double v[QR_NB];
-      qr_load_vrow(v, Cp, ldc, j0, row, nbw);
-#pragma unroll
-      for (int b = 0; b < QF_CPW; ++b)
-#pragma unroll
-        for (int a = 0; a < QR_NB; ++a) acc[a + QR_NB * b] = fma(v[a], d[q][b], acc[a + QR_NB * b]);
-    }
-  }
-  int slot;
-  const double ws = wave_transpose_sum<NW>(acc, lane, &slot);
-  if ((lane & (64 / NW - 1)) == 0) part[wave][slot] = ws;
-  __syncthreads();
-  if (t < NW) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < QF_T / 64; ++w) s += part[w][t];
-    Ws[t] = s;
+    for (int l = 0; l < QR_NB; ++l) sum = fma(sT[a][l], sW[l][jj], sum);
+    sW2[a][jj] = sum;
   }
   __syncthreads();
-  if (t < NW) {
-    const int a = t % QR_NB, b = t / QR_NB;
-    double s = 0.0;
 #pragma unroll
-    for (int l = 0; l < QR_NB; ++l) s = fma(sT[a][l], Ws[l + QR_NB * b], s);
-    W2s[t] = s;
-  }
-  __syncthreads();
-  double w2[QF_CPW][QR_NB];
+  for (int q = 0; q < QI_RPT; ++q) {
+    const int64_t row = r0 + wq + QI_RG * q;
+    double sum = 0.0;
 #pragma unroll
-  for (int b = 0; b < QF_CPW; ++b)
-#pragma unroll
-    for (int a = 0; a < QR_NB; ++a) w2[b][a] = W2s[a + QR_NB * b];
-#pragma unroll
-  for (int q = 0; q < QF_RPT; ++q) {
-    const int64_t row = t + (int64_t)QF_T * q;
-    if (row < Mp) {
-      double v[QR_NB];
-      qr_load_vrow(v, Cp, ldc, j0, row, nbw);
-#pragma unroll
-      for (int b = 0; b < QF_CPW; ++b) {
-        double s = 0.0;
-#pragma unroll
-        for (int a = 0; a < QR_NB; ++a) s = fma(v[a], w2[b][a], s);
-        if (c0 + b < ncols) D[(j0 + row) * ldd + col0 + c0 + b] = d[q][b] - s;
-      }
-    }
+    for (int c = 0; c < QR_NB; ++c) sum = fma(sV[wq + QI_RG * q][c], sW2[c][j], sum);
+    if (jok && row < Mp) D[(j0 + row) * ldd + col0 + jg] = d[q] - sum;
   }
 }
 
@@ -890,11 +909,15 @@ gn_status run_panel(double* C, int64_t ldc, int64_t M, int64_t j0, int nbw, doub
 
 gn_status run_update(const double* Cp, int64_t ldc, int64_t M, int64_t j0, int nbw, double* D,
                     int64_t ldd, int64_t col0, int64_t ncols, const double* Tp, int trans,
-                    const int32_t* gate, int64_t gate_n, hipStream_t s) {
+                    double* Wp, const int32_t* gate, int64_t gate_n, hipStream_t s) {
   if (ncols <= 0) return GN_OK;
   if (M - j0 > QR_MAXROWS) return GN_ERR_UNSUPPORTED;
-  qr_upd_fused<<<dim3((unsigned)cdiv(ncols, QF_CPW)), dim3(QF_T), 0, s>>>(
-      Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Tp, trans, gate, gate_n);
+  const int nch = (int)cdiv(M - j0, QI_CH);
+  const dim3 g((unsigned)nch, (unsigned)cdiv(ncols, QR_NB)), b(256);
+  qr_iupd_w<<<g, b, 0, s>>>(Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Wp, gate, gate_n);
+  GN_LAUNCH_CHECK();
+  qr_iupd_apply<<<g, b, 0, s>>>(Cp, ldc, M, j0, nbw, D, ldd, col0, ncols, Wp, nch, Tp, trans, gate,
+                                gate_n);
   GN_LAUNCH_CHECK();
   return GN_OK;
 }
@@ -906,7 +929,7 @@ static size_t qr_t_bytes(int64_t N) {
   return align_up((size_t)(cdiv(N, 8) + 1) * QR_NB * QR_NB * sizeof(double));
 }
 struct QrWs {
-  size_t tin, vb, vt, w2, part, g, tout, total;
+  size_t tin, wp, vb, vt, w2, part, g, tout, total;
 };
 static QrWs qr_ws_layout(int64_t M, int64_t N) {
   QrWs q{};
@@ -918,6 +941,7 @@ static QrWs qr_ws_layout(int64_t M, int64_t N) {
   };
   const int64_t nw = N > QR_OB ? N : QR_OB;  // widest target (the trailing columns, or V itself)
   q.tin = take(qr_t_bytes(N));
+  q.wp = take((size_t)cdiv(M, QI_CH) * QR_NB * QR_OB * sizeof(double));  // inner updates
   q.vb = take((size_t)M * QR_OB * sizeof(double));
   q.vt = take((size_t)M * QR_OB * sizeof(double));
   q.w2 = take((size_t)QR_OB * nw * sizeof(double));
@@ -942,6 +966,7 @@ gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int
   const QrWs L = qr_ws_layout(M, N);
   char* base = (char*)ws;
   double* Tin = (double*)(base + L.tin);
+  double* Wp = (double*)(base + L.wp);
   double* Vb = (double*)(base + L.vb);
   double* Vt = (double*)(base + L.vt);
   double* W2 = (double*)(base + L.w2);
@@ -977,8 +1002,8 @@ gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int
       const int nbw = (int)((J1 - j0 < nb) ? (J1 - j0) : nb);
       double* Tp = Tin + (size_t)pi * QR_NB * QR_NB;
       GN_TRY(run_panel(C, ldc, M, j0, nbw, Tp, gate_k, gate_n, s));
-      GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, j0 + nbw, J1 - j0 - nbw, Tp, 1, gate_k, gate_n,
-                        s));
+      GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, j0 + nbw, J1 - j0 - nbw, Tp, 1, Wp, gate_k,
+                        gate_n, s));
       op.off[op.count] = (int)(j0 - J0);
       op.width[op.count] = nbw;
       op.tidx[op.count] = pi;
