@@ -36,6 +36,25 @@ constexpr int QP_T = 512;  // largest panel workgroup (and the batched panel's)
 constexpr int QR_MAXROWS = 4096;
 constexpr int QR_NB = 16;  // largest panel width
 
+// sqrt(s) and 1/b for s, b in the normal range with |result| normal: the hardware
+// approximation refined by Newton steps (to within a few ulp).
+__device__ __forceinline__ double qr_sqrt_nr(double s) {
+  const double y = __builtin_amdgcn_rsq(s);
+  double g = s * y, h = 0.5 * y;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, s);
+  return fma(d, h, g);
+}
+__device__ __forceinline__ double qr_rcp_nr(double b) {
+  double y = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-b, y, 1.0);
+  return fma(y, e, y);
+}
+
 // One column step of the panel, c a compile-time column index: every register
 // array is indexed by constants, and only row c's thread and the rows above the
 // pivot (all in the first register row, c < NB) need run-time predicates.
@@ -68,25 +87,46 @@ __device__ __forceinline__ void qr_column(double (&p)[RPT][NB], int t, int lane,
   const double ws = wave_transpose_sum<NB>(acc, lane, &slot);
   if ((lane & (kLowBits - 1)) == 0) part[buf][wave][slot] = ws;
   __syncthreads();
-  // lane l holds the total of slot l % NB (summed over waves in a fixed order)
-  // and the pivot row's entry P_l; sigma and alpha are made uniform
+  // lane l holds the total of slot l % NB (the waves' partials summed as a
+  // balanced tree in a fixed order) and the pivot row's entry P_l; sigma and alpha
+  // are made uniform
   const int sl = lane % NB;
-  double tot = 0.0;
+  double pw[NT / 64];
 #pragma unroll
-  for (int w = 0; w < NT / 64; ++w) tot += part[buf][w][sl];
+  for (int w = 0; w < NT / 64; ++w) pw[w] = part[buf][w][sl];
+#pragma unroll
+  for (int h = NT / 128; h >= 1; h >>= 1)
+#pragma unroll
+    for (int w = 0; w < h; ++w) pw[w] += pw[w + h];
+  const double tot = pw[0];
   const double Pl = prow[buf][sl];
   const double sigma = readlane_f64(tot, c), alpha = prow[buf][c];
-  double beta = alpha, tau = 0.0, scale = 0.0;
+  // beta = -sign(alpha) ||x(c:)||, tau = (beta - alpha) / beta, scale = 1 / (alpha - beta),
+  // rb = 1 / beta.  In the normal range the square root and the reciprocals are
+  // refined hardware approximations (a few-ulp error, like any Householder
+  // implementation's reflector), keeping the chain of dependent operations short;
+  // elsewhere they are the correctly rounded operations.
+  double beta = alpha, tau = 0.0, scale = 0.0, rb = 0.0;
   if (sigma != 0.0) {
-    const double nrm = sqrt(fma(alpha, alpha, sigma));
-    beta = (alpha >= 0.0) ? -nrm : nrm;
-    tau = (beta - alpha) / beta;
-    scale = 1.0 / (alpha - beta);
+    const double s2 = fma(alpha, alpha, sigma);
+    if (s2 >= 0x1p-960 && s2 <= 0x1p960) {
+      const double nrm = qr_sqrt_nr(s2);
+      beta = (alpha >= 0.0) ? -nrm : nrm;
+      rb = qr_rcp_nr(beta);
+      scale = qr_rcp_nr(alpha - beta);
+      tau = (beta - alpha) * rb;
+    } else {
+      const double nrm = sqrt(s2);
+      beta = (alpha >= 0.0) ? -nrm : nrm;
+      rb = 1.0 / beta;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
   }
-  // tw_j = -tau v^T p_j with v^T p_j = (x.p_j - beta p_j[c]) / (alpha - beta), one
-  // j per lane, then made uniform: the update of the columns right of c and, for
-  // j < c, the y of the T recurrence
-  const double twl = (tau != 0.0) ? -tau * (scale * fma(-beta, Pl, tot)) : 0.0;
+  // tw_j = -tau v^T p_j = -tau scale (x.p_j - beta p_j[c]) = x.p_j / beta - p_j[c]
+  // (since -tau scale = 1 / beta), one j per lane, then made uniform: the update of
+  // the columns right of c and, for j < c, the y of the T recurrence
+  const double twl = (tau != 0.0) ? fma(tot, rb, -Pl) : 0.0;
   double tw[NB];
 #pragma unroll
   for (int cc = 0; cc < NB; ++cc) tw[cc] = readlane_f64(twl, cc);
