@@ -130,7 +130,7 @@ CoreWs core_ws(const Plan& P) {
 }
 
 struct ApplyWs {
-  size_t t1, t2, t3, split, split_bytes, total;
+  size_t t1, t2, t3, split, split_bytes, solve, total;
 };
 ApplyWs apply_ws(const Plan& P, int64_t kc) {
   ApplyWs w{};
@@ -143,7 +143,8 @@ ApplyWs apply_ws(const Plan& P, int64_t kc) {
   const size_t s0 = dgemm_split_ws_bytes(P.rl, k1, P.n);  // (Y^T A) W
   const size_t s1 = dgemm_split_ws_bytes(k1, P.r, P.m);   // W (AX)
   w.split_bytes = s0 > s1 ? s0 : s1;
-  w.total = w.split + w.split_bytes;
+  w.solve = w.split + align_up(w.split_bytes);
+  w.total = w.solve + (kc <= small_solve_max_rhs() ? small_solve_ws_bytes(P.r) : 0);
   return w;
 }
 
@@ -593,8 +594,12 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
     GN_TRY(launch_dgemm(P.r, kc, P.rl, 1.0, MatRef{core->Q1, GN_DT_F64, 1, P.r},
                         MatRef{t1, GN_DT_F64, kc, 1}, 0.0, t2, kc, 1, core->k, true, s));
     // t2 <- R^{-1} t2  or  R2^{-T} t2   (left solve on the transposed view)
-    GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, 1, kc, true, true, s,
-                            false, P.pinv_form));
+    if (kc <= small_solve_max_rhs())
+      GN_TRY(launch_small_solve(P.r, core->R, core->R2, core->k, P.pinv_form, true, t2, kc, 1, kc,
+                                base + Wl.solve, s));
+    else
+      GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, 1, kc, true, true, s,
+                              false, P.pinv_form));
     // t3 = t2 (k == r)  or  Q2 t2 (k < r)
     GN_TRY(widen(P.r, kc, t2, GN_DT_F64, kc, t3, kc, core->k, P.gate_r, s));
     GN_TRY(launch_dgemm(P.r, kc, P.r, 1.0, MatRef{core->Q2, GN_DT_F64, P.r, 1},
@@ -612,8 +617,12 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
     GN_TRY(launch_dgemm(kc, P.r, P.r, 1.0, MatRef{t1, GN_DT_F64, P.r, 1},
                         MatRef{core->Q2, GN_DT_F64, P.r, 1}, 0.0, t2, P.r, 1, nullptr, false, s,
                         core->k, P.gate_r, true));
-    GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, P.r, 1, false, true, s,
-                            false, P.pinv_form));
+    if (kc <= small_solve_max_rhs())
+      GN_TRY(launch_small_solve(P.r, core->R, core->R2, core->k, P.pinv_form, false, t2, kc, P.r, 1,
+                                base + Wl.solve, s));
+    else
+      GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, P.r, 1, false, true, s,
+                              false, P.pinv_form));
     // t3 = t2 Q1^T : kc x rl   (columns of t2 beyond k are zero)
     GN_TRY(launch_dgemm(kc, P.rl, P.r, 1.0, MatRef{t2, GN_DT_F64, P.r, 1},
                         MatRef{core->Q1, GN_DT_F64, 1, P.r}, 0.0, t3, P.rl, 1, nullptr, false, s));

@@ -321,7 +321,8 @@ size_t residual_ws_bytes(int64_t M, int64_t N) {
 gn_status launch_residual(int64_t M, int64_t N, int64_t K, MatRef Ref, const float* ref_scales,
                           MatRef A, MatRef B, double* partial, double* out, hipStream_t s) {
   const int64_t tiles = cdiv(M, D_BM) * cdiv(N, D_BN);
-  DArgs g{M, N, K, A, B, 1.0, 0.0, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0, 1, K, nullptr};
+  DArgs g{M, N, K, A, B, 1.0, 0.0, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0, 1, K, nullptr,
+          GN_DT_F64};  // no D: the tiles feed the residual
   RArgs rr{Ref, ref_scales, cdiv(N, 128), partial};
   residual_kernel<<<dim3((unsigned)tiles), dim3(256), 0, s>>>(g, rr);
   GN_LAUNCH_CHECK();

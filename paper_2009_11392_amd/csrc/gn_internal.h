@@ -282,6 +282,16 @@ gn_status launch_rrqr_core(int64_t r, int64_t rl, const double* R, int64_t ldr, 
 gn_status launch_lift_diag(int64_t r, double* R, int64_t ldr, double tau, int32_t* k,
                            int32_t* status, hipStream_t s);
 size_t power_ws_bytes(int64_t r, int32_t nv);
+// X T = B for a few right-hand sides (rows of X, at most small_solve_max_rhs() is the
+// intended use): the same triangle and gating as launch_trsm_core (left product:
+// T = R^T, or R2 when truncated or forced; right product: T = R, or R2^T), solved by
+// one workgroup per group of right-hand sides held in LDS with inverted diagonal
+// blocks.  ws: small_solve_ws_bytes(r).
+size_t small_solve_ws_bytes(int64_t r);
+int64_t small_solve_max_rhs();
+gn_status launch_small_solve(int64_t r, const double* R, const double* R2, const int32_t* k,
+                             bool force, bool left, double* X, int64_t nrhs, int64_t rsx,
+                             int64_t csx, void* ws, hipStream_t s);
 // force_trunc: the core is in the factored form Q2 R2^{-T} Q1^T whatever k is.
 gn_status launch_power_check(int64_t r, uint64_t seed, int32_t nv, int32_t iters,
                              const double* R, const double* R2, const int32_t* k, bool force_trunc,

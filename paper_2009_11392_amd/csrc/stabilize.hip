@@ -1004,18 +1004,49 @@ __global__ void __launch_bounds__(kPowerThreads) power_iterate(const double* __r
   if (threadIdx.x == 0) *est = best;
 }
 
-// ---------------------------------------------------------------------------- Jacobi driver
-struct JacobiShape {
-  int rpt, b;
-};
-JacobiShape jacobi_shape(int64_t r) {
-  if (r <= 256) return {1, 8};
-  if (r <= 512) return {2, 8};
-  if (r <= 1024) return {4, 8};
-  if (r <= 2048) return {8, 4};
-  return {16, 2};
+// Triangular solve for a few right-hand sides (the columns of a factored product):
+// right-hand side v of this workgroup is entry i of row v0 + v of Xg, i.e.
+// Xg[(v0 + v) rsx + i csx], held in LDS (rows padded to a multiple of 64) and
+// solved with the same blocked substitution as the check.  The factor and the
+// direction follow the kept rank on the device: U = R2 when truncated (or forced)
+// and R otherwise; a left product solves U x = b with U = R and U^T x = b with
+// U = R2, a right product the other way round.  Entries at or beyond the kept
+// size come back zero.
+__global__ void __launch_bounds__(kPowerThreads) small_solve(const double* __restrict__ R,
+                                                             const double* __restrict__ R2,
+                                                             int64_t r, const int32_t* kdev,
+                                                             int force, int left,
+                                                             const double* __restrict__ Dinv,
+                                                             const double* __restrict__ Ut,
+                                                             double* __restrict__ Xg, int64_t nrhs,
+                                                             int64_t rsx, int64_t csx, int nvwg) {
+  __shared__ double X[kPowerLds];
+  __shared__ double xtmp[16 * PB];
+  int64_t k;
+  bool use2;
+  const double* U = power_factor(R, R2, r, kdev, force, k, use2);
+  const bool fwd = left ? use2 : !use2;
+  const int64_t kp = cdiv_d(k, PB) * PB;
+  const int64_t v0 = (int64_t)blockIdx.x * nvwg;
+  const int nv = (int)((nrhs - v0 < nvwg) ? nrhs - v0 : nvwg);
+  for (int64_t e = threadIdx.x; e < (int64_t)nv * kp; e += kPowerThreads) {
+    const int64_t v = e / kp, i = e - v * kp;
+    X[e] = (i < k) ? Xg[(v0 + v) * rsx + i * csx] : 0.0;
+  }
+  __syncthreads();
+  if (k > 0) {
+    if (fwd)
+      power_solve<true>(X, xtmp, nv, k, r, U, Ut, Dinv);
+    else
+      power_solve<false>(X, xtmp, nv, k, r, U, Ut, Dinv);
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)nv * r; e += kPowerThreads) {
+    const int64_t v = e / r, i = e - v * r;
+    Xg[(v0 + v) * rsx + i * csx] = (i < k) ? X[v * kp + i] : 0.0;
+  }
 }
 
+// ---------------------------------------------------------------------------- Jacobi driver
 template <int E, int B>
 gn_status run_jacobi_ring(double* W, double* J, int32_t* ctl, int64_t r, double tol,
                           hipStream_t s) {
@@ -1208,6 +1239,34 @@ gn_status launch_rrqr_core(int64_t r, int64_t rl, const double* R, int64_t ldr, 
 gn_status launch_lift_diag(int64_t r, double* R, int64_t ldr, double tau, int32_t* k,
                            int32_t* status, hipStream_t s) {
   lift_scan<<<dim3(1), dim3(256), 0, s>>>(R, ldr, r, tau, 1, k, status);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+size_t small_solve_ws_bytes(int64_t r) {
+  return align_up((size_t)cdiv(r, PB) * PB * PB * 8) + align_up((size_t)r * r * 8);
+}
+
+int64_t small_solve_max_rhs() { return 32; }
+
+gn_status launch_small_solve(int64_t r, const double* R, const double* R2, const int32_t* k,
+                             bool force, bool left, double* X, int64_t nrhs, int64_t rsx,
+                             int64_t csx, void* ws, hipStream_t s) {
+  if (nrhs <= 0) return GN_OK;
+  const int64_t kpmax = cdiv(r, PB) * PB;
+  if (kpmax > kPowerLds) return GN_ERR_UNSUPPORTED;
+  double* Dinv = (double*)ws;
+  double* Ut = (double*)((char*)ws + align_up((size_t)cdiv(r, PB) * PB * PB * 8));
+  power_block_inverse<<<dim3((unsigned)cdiv(r, PB)), dim3(PB), 0, s>>>(R, R2, r, k, force ? 1 : 0,
+                                                                       Dinv);
+  GN_LAUNCH_CHECK();
+  power_transpose<<<dim3((unsigned)cdiv(r, 32), (unsigned)cdiv(r, 32)), dim3(256), 0, s>>>(
+      R, R2, r, k, force ? 1 : 0, Ut);
+  GN_LAUNCH_CHECK();
+  int nvwg = (int)(kPowerLds / kpmax);
+  if (nvwg > 16) nvwg = 16;
+  small_solve<<<dim3((unsigned)cdiv(nrhs, nvwg)), dim3(kPowerThreads), 0, s>>>(
+      R, R2, r, k, force ? 1 : 0, left ? 1 : 0, Dinv, Ut, X, nrhs, rsx, csx, nvwg);
   GN_LAUNCH_CHECK();
   return GN_OK;
 }

@@ -277,6 +277,29 @@ def test_low_precision_solve_within_5pct_of_oracle(G, mode, kind_x):
     assert e_gpu <= 1.05 * e_ref, (e_gpu, e_ref)
 
 
+# ----------------------------------------------------------------------------- products, several blocks
+# r = 300: five 64-row blocks of the triangular solve, the last ragged.  16
+# right-hand sides take the few-right-hand-side solver, 40 the blocked one; both
+# against the oracle's products, untruncated (k = r) and truncated (k = 220).
+@pytest.mark.parametrize("rank", [300, 220])
+def test_apply_multiblock(G, rank):
+    m, n, r = 900, 700, 300
+    A = W.spectrum_matrix(m, n, 0.97 ** np.arange(rank), seed=31)
+    p = G.Problem(m, n, r, seed=19, mode="f64", eps=1e-12)
+    X = OP.gaussian(p.seed, OP.STREAM_X, n, r)
+    Y = OP.gaussian(p.seed, OP.STREAM_Y, m, p.rl)
+    ref = OG.gn(A, X, Y, tau_of(p))
+    AX, YtA, core = G.solve(p, dev(A))
+    assert core.rank() == ref.core.k == min(rank, r)
+    for kc in (16, 40):
+        Wr = W.host_gaussian(n, kc, 30 + kc)
+        Wl = W.host_gaussian(kc, m, 31 + kc)
+        outr = host(G.gn_apply(p, 0, AX, YtA, core, dev(Wr)))
+        outl = host(G.gn_apply(p, 1, AX, YtA, core, dev(Wl)))
+        assert relerr(outr, OG.apply_right(ref.AX, ref.YA, ref.core, Wr)) <= 1e-10
+        assert relerr(outl, OG.apply_left(ref.AX, ref.YA, ref.core, Wl)) <= 1e-10
+
+
 # ----------------------------------------------------------------------------- larger cores
 # Core shapes that exercise every panel configuration of the QR (1 to 8 rows per
 # thread, panel widths 16 and 8) and the second QR of a truncated core.
