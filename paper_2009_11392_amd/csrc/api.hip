@@ -3,6 +3,8 @@
 // stream and returns without synchronizing.
 #include <math.h>
 
+#include <mutex>
+
 #include "gn_internal.h"
 
 using namespace gn;
@@ -24,6 +26,40 @@ struct Plan {
 };
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// A second stream per device (non-blocking, default priority) for work that runs
+// beside the caller's stream, with the events of one fork and its join.  Created
+// on first use and kept until the process ends; the mutex is held from the fork
+// to the join, so concurrent callers never share the events.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_side_mu;
+SideStream g_side[kMaxDevices];
+
+gn_status side_stream(SideStream** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GN_ERR_HIP;
+  SideStream& ss = g_side[dev];
+  if (!ss.s) {
+    hipStream_t st = nullptr;
+    hipEvent_t ef = nullptr, ej = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return GN_ERR_HIP;
+    if (hipEventCreateWithFlags(&ef, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ej, hipEventDisableTiming) != hipSuccess) {
+      if (ef) (void)hipEventDestroy(ef);
+      (void)hipStreamDestroy(st);
+      return GN_ERR_HIP;
+    }
+    ss.s = st;
+    ss.fork = ef;
+    ss.join = ej;
+  }
+  *out = &ss;
+  return GN_OK;
+}
 
 gn_status make_plan(const gn_problem* p, Plan& P) {
   if (!p) return GN_ERR_ARG;
@@ -140,9 +176,14 @@ ApplyWs apply_ws(const Plan& P, int64_t kc) {
   w.t2 = blk;
   w.t3 = 2 * blk;
   w.split = 3 * blk;
-  const size_t s0 = dgemm_split_ws_bytes(P.rl, k1, P.n);  // (Y^T A) W
-  const size_t s1 = dgemm_split_ws_bytes(k1, P.r, P.m);   // W (AX)
-  w.split_bytes = s0 > s1 ? s0 : s1;
+  // K-slice partials of the products that split K (both sides)
+  const int64_t shapes[6][3] = {{P.rl, k1, P.n}, {P.r, k1, P.rl}, {P.m, k1, P.r},
+                                {k1, P.r, P.m},  {k1, P.rl, P.r}, {k1, P.n, P.rl}};
+  w.split_bytes = 0;
+  for (const auto& sh : shapes) {
+    const size_t b = dgemm_split_ws_bytes(sh[0], sh[1], sh[2]);
+    if (b > w.split_bytes) w.split_bytes = b;
+  }
   w.solve = w.split + align_up(w.split_bytes);
   w.total = w.solve + (kc <= small_solve_max_rhs() ? small_solve_ws_bytes(P.r) : 0);
   return w;
@@ -475,13 +516,25 @@ gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void*
   }
   double* qws = (double*)(base + W.qr);
   switch (P.method) {
-    case GN_CORE_QR:
-      // Householder QR, kept rank, and the second QR when truncated
-      GN_TRY(launch_qr(P.rl, P.r, C, P.r, out->Q1, P.r, out->R, P.r, qws, nullptr, s));
-      GN_TRY(launch_truncate(P.r, out->R, P.r, P.tau, out->k, out->status, Z, P.r, s));
+    case GN_CORE_QR: {
+      // Householder QR; then, on a side stream, the kept rank and the second QR
+      // (whose kernels return at once unless truncated) while this stream forms Q1;
+      // the two meet again before the call's later work.
+      GN_TRY(launch_qr_factor(P.rl, P.r, C, P.r, out->R, P.r, qws, nullptr, s));
+      std::lock_guard<std::mutex> lock(g_side_mu);
+      SideStream* ss = nullptr;
+      GN_TRY(side_stream(&ss));
+      if (hipEventRecord(ss->fork, s) != hipSuccess ||
+          hipStreamWaitEvent(ss->s, ss->fork, 0) != hipSuccess)
+        return GN_ERR_HIP;
+      GN_TRY(launch_truncate(P.r, out->R, P.r, P.tau, out->k, out->status, Z, P.r, ss->s));
       GN_TRY(launch_qr(P.r, P.r, Z, P.r, out->Q2, P.r, out->R2, P.r, (double*)(base + W.qr2),
-                       out->k, s));
+                       out->k, ss->s));
+      if (hipEventRecord(ss->join, ss->s) != hipSuccess) return GN_ERR_HIP;
+      GN_TRY(launch_qr_form_q(P.rl, P.r, C, P.r, out->Q1, P.r, qws, nullptr, s));
+      if (hipStreamWaitEvent(s, ss->join, 0) != hipSuccess) return GN_ERR_HIP;
       break;
+    }
     case GN_CORE_LIFT_DIAG:
       GN_TRY(launch_qr(P.rl, P.r, C, P.r, out->Q1, P.r, out->R, P.r, qws, nullptr, s));
       GN_TRY(launch_lift_diag(P.r, out->R, P.r, P.tau, out->k, out->status, s));
@@ -592,7 +645,8 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
                         nullptr, false, s, nullptr, 0, true, sp, Wl.split_bytes));
     // t2 = Q1[:, :k]^T t1 : r x kc (rows >= k zero)
     GN_TRY(launch_dgemm(P.r, kc, P.rl, 1.0, MatRef{core->Q1, GN_DT_F64, 1, P.r},
-                        MatRef{t1, GN_DT_F64, kc, 1}, 0.0, t2, kc, 1, core->k, true, s));
+                        MatRef{t1, GN_DT_F64, kc, 1}, 0.0, t2, kc, 1, core->k, true, s, nullptr,
+                        0, true, sp, Wl.split_bytes));
     // t2 <- R^{-1} t2  or  R2^{-T} t2   (left solve on the transposed view)
     if (kc <= small_solve_max_rhs())
       GN_TRY(launch_small_solve(P.r, core->R, core->R2, core->k, P.pinv_form, true, t2, kc, 1, kc,
@@ -607,7 +661,7 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
                         P.gate_r, true));
     // out = AX t3 : m x kc
     GN_TRY(launch_dgemm(P.m, kc, P.r, 1.0, ax, MatRef{t3, GN_DT_F64, kc, 1}, 0.0, out, ldo, 1,
-                        nullptr, false, s));
+                        nullptr, false, s, nullptr, 0, true, sp, Wl.split_bytes));
   } else {
     // t1 = W AX : kc x r
     GN_TRY(launch_dgemm(kc, P.r, P.m, 1.0, MatRef{W, GN_DT_F64, ldw, 1}, ax, 0.0, t1, P.r, 1,
@@ -625,10 +679,11 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
                               false, P.pinv_form));
     // t3 = t2 Q1^T : kc x rl   (columns of t2 beyond k are zero)
     GN_TRY(launch_dgemm(kc, P.rl, P.r, 1.0, MatRef{t2, GN_DT_F64, P.r, 1},
-                        MatRef{core->Q1, GN_DT_F64, 1, P.r}, 0.0, t3, P.rl, 1, nullptr, false, s));
+                        MatRef{core->Q1, GN_DT_F64, 1, P.r}, 0.0, t3, P.rl, 1, nullptr, false, s,
+                        nullptr, 0, true, sp, Wl.split_bytes));
     // out = t3 (Y^T A) : kc x n
     GN_TRY(launch_dgemm(kc, P.n, P.rl, 1.0, MatRef{t3, GN_DT_F64, P.rl, 1}, yta, 0.0, out, ldo, 1,
-                        nullptr, false, s));
+                        nullptr, false, s, nullptr, 0, true, sp, Wl.split_bytes));
   }
   return GN_OK;
 }

@@ -11,6 +11,7 @@
 // stride is 1.  Products with few output tiles and a long K are split along K
 // into fixed slices whose partial results are summed in slice order.
 #include "gn_internal.h"
+#include "wave_ops.h"
 
 namespace gn {
 namespace {
@@ -208,6 +209,179 @@ __global__ void __launch_bounds__(256) dgemm_reduce(DArgs g) {
   store_d(g, i, j, s, g.kmask ? *g.kmask : 0);
 }
 
+// Products with a narrow right factor B (N <= NW_N columns: a block of a few
+// right-hand sides), for which 64x64 MFMA tiles would leave most of the chip idle
+// and most of each tile empty.  They are bound by the one read of A, so A streams
+// through coalesced loads and is read once; B's rows are staged in LDS per K chunk.
+// K is split into slices (blockIdx.y) summed afterwards in slice order by
+// dgemm_reduce, so results do not depend on scheduling.
+//  * dgemm_narrow, A k-contiguous (A.cs == 1): a 512-thread workgroup owns NW_RW
+//    rows per wave, lanes along K; B's chunk is stored by columns so each lane
+//    reads consecutive LDS words; a wave's NW_RW x NW_N sums finish in one
+//    transposing wave sum.
+//  * dgemm_narrow_t, A m-contiguous (A.rs == 1): one row per thread, lanes along
+//    M, the chunk of B read by every lane at the same LDS address (broadcast).
+constexpr int NW_N = 16, NW_RW = 2, NW_T = 512, NW_KC = 256;
+constexpr int NT_T = 256, NT_KC = 16;
+
+// A's entries in their stored type (FP64, FP32, or BF16 widened to FP32 exactly).
+template <int DT> struct NwElem { using T = float; };
+template <> struct NwElem<GN_DT_F64> { using T = double; };
+template <int DT>
+__device__ __forceinline__ typename NwElem<DT>::T nw_load(const void* p, int64_t off) {
+  if constexpr (DT == GN_DT_F64) return reinterpret_cast<const double*>(p)[off];
+  else if constexpr (DT == GN_DT_F32) return reinterpret_cast<const float*>(p)[off];
+  else return bf16_bits_to_f32(reinterpret_cast<const uint16_t*>(p)[off]);
+}
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations,
+// leaving its global loads in flight (__syncthreads waits for those as well).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+__device__ __forceinline__ void nw_store(const DArgs& g, int64_t s, int64_t i, int64_t j, double v) {
+  if (g.ksplit > 1)
+    g.partial[s * g.M * g.N + i * g.N + j] = v;
+  else
+    store_d(g, i, j, v, g.kmask ? *g.kmask : 0);
+}
+
+// Loads below are unconditional, from clamped (in-range) indices, with values
+// outside the operands replaced by zero only after the barrier: a predicated load
+// compiles to a branch that waits for each load before issuing the next.
+template <int DT>
+__global__ void __launch_bounds__(NW_T) dgemm_narrow(DArgs g) {
+  using E = typename NwElem<DT>::T;
+  constexpr int kStage = NW_KC * NW_N / NW_T;  // B entries staged per thread
+  __shared__ double Bs[NW_N][NW_KC + 1];
+  if (gated_off(g)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = ((int64_t)blockIdx.x * (NW_T / 64) + wave) * NW_RW;
+  const int64_t s = blockIdx.y;
+  const int64_t kb = s * g.kslice;
+  const int64_t ke = (kb + g.kslice < g.K) ? kb + g.kslice : g.K;
+  const double* B = reinterpret_cast<const double*>(g.B.p);
+  double bv[kStage];
+  E a[NW_KC / 64][NW_RW];
+  // chunk k0's loads: B's first, then A's (loads complete in order, so the staging
+  // of B waits for B only)
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+      const int e = tid + q * NW_T, kk = e / NW_N, c = e % NW_N;
+      const int64_t k = k0 + kk;
+      const int64_t kc = k < ke ? k : ke - 1, cc = c < g.N ? c : g.N - 1;
+      bv[q] = B[kc * g.B.rs + cc * g.B.cs];
+    }
+#pragma unroll
+    for (int u = 0; u < NW_KC / 64; ++u)
+#pragma unroll
+      for (int rr = 0; rr < NW_RW; ++rr) {
+        const int64_t row = row0 + rr, k = k0 + u * 64 + lane;
+        const int64_t rc = row < g.M ? row : g.M - 1, kc = k < ke ? k : ke - 1;
+        a[u][rr] = nw_load<DT>(g.A.p, rc * g.A.rs + kc);
+      }
+  };
+  double acc[NW_RW * NW_N];
+#pragma unroll
+  for (int e = 0; e < NW_RW * NW_N; ++e) acc[e] = 0.0;
+  load(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += NW_KC) {
+    lds_barrier();  // every wave has read the previous chunk
+    // entries outside the operands are zeroed here, past the barrier that no load
+    // crosses, so the loads stay unconditional
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+      const int e = tid + q * NW_T, kk = e / NW_N, c = e % NW_N;
+      Bs[c][kk] = (k0 + kk < ke && c < g.N) ? bv[q] : 0.0;
+    }
+    lds_barrier();
+    double av[NW_KC / 64][NW_RW];
+#pragma unroll
+    for (int u = 0; u < NW_KC / 64; ++u) {
+      const bool kin = k0 + u * 64 + lane < ke;
+#pragma unroll
+      for (int rr = 0; rr < NW_RW; ++rr)
+        av[u][rr] = (kin && row0 + rr < g.M) ? (double)a[u][rr] : 0.0;
+    }
+    load(k0 + NW_KC);  // the next chunk (clamped indices past the slice)
+    asm volatile("" ::: "memory");  // keeps those loads ahead of this chunk's products
+#pragma unroll
+    for (int u = 0; u < NW_KC / 64; ++u) {
+#pragma unroll
+      for (int c = 0; c < NW_N; ++c) {
+        const double b = Bs[c][u * 64 + lane];
+#pragma unroll
+        for (int rr = 0; rr < NW_RW; ++rr)
+          acc[rr * NW_N + c] = fma(av[u][rr], b, acc[rr * NW_N + c]);
+      }
+    }
+  }
+  int slot;
+  const double v = wave_transpose_sum<NW_RW * NW_N>(acc, lane, &slot);
+  const int64_t row = row0 + slot / NW_N;
+  const int c = slot % NW_N;
+  if (row < g.M && c < g.N) nw_store(g, s, row, c, v);
+}
+
+template <int DT>
+__global__ void __launch_bounds__(NT_T) dgemm_narrow_t(DArgs g) {
+  using E = typename NwElem<DT>::T;
+  constexpr int kStage = NT_KC * NW_N / NT_T;
+  __shared__ double Bs[NT_KC][NW_N];
+  if (gated_off(g)) return;
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * NT_T + tid;
+  const int64_t ic = i < g.M ? i : g.M - 1;
+  const int64_t s = blockIdx.y;
+  const int64_t kb = s * g.kslice;
+  const int64_t ke = (kb + g.kslice < g.K) ? kb + g.kslice : g.K;
+  const double* B = reinterpret_cast<const double*>(g.B.p);
+  double bv[kStage];
+  E a[NT_KC];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+      const int e = tid + q * NT_T, kk = e / NW_N, c = e % NW_N;
+      const int64_t k = k0 + kk;
+      const int64_t kc = k < ke ? k : ke - 1, cc = c < g.N ? c : g.N - 1;
+      bv[q] = B[kc * g.B.rs + cc * g.B.cs];
+    }
+#pragma unroll
+    for (int kk = 0; kk < NT_KC; ++kk) {
+      const int64_t k = k0 + kk, kc = k < ke ? k : ke - 1;
+      a[kk] = nw_load<DT>(g.A.p, ic + kc * g.A.cs);
+    }
+  };
+  double acc[NW_N];
+#pragma unroll
+  for (int c = 0; c < NW_N; ++c) acc[c] = 0.0;
+  load(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += NT_KC) {
+    lds_barrier();  // every wave has read the previous chunk
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+      const int e = tid + q * NT_T, kk = e / NW_N, c = e % NW_N;
+      Bs[kk][c] = (k0 + kk < ke && c < g.N) ? bv[q] : 0.0;
+    }
+    lds_barrier();
+    double av[NT_KC];
+#pragma unroll
+    for (int kk = 0; kk < NT_KC; ++kk) av[kk] = (i < g.M && k0 + kk < ke) ? (double)a[kk] : 0.0;
+    load(k0 + NT_KC);  // the next chunk (clamped indices past the slice)
+    asm volatile("" ::: "memory");  // keeps those loads ahead of this chunk's products
+#pragma unroll
+    for (int kk = 0; kk < NT_KC; ++kk)
+#pragma unroll
+      for (int c = 0; c < NW_N; ++c) acc[c] = fma(av[kk], Bs[kk][c], acc[c]);
+  }
+  if (i >= g.M) return;
+#pragma unroll
+  for (int c = 0; c < NW_N; ++c)
+    if (c < g.N) nw_store(g, s, i, c, acc[c]);
+}
+
 struct RArgs {
   MatRef ref;
   const float* ref_scales;  // bf16 reference: 128 x 128 block scales
@@ -265,6 +439,30 @@ constexpr int64_t kMinSlice = 64;   // slices of at least 64 (four staged K bloc
 
 }  // namespace
 
+// A product for the narrow kernels: one factor of at most NW_N columns (or rows),
+// the other contiguous along K or along M, stored FP64, FP32 or BF16.
+static bool narrow_eligible(int64_t M, int64_t N, int64_t K, const MatRef& A, const MatRef& B,
+                     int32_t d_dtype) {
+  if (K <= 0 || (d_dtype != GN_DT_F64 && d_dtype != GN_DT_F32)) return false;
+  const MatRef& wide = N <= NW_N ? A : B;
+  const MatRef& thin = N <= NW_N ? B : A;
+  if (thin.dtype != GN_DT_F64) return false;
+  if (wide.dtype != GN_DT_F64 && wide.dtype != GN_DT_F32 && wide.dtype != GN_DT_BF16) return false;
+  if (N <= NW_N) return A.cs == 1 || A.rs == 1;
+  if (M <= NW_N) return B.rs == 1 || B.cs == 1;  // B^T is k- or m-contiguous
+  return false;
+}
+
+// K slices for the narrow kernels: about kTargetWG workgroups, slices of at least
+// 2048 (k-contiguous) or 64 (m-contiguous) entries, at most 32.
+static int64_t narrow_split(int64_t rb, int64_t K, bool kcont) {
+  int64_t ks = cdiv(kTargetWG, rb);
+  const int64_t kmax = kcont ? cdiv(K, 2048) : cdiv(K, 64);
+  if (ks > kmax) ks = kmax;
+  if (ks > 32) ks = 32;
+  return ks < 1 ? 1 : ks;
+}
+
 int32_t dgemm_split(int64_t M, int64_t N, int64_t K) {
   const int64_t tiles = cdiv(M, D_BM) * cdiv(N, D_BN);
   if (tiles >= kTargetWG || K < 2 * kMinSlice) return 1;
@@ -276,7 +474,14 @@ int32_t dgemm_split(int64_t M, int64_t N, int64_t K) {
 }
 
 size_t dgemm_split_ws_bytes(int64_t M, int64_t N, int64_t K) {
-  const int32_t s = dgemm_split(M, N, K);
+  int64_t s = dgemm_split(M, N, K);
+  if (N <= NW_N || M <= NW_N) {  // the narrow kernels' largest split, either layout
+    const int64_t wide = N <= NW_N ? M : N;
+    const int64_t a = narrow_split(cdiv(wide, (NW_T / 64) * NW_RW), K, true);
+    const int64_t b = narrow_split(cdiv(wide, NT_T), K, false);
+    if (a > s) s = a;
+    if (b > s) s = b;
+  }
   return s > 1 ? align_up((size_t)s * M * N * sizeof(double)) : 0;
 }
 
@@ -288,6 +493,50 @@ gn_status launch_dgemm_to(int64_t M, int64_t N, int64_t K, double alpha, MatRef 
   if (M <= 0 || N <= 0) return GN_OK;
   DArgs g{M,    N,          K,          A,   B,   alpha, beta, D, rsd, csd, kmask, mask_rows ? 1 : 0,
           gate, gate_n, gate_trunc ? 1 : 0, 1, K > 0 ? K : 1, nullptr, d_dtype};
+  if (narrow_eligible(M, N, K, A, B, d_dtype)) {
+    // a narrow left factor becomes a narrow right one: D^T = B^T A^T
+    if (N > NW_N) {
+      const MatRef At{B.p, B.dtype, B.cs, B.rs}, Bt{A.p, A.dtype, A.cs, A.rs};
+      g.M = N;
+      g.N = M;
+      g.A = At;
+      g.B = Bt;
+      g.rsd = csd;
+      g.csd = rsd;
+      g.mask_rows = mask_rows ? 0 : 1;
+    }
+    const bool kcont = g.A.cs == 1;
+    const int64_t rb = kcont ? cdiv(g.M, (NW_T / 64) * NW_RW) : cdiv(g.M, NT_T);
+    int64_t ks = narrow_split(rb, K, kcont);
+    if (ks > 1 && (!split_ws || split_ws_bytes < (size_t)ks * M * N * sizeof(double))) ks = 1;
+    g.kslice = cdiv(cdiv(K, ks), 64) * 64;  // slices start on 64-entry boundaries
+    ks = cdiv(K, g.kslice);
+    g.ksplit = (int32_t)ks;
+    g.partial = split_ws;
+    const dim3 grid((unsigned)rb, (unsigned)ks);
+    const int32_t dt = g.A.dtype;
+    if (kcont) {
+      if (dt == GN_DT_F64)
+        dgemm_narrow<GN_DT_F64><<<grid, dim3(NW_T), 0, s>>>(g);
+      else if (dt == GN_DT_F32)
+        dgemm_narrow<GN_DT_F32><<<grid, dim3(NW_T), 0, s>>>(g);
+      else
+        dgemm_narrow<GN_DT_BF16><<<grid, dim3(NW_T), 0, s>>>(g);
+    } else {
+      if (dt == GN_DT_F64)
+        dgemm_narrow_t<GN_DT_F64><<<grid, dim3(NT_T), 0, s>>>(g);
+      else if (dt == GN_DT_F32)
+        dgemm_narrow_t<GN_DT_F32><<<grid, dim3(NT_T), 0, s>>>(g);
+      else
+        dgemm_narrow_t<GN_DT_BF16><<<grid, dim3(NT_T), 0, s>>>(g);
+    }
+    GN_LAUNCH_CHECK();
+    if (ks > 1) {
+      dgemm_reduce<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(g);
+      GN_LAUNCH_CHECK();
+    }
+    return GN_OK;
+  }
   const int64_t tiles = cdiv(M, D_BM) * cdiv(N, D_BN);
   int32_t ks = split_ws ? dgemm_split(M, N, K) : 1;
   if (ks > 1 && split_ws_bytes < (size_t)ks * M * N * sizeof(double)) ks = 1;

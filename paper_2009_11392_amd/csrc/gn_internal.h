@@ -212,6 +212,13 @@ size_t residual_ws_bytes(int64_t M, int64_t N);
 // immediately unless *gate_k < N (the second QR, needed only when truncated).
 gn_status launch_qr(int64_t M, int64_t N, double* Aq, int64_t lda, double* Q, int64_t ldq,
                     double* R, int64_t ldr, double* ws, const int32_t* gate_k, hipStream_t s);
+// launch_qr in two parts on possibly different streams: the factorization with R,
+// then the explicit Q (which reads the factored matrix and the block reflectors'
+// T factors kept in ws, so it must follow the first part, with the same ws).
+gn_status launch_qr_factor(int64_t M, int64_t N, double* Aq, int64_t lda, double* R, int64_t ldr,
+                           double* ws, const int32_t* gate_k, hipStream_t s);
+gn_status launch_qr_form_q(int64_t M, int64_t N, const double* Aq, int64_t lda, double* Q,
+                           int64_t ldq, double* ws, const int32_t* gate_k, hipStream_t s);
 size_t qr_ws_bytes(int64_t M, int64_t N);
 
 // Batched QR: job z factors C (M x N, M <= 512) in place, writes Q, R (R_ii >=

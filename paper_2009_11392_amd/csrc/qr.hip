@@ -553,6 +553,30 @@ __global__ void __launch_bounds__(256) qr_signfix_b(const QrJob* __restrict__ jo
   qr_signfix_body(J.C, J.ldc, J.Q, J.ldq, J.R, J.ldr, J.M, J.N);
 }
 
+// The two halves of qr_signfix as separate launches: R (upper triangle of the
+// factored matrix, row i scaled by the sign of its Householder diagonal) as soon
+// as the factorization ends, and the column signs of Q once Q is formed.
+__global__ void __launch_bounds__(256) qr_extract_r(const double* C, int64_t ldc, double* R,
+                                                    int64_t ldr, int64_t N, const int32_t* gate,
+                                                    int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * N) return;
+  const int64_t i = e / N, j = e - i * N;
+  const double sg = (C[i * ldc + i] < 0.0) ? -1.0 : 1.0;
+  R[i * ldr + j] = (j >= i) ? sg * C[i * ldc + j] : 0.0;
+}
+
+__global__ void __launch_bounds__(256) qr_sign_q(const double* C, int64_t ldc, double* Q,
+                                                 int64_t ldq, int64_t M, int64_t N,
+                                                 const int32_t* gate, int64_t gate_n) {
+  if (gate && *gate >= gate_n) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  const int64_t i = e / N, j = e - i * N;
+  if (C[j * ldc + j] < 0.0) Q[i * ldq + j] = -Q[i * ldq + j];
+}
+
 // Kept rank: k = first i whose diagonal fails the keep test (|R_ii| >= tau, or
 // |R_ii| > 0 when tau <= 0; non-finite always fails); status flags.
 __device__ __forceinline__ void trunc_scan_body(int64_t r, const double* R, int64_t ldr,
@@ -999,50 +1023,57 @@ size_t qr_ws_bytes(int64_t M, int64_t N) { return qr_ws_layout(M, N).total; }
 // of QR_OB columns, panel updates restricted to the block, then one block
 // reflector per outer block applied by FP64 MFMA products to the trailing
 // columns; Q formed from [I; 0] by the outer blocks right to left.
-gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int64_t ldq, double* R,
-                    int64_t ldr, double* ws, const int32_t* gate_k, hipStream_t s) {
-  if (M < N || M > QR_MAXROWS || N < 1) return GN_ERR_UNSUPPORTED;
-  const int64_t gate_n = N;
+namespace {
+// Pointers into the QR workspace.
+struct QrPtrs {
+  double *Tin, *Wp, *Vb, *Vt, *W2, *part, *G, *Tout;
+};
+QrPtrs qr_ptrs(int64_t M, int64_t N, double* ws) {
   const QrWs L = qr_ws_layout(M, N);
   char* base = (char*)ws;
-  double* Tin = (double*)(base + L.tin);
-  double* Wp = (double*)(base + L.wp);
-  double* Vb = (double*)(base + L.vb);
-  double* Vt = (double*)(base + L.vt);
-  double* W2 = (double*)(base + L.w2);
-  double* part = (double*)(base + L.part);
-  double* G = (double*)(base + L.g);
-  double* Tout = (double*)(base + L.tout);
-  // D <- (I - V T' V^T) D for the outer block at J0 (Mp rows), D with ncols columns
-  auto apply_block = [&](int64_t Mp, double* D, int64_t ldd, int64_t ncols, const double* Tb,
-                         int trans) -> gn_status {
-    if (ncols <= 0) return GN_OK;
-    const unsigned nch = (unsigned)cdiv(Mp, QO_CH), nst = (unsigned)cdiv(ncols, QO_CG);
-    qr_oupd_w<<<dim3(nch, nst), dim3(256), 0, s>>>(Vb, Mp, D, ldd, ncols, part, gate_k, gate_n);
-    GN_LAUNCH_CHECK();
-    qr_oupd_w2<<<dim3((unsigned)cdiv(ncols, QO_CW)), dim3(256), 0, s>>>(part, (int)nch, ncols, Tb,
-                                                                         trans, W2, gate_k, gate_n);
-    GN_LAUNCH_CHECK();
-    qr_oupd_apply<<<dim3((unsigned)cdiv(Mp, QO_CA), nst), dim3(256), 0, s>>>(Vt, Mp, D, ldd, ncols,
-                                                                            W2, gate_k, gate_n);
-    GN_LAUNCH_CHECK();
-    return GN_OK;
-  };
+  return QrPtrs{(double*)(base + L.tin), (double*)(base + L.wp),   (double*)(base + L.vb),
+                (double*)(base + L.vt),  (double*)(base + L.w2),   (double*)(base + L.part),
+                (double*)(base + L.g),   (double*)(base + L.tout)};
+}
+
+// D <- (I - V T' V^T) D for an outer block (Mp rows of V), D with ncols columns.
+gn_status qr_apply_block(const QrPtrs& w, int64_t Mp, double* D, int64_t ldd, int64_t ncols,
+                         const double* Tb, int trans, const int32_t* gate_k, int64_t gate_n,
+                         hipStream_t s) {
+  if (ncols <= 0) return GN_OK;
+  const unsigned nch = (unsigned)cdiv(Mp, QO_CH), nst = (unsigned)cdiv(ncols, QO_CG);
+  qr_oupd_w<<<dim3(nch, nst), dim3(256), 0, s>>>(w.Vb, Mp, D, ldd, ncols, w.part, gate_k, gate_n);
+  GN_LAUNCH_CHECK();
+  qr_oupd_w2<<<dim3((unsigned)cdiv(ncols, QO_CW)), dim3(256), 0, s>>>(w.part, (int)nch, ncols, Tb,
+                                                                       trans, w.W2, gate_k, gate_n);
+  GN_LAUNCH_CHECK();
+  qr_oupd_apply<<<dim3((unsigned)cdiv(Mp, QO_CA), nst), dim3(256), 0, s>>>(w.Vt, Mp, D, ldd, ncols,
+                                                                          w.W2, gate_k, gate_n);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+}  // namespace
+
+gn_status launch_qr_factor(int64_t M, int64_t N, double* C, int64_t ldc, double* R, int64_t ldr,
+                           double* ws, const int32_t* gate_k, hipStream_t s) {
+  if (M < N || M > QR_MAXROWS || N < 1) return GN_ERR_UNSUPPORTED;
+  const int64_t gate_n = N;
+  const QrPtrs w = qr_ptrs(M, N, ws);
   const int64_t nob = cdiv(N, QR_OB);
   std::vector<OuterPanels> ops((size_t)nob);
   int pi = 0;
-  // factor: outer blocks left to right
+  // outer blocks left to right
   for (int64_t ob = 0; ob < nob; ++ob) {
     const int64_t J0 = ob * QR_OB, J1 = (J0 + QR_OB < N) ? J0 + QR_OB : N;
-    const int w = (int)(J1 - J0);
+    const int nbo = (int)(J1 - J0);
     OuterPanels& op = ops[(size_t)ob];
     op.count = 0;
     for (int64_t j0 = J0; j0 < J1;) {
       const int nb = panel_shape(M - j0).nb;
       const int nbw = (int)((J1 - j0 < nb) ? (J1 - j0) : nb);
-      double* Tp = Tin + (size_t)pi * QR_NB * QR_NB;
+      double* Tp = w.Tin + (size_t)pi * QR_NB * QR_NB;
       GN_TRY(run_panel(C, ldc, M, j0, nbw, Tp, gate_k, gate_n, s));
-      GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, j0 + nbw, J1 - j0 - nbw, Tp, 1, Wp, gate_k,
+      GN_TRY(run_update(C, ldc, M, j0, nbw, C, ldc, j0 + nbw, J1 - j0 - nbw, Tp, 1, w.Wp, gate_k,
                         gate_n, s));
       op.off[op.count] = (int)(j0 - J0);
       op.width[op.count] = nbw;
@@ -1052,37 +1083,57 @@ gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int
       j0 += nbw;
     }
     const int64_t Mp = M - J0;
-    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w, Vb, Vt,
-                                                                         gate_k, gate_n);
+    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, nbo, w.Vb,
+                                                                         w.Vt, gate_k, gate_n);
     GN_LAUNCH_CHECK();
     const unsigned nchg = (unsigned)cdiv(Mp, QO_CH);  // G = V^T V
-    qr_oupd_w<<<dim3(nchg, 1), dim3(256), 0, s>>>(Vb, Mp, Vb, QR_OB, QR_OB, part, gate_k, gate_n);
+    qr_oupd_w<<<dim3(nchg, 1), dim3(256), 0, s>>>(w.Vb, Mp, w.Vb, QR_OB, QR_OB, w.part, gate_k,
+                                                  gate_n);
     GN_LAUNCH_CHECK();
-    qr_sum_g<<<dim3(QR_OB * QR_OB / 256), dim3(256), 0, s>>>(part, (int)nchg, G, gate_k, gate_n);
+    qr_sum_g<<<dim3(QR_OB * QR_OB / 256), dim3(256), 0, s>>>(w.part, (int)nchg, w.G, gate_k, gate_n);
     GN_LAUNCH_CHECK();
-    double* Tb = Tout + (size_t)ob * QR_OB * QR_OB;
-    qr_merge_t<<<dim3(1), dim3(256), 0, s>>>(G, Tin, op, w, Tb, gate_k, gate_n);
+    double* Tb = w.Tout + (size_t)ob * QR_OB * QR_OB;
+    qr_merge_t<<<dim3(1), dim3(256), 0, s>>>(w.G, w.Tin, op, nbo, Tb, gate_k, gate_n);
     GN_LAUNCH_CHECK();
     // C2 <- (I - V T^T V^T) C2 on the columns past the block
-    GN_TRY(apply_block(Mp, C + J0 * ldc + J1, ldc, N - J1, Tb, 1));
+    GN_TRY(qr_apply_block(w, Mp, C + J0 * ldc + J1, ldc, N - J1, Tb, 1, gate_k, gate_n, s));
   }
-  // explicit Q: start from [I; 0] and apply the outer blocks right to left,
+  qr_extract_r<<<dim3((unsigned)cdiv(N * N, 256)), dim3(256), 0, s>>>(C, ldc, R, ldr, N, gate_k,
+                                                                     gate_n);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
+}
+
+gn_status launch_qr_form_q(int64_t M, int64_t N, const double* C, int64_t ldc, double* Q,
+                           int64_t ldq, double* ws, const int32_t* gate_k, hipStream_t s) {
+  if (M < N || M > QR_MAXROWS || N < 1) return GN_ERR_UNSUPPORTED;
+  const int64_t gate_n = N;
+  const QrPtrs w = qr_ptrs(M, N, ws);
+  const int64_t nob = cdiv(N, QR_OB);
+  // start from [I; 0] and apply the outer blocks right to left,
   // Q2 <- (I - V T V^T) Q2 on rows and columns J0..
   qr_init_q<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(Q, ldq, M, N, gate_k, gate_n);
   GN_LAUNCH_CHECK();
   for (int64_t ob = nob - 1; ob >= 0; --ob) {
     const int64_t J0 = ob * QR_OB, J1 = (J0 + QR_OB < N) ? J0 + QR_OB : N;
-    const int w = (int)(J1 - J0);
+    const int nbo = (int)(J1 - J0);
     const int64_t Mp = M - J0, nq = N - J0;
-    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, w, Vb, Vt,
-                                                                         gate_k, gate_n);
+    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, nbo, w.Vb,
+                                                                         w.Vt, gate_k, gate_n);
     GN_LAUNCH_CHECK();
-    GN_TRY(apply_block(Mp, Q + J0 * ldq + J0, ldq, nq, Tout + (size_t)ob * QR_OB * QR_OB, 0));
+    GN_TRY(qr_apply_block(w, Mp, Q + J0 * ldq + J0, ldq, nq, w.Tout + (size_t)ob * QR_OB * QR_OB, 0,
+                          gate_k, gate_n, s));
   }
-  qr_signfix<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(C, ldc, Q, ldq, R, ldr, M, N,
-                                                                   gate_k, gate_n);
+  qr_sign_q<<<dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s>>>(C, ldc, Q, ldq, M, N, gate_k,
+                                                                  gate_n);
   GN_LAUNCH_CHECK();
   return GN_OK;
+}
+
+gn_status launch_qr(int64_t M, int64_t N, double* C, int64_t ldc, double* Q, int64_t ldq, double* R,
+                    int64_t ldr, double* ws, const int32_t* gate_k, hipStream_t s) {
+  GN_TRY(launch_qr_factor(M, N, C, ldc, R, ldr, ws, gate_k, s));
+  return launch_qr_form_q(M, N, C, ldc, Q, ldq, ws, gate_k, s);
 }
 
 gn_status launch_truncate(int64_t r, const double* R, int64_t ldr, double tau, int32_t* k,

@@ -300,6 +300,29 @@ def test_apply_multiblock(G, rank):
         assert relerr(outl, OG.apply_left(ref.AX, ref.YA, ref.core, Wl)) <= 1e-10
 
 
+# ----------------------------------------------------------------------------- few-column products
+# FP32 factors (AX, Y^T A as the FP32 pass stores them): products with 1, 7 and 16
+# columns (rows) take the narrow-factor kernels -- K-contiguous and M-contiguous
+# left factors, several K slices with ragged ends -- and 17 the tiled kernel.  All
+# are checked against the materialized factors F, G (gn_factors: a separate path)
+# multiplied on the host in FP64.
+def test_apply_few_columns_f32(G):
+    m, n, r, l = 3000, 2500, 200, 100
+    A = W.spectrum_matrix(m, n, 0.97 ** np.arange(300), seed=33).astype(np.float32)
+    p = G.Problem(m, n, r, l, seed=23, mode="f32", eps=1e-6)
+    AX, YtA, core = G.solve(p, dev(A, torch.float32))
+    assert AX.dtype == torch.float32 and YtA.dtype == torch.float32
+    F, Gm = G.gn_factors(p, AX, YtA, core)
+    Fh, Gh = host(F), host(Gm)
+    for kc in (1, 7, 16, 17):
+        Wr = W.host_gaussian(n, kc, 50 + kc)
+        Wl = W.host_gaussian(kc, m, 51 + kc)
+        outr = host(G.gn_apply(p, 0, AX, YtA, core, dev(Wr)))
+        outl = host(G.gn_apply(p, 1, AX, YtA, core, dev(Wl)))
+        assert relerr(outr, Fh @ (Gh @ Wr)) <= 1e-10, kc
+        assert relerr(outl, (Wl @ Fh) @ Gh) <= 1e-10, kc
+
+
 # ----------------------------------------------------------------------------- larger cores
 # Core shapes that exercise every panel configuration of the QR (1 to 8 rows per
 # thread, panel widths 16 and 8) and the second QR of a truncated core.
