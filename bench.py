@@ -115,7 +115,7 @@ class Runner:
         ev[1].record()
         gn.gn_sketch_pass(p, self.A, self.ws, scales=self.scales, AX=self.AX, YtA=self.YtA)
         ev[2].record()
-        gn.gn_core(p, self.AX, out=self.core, ws=self.ws_core)
+        gn.gn_core(p, self.AX, out=self.core, ws=self.ws_core, YtA=self.YtA)
         ev[3].record()
         gn.gn_apply(p, 0, self.AX, self.YtA, self.core, self.W, out=self.out)
         ev[4].record()
@@ -175,7 +175,7 @@ def grad_bench(gn, W, steps=5, warmup=2):
 
     def fwd():
         gn.gn_sketch(p, A, AX=AX, YtA=YtA, ws=ws_s)
-        gn.gn_core(p, AX, out=core, ws=ws_c)
+        gn.gn_core(p, AX, out=core, ws=ws_c, YtA=YtA)
         gn.gn_materialize(p, AX, YtA, core, out=Ahat)
 
     def bwd(recompute):
@@ -295,7 +295,7 @@ def stabilize_bench(gn, run, steps=3, warmup=1):
         p = dataclasses.replace(run.p, core_method=method)
         ws = gn.workspace(p, gn.C.GN_OP_CORE)
         core = gn.new_core(p)
-        ms = timeit(lambda: gn.gn_core(p, run.AX, out=core, ws=ws))
+        ms = timeit(lambda: gn.gn_core(p, run.AX, out=core, ws=ws, YtA=run.YtA))
         F, G = gn.gn_factors(p, run.AX, run.YtA, core)
         e = math.sqrt(float(gn.gn_residual(run.A, F, G, scales=run.scales).item()))
         out["methods"][method] = {"core_ms": ms, "kept_rank": core.rank(),
@@ -304,7 +304,7 @@ def stabilize_bench(gn, run, steps=3, warmup=1):
         del F, G, ws, core
         torch.cuda.empty_cache()
     plain = dataclasses.replace(run.p, eps=0.0, core_method="qr")
-    core = gn.gn_core(plain, run.AX)
+    core = gn.gn_core(plain, run.AX, YtA=run.YtA)
     est = torch.zeros(1, dtype=torch.float64, device="cuda")
     ms = timeit(lambda: gn.gn_core_check(plain, core, run.p.eps, 8, 4, est=est))
     out["check"] = {"ms": ms, "start_vectors": 8, "iterations": 4,

@@ -222,10 +222,16 @@ gn_status gn_sketch(const gn_problem* p, const void* A, int64_t lda, const float
  * one-sided Jacobi (SVD, LIFT_SVD; r <= 4096); QR with column pivoting of R
  * followed by two QRs (LIFT_RRQR); or R's diagonal raised (LIFT_DIAG).  See
  * gn_core_out for what each leaves in `out`.  AX as produced by gn_sketch (ld
- * ldax).  The cost beyond the QR is O(r^3) for SVD / LIFT_SVD (a few sweeps of
- * r^3 rotations) and LIFT_RRQR (2 r launches for the pivot order, two QRs). */
-gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void* Y_user,
-                  int64_t ldy, const gn_core_out* out /*host struct of device ptrs*/, void* ws,
+ * ldax).  YtA (ld ldya >= n, 16-byte aligned) may be NULL; when it is given
+ * with an SRHT X in FP32 or BF16 mode, C is formed as (Y^T A) X instead: the
+ * r + l rows of Y^T A sign-flipped, Walsh-Hadamard transformed and sampled in
+ * FP64 (Section 2.3 costs the core this way, O(n (r + l) log n) instead of the
+ * O(m r (r + l)) product; Y is then not regenerated), and in every other case it
+ * is ignored.  The cost beyond the QR is O(r^3) for SVD / LIFT_SVD (a few sweeps
+ * of r^3 rotations) and LIFT_RRQR (2 r launches for the pivot order, two QRs). */
+gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void* YtA,
+                  int64_t ldya, const void* Y_user, int64_t ldy,
+                  const gn_core_out* out /*host struct of device ptrs*/, void* ws,
                   size_t ws_bytes, gn_stream_t stream);
 
 /* Section 5.1.2: check a core for the instability plain GN can show.  A power

@@ -18,6 +18,7 @@ What is computed, and where the paper defines it:
 
 Readings taken where the paper is silent or garbled:
   * the core is formed as Y^T (AX) (the order of the Section 5.1 MATLAB line);
+    core_right forms it as (Y^T A) X, the order Section 2.3 counts;
   * Householder QR without pivoting; R's diagonal made non-negative by flipping
     the matching columns of Q (the approximant does not depend on it);
   * truncation threshold tau = eps * nu_X * nu_Y on |R_ii|, with nu the sketch
@@ -145,7 +146,18 @@ def _qr_nonneg(M: np.ndarray):
 
 def core(AX: np.ndarray, Y: np.ndarray, tau: float) -> Core:
     """Core matrix, its QR and the epsilon-truncation (Alg. 2.1 step 2; Sec. 5.1.1)."""
-    C = Y.T @ AX
+    return core_of(Y.T @ AX, tau)
+
+
+def core_right(YA: np.ndarray, X: np.ndarray, tau: float) -> Core:
+    """The same with the core matrix formed as (Y^T A) X, the order the cost
+    count of Section 2.3 uses (a fast transform of the rows of Y^T A when X is
+    structured)."""
+    return core_of(YA @ X, tau)
+
+
+def core_of(C: np.ndarray, tau: float) -> Core:
+    """QR of a given core matrix C ((r+l) x r) and the epsilon-truncation."""
     r = C.shape[1]
     Q, R = _qr_nonneg(C)
     d = np.abs(np.diag(R))

@@ -90,8 +90,8 @@ def lib(path: str = LIB_PATH):
                                     c_void_p, c_size_t, c_void_p]
     L.gn_sketch_pass.argtypes = [P, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p,
                                  c_int64, c_void_p, c_size_t, c_void_p]
-    L.gn_core.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, POINTER(GnCoreOut), c_void_p,
-                          c_size_t, c_void_p]
+    L.gn_core.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                          POINTER(GnCoreOut), c_void_p, c_size_t, c_void_p]
     L.gn_core_check.argtypes = [P, POINTER(GnCoreOut), c_double, c_int32, c_int32, c_void_p,
                                 c_void_p, c_size_t, c_void_p]
     L.gn_factors.argtypes = [P, c_void_p, c_int64, c_void_p, c_int64, POINTER(GnCoreOut), c_void_p,

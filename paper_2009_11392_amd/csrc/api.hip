@@ -132,7 +132,7 @@ SketchWs sketch_ws(const Plan& P) {
 }
 
 struct CoreWs {
-  size_t yt, c, qr, z, qr2, split, q1, stab, total;
+  size_t yt, c, qr, z, qr2, split, q1, stab, signs, idx, keys, total;
 };
 CoreWs core_ws(const Plan& P) {
   CoreWs w{};
@@ -161,6 +161,15 @@ CoreWs core_ws(const Plan& P) {
   if (P.pinv_form) off += align_up((size_t)P.rl * P.r * 8);
   w.stab = off;
   off += align_up(stabilize_ws_bytes(P.method, P.r));
+  // SRHT signs and sampled columns for the core matrix as (Y^T A) X
+  w.signs = w.idx = w.keys = off;
+  if (P.kx == GN_SKETCH_SRHT && P.mode != GN_MODE_F64) {
+    off += align_up((size_t)P.npad);
+    w.idx = off;
+    off += align_up((size_t)P.r * 4);
+    w.keys = off;
+    off += align_up(srht_ws_bytes(P.npad));
+  }
   w.total = off;
   return w;
 }
@@ -462,8 +471,9 @@ gn_status gn_sketch(const gn_problem* p, const void* A, int64_t lda, const float
   return gn_sketch_pass(p, A, lda, A_scales, AX, ldax, YtA, ldya, ws, ws_bytes, stream);
 }
 
-gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void* Y_user, int64_t ldy,
-                  const gn_core_out* out, void* ws, size_t ws_bytes, gn_stream_t stream_) {
+gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void* YtA, int64_t ldya,
+                  const void* Y_user, int64_t ldy, const gn_core_out* out, void* ws,
+                  size_t ws_bytes, gn_stream_t stream_) {
   Plan P;
   GN_TRY(make_plan(p, P));
   hipStream_t s = (hipStream_t)stream_;
@@ -472,7 +482,8 @@ gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void*
   if (P.ky == GN_SKETCH_USER && !Y_user) return GN_ERR_ARG;
   if (ldax < P.r) return GN_ERR_SHAPE;
   if (P.ky == GN_SKETCH_USER && ldy < P.rl) return GN_ERR_SHAPE;
-  if (!aligned16(AX) || !aligned16(ws)) return GN_ERR_ALIGN;
+  if (YtA && ldya < P.n) return GN_ERR_SHAPE;
+  if (!aligned16(AX) || !aligned16(ws) || (YtA && !aligned16(YtA))) return GN_ERR_ALIGN;
   const CoreWs W = core_ws(P);
   if (ws_bytes < W.total) return GN_ERR_WORKSPACE;
   char* base = (char*)ws;
@@ -481,8 +492,16 @@ gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void*
 
   // C = Y^T (AX) (the order of the Section 5.1 evaluation): FP64 in F64 mode;
   // in F32 / BF16 modes on the FP32 matrix cores (the pass precision) with the
-  // K slices summed in FP64.
-  if (P.mode == GN_MODE_F64) {
+  // K slices summed in FP64.  With an SRHT X and Y^T A given (F32 / BF16 modes),
+  // C = (Y^T A) X instead, the order Section 2.3 costs: the r + l rows of Y^T A
+  // sign-flipped, Walsh-Hadamard transformed and sampled in FP64, with the signs
+  // and columns regenerated from the seed (bit-identical to the pass's).
+  if (YtA && P.kx == GN_SKETCH_SRHT && P.mode != GN_MODE_F64) {
+    int8_t* sg = (int8_t*)(base + W.signs);
+    int32_t* ix = (int32_t*)(base + W.idx);
+    GN_TRY(launch_srht(p->seed, P.npad, P.r, sg, ix, (uint64_t*)(base + W.keys), s));
+    GN_TRY(launch_srht_right(P.rl, P.n, P.r, (const float*)YtA, ldya, sg, ix, C, P.r, s));
+  } else if (P.mode == GN_MODE_F64) {
     MatRef yt;
     if (P.ky == GN_SKETCH_GAUSSIAN) {
       void* Yt = base + W.yt;

@@ -114,6 +114,11 @@ gn_status launch_srht(uint64_t seed, int64_t npad, int64_t r, int8_t* signs, int
 gn_status launch_transpose(const void* in, int64_t rows, int64_t cols, int64_t ldi, int32_t dtype,
                            void* out, int64_t ldo, hipStream_t s);
 size_t srht_ws_bytes(int64_t npad);
+// out (rows x r, FP64, ld ldo) = B D H S for B (rows x n, FP32, ld ldb), the SRHT
+// with the signs and sampled columns of launch_srht, transformed in FP64.
+gn_status launch_srht_right(int64_t rows, int64_t n, int64_t r, const float* B, int64_t ldb,
+                            const int8_t* signs, const int32_t* idx, double* out, int64_t ldo,
+                            hipStream_t s);
 // Batched row-major Gaussian blocks (rows x cols from (0, 0), stream sid, seed)
 // in GN_DT_F64 or GN_DT_F32.
 struct GaussJob {

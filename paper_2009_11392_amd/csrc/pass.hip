@@ -282,6 +282,16 @@ __global__ void __launch_bounds__(256) pass_f64_srht(SrhtArgs sr) {
   srht_rows<double, GN_MODE_F64, RPL>(sr, blockIdx.x, smem);
 }
 
+// B D H S for the rows of a row-major FP32 matrix B: the SRHT applied from the
+// right exactly as the pass applies it to A, with the transform and the sums in
+// FP64.  Gives the core matrix as (Y^T A) X for an SRHT X (Section 2.3's cost
+// model: a transform of the r + l rows of Y^T A instead of a product over m).
+template <int RPL>
+__global__ void __launch_bounds__(256) srht_right_f64(SrhtArgs sr) {
+  __shared__ __attribute__((aligned(16))) char smem[SR_SMEM_F64];
+  srht_rows<double, GN_MODE_F32, RPL>(sr, blockIdx.x, smem);
+}
+
 int srht_rpl(int64_t r) {
   const int64_t q = cdiv(r, 64);
   return q <= 1 ? 1 : q <= 2 ? 2 : q <= 4 ? 4 : q <= 8 ? 8 : q <= 16 ? 16 : q <= 32 ? 32 : 0;
@@ -462,6 +472,20 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
   return launch_bf16_cfg<BF16Pass>(srht, kSrhtFirst, kSrhtRows, m, n, r, rl,
                                    (const uint16_t*)A, lda, scales, (const uint16_t*)Xs,
                                    (const uint16_t*)Ys, sr, (float*)AX, ldax, (float*)YtA, ldya, s);
+}
+
+gn_status launch_srht_right(int64_t rows, int64_t n, int64_t r, const float* B, int64_t ldb,
+                            const int8_t* signs, const int32_t* idx, double* out, int64_t ldo,
+                            hipStream_t s) {
+  if (rows <= 0) return GN_OK;
+  // four waves, one row each
+  const SrhtArgs sr{4, rows, n, r, B, ldb, nullptr, 0, signs, idx, out, ldo};
+  const dim3 grid((unsigned)cdiv(rows, 4));
+#define GN_SRR(R) srht_right_f64<R><<<grid, dim3(256), 0, s>>>(sr)
+  GN_RPL_SWITCH(srht_rpl(r), GN_SRR);
+#undef GN_SRR
+  GN_LAUNCH_CHECK();
+  return GN_OK;
 }
 
 size_t pass_split_ws_bytes(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_t r,

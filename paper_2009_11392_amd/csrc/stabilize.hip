@@ -923,8 +923,12 @@ __device__ void power_solve(double* X, double* xtmp, int nv, int64_t k, int64_t 
 #pragma unroll
           for (int u = 0; u < 32; ++u)
             d[u] = FORWARD ? D[(u0 + u) * PB + j] : D[j * PB + u0 + u];
+          double xv[32];
 #pragma unroll
-          for (int u = 0; u < 32; ++u) acc = fma(d[u], xb[u0 + u], acc);
+          for (int u = 0; u < 32; ++u) xv[u] = xb[u0 + u];
+          __builtin_amdgcn_sched_barrier(0);  // every LDS read issued before the first use
+#pragma unroll
+          for (int u = 0; u < 32; ++u) acc = fma(d[u], xv[u], acc);
         }
       }
       xtmp[v * PB + j] = acc;
@@ -946,10 +950,14 @@ __device__ void power_solve(double* X, double* xtmp, int nv, int64_t k, int64_t 
 #pragma unroll 1
         for (int q = 0; q < nv; ++q) {
           const double* xq = X + q * kp + j0 + t0;
-          double a = 0.0;
+          double xv[32];
 #pragma unroll
-          for (int t = 0; t < 32; ++t) a = fma(u[t], xq[t], a);
-          X[q * kp + c] -= a;
+          for (int t = 0; t < 32; ++t) xv[t] = xq[t];
+          __builtin_amdgcn_sched_barrier(0);  // every LDS read issued before the first use
+          double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int t = 0; t < 32; ++t) a[t & 3] = fma(u[t], xv[t], a[t & 3]);
+          X[q * kp + c] -= (a[0] + a[1]) + (a[2] + a[3]);
         }
       }
     }

@@ -184,12 +184,16 @@ def new_core(p: Problem, device="cuda") -> CoreResult:
                       torch.empty(p.r, p.r, **f))
 
 
-def gn_core(p: Problem, AX: torch.Tensor, Y_user=None, out: CoreResult | None = None, ws=None):
-    _need_cuda(AX, Y_user)
+def gn_core(p: Problem, AX: torch.Tensor, Y_user=None, out: CoreResult | None = None, ws=None,
+            YtA: torch.Tensor | None = None):
+    """The core from AX (and Y^T A: with an SRHT X in FP32 / BF16 mode the core
+    matrix is then (Y^T A) X, see gn.h)."""
+    _need_cuda(AX, Y_user, YtA)
     out = new_core(p, AX.device) if out is None else out
     ws = workspace(p, C.GN_OP_CORE) if ws is None else ws
     pc, oc = p.c(), out.c()
-    C.check(C.lib().gn_core(ctypes.byref(pc), _ptr(AX), AX.stride(0), _ptr(Y_user),
+    C.check(C.lib().gn_core(ctypes.byref(pc), _ptr(AX), AX.stride(0), _ptr(YtA),
+                            YtA.stride(0) if YtA is not None else 0, _ptr(Y_user),
                             Y_user.stride(0) if Y_user is not None else 0, ctypes.byref(oc),
                             _ptr(ws), ws.numel(), _stream()), "gn_core")
     return out
@@ -274,7 +278,7 @@ def gn_quantize_bf16_bs(A: torch.Tensor):
 def solve(p: Problem, A: torch.Tensor, scales=None, X_user=None, Y_user=None):
     """Sketch pass + core: returns (AX, YtA, core)."""
     AX, YtA, _, _ = gn_sketch(p, A, scales=scales, X_user=X_user, Y_user=Y_user)
-    core = gn_core(p, AX, Y_user=Y_user)
+    core = gn_core(p, AX, Y_user=Y_user, YtA=YtA)
     return AX, YtA, core
 
 

@@ -118,8 +118,8 @@ def test_entry_points_reject_before_enqueue(lib):
                          1000, null, null, fake, 1 << 30, null) == C.GN_ERR_ARG
     # core output struct with a null member
     out = C.GnCoreOut(1 << 20, 0, 1 << 20, 1 << 20, 1 << 20, 1 << 20)
-    assert lib.gn_core(ctypes.byref(p), fake, 50, null, 0, ctypes.byref(out), fake, 1 << 30,
-                       null) == C.GN_ERR_ARG
+    assert lib.gn_core(ctypes.byref(p), fake, 50, null, 0, null, 0, ctypes.byref(out), fake,
+                       1 << 30, null) == C.GN_ERR_ARG
     assert lib.gn_apply(ctypes.byref(p), 3, fake, 50, fake, 1000, ctypes.byref(out), fake, 1, 1,
                         fake, 1, fake, 1 << 30, null) == C.GN_ERR_ARG
     good = C.GnCoreOut(1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20)

@@ -300,6 +300,25 @@ def test_apply_multiblock(G, rank):
         assert relerr(outl, OG.apply_left(ref.AX, ref.YA, ref.core, Wl)) <= 1e-10
 
 
+# ----------------------------------------------------------------------------- core as (Y^T A) X
+# FP32 pass with an SRHT X: gn_core given Y^T A forms the core matrix as
+# (Y^T A) X by the FP64 transform of Y^T A's rows; against the oracle's QR of
+# (Y^T A) X on the same FP32 sketch (widened), and products with both cores.
+def test_core_right_srht_f32(G):
+    m, n, r, l = 1500, 1200, 100, 50     # n' = 2048: four 512-column chunks, ragged
+    A = W.spectrum_matrix(m, n, 0.97 ** np.arange(300), seed=35).astype(np.float32)
+    p = G.Problem(m, n, r, l, kind_x="srht", seed=27, mode="f32", eps=1e-7)
+    AX, YtA, _, _ = G.gn_sketch(p, dev(A, torch.float32))
+    core = G.gn_core(p, AX, YtA=YtA)
+    ya = host(YtA)
+    ref = OG.core_right(ya, OP.srht_matrix(27, n, r), tau_of(p))
+    assert core.rank() == ref.k
+    assert relerr(host(core.R), ref.R) <= 1e-12
+    Wr = W.host_gaussian(n, 8, 61)
+    out = host(G.gn_apply(p, 0, AX, YtA, core, dev(Wr)))
+    assert relerr(out, OG.apply_right(host(AX), ya, ref, Wr)) <= 1e-10
+
+
 # ----------------------------------------------------------------------------- few-column products
 # FP32 factors (AX, Y^T A as the FP32 pass stores them): products with 1, 7 and 16
 # columns (rows) take the narrow-factor kernels -- K-contiguous and M-contiguous

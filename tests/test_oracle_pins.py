@@ -66,6 +66,26 @@ def test_p2_truncation_rank_exact():
     assert relerr(res.approx, sv) <= 1e-10
 
 
+def test_core_right_order_equals_left_order():
+    """(Y^T A) X = Y^T (A X): on integer data (exact in FP64) the two orders give
+    the same core matrix bit for bit, hence the same QR and kept rank; on a
+    graded matrix with an SRHT X the QR factors agree to rounding."""
+    rng = np.random.default_rng(3)
+    m, n, r, l = 60, 48, 9, 5
+    A = rng.integers(-3, 4, size=(m, n)).astype(np.float64)
+    X = rng.integers(-2, 3, size=(n, r)).astype(np.float64)
+    Y = rng.integers(-2, 3, size=(m, r + l)).astype(np.float64)
+    left, right = G.core(A @ X, Y, 1e-9), G.core_right(Y.T @ A, X, 1e-9)
+    assert np.array_equal(left.C, right.C)
+    assert np.array_equal(left.R, right.R) and left.k == right.k
+    w, _, Y2, tau = _small_setup()
+    A2 = W.spectrum_matrix(w.m, w.n, w.sigma(), seed=9)
+    X2 = philox.srht_matrix(5, w.n, w.r)
+    c1, c2 = G.core(A2 @ X2, Y2, tau), G.core_right(Y2.T @ A2, X2, tau)
+    assert c1.k == c2.k
+    assert relerr(c2.R, c1.R) <= 1e-12 and relerr(c2.Q, c1.Q) <= 1e-10
+
+
 # --------------------------------------------------------------------------- P3, P4
 def test_p3_p4_theorem_bounds(small):
     w, A, _, _, tau = small
