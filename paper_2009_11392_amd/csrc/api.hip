@@ -658,6 +658,25 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
   double* sp = (double*)(base + Wl.split);
   MatRef ax{AX, P.adt, ldax, 1};
   MatRef yta{YtA, P.adt, ldya, 1};
+  // few right-hand sides: the solve's preparation (block inverses, transposed
+  // factor; it needs only the core) runs on the side stream during the products
+  // that precede the solve
+  const bool few = kc <= small_solve_max_rhs();
+  std::unique_lock<std::mutex> lock(g_side_mu, std::defer_lock);
+  SideStream* ss = nullptr;
+  if (few) {
+    lock.lock();
+    GN_TRY(side_stream(&ss));
+    if (hipEventRecord(ss->fork, s) != hipSuccess ||
+        hipStreamWaitEvent(ss->s, ss->fork, 0) != hipSuccess)
+      return GN_ERR_HIP;
+    GN_TRY(launch_small_solve_prep(P.r, core->R, core->R2, core->k, P.pinv_form, base + Wl.solve,
+                                   ss->s));
+    if (hipEventRecord(ss->join, ss->s) != hipSuccess) return GN_ERR_HIP;
+  }
+  auto join = [&]() -> gn_status {
+    return hipStreamWaitEvent(s, ss->join, 0) == hipSuccess ? GN_OK : GN_ERR_HIP;
+  };
   if (side == 0) {
     // t1 = (Y^T A) W : rl x kc
     GN_TRY(launch_dgemm(P.rl, kc, P.n, 1.0, yta, MatRef{W, GN_DT_F64, ldw, 1}, 0.0, t1, kc, 1,
@@ -667,10 +686,11 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
                         MatRef{t1, GN_DT_F64, kc, 1}, 0.0, t2, kc, 1, core->k, true, s, nullptr,
                         0, true, sp, Wl.split_bytes));
     // t2 <- R^{-1} t2  or  R2^{-T} t2   (left solve on the transposed view)
-    if (kc <= small_solve_max_rhs())
+    if (few) {
+      GN_TRY(join());
       GN_TRY(launch_small_solve(P.r, core->R, core->R2, core->k, P.pinv_form, true, t2, kc, 1, kc,
                                 base + Wl.solve, s));
-    else
+    } else
       GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, 1, kc, true, true, s,
                               false, P.pinv_form));
     // t3 = t2 (k == r)  or  Q2 t2 (k < r)
@@ -690,10 +710,11 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
     GN_TRY(launch_dgemm(kc, P.r, P.r, 1.0, MatRef{t1, GN_DT_F64, P.r, 1},
                         MatRef{core->Q2, GN_DT_F64, P.r, 1}, 0.0, t2, P.r, 1, nullptr, false, s,
                         core->k, P.gate_r, true));
-    if (kc <= small_solve_max_rhs())
+    if (few) {
+      GN_TRY(join());
       GN_TRY(launch_small_solve(P.r, core->R, core->R2, core->k, P.pinv_form, false, t2, kc, P.r, 1,
                                 base + Wl.solve, s));
-    else
+    } else
       GN_TRY(launch_trsm_core(kc, P.r, core->R, core->R2, P.r, core->k, t2, P.r, 1, false, true, s,
                               false, P.pinv_form));
     // t3 = t2 Q1^T : kc x rl   (columns of t2 beyond k are zero)

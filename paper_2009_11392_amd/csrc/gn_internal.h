@@ -294,13 +294,17 @@ gn_status launch_rrqr_core(int64_t r, int64_t rl, const double* R, int64_t ldr, 
 gn_status launch_lift_diag(int64_t r, double* R, int64_t ldr, double tau, int32_t* k,
                            int32_t* status, hipStream_t s);
 size_t power_ws_bytes(int64_t r, int32_t nv);
-// X T = B for a few right-hand sides (rows of X, at most small_solve_max_rhs() is the
-// intended use): the same triangle and gating as launch_trsm_core (left product:
-// T = R^T, or R2 when truncated or forced; right product: T = R, or R2^T), solved by
-// one workgroup per group of right-hand sides held in LDS with inverted diagonal
-// blocks.  ws: small_solve_ws_bytes(r).
+// X T = B for at most small_solve_max_rhs() right-hand sides (rows of X): the same
+// triangle and gating as launch_trsm_core (left product: T = R^T, or R2 when
+// truncated or forced; right product: T = R, or R2^T), solved with inverted 64 x 64
+// diagonal blocks, one launch per block, the off-diagonal updates spread over
+// workgroups.  launch_small_solve_prep (the block inverses and the transposed
+// factor, from R, R2 and k only) must precede launch_small_solve on the same ws,
+// possibly from another stream.  ws: small_solve_ws_bytes(r).
 size_t small_solve_ws_bytes(int64_t r);
 int64_t small_solve_max_rhs();
+gn_status launch_small_solve_prep(int64_t r, const double* R, const double* R2, const int32_t* k,
+                                  bool force, void* ws, hipStream_t s);
 gn_status launch_small_solve(int64_t r, const double* R, const double* R2, const int32_t* k,
                              bool force, bool left, double* X, int64_t nrhs, int64_t rsx,
                              int64_t csx, void* ws, hipStream_t s);

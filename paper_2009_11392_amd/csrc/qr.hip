@@ -906,34 +906,62 @@ __global__ void __launch_bounds__(256) qr_merge_t(const double* __restrict__ G,
   __shared__ double Gs[QR_OB][QR_OB + 1];
   __shared__ double Y[QR_OB][QR_NB + 1];
   const int tid = threadIdx.x;
-  for (int e = tid; e < QR_OB * QR_OB; e += 256) {
+  // G and every panel's T loaded up front (all loads in flight at once)
+  constexpr int kG = QR_OB * QR_OB / 256;
+  double gv[kG];
+#pragma unroll
+  for (int q = 0; q < kG; ++q) gv[q] = G[tid + 256 * q];
+  double tv[QR_OB / 8];
+#pragma unroll
+  for (int b = 0; b < QR_OB / 8; ++b) {
+    const int wb = (b < op.count) ? op.width[b] : 0;
+    tv[b] = (tid < wb * wb)
+                ? Tpanels[(size_t)op.tidx[b] * QR_NB * QR_NB + (tid / wb) * QR_NB + tid % wb]
+                : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < kG; ++q) {
+    const int e = tid + 256 * q;
     T[e / QR_OB][e % QR_OB] = 0.0;
-    Gs[e / QR_OB][e % QR_OB] = G[e];
+    Gs[e / QR_OB][e % QR_OB] = gv[q];
   }
   __syncthreads();
-  for (int b = 0; b < op.count; ++b) {
+#pragma unroll
+  for (int b = 0; b < QR_OB / 8; ++b) {
+    const int wb = (b < op.count) ? op.width[b] : 0;
+    if (tid < wb * wb) T[op.off[b] + tid / wb][op.off[b] + tid % wb] = tv[b];
+  }
+  __syncthreads();
+  // T[0:o, o:o+wb] = -T_a (V_a^T V_b) T_b for each later panel, in order; the dot
+  // products are split over four partial sums
+  for (int b = 1; b < op.count; ++b) {
     const int o = op.off[b], wb = op.width[b];
-    const double* Tb = Tpanels + (size_t)op.tidx[b] * QR_NB * QR_NB;
-    for (int e = tid; e < wb * wb; e += 256) T[o + e / wb][o + e % wb] = Tb[(e / wb) * QR_NB + e % wb];
-    __syncthreads();
-    if (o > 0) {
-      // Y = T_a G[0:o, o:o+wb]   (o x wb)
-      for (int e = tid; e < o * wb; e += 256) {
-        const int i = e / wb, j = e % wb;
-        double acc = 0.0;
-        for (int l = i; l < o; ++l) acc = fma(T[i][l], Gs[l][o + j], acc);
-        Y[i][j] = acc;
+    // Y = T_a G[0:o, o:o+wb]   (o x wb)
+    for (int e = tid; e < o * wb; e += 256) {
+      const int i = e / wb, j = e % wb;
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};
+      int l = i;
+      for (; l + 3 < o; l += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a4[u] = fma(T[i][l + u], Gs[l + u][o + j], a4[u]);
       }
-      __syncthreads();
-      // T[0:o, o:o+wb] = -Y T_b
-      for (int e = tid; e < o * wb; e += 256) {
-        const int i = e / wb, j = e % wb;
-        double acc = 0.0;
-        for (int l = 0; l <= j; ++l) acc = fma(Y[i][l], T[o + l][o + j], acc);
-        T[i][o + j] = -acc;
-      }
-      __syncthreads();
+      for (; l < o; ++l) a4[0] = fma(T[i][l], Gs[l][o + j], a4[0]);
+      Y[i][j] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
     }
+    __syncthreads();
+    // T[0:o, o:o+wb] = -Y T_b
+    for (int e = tid; e < o * wb; e += 256) {
+      const int i = e / wb, j = e % wb;
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};
+      int l = 0;
+      for (; l + 3 <= j; l += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a4[u] = fma(Y[i][l + u], T[o + l + u][o + j], a4[u]);
+      }
+      for (; l <= j; ++l) a4[0] = fma(Y[i][l], T[o + l][o + j], a4[0]);
+      T[i][o + j] = -((a4[0] + a4[1]) + (a4[2] + a4[3]));
+    }
+    __syncthreads();
   }
   for (int e = tid; e < QR_OB * QR_OB; e += 256) {
     const int i = e / QR_OB, j = e % QR_OB;

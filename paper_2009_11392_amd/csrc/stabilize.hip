@@ -1012,46 +1012,104 @@ __global__ void __launch_bounds__(kPowerThreads) power_iterate(const double* __r
   if (threadIdx.x == 0) *est = best;
 }
 
-// Triangular solve for a few right-hand sides (the columns of a factored product):
-// right-hand side v of this workgroup is entry i of row v0 + v of Xg, i.e.
-// Xg[(v0 + v) rsx + i csx], held in LDS (rows padded to a multiple of 64) and
-// solved with the same blocked substitution as the check.  The factor and the
-// direction follow the kept rank on the device: U = R2 when truncated (or forced)
-// and R otherwise; a left product solves U x = b with U = R and U^T x = b with
-// U = R2, a right product the other way round.  Entries at or beyond the kept
-// size come back zero.
-__global__ void __launch_bounds__(kPowerThreads) small_solve(const double* __restrict__ R,
-                                                             const double* __restrict__ R2,
-                                                             int64_t r, const int32_t* kdev,
-                                                             int force, int left,
-                                                             const double* __restrict__ Dinv,
-                                                             const double* __restrict__ Ut,
-                                                             double* __restrict__ Xg, int64_t nrhs,
-                                                             int64_t rsx, int64_t csx, int nvwg) {
-  __shared__ double X[kPowerLds];
-  __shared__ double xtmp[16 * PB];
+// Triangular solve for a few right-hand sides (the columns of a factored product),
+// spread over workgroups with one launch per 64-row block of the factor, in the
+// order the direction gives.  Right-hand side v is entry i of row v of Xg, i.e.
+// Xg[v rsx + i csx].  The factor and the direction follow the kept rank on the
+// device: U = R2 when truncated (or forced) and R otherwise; a left product
+// solves U x = b with U = R and U^T x = b with U = R2, a right product the other
+// way round.  In launch `step` every workgroup forms the block's unknowns x_b from
+// the block's right-hand sides with the block's inverse (the same blocked
+// substitution as the check), workgroup 0 stores them in S (v * r + i), and each
+// workgroup subtracts their contribution from its own 64 of the right-hand-side
+// rows still to be solved.  msolve_finish copies S back, zero at and beyond the
+// kept size.
+constexpr int MS_T = 256, MS_NV = 32;
+
+__global__ void __launch_bounds__(MS_T) msolve_step(const double* __restrict__ R,
+                                                    const double* __restrict__ R2, int64_t r,
+                                                    const int32_t* kdev, int force, int left,
+                                                    const double* __restrict__ Dinv,
+                                                    const double* __restrict__ Ut,
+                                                    double* __restrict__ Xg, int nrhs, int64_t rsx,
+                                                    int64_t csx, double* __restrict__ S, int step) {
+  __shared__ double rb[PB][MS_NV + 1];  // the block's right-hand sides, then its unknowns
+  __shared__ double Ds[PB][PB + 1];     // the block's inverse
   int64_t k;
   bool use2;
   const double* U = power_factor(R, R2, r, kdev, force, k, use2);
   const bool fwd = left ? use2 : !use2;
-  const int64_t kp = cdiv_d(k, PB) * PB;
-  const int64_t v0 = (int64_t)blockIdx.x * nvwg;
-  const int nv = (int)((nrhs - v0 < nvwg) ? nrhs - v0 : nvwg);
-  for (int64_t e = threadIdx.x; e < (int64_t)nv * kp; e += kPowerThreads) {
-    const int64_t v = e / kp, i = e - v * kp;
-    X[e] = (i < k) ? Xg[(v0 + v) * rsx + i * csx] : 0.0;
+  const int nblk = (int)cdiv_d(k, PB);
+  if (step >= nblk) return;
+  const int b = fwd ? step : nblk - 1 - step;
+  const int64_t j0 = (int64_t)b * PB;
+  const int w = (int)((k - j0 < PB) ? (k - j0) : PB);
+  const int64_t c_lo = fwd ? j0 + w : 0, c_hi = fwd ? k : j0;
+  const int64_t c0 = c_lo + (int64_t)blockIdx.x * PB;
+  if (blockIdx.x > 0 && c0 >= c_hi) return;
+  const int tid = threadIdx.x, j = tid % PB, grp = tid / PB;
+  constexpr int NG = MS_T / PB;          // right-hand-side groups
+  constexpr int NVT = MS_NV / NG;        // right-hand sides per thread
+  // every global load first: this workgroup's strip of U (rows j0 .. j0 + w of the
+  // factor, columns c0 + j; forward U[j0 + t][c], backward U[c][j0 + t] = Ut[j0 + t][c];
+  // read in range, zeroed past w), the block's right-hand sides (zero past the
+  // kept size) and the block's inverse (the identity past the kept size)
+  const int64_t c = c0 + j;
+  const int64_t cc = (c < c_hi) ? c : ((c_hi > 0) ? c_hi - 1 : 0);
+  const double* Ub = fwd ? U : Ut;
+  double u[PB];
+#pragma unroll
+  for (int t = 0; t < PB; ++t) u[t] = Ub[(j0 + (t < w ? t : w - 1)) * r + cc];
+  for (int e = tid; e < PB * MS_NV; e += MS_T) {
+    const int t = e / MS_NV, v = e % MS_NV;
+    rb[t][v] = (t < w && v < nrhs) ? Xg[v * rsx + (j0 + t) * csx] : 0.0;
   }
+  const double* D = Dinv + (int64_t)b * PB * PB;
+  for (int e = tid; e < PB * PB; e += MS_T) Ds[e / PB][e % PB] = D[e];
   __syncthreads();
-  if (k > 0) {
-    if (fwd)
-      power_solve<true>(X, xtmp, nv, k, r, U, Ut, Dinv);
-    else
-      power_solve<false>(X, xtmp, nv, k, r, U, Ut, Dinv);
+  // x_j = sum_u D[u][j] b_u (forward, D^T b) or sum_u D[j][u] b_u (backward)
+  double x[NVT];
+#pragma unroll
+  for (int q = 0; q < NVT; ++q) {
+    const int v = grp + NG * q;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int uu = 0; uu < PB; ++uu)
+      a4[uu & 3] = fma(fwd ? Ds[uu][j] : Ds[j][uu], rb[uu][v], a4[uu & 3]);
+    x[q] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   }
-  for (int64_t e = threadIdx.x; e < (int64_t)nv * r; e += kPowerThreads) {
-    const int64_t v = e / r, i = e - v * r;
-    Xg[(v0 + v) * rsx + i * csx] = (i < k) ? X[v * kp + i] : 0.0;
+  __syncthreads();  // every thread has read the right-hand sides
+#pragma unroll
+  for (int q = 0; q < NVT; ++q) rb[j][grp + NG * q] = x[q];
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int e = tid; e < PB * MS_NV; e += MS_T) {
+      const int t = e / MS_NV, v = e % MS_NV;
+      if (t < w && v < nrhs) S[(int64_t)v * r + j0 + t] = rb[t][v];
+    }
   }
+  if (c0 >= c_hi) return;
+  // rows c0 .. c0 + 63 of the remaining right-hand sides take the block's part:
+  // forward  b_c -= sum_t U[j0 + t][c] x_t,  backward  b_c -= sum_t U[c][j0 + t] x_t
+#pragma unroll
+  for (int t = 0; t < PB; ++t) u[t] = (t < w) ? u[t] : 0.0;
+  for (int v = grp; v < nrhs; v += NG) {
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < PB; ++t) a4[t & 3] = fma(u[t], rb[t][v], a4[t & 3]);
+    if (c < c_hi) Xg[v * rsx + c * csx] -= (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  }
+}
+
+__global__ void __launch_bounds__(256) msolve_finish(int64_t r, const int32_t* kdev,
+                                                     double* __restrict__ Xg, int nrhs,
+                                                     int64_t rsx, int64_t csx,
+                                                     const double* __restrict__ S) {
+  const int64_t k = (*kdev < r) ? *kdev : r;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)nrhs * r) return;
+  const int64_t v = e / r, i = e - v * r;
+  Xg[v * rsx + i * csx] = (i < k) ? S[e] : 0.0;
 }
 
 // ---------------------------------------------------------------------------- Jacobi driver
@@ -1252,29 +1310,45 @@ gn_status launch_lift_diag(int64_t r, double* R, int64_t ldr, double tau, int32_
 }
 
 size_t small_solve_ws_bytes(int64_t r) {
-  return align_up((size_t)cdiv(r, PB) * PB * PB * 8) + align_up((size_t)r * r * 8);
+  return align_up((size_t)cdiv(r, PB) * PB * PB * 8) + align_up((size_t)r * r * 8) +
+         align_up((size_t)MS_NV * r * 8);
 }
 
-int64_t small_solve_max_rhs() { return 32; }
+int64_t small_solve_max_rhs() { return MS_NV; }
 
-gn_status launch_small_solve(int64_t r, const double* R, const double* R2, const int32_t* k,
-                             bool force, bool left, double* X, int64_t nrhs, int64_t rsx,
-                             int64_t csx, void* ws, hipStream_t s) {
-  if (nrhs <= 0) return GN_OK;
-  const int64_t kpmax = cdiv(r, PB) * PB;
-  if (kpmax > kPowerLds) return GN_ERR_UNSUPPORTED;
+gn_status launch_small_solve_prep(int64_t r, const double* R, const double* R2, const int32_t* k,
+                                  bool force, void* ws, hipStream_t s) {
+  const size_t dbytes = align_up((size_t)cdiv(r, PB) * PB * PB * 8);
   double* Dinv = (double*)ws;
-  double* Ut = (double*)((char*)ws + align_up((size_t)cdiv(r, PB) * PB * PB * 8));
+  double* Ut = (double*)((char*)ws + dbytes);
   power_block_inverse<<<dim3((unsigned)cdiv(r, PB)), dim3(PB), 0, s>>>(R, R2, r, k, force ? 1 : 0,
                                                                        Dinv);
   GN_LAUNCH_CHECK();
   power_transpose<<<dim3((unsigned)cdiv(r, 32), (unsigned)cdiv(r, 32)), dim3(256), 0, s>>>(
       R, R2, r, k, force ? 1 : 0, Ut);
   GN_LAUNCH_CHECK();
-  int nvwg = (int)(kPowerLds / kpmax);
-  if (nvwg > 16) nvwg = 16;
-  small_solve<<<dim3((unsigned)cdiv(nrhs, nvwg)), dim3(kPowerThreads), 0, s>>>(
-      R, R2, r, k, force ? 1 : 0, left ? 1 : 0, Dinv, Ut, X, nrhs, rsx, csx, nvwg);
+  return GN_OK;
+}
+
+gn_status launch_small_solve(int64_t r, const double* R, const double* R2, const int32_t* k,
+                             bool force, bool left, double* X, int64_t nrhs, int64_t rsx,
+                             int64_t csx, void* ws, hipStream_t s) {
+  if (nrhs <= 0) return GN_OK;
+  if (nrhs > MS_NV) return GN_ERR_UNSUPPORTED;
+  const size_t dbytes = align_up((size_t)cdiv(r, PB) * PB * PB * 8);
+  const double* Dinv = (const double*)ws;
+  const double* Ut = (const double*)((char*)ws + dbytes);
+  double* S = (double*)((char*)ws + dbytes + align_up((size_t)r * r * 8));
+  // one launch per block of the largest kept size; launches past the kept
+  // size's blocks return at once
+  const int nb = (int)cdiv(r, PB);
+  for (int st = 0; st < nb; ++st) {
+    msolve_step<<<dim3((unsigned)nb), dim3(MS_T), 0, s>>>(R, R2, r, k, force ? 1 : 0, left ? 1 : 0,
+                                                          Dinv, Ut, X, (int)nrhs, rsx, csx, S, st);
+    GN_LAUNCH_CHECK();
+  }
+  msolve_finish<<<dim3((unsigned)cdiv(nrhs * r, 256)), dim3(256), 0, s>>>(r, k, X, (int)nrhs, rsx,
+                                                                        csx, S);
   GN_LAUNCH_CHECK();
   return GN_OK;
 }
