@@ -16,6 +16,8 @@
 //     H_{n'} = H_{n'/512} (x) H_512.
 // FP64 mode (the parity mode) runs the same SRHT body and the FP64 strided GEMM
 // as separate launches.
+#include <type_traits>
+
 #include "gemm_tiles.h"
 
 namespace gn {
@@ -78,6 +80,62 @@ __device__ __forceinline__ void srht_load8(const SrhtArgs& a, int64_t i, int64_t
   }
 }
 
+// Orders this wave's LDS accesses (a wave-scope fence): enough where a wave
+// stores to and reads from LDS that no other wave touches.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The 32-bit word of lane `lane ^ LM` (LM a power of two below 64) by lane moves
+// that stay out of LDS: DPP copies within a row (xor 4 as the mirror of eight lanes
+// followed by the mirror of four) and the gfx950 row and half-wave swaps.
+template <int LM>
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int lane) {
+  if constexpr (LM == 1) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+  } else if constexpr (LM == 2) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+  } else if constexpr (LM == 4) {
+    const int m = __builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, false);      // quad_perm 3,2,1,0
+  } else if constexpr (LM == 8) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (LM == 16) {
+    // odd rows of the first operand trade places with even rows of the second
+    const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane & 16) ? (uint32_t)p[0] : (uint32_t)p[1];
+  } else {
+    // the upper half of the first operand trades places with the lower half of the second
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32) ? (uint32_t)p[0] : (uint32_t)p[1];
+  }
+}
+
+template <int LM>
+__device__ __forceinline__ float xor_lane(float v, int lane) {
+  return __uint_as_float(xor_lane_u32<LM>(__float_as_uint(v), lane));
+}
+template <int LM>
+__device__ __forceinline__ double xor_lane(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = xor_lane_u32<LM>((uint32_t)b, lane);
+  const uint32_t hi = xor_lane_u32<LM>((uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One Walsh-Hadamard stage across lanes: lane pairs (l, l ^ LM), the lower lane
+// keeping the sum and the upper the difference (lower minus upper).
+template <int LM, typename T>
+__device__ __forceinline__ void srht_stage(T (&x)[8], int lane) {
+  const bool upper = (lane & LM) != 0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const T y = xor_lane<LM>(x[e], lane);
+    x[e] = upper ? (y - x[e]) : (x[e] + y);
+  }
+}
+
 // Rows [local * rows_per_wg, ...) of AX = A D H S.  Each wave owns one row at a
 // time (rows advance by the number of waves per step); at most 16 waves.
 template <typename T, int MODE, int RPL>
@@ -96,37 +154,42 @@ __device__ void srht_rows(const SrhtArgs& a, int64_t local, char* smem) {
     s_lo[t] = sv & (SR_CHUNK - 1);
     s_hi[t] = sv >> 9;
   }
+  // one chunk's entries of row i (as loaded: float, or double in FP64 mode) and
+  // their signs; the loop below keeps the next chunk's loads in flight while it
+  // transforms the current one
+  using L = typename std::conditional<MODE == GN_MODE_F64, double, float>::type;
+  auto load_chunk = [&](int64_t i, int64_t j0, L (&xl)[8], uint64_t& sg) {
+    const int64_t j = j0 + 8 * lane;
+    if constexpr (MODE == GN_MODE_F64) {
+      const double* row = reinterpret_cast<const double*>(a.A) + i * a.lda;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xl[e] = (j + e < a.n) ? row[j + e] : 0.0;
+    } else {
+      srht_load8<MODE>(a, i, j, xl);
+    }
+    sg = 0;
+    if (j + 7 < a.n) {
+      sg = *reinterpret_cast<const uint64_t*>(a.signs + j);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (j + e < a.n) sg |= (uint64_t)(uint8_t)a.signs[j + e] << (8 * e);
+    }
+  };
   for (int64_t ib = row_begin; ib < row_end; ib += nw) {
     const int64_t i = ib + wave;
     const bool active = i < row_end;
     T acc[RPL];
 #pragma unroll
     for (int t = 0; t < RPL; ++t) acc[t] = (T)0;
-    for (int64_t j0 = 0; j0 < a.n; j0 += SR_CHUNK) {
-      const int64_t j = j0 + 8 * lane;
+    // one chunk: sign flips, H_512, and the sampled columns added with the sign of
+    // the outer factor
+    auto process = [&](const L (&xl)[8], uint64_t sg, int64_t j0) {
       T x[8];
       if (active) {
-        if constexpr (MODE == GN_MODE_F64) {
-          const double* row = reinterpret_cast<const double*>(a.A) + i * a.lda;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) x[e] = (j + e < a.n) ? row[j + e] : 0.0;
-        } else {
-          float xf[8];
-          srht_load8<MODE>(a, i, j, xf);
-#pragma unroll
-          for (int e = 0; e < 8; ++e) x[e] = xf[e];
-        }
         // D: Rademacher sign flips (entries beyond n are already zero)
-        uint64_t sg = 0;
-        if (j + 7 < a.n) {
-          sg = *reinterpret_cast<const uint64_t*>(a.signs + j);
-        } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (j + e < a.n) sg |= (uint64_t)(uint8_t)a.signs[j + e] << (8 * e);
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = flip_if(x[e], (uint32_t)((sg >> (8 * e + 7)) & 1u));
+        for (int e = 0; e < 8; ++e) x[e] = flip_if((T)xl[e], (uint32_t)((sg >> (8 * e + 7)) & 1u));
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = (T)0;
@@ -142,25 +205,36 @@ __device__ void srht_rows(const SrhtArgs& a, int64_t local, char* smem) {
             x[e | h] = u - v;
           }
       // widths 8 .. 256 across lanes (lane xor 1 .. 32)
-#pragma unroll
-      for (int lm = 1; lm < 64; lm <<= 1) {
-        const bool upper = (lane & lm) != 0;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const T y = __shfl_xor(x[e], lm, 64);
-          x[e] = upper ? (y - x[e]) : (x[e] + y);
-        }
-      }
+      srht_stage<1>(x, lane);
+      srht_stage<2>(x, lane);
+      srht_stage<4>(x, lane);
+      srht_stage<8>(x, lane);
+      srht_stage<16>(x, lane);
+      srht_stage<32>(x, lane);
 #pragma unroll
       for (int e = 0; e < 8; ++e) slot[wave][8 * lane + e] = x[e];
-      __syncthreads();
+      // the slot is this wave's own: its LDS operations complete in order, so
+      // ordering within the wave is enough (no workgroup barrier, waves drift)
+      wave_lds_fence();
       const uint32_t chunk = (uint32_t)(j0 >> 9);
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const T v = slot[wave][s_lo[t]];
         acc[t] += flip_if(v, (uint32_t)(__popc(chunk & (uint32_t)s_hi[t]) & 1));
       }
-      __syncthreads();
+      wave_lds_fence();  // the gathers are done before the next chunk's stores
+    };
+    // the next chunk's loads are in flight while this one is transformed
+    L xn[8];
+    uint64_t sgn = 0;
+    if (active) load_chunk(i, 0, xn, sgn);
+    for (int64_t j0 = 0; j0 < a.n; j0 += SR_CHUNK) {
+      L xc[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xc[e] = xn[e];
+      const uint64_t sc = sgn;
+      if (active && j0 + SR_CHUNK < a.n) load_chunk(i, j0 + SR_CHUNK, xn, sgn);
+      process(xc, sc, j0);
     }
     if (active) {
       T* out = reinterpret_cast<T*>(a.AX) + i * a.ldax;
