@@ -154,8 +154,13 @@ CoreWs core_ws(const Plan& P) {
   w.qr2 = off;
   off += qr_ws_bytes(P.r, P.r);
   w.split = off;
-  off += (P.mode == GN_MODE_F64) ? dgemm_split_ws_bytes(P.rl, P.r, P.m)
-                                 : core_product_ws_bytes(P.m, P.rl, P.r);
+  if (P.mode == GN_MODE_F64) {
+    off += dgemm_split_ws_bytes(P.rl, P.r, P.m);
+  } else {
+    const size_t a = core_product_ws_bytes(P.m, P.rl, P.r);
+    const size_t b = (P.mode == GN_MODE_BF16_BS) ? core_product_bf16_ws_bytes(P.m, P.rl, P.r) : 0;
+    off += a > b ? a : b;
+  }
   // the QR's Q before the SVD / pivoting turns it into Q1, and that method's scratch
   w.q1 = off;
   if (P.pinv_form) off += align_up((size_t)P.rl * P.r * 8);
@@ -491,8 +496,8 @@ gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void*
   double* Z = (double*)(base + W.z);
 
   // C = Y^T (AX) (the order of the Section 5.1 evaluation): FP64 in F64 mode;
-  // in F32 / BF16 modes on the FP32 matrix cores (the pass precision) with the
-  // K slices summed in FP64.  With an SRHT X and Y^T A given (F32 / BF16 modes),
+  // in F32 mode (and BF16 mode with a user Y) on the FP32 matrix cores (the pass
+  // precision), in BF16 mode on the BF16 matrix cores, the K slices summed in FP64.  With an SRHT X and Y^T A given (F32 / BF16 modes),
   // C = (Y^T A) X instead, the order Section 2.3 costs: the r + l rows of Y^T A
   // sign-flipped, Walsh-Hadamard transformed and sampled in FP64, with the signs
   // and columns regenerated from the seed (bit-identical to the pass's).
@@ -513,6 +518,13 @@ gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void*
     MatRef ax{AX, P.adt, ldax, 1};
     GN_TRY(launch_dgemm(P.rl, P.r, P.m, 1.0, yt, ax, 0.0, C, P.r, 1, nullptr, false, s, nullptr,
                         0, true, (double*)(base + W.split), W.total - W.split));
+  } else if (P.mode == GN_MODE_BF16_BS && P.ky == GN_SKETCH_GAUSSIAN) {
+    // BF16 mode: Y's bfloat16 values (transposed, as the pass reads them) on the
+    // BF16 matrix cores, AX in two bfloat16 terms
+    uint16_t* Yt = (uint16_t*)(base + W.yt);
+    GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, GN_DT_BF16, 1, Yt, P.m, s));
+    GN_TRY(launch_core_product_bf16(P.m, P.rl, P.r, Yt, (const float*)AX, ldax, base + W.split, C,
+                                    s));
   } else {
     const float* Yf;
     int64_t ldyf;

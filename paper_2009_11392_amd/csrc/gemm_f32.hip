@@ -5,6 +5,8 @@
 //     along K when there are too few output tiles to fill the chip (slices
 //     written to their own partials and summed in slice order, in FP64, then
 //     rounded once: deterministic);
+//   * the core product of the BF16 mode on the BF16 matrix cores (Y is stored as
+//     bfloat16 values, AX split into two bfloat16 terms);
 //   * bfloat16 -> float widening of user sketches.
 #include "gn_internal.h"
 #include "gemm_tiles.h"
@@ -28,6 +30,63 @@ __global__ void __launch_bounds__(CoreCfg::T) core_product_f32(GemmF32 g, int64_
   gs.D = g.D + s * g.M * g.N;
   if (gs.K <= 0) return;
   f32_tile_cfg<CoreCfg, false, false, VEC>(gs, blockIdx.x, smem);
+}
+
+// ------------------------------------------------------------------ BF16 core product
+// In BF16 mode Y holds bfloat16 values, so C = Y^T (AX) runs on the BF16 matrix
+// cores: AX (FP32) is split into two bfloat16 terms, AX = hi + lo with hi =
+// bf16(AX) and lo = bf16(AX - hi) (16 significant bits: the representation error,
+// below 2^-17 |AX|, is far under the BF16 pass's own), and C = Y^T hi + Y^T lo
+// with FP32 accumulation, K = m split into slices; the 2 x slices partial
+// products are summed in FP64 in a fixed order.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ void __launch_bounds__(256) split_bf16x2(const float* __restrict__ AX, int64_t ldax,
+                                                    int64_t m, int64_t r, uint16_t* __restrict__ hi,
+                                                    uint16_t* __restrict__ lo) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= m * r) return;
+  const int64_t i = e / r, j = e - i * r;
+  const float x = AX[i * ldax + j];
+  const uint16_t h = f32_to_bf16_rne(x);
+  hi[e] = h;
+  lo[e] = f32_to_bf16_rne(x - bf16_bits_to_f32(h));  // the difference is exact in FP32
+}
+
+__global__ void __launch_bounds__(256) fill_f32(float* p, int64_t n, float v) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
+// slice blockIdx.y of K (length kslice), term blockIdx.z (0: hi, 1: lo) to
+// partial + (2 slice + term) M N
+__global__ void __launch_bounds__(BF16Pass::T) core_product_bf16(GemmBF16 g, int64_t kslice,
+                                                                 const uint16_t* hi,
+                                                                 const uint16_t* lo,
+                                                                 float* partial) {
+  __shared__ __attribute__((aligned(16))) char smem[BF16Pass::smem()];
+  const int64_t sl = blockIdx.y, term = blockIdx.z;
+  const int64_t k0 = sl * kslice;
+  GemmBF16 gs = g;
+  gs.K = (k0 + kslice < g.K) ? kslice : g.K - k0;
+  if (gs.K <= 0) return;
+  gs.A = g.A + k0;
+  gs.B = (term ? lo : hi) + k0 * g.ldb;
+  gs.D = partial + (2 * sl + term) * g.M * g.N;
+  bf16_tile_cfg<BF16Pass, true, false>(gs, blockIdx.x, smem);
+}
+
+__global__ void __launch_bounds__(256) core_product_sum2(const float* partial, int64_t nslice,
+                                                         int64_t mn, double* C) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mn) return;
+  double acc = 0.0;
+  for (int64_t q = 0; q < nslice; ++q)
+    acc += (double)partial[2 * q * mn + e] + (double)partial[(2 * q + 1) * mn + e];
+  C[e] = acc;
 }
 
 __global__ void __launch_bounds__(256) core_product_sum(const float* partial, int64_t nslice,
@@ -134,6 +193,66 @@ gn_status launch_splitk_sum_f32(const float* partial, int64_t nslice, int64_t M,
 
 size_t core_product_ws_bytes(int64_t m, int64_t rl, int64_t r) {
   return align_up((size_t)core_slices(m, rl, r) * rl * r * sizeof(float));
+}
+
+// K slices of the BF16 core product: about 512 workgroups over the two terms, slices
+// at least 1024 long and a multiple of 128, at most 16.
+struct Bf16CoreLayout {
+  int64_t kslice, nslice, nsb;
+  size_t hi, lo, ones, partial, total;
+};
+static Bf16CoreLayout bf16_core_layout(int64_t m, int64_t rl, int64_t r) {
+  Bf16CoreLayout L{};
+  const int64_t tiles = cdiv(rl, BF16Pass::BM) * cdiv(r, BF16Pass::BN);
+  int64_t sl = cdiv(512, 2 * tiles);
+  if (sl > cdiv(m, 1024)) sl = cdiv(m, 1024);
+  if (sl > 16) sl = 16;
+  if (sl < 1) sl = 1;
+  L.kslice = cdiv(cdiv(m, sl), 128) * 128;
+  L.nslice = cdiv(m, L.kslice);
+  L.nsb = L.kslice / 128;
+  size_t off = 0;
+  L.hi = off;
+  off += align_up((size_t)m * r * 2);
+  L.lo = off;
+  off += align_up((size_t)m * r * 2);
+  L.ones = off;
+  off += align_up((size_t)cdiv(rl, 128) * L.nsb * 4);
+  L.partial = off;
+  off += align_up((size_t)2 * L.nslice * rl * r * 4);
+  L.total = off;
+  return L;
+}
+
+size_t core_product_bf16_ws_bytes(int64_t m, int64_t rl, int64_t r) {
+  return bf16_core_layout(m, rl, r).total;
+}
+
+gn_status launch_core_product_bf16(int64_t m, int64_t rl, int64_t r, const uint16_t* Yt,
+                                   const float* AX, int64_t ldax, void* ws, double* C,
+                                   hipStream_t s) {
+  const Bf16CoreLayout L = bf16_core_layout(m, rl, r);
+  char* base = (char*)ws;
+  uint16_t* hi = (uint16_t*)(base + L.hi);
+  uint16_t* lo = (uint16_t*)(base + L.lo);
+  float* ones = (float*)(base + L.ones);
+  float* partial = (float*)(base + L.partial);
+  split_bf16x2<<<dim3((unsigned)cdiv(m * r, 256)), dim3(256), 0, s>>>(AX, ldax, m, r, hi, lo);
+  GN_LAUNCH_CHECK();
+  const int64_t nones = cdiv(rl, 128) * L.nsb;
+  fill_f32<<<dim3((unsigned)cdiv(nones, 256)), dim3(256), 0, s>>>(ones, nones, 1.0f);
+  GN_LAUNCH_CHECK();
+  // A = Y^T (rl x m, k-contiguous) with unit block scales, B = hi / lo (m x r)
+  const int vec = (m % 8 == 0) && (r % 8 == 0) && ((uintptr_t)Yt % 16 == 0) ? 1 : 0;
+  const GemmBF16 g{rl, r, m, Yt, m, hi, r, ones, L.nsb, partial, r, 1, vec};
+  const int64_t tiles = cdiv(rl, BF16Pass::BM) * cdiv(r, BF16Pass::BN);
+  const dim3 grid((unsigned)(8 * cdiv(tiles, 8)), (unsigned)L.nslice, 2u);
+  core_product_bf16<<<grid, dim3(BF16Pass::T), 0, s>>>(g, L.kslice, hi, lo, partial);
+  GN_LAUNCH_CHECK();
+  core_product_sum2<<<dim3((unsigned)cdiv(rl * r, 256)), dim3(256), 0, s>>>(partial, L.nslice,
+                                                                          rl * r, C);
+  GN_LAUNCH_CHECK();
+  return GN_OK;
 }
 
 gn_status launch_core_product_f32(int64_t m, int64_t rl, int64_t r, const float* Y, int64_t ldy,

@@ -11,6 +11,7 @@ Tolerances:
     bound gamma_K * (|A| |X|)_ij with gamma_K = K u / (1 - K u), u = 2^-24,
     which holds for any summation order.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -275,6 +276,30 @@ def test_low_precision_solve_within_5pct_of_oracle(G, mode, kind_x):
     ref = OG.gn(A, X, Y, OG.threshold(eps, nx, OG.nu_gaussian(m, r + l)))
     e_ref = OG.residual_fro(A, ref.F, ref.G)
     assert e_gpu <= 1.05 * e_ref, (e_gpu, e_ref)
+
+
+# BF16 mode: the core matrix on the BF16 matrix cores (Y's bfloat16 values, AX in
+# two bfloat16 terms, FP32 accumulation) against the oracle's FP64 Y^T (AX) on the
+# same sketch values, next to the FP32-matrix-core product the mode uses for a user
+# Y (the same Y given as user values).  Both carry FP32 accumulation error; the
+# two-term split adds at most 2^-17 relative per entry of AX, so the BF16 product
+# may not be more than a few times further from the oracle than the FP32 one.
+def test_core_bf16_product(G):
+    m, n, r, l = 3000, 2000, 200, 100
+    A = _noisy(m, n, 21)
+    p = G.Problem(m, n, r, l, seed=17, mode="bf16", eps=10 * U32)
+    Ad, sc = G.gn_quantize_bf16_bs(dev(A))
+    AX, YtA, _, _ = G.gn_sketch(p, Ad, scales=sc)
+    core = G.gn_core(p, AX)
+    Yb = G.gn_generate_gaussian(17, 2, m, p.rl, dtype=torch.bfloat16)
+    pu = dataclasses.replace(p, kind_y="user", nu_y=OG.nu_gaussian(m, p.rl))
+    core32 = G.gn_core(pu, AX, Y_user=Yb)
+    Y = OG.round_mode(OP.gaussian(17, OP.STREAM_Y, m, p.rl), "bf16")
+    assert np.array_equal(Yb.float().cpu().numpy().astype(np.float64), Y)
+    ref = OG.core(host(AX), Y, 0.0)
+    e16, e32 = relerr(host(core.R), ref.R), relerr(host(core32.R), ref.R)
+    assert e16 <= 1e-5 and e32 <= 1e-5, (e16, e32)
+    assert core.rank() == core32.rank()
 
 
 # ----------------------------------------------------------------------------- products, several blocks
