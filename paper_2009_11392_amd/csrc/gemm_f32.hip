@@ -16,7 +16,8 @@ namespace {
 
 using namespace tiles;
 
-using CoreCfg = F32Cfg<128, 128, 16, 2, 2, 32>;
+// The pass's 256 x 256 tile (16 waves, one workgroup per CU).
+using CoreCfg = F32Pass;
 
 template <bool VEC>
 __global__ void __launch_bounds__(CoreCfg::T) core_product_f32(GemmF32 g, int64_t kslice) {
@@ -98,13 +99,20 @@ __global__ void __launch_bounds__(256) core_product_sum(const float* partial, in
   C[e] = acc;
 }
 
+// K slices: the count (at most 16, slices at least 1024 long) that minimizes the
+// number of rounds of one workgroup per CU times the slice length.
 int64_t core_slices(int64_t m, int64_t rl, int64_t r) {
   const int64_t tiles = cdiv(rl, CoreCfg::BM) * cdiv(r, CoreCfg::BN);
-  int64_t sl = cdiv(512, tiles);
-  const int64_t smax = cdiv(m, 512);
-  if (sl > smax) sl = smax;
-  if (sl > 16) sl = 16;
-  return sl < 1 ? 1 : sl;
+  int64_t best = 1;
+  double best_cost = (double)cdiv(tiles, 256) * (double)m;
+  for (int64_t sl = 2; sl <= 16 && cdiv(m, sl) >= 1024; ++sl) {
+    const double c = (double)cdiv(tiles * sl, 256) * (double)cdiv(m, sl);
+    if (c < best_cost) {
+      best_cost = c;
+      best = sl;
+    }
+  }
+  return best;
 }
 
 // D = A B; with `partial`, slice blockIdx.y of K (length kslice) goes to
@@ -259,7 +267,7 @@ gn_status launch_core_product_f32(int64_t m, int64_t rl, int64_t r, const float*
                                   const float* AX, int64_t ldax, float* partial, double* C,
                                   hipStream_t s) {
   const int64_t sl = core_slices(m, rl, r);
-  const int64_t kslice = cdiv(cdiv(m, sl), 16) * 16;
+  const int64_t kslice = cdiv(cdiv(m, sl), CoreCfg::BK) * CoreCfg::BK;
   const int64_t tiles = cdiv(rl, CoreCfg::BM) * cdiv(r, CoreCfg::BN);
   GemmF32 g{rl, r, m, Y, ldy, AX, ldax, partial, r, 1};
   const bool vec = (ldy % 4 == 0) && (ldax % 4 == 0) && ((uintptr_t)Y % 16 == 0) &&
