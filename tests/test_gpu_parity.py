@@ -174,6 +174,40 @@ def test_truncation_rank_on_gpu(G, small):
     assert relerr(host(G.gn_apply(p, 1, AX, YtA, core, dev(Wl))), Wl @ ref.approx) <= 1e-10
 
 
+# gn_core runs the kept-rank scan and the second QR on a per-device side stream
+# (joined before it returns) and gn_apply prepares its solve there.  Two solves
+# enqueued back to back on two streams -- one truncated, so the second QR does
+# real work -- give bit for bit the results of the same solves one at a time
+# (every kernel sums in a fixed order).
+def test_solves_on_two_streams(G, small):
+    w, _, p, _, _, _ = small
+    mats = [W.spectrum_matrix(w.m, w.n, w.sigma()[:40], seed=8),
+            W.spectrum_matrix(w.m, w.n, w.sigma(), seed=9)]
+    Wr = W.host_gaussian(w.n, 5, 77)
+    serial = []
+    for A in mats:
+        AX, YtA, core = G.solve(p, dev(A))
+        serial.append((core, host(G.gn_apply(p, 0, AX, YtA, core, dev(Wr)))))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    both = []
+    for A, st in zip(mats, streams):
+        with torch.cuda.stream(st):
+            AX, YtA, core = G.solve(p, dev(A))
+            both.append((core, G.gn_apply(p, 0, AX, YtA, core, dev(Wr))))
+    torch.cuda.synchronize()
+    assert serial[0][0].rank() == 40 and serial[1][0].rank() == w.r
+    for (c0, o0), (c1, o1) in zip(serial, both):
+        k = c0.rank()
+        assert c1.rank() == k and c1.flags() == c0.flags()
+        for name in ("R", "Q1"):
+            assert np.array_equal(host(getattr(c0, name)), host(getattr(c1, name))), name
+        if k < w.r:
+            assert np.array_equal(host(c0.Q2)[:, :k], host(c1.Q2)[:, :k])
+            assert np.array_equal(host(c0.R2)[:k, :k], host(c1.R2)[:k, :k])
+        assert np.array_equal(o0, host(o1))
+
+
 # ----------------------------------------------------------------------------- FP32 / BF16 pass
 def test_pass_f32_gaussian_ragged(G):
     m, n, r, l = 777, 1234, 37, 19
