@@ -16,12 +16,14 @@ namespace {
 
 using namespace tiles;
 
-// The pass's 256 x 256 tile (16 waves, one workgroup per CU).
-using CoreCfg = F32Pass;
+// Large cores take the pass's 256 x 256 tile (16 waves, one workgroup per CU),
+// small ones a 128 x 128 tile (4 waves) that gives them more workgroups.
+using CoreBig = F32Pass;
+using CoreSmall = F32Cfg<128, 128, 16, 2, 2, 32>;
 
-template <bool VEC>
+template <class CoreCfg, bool VEC>
 __global__ void __launch_bounds__(CoreCfg::T) core_product_f32(GemmF32 g, int64_t kslice) {
-  __shared__ __attribute__((aligned(16))) char smem[CoreCfg::smem<false, false>()];
+  __shared__ __attribute__((aligned(16))) char smem[CoreCfg::template smem<false, false>()];
   const int64_t s = blockIdx.y;
   const int64_t k0 = s * kslice;
   GemmF32 gs = g;
@@ -99,10 +101,22 @@ __global__ void __launch_bounds__(256) core_product_sum(const float* partial, in
   C[e] = acc;
 }
 
-// K slices: the count (at most 16, slices at least 1024 long) that minimizes the
-// number of rounds of one workgroup per CU times the slice length.
+bool core_big(int64_t rl, int64_t r) {
+  return cdiv(rl, CoreBig::BM) * cdiv(r, CoreBig::BN) >= 32;
+}
+
+// K slices.  256 x 256 tiles: the count (at most 16, slices at least 1024 long)
+// that minimizes the rounds of one workgroup per CU times the slice length.
+// 128 x 128 tiles: about 512 workgroups, slices at least 512 long.
 int64_t core_slices(int64_t m, int64_t rl, int64_t r) {
-  const int64_t tiles = cdiv(rl, CoreCfg::BM) * cdiv(r, CoreCfg::BN);
+  if (!core_big(rl, r)) {
+    const int64_t tiles = cdiv(rl, CoreSmall::BM) * cdiv(r, CoreSmall::BN);
+    int64_t sl = cdiv(512, tiles);
+    if (sl > cdiv(m, 512)) sl = cdiv(m, 512);
+    if (sl > 16) sl = 16;
+    return sl < 1 ? 1 : sl;
+  }
+  const int64_t tiles = cdiv(rl, CoreBig::BM) * cdiv(r, CoreBig::BN);
   int64_t best = 1;
   double best_cost = (double)cdiv(tiles, 256) * (double)m;
   for (int64_t sl = 2; sl <= 16 && cdiv(m, sl) >= 1024; ++sl) {
@@ -267,16 +281,26 @@ gn_status launch_core_product_f32(int64_t m, int64_t rl, int64_t r, const float*
                                   const float* AX, int64_t ldax, float* partial, double* C,
                                   hipStream_t s) {
   const int64_t sl = core_slices(m, rl, r);
-  const int64_t kslice = cdiv(cdiv(m, sl), CoreCfg::BK) * CoreCfg::BK;
-  const int64_t tiles = cdiv(rl, CoreCfg::BM) * cdiv(r, CoreCfg::BN);
   GemmF32 g{rl, r, m, Y, ldy, AX, ldax, partial, r, 1};
   const bool vec = (ldy % 4 == 0) && (ldax % 4 == 0) && ((uintptr_t)Y % 16 == 0) &&
                    ((uintptr_t)AX % 16 == 0);
-  const dim3 grid((unsigned)(8 * cdiv(tiles, 8)), (unsigned)sl);
-  if (vec)
-    core_product_f32<true><<<grid, dim3(CoreCfg::T), 0, s>>>(g, kslice);
-  else
-    core_product_f32<false><<<grid, dim3(CoreCfg::T), 0, s>>>(g, kslice);
+  if (core_big(rl, r)) {
+    const int64_t kslice = cdiv(cdiv(m, sl), CoreBig::BK) * CoreBig::BK;
+    const int64_t tiles = cdiv(rl, CoreBig::BM) * cdiv(r, CoreBig::BN);
+    const dim3 grid((unsigned)(8 * cdiv(tiles, 8)), (unsigned)sl);
+    if (vec)
+      core_product_f32<CoreBig, true><<<grid, dim3(CoreBig::T), 0, s>>>(g, kslice);
+    else
+      core_product_f32<CoreBig, false><<<grid, dim3(CoreBig::T), 0, s>>>(g, kslice);
+  } else {
+    const int64_t kslice = cdiv(cdiv(m, sl), 16) * 16;
+    const int64_t tiles = cdiv(rl, CoreSmall::BM) * cdiv(r, CoreSmall::BN);
+    const dim3 grid((unsigned)(8 * cdiv(tiles, 8)), (unsigned)sl);
+    if (vec)
+      core_product_f32<CoreSmall, true><<<grid, dim3(CoreSmall::T), 0, s>>>(g, kslice);
+    else
+      core_product_f32<CoreSmall, false><<<grid, dim3(CoreSmall::T), 0, s>>>(g, kslice);
+  }
   GN_LAUNCH_CHECK();
   core_product_sum<<<dim3((unsigned)cdiv(rl * r, 256)), dim3(256), 0, s>>>(partial, sl, rl * r, C);
   GN_LAUNCH_CHECK();
