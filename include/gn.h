@@ -20,7 +20,13 @@
  *   * Pointers are device pointers unless marked (host).  All matrices are
  *     row-major; "ld" arguments are row strides in elements.
  *   * The caller owns every buffer, including the workspace `ws`; the library
- *     never allocates or frees device memory and keeps no state between calls.
+ *     never allocates or frees device memory.  Its only state is one more stream
+ *     (non-blocking, default priority) and two events per device, created at the
+ *     first gn_core / gn_apply call on that device and kept until the process
+ *     ends: those calls run independent parts of their work (the kept-rank scan
+ *     and second QR; the solve's block inverses) on it, joined back to `stream`
+ *     by an event before returning, so work enqueued later on `stream` sees every
+ *     result (the fork and join are also recorded under stream capture).
  *   * Arguments are validated synchronously; on an error the call returns
  *     before anything is enqueued.  Otherwise the work is enqueued on `stream`
  *     and the call returns without synchronizing.  GN_ERR_HIP reports a failed
@@ -28,7 +34,8 @@
  *     diagonal, kept rank 0) are reported through the device status word of
  *     gn_core_out, never by aborting.
  *   * Calls are reentrant; calls on different streams with disjoint buffers may
- *     run concurrently.
+ *     run concurrently (the forks above are serialized by a host mutex, and their
+ *     side-stream parts run one after the other).
  */
 #ifndef GN_H_
 #define GN_H_
