@@ -497,10 +497,11 @@ gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void*
 
   // C = Y^T (AX) (the order of the Section 5.1 evaluation): FP64 in F64 mode;
   // in F32 mode (and BF16 mode with a user Y) on the FP32 matrix cores (the pass
-  // precision), in BF16 mode on the BF16 matrix cores, the K slices summed in FP64.  With an SRHT X and Y^T A given (F32 / BF16 modes),
-  // C = (Y^T A) X instead, the order Section 2.3 costs: the r + l rows of Y^T A
-  // sign-flipped, Walsh-Hadamard transformed and sampled in FP64, with the signs
-  // and columns regenerated from the seed (bit-identical to the pass's).
+  // precision), in BF16 mode on the BF16 matrix cores, the K slices summed in
+  // FP64.  With an SRHT X and Y^T A given (F32 / BF16 modes), C = (Y^T A) X
+  // instead, the order Section 2.3 costs: the r + l rows of Y^T A sign-flipped,
+  // Walsh-Hadamard transformed and sampled in FP64, with the signs and columns
+  // regenerated from the seed (bit-identical to the pass's).
   if (YtA && P.kx == GN_SKETCH_SRHT && P.mode != GN_MODE_F64) {
     int8_t* sg = (int8_t*)(base + W.signs);
     int32_t* ix = (int32_t*)(base + W.idx);
