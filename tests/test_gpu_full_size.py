@@ -1,0 +1,170 @@
+"""Full-size GPU parity: the 32768 x 32768 FP32 solve with an SRHT X (r = 1000)
+and a Gaussian Y (l = 500), called exactly as the benchmark times it
+(prepare, fused pass, core from (Y^T A) X, right apply), checked on outputs the
+oracle can compute one by one and on properties that hold at any size.
+
+  * pass: sampled rows of AX (A's rows times the oracle's explicit SRHT matrix,
+    Section 4) and sampled rows of Y^T A (the oracle's Philox columns of Y times
+    A, summed over row blocks of A on the host), each entry within the
+    inner-product bound gamma_K (|.| |.|)_ij and the rows within a relative
+    Frobenius error 2e-5 (sequential FP32 accumulation over K = 32768 gives
+    about 2.4e-6 on Gaussian data);
+  * SRHT signs and sample: bit-exact;
+  * core (Section 5.1, 5.1.1): Q orthonormal, R upper triangular with a
+    non-negative diagonal, Q R equal to sampled columns of (Y^T A) X, the kept
+    rank the first diagonal below the threshold, and R_1^T = Q_2 R_2 when
+    truncated;
+  * apply (Section 2): sampled rows of A_hat W equal the factored form
+    AX R^-1 Q^T (Y^T A W) (or its truncated form) evaluated on the host from the
+    library's own factors.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+torch = pytest.importorskip("torch")
+
+from oracle import gn as OG, philox as OP  # noqa: E402
+from paper_2009_11392_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def gamma(K, u=U32):
+    return K * u / (1 - K * u)
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def host(t):
+    return t.detach().cpu().double().numpy()
+
+
+@pytest.fixture(scope="module")
+def full():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_11392_amd import gn
+    w = W.SRHT32K
+    print(f"\n[full-size] {w.name}: generating A on the device", flush=True)
+    A = W.device_matrix(w)
+    p = gn.Problem(w.m, w.n, w.r, w.l, kind_x=w.kind_x, kind_y=w.kind_y, seed=w.seed,
+                   mode=w.mode, eps=w.eps)
+    ws = gn.workspace(p, gn.C.GN_OP_SKETCH)
+    ws_core = gn.workspace(p, gn.C.GN_OP_CORE)
+    AX = torch.empty(w.m, w.r, dtype=torch.float32, device="cuda")
+    YtA = torch.empty(p.rl, w.n, dtype=torch.float32, device="cuda")
+    core = gn.new_core(p)
+    Wr = W.host_gaussian(w.n, 16, 99)
+    Wd = torch.from_numpy(Wr).cuda()
+    out = torch.empty(w.m, 16, dtype=torch.float64, device="cuda")
+    print("[full-size] prepare, pass, core, apply", flush=True)
+    signs, idx = gn.gn_sketch_prepare(p, ws, want_srht=True)
+    gn.gn_sketch_pass(p, A, ws, AX=AX, YtA=YtA)
+    gn.gn_core(p, AX, out=core, ws=ws_core, YtA=YtA)
+    gn.gn_apply(p, 0, AX, YtA, core, Wd, out=out)
+    torch.cuda.synchronize()
+    npad = OP.next_pow2(w.n)
+    print("[full-size] oracle SRHT matrix", flush=True)
+    X = OP.srht_matrix(w.seed, w.n, w.r)
+    return dict(gn=gn, w=w, p=p, A=A, AX=AX, YtA=YtA, core=core, Wr=Wr, out=out,
+                signs=signs.cpu().numpy(), idx=idx.cpu().numpy(), npad=npad, X=X)
+
+
+def test_full_srht_parameters_bit_exact(full):
+    w, npad = full["w"], full["npad"]
+    assert np.array_equal(full["signs"], OP.srht_signs(w.seed, npad))
+    assert np.array_equal(full["idx"], OP.srht_sample(w.seed, npad, w.r))
+
+
+def test_full_pass_ax_sampled_rows(full):
+    w, A, X = full["w"], full["A"], full["X"]
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([[0, 1, 255, 256, 16383, 16384, w.m - 2, w.m - 1],
+                                     rng.integers(0, w.m, 24)]))
+    rt = torch.from_numpy(rows).cuda()
+    Ar = host(A.index_select(0, rt))
+    ref = Ar @ X
+    got = host(full["AX"].index_select(0, rt))
+    bound = gamma(w.n) * (np.abs(Ar) @ np.abs(X))
+    assert np.all(np.abs(got - ref) <= bound)
+    e = relerr(got, ref)
+    print(f"AX sampled rows: rel err {e:.3e}")
+    assert e <= 2e-5
+
+
+def test_full_pass_yta_sampled_rows(full):
+    w, p, A = full["w"], full["p"], full["A"]
+    rng = np.random.default_rng(8)
+    sel = np.unique(np.concatenate([[0, 1, 255, 256, 999, 1000, 1279, 1280, p.rl - 1],
+                                    rng.integers(0, p.rl, 7)]))
+    # the oracle's Y columns (Philox stream of Y), rounded to the working precision
+    Ys = np.concatenate([OG.round_mode(OP.gaussian(w.seed, OP.STREAM_Y, w.m, 1, col0=int(a)), "f32")
+                         for a in sel], axis=1)
+    ref = np.zeros((len(sel), w.n))
+    mag = np.zeros((len(sel), w.n))
+    step = 2048
+    for i0 in range(0, w.m, step):
+        Ab = host(A[i0:i0 + step])
+        yb = Ys[i0:i0 + step]
+        ref += yb.T @ Ab
+        mag += np.abs(yb).T @ np.abs(Ab)
+    got = host(full["YtA"].index_select(0, torch.from_numpy(sel).cuda()))
+    assert np.all(np.abs(got - ref) <= gamma(w.m) * mag)
+    e = relerr(got, ref)
+    print(f"Y^T A sampled rows: rel err {e:.3e}")
+    assert e <= 2e-5
+
+
+def test_full_core_properties(full):
+    w, p, core, X = full["w"], full["p"], full["core"], full["X"]
+    k, r = core.rank(), w.r
+    assert (core.flags() & 3) == 0
+    Q, R = host(core.Q1), host(core.R)
+    assert Q.shape == (p.rl, r)
+    assert np.all(np.tril(R, -1) == 0)
+    d = np.diag(R)
+    assert np.all(d >= 0)
+    assert np.max(np.abs(Q.T @ Q - np.eye(r))) <= 1e-12
+    # Q R against sampled columns of the core matrix (Y^T A) X
+    rng = np.random.default_rng(9)
+    cols = np.unique(np.concatenate([[0, 1, r - 1], rng.integers(0, r, 13)]))
+    YA = host(full["YtA"])
+    Cs = YA @ X[:, cols]
+    assert relerr(Q @ R[:, cols], Cs) <= 1e-11
+    # kept rank: the first diagonal entry below the threshold (Section 5.1.1)
+    nx, ny = OG.nu_srht(p.n), OG.nu_gaussian(p.m, p.rl)
+    tau = OG.threshold(p.eps, nx, ny)
+    assert np.all(d[:k] >= tau)
+    assert k == r or d[k] < tau
+    print(f"core: kept rank {k} of {r}, tau {tau:.3e}, R diagonal {d[0]:.3e} .. {d[-1]:.3e}")
+    if k < r:
+        Q2, R2 = host(core.Q2)[:, :k], host(core.R2)[:k, :k]
+        assert np.max(np.abs(Q2.T @ Q2 - np.eye(k))) <= 1e-12
+        assert np.all(np.tril(R2, -1) == 0)
+        assert relerr(Q2 @ R2, R[:k, :].T) <= 1e-12
+
+
+def test_full_apply_sampled_rows(full):
+    p, core = full["p"], full["core"]
+    k, r = core.rank(), p.r
+    Q, R = host(core.Q1), host(core.R)
+    YA, Wr = host(full["YtA"]), full["Wr"]
+    t = Q[:, :k].T @ (YA @ Wr)                   # Q_1^T (Y^T A W), k x 16
+    rng = np.random.default_rng(10)
+    rows = np.unique(np.concatenate([[0, p.m - 1], rng.integers(0, p.m, 30)]))
+    rt = torch.from_numpy(rows).cuda()
+    AXr = host(full["AX"].index_select(0, rt))
+    if k == r:
+        ref = AXr @ sla.solve_triangular(R, t, lower=False)
+    else:
+        Q2, R2 = host(core.Q2)[:, :k], host(core.R2)[:k, :k]
+        ref = (AXr @ Q2) @ sla.solve_triangular(R2, t, trans="T", lower=False)
+    got = host(full["out"].index_select(0, rt))
+    e = relerr(got, ref)
+    print(f"apply sampled rows: rel err {e:.3e}")
+    assert e <= 1e-12
