@@ -168,3 +168,125 @@ def test_full_apply_sampled_rows(full):
     e = relerr(got, ref)
     print(f"apply sampled rows: rel err {e:.3e}")
     assert e <= 1e-12
+
+
+# ----------------------------------------------------------------------------- BF16 precision variant
+# The same spectrum-controlled 32768 x 32768 matrix stored in bfloat16 with
+# power-of-two scales per 128 x 128 block, Gaussian X and Y in bfloat16
+# (r = 2000, l = 1000), FP32 accumulation, the core product on the BF16 matrix
+# cores, as the benchmark's BF16 solve runs it.  Products of bfloat16 values are
+# exact in FP32 and the block scales are powers of two, so every entry of AX and
+# Y^T A obeys the FP32 inner-product bound against the dequantized matrix.  The
+# core matrix Y^T (AX) takes AX in two bfloat16 terms (at most 2^-17 relative per
+# entry) with FP32 accumulation: rows of Q R within 5e-5 of Y^T AX in FP64.
+@pytest.fixture(scope="module")
+def full_bf16():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_11392_amd import gn
+    w = W.BF16_32K
+    print(f"\n[full-size] {w.name}: generating A on the device", flush=True)
+    A32 = W.device_matrix(W.F32_32K)
+    bits, scales = gn.gn_quantize_bf16_bs(A32)
+    p = gn.Problem(w.m, w.n, w.r, w.l, kind_x=w.kind_x, kind_y=w.kind_y, seed=w.seed,
+                   mode=w.mode, eps=w.eps)
+    ws = gn.workspace(p, gn.C.GN_OP_SKETCH)
+    ws_core = gn.workspace(p, gn.C.GN_OP_CORE)
+    AX = torch.empty(w.m, w.r, dtype=torch.float32, device="cuda")
+    YtA = torch.empty(p.rl, w.n, dtype=torch.float32, device="cuda")
+    core = gn.new_core(p)
+    Wr = W.host_gaussian(w.n, 16, 98)
+    out = torch.empty(w.m, 16, dtype=torch.float64, device="cuda")
+    print("[full-size] BF16 prepare, pass, core, apply", flush=True)
+    gn.gn_sketch_prepare(p, ws)
+    gn.gn_sketch_pass(p, bits, ws, scales=scales, AX=AX, YtA=YtA)
+    gn.gn_core(p, AX, out=core, ws=ws_core, YtA=YtA)
+    gn.gn_apply(p, 0, AX, YtA, core, torch.from_numpy(Wr).cuda(), out=out)
+    torch.cuda.synchronize()
+    return dict(w=w, p=p, A32=A32, bits=bits, scales=scales, AX=AX, YtA=YtA, core=core,
+                Wr=Wr, out=out)
+
+
+def _bits_host(t):
+    return t.view(torch.int16).cpu().numpy().view(np.uint16)
+
+
+def test_full_bf16_quantization_sampled_blocks(full_bf16):
+    A32, bits, scales = full_bf16["A32"], full_bf16["bits"], full_bf16["scales"]
+    nb = scales.shape[0]
+    sc = scales.cpu().numpy()
+    for bi, bj in ((0, 0), (nb - 1, nb - 1), (17, 200), (255, 3), (100, 100)):
+        blk = host(A32[bi * 128:(bi + 1) * 128, bj * 128:(bj + 1) * 128])
+        rb, rs = OG.block_quantize_bf16(blk)
+        got = _bits_host(bits[bi * 128:(bi + 1) * 128, bj * 128:(bj + 1) * 128])
+        assert np.array_equal(got, rb), (bi, bj)
+        assert sc[bi, bj] == rs[0, 0], (bi, bj)
+
+
+def test_full_bf16_pass_sampled(full_bf16):
+    w, p = full_bf16["w"], full_bf16["p"]
+    rng = np.random.default_rng(11)
+    cols = np.unique(np.concatenate([[0, 1, 255, 256, w.r - 1], rng.integers(0, w.r, 11)]))
+    sel = np.unique(np.concatenate([[0, 1, 255, 256, 2047, 2048, p.rl - 1],
+                                    rng.integers(0, p.rl, 9)]))
+    Xs = np.concatenate([OG.round_mode(OP.gaussian(w.seed, OP.STREAM_X, w.n, 1, col0=int(c)), "bf16")
+                         for c in cols], axis=1)
+    Ys = np.concatenate([OG.round_mode(OP.gaussian(w.seed, OP.STREAM_Y, w.m, 1, col0=int(a)), "bf16")
+                         for a in sel], axis=1)
+    sc = full_bf16["scales"].cpu().numpy()
+    ax_ref = np.zeros((w.m, len(cols)))
+    ax_mag = np.zeros((w.m, len(cols)))
+    ya_ref = np.zeros((len(sel), w.n))
+    ya_mag = np.zeros((len(sel), w.n))
+    step = 2048
+    for i0 in range(0, w.m, step):
+        Ab = OG.block_dequantize_bf16(_bits_host(full_bf16["bits"][i0:i0 + step]),
+                                      sc[i0 // 128:(i0 + step) // 128])
+        ax_ref[i0:i0 + step] = Ab @ Xs
+        ax_mag[i0:i0 + step] = np.abs(Ab) @ np.abs(Xs)
+        yb = Ys[i0:i0 + step]
+        ya_ref += yb.T @ Ab
+        ya_mag += np.abs(yb).T @ np.abs(Ab)
+    ax = host(full_bf16["AX"].index_select(1, torch.from_numpy(cols).cuda()))
+    ya = host(full_bf16["YtA"].index_select(0, torch.from_numpy(sel).cuda()))
+    assert np.all(np.abs(ax - ax_ref) <= gamma(w.n) * ax_mag)
+    assert np.all(np.abs(ya - ya_ref) <= gamma(w.m) * ya_mag)
+    e_ax, e_ya = relerr(ax, ax_ref), relerr(ya, ya_ref)
+    print(f"BF16 AX sampled columns: rel err {e_ax:.3e}; Y^T A sampled rows: rel err {e_ya:.3e}")
+    assert e_ax <= 2e-5 and e_ya <= 2e-5
+
+
+def test_full_bf16_core_and_apply(full_bf16):
+    w, p, core = full_bf16["w"], full_bf16["p"], full_bf16["core"]
+    k, r = core.rank(), w.r
+    assert (core.flags() & 3) == 0
+    Q, R = host(core.Q1), host(core.R)
+    assert np.all(np.tril(R, -1) == 0)
+    d = np.diag(R)
+    assert np.all(d >= 0)
+    assert np.max(np.abs(Q.T @ Q - np.eye(r))) <= 1e-12
+    rng = np.random.default_rng(12)
+    sel = np.unique(np.concatenate([[0, p.rl - 1], rng.integers(0, p.rl, 14)]))
+    Ys = np.concatenate([OG.round_mode(OP.gaussian(w.seed, OP.STREAM_Y, w.m, 1, col0=int(a)), "bf16")
+                         for a in sel], axis=1)
+    AXh = host(full_bf16["AX"])
+    e_c = relerr(Q[sel] @ R, Ys.T @ AXh)
+    tau = OG.threshold(p.eps, OG.nu_gaussian(p.n, p.r), OG.nu_gaussian(p.m, p.rl))
+    print(f"BF16 core: rows of QR vs Y^T AX rel err {e_c:.3e}; kept rank {k} of {r}, "
+          f"tau {tau:.3e}, R diagonal {d[0]:.3e} .. {d[-1]:.3e}")
+    assert e_c <= 5e-5
+    assert np.all(d[:k] >= tau)
+    assert k == r or d[k] < tau
+    YA, Wr = host(full_bf16["YtA"]), full_bf16["Wr"]
+    t = Q[:, :k].T @ (YA @ Wr)
+    rows = np.unique(np.concatenate([[0, p.m - 1], rng.integers(0, p.m, 30)]))
+    AXr = AXh[rows]
+    if k == r:
+        ref = AXr @ sla.solve_triangular(R, t, lower=False)
+    else:
+        Q2, R2 = host(core.Q2)[:, :k], host(core.R2)[:k, :k]
+        assert relerr(Q2 @ R2, R[:k, :].T) <= 1e-12
+        ref = (AXr @ Q2) @ sla.solve_triangular(R2, t, trans="T", lower=False)
+    e = relerr(host(full_bf16["out"].index_select(0, torch.from_numpy(rows).cuda())), ref)
+    print(f"BF16 apply sampled rows: rel err {e:.3e}")
+    assert e <= 1e-12
