@@ -64,7 +64,7 @@ def pass_algorithmic(w, npad):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("pass.hip", "gemm_tiles.h", "gn_internal.h"):
+    for f in ("pass.hip", "gemm_tiles.h", "gn_internal.h", "lane_ops.h"):
         with open(os.path.join(ROOT, "paper_2009_11392_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -363,6 +363,8 @@ def main():
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the reverse-mode measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
+    ap.add_argument("--no-small-r", action="store_true",
+                    help="skip the small-r (HBM-bound) pass measurement")
     ap.add_argument("--no-stab", action="store_true",
                     help="skip the timing of the other core stabilizations and the check")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -443,6 +445,22 @@ def main():
     if not args.no_stab:
         log("core stabilizations and the plain-GN check")
         res["stabilizations"] = stabilize_bench(gn, run)
+
+    if not args.no_small_r and w is W.SRHT32K:
+        # the same resident matrix at r = 10, l = 5: the pass is then bound by
+        # HBM bandwidth (45 flops per 4-byte element), not by the matrix cores
+        ws_ = W.SRHT32K_R10
+        log(f"small r: {ws_.name}")
+        rs = Runner(gn, ws_, A)
+        ts = rs.timed(20, 3)
+        fl, by = pass_algorithmic(ws_, npad)
+        gb = by / (ts["pass"] / 1e3) / 1e9
+        res["small_r"] = {"workload": ws_.name, "r": ws_.r, "l": ws_.l, "pass_ms": ts["pass"],
+                          "bound": "hbm", "achieved_gbps": gb, "peak_gbps": HBM_PEAK_GBS,
+                          "frac": gb / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": by,
+                          "solves_per_sec": 1e3 / (ts["prepare"] + ts["pass"] + ts["core"])}
+        log(f"small r pass {ts['pass']:.3f} ms  {gb:.0f} GB/s ({gb / HBM_PEAK_GBS:.3f} of HBM peak)")
+        del rs
 
     if not args.no_compare and w.m == 32768 and w.n == 32768:
         cmp = {}

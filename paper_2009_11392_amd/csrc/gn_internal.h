@@ -157,6 +157,18 @@ SplitK f32_split(int64_t tiles, int64_t K);
 SplitK f32_split2(int64_t tiles1, int64_t K1, int64_t tiles2, int64_t K2);
 // D[i*ldd + j] = sum over nslice partials (each M x N, row stride N) in slice
 // order in FP64, rounded to float.
+// FP32 pass with an SRHT X when r + l <= 16, n % 4 == 0, n' >= 1024 and A is
+// 16-byte aligned with lda % 4 == 0: one read of A (each wave one 256-column
+// chunk: the order-256 Walsh-Hadamard transform and the Y^T A product on the
+// matrix cores from the same registers), per-chunk and per-row-range partial
+// sums in ws added in a fixed order.  GN_ERR_UNSUPPORTED (nothing enqueued)
+// when the shape or ws (narrow_srht_ws_bytes) does not fit.
+size_t narrow_srht_ws_bytes(int64_t m, int64_t n, int64_t r, int64_t rl);
+gn_status launch_f32_srht_narrow(int64_t m, int64_t n, int64_t r, int64_t rl, const float* A,
+                                 int64_t lda, const float* Y, const int8_t* signs,
+                                 const int32_t* idx, float* AX, int64_t ldax, float* YtA,
+                                 int64_t ldya, void* ws, size_t ws_bytes, hipStream_t s);
+
 gn_status launch_splitk_sum_f32(const float* partial, int64_t nslice, int64_t M, int64_t N,
                                 float* D, int64_t ldd, hipStream_t s);
 

@@ -19,6 +19,7 @@
 #include <type_traits>
 
 #include "gemm_tiles.h"
+#include "lane_ops.h"
 
 namespace gn {
 namespace {
@@ -82,48 +83,6 @@ __device__ __forceinline__ void srht_load8(const SrhtArgs& a, int64_t i, int64_t
 
 // Orders this wave's LDS accesses (a wave-scope fence): enough where a wave
 // stores to and reads from LDS that no other wave touches.
-__device__ __forceinline__ void wave_lds_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// The 32-bit word of lane `lane ^ LM` (LM a power of two below 64) by lane moves
-// that stay out of LDS: DPP copies within a row (xor 4 as the mirror of eight lanes
-// followed by the mirror of four) and the gfx950 row and half-wave swaps.
-template <int LM>
-__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int lane) {
-  if constexpr (LM == 1) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
-  } else if constexpr (LM == 2) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
-  } else if constexpr (LM == 4) {
-    const int m = __builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-    return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, false);      // quad_perm 3,2,1,0
-  } else if constexpr (LM == 8) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
-  } else if constexpr (LM == 16) {
-    // odd rows of the first operand trade places with even rows of the second
-    const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-    return (lane & 16) ? (uint32_t)p[0] : (uint32_t)p[1];
-  } else {
-    // the upper half of the first operand trades places with the lower half of the second
-    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-    return (lane & 32) ? (uint32_t)p[0] : (uint32_t)p[1];
-  }
-}
-
-template <int LM>
-__device__ __forceinline__ float xor_lane(float v, int lane) {
-  return __uint_as_float(xor_lane_u32<LM>(__float_as_uint(v), lane));
-}
-template <int LM>
-__device__ __forceinline__ double xor_lane(double v, int lane) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const uint32_t lo = xor_lane_u32<LM>((uint32_t)b, lane);
-  const uint32_t hi = xor_lane_u32<LM>((uint32_t)(b >> 32), lane);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // One Walsh-Hadamard stage across lanes: lane pairs (l, l ^ LM), the lower lane
 // keeping the sum and the upper the difference (lower minus upper).
 template <int LM, typename T>
@@ -538,6 +497,12 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
                               (const float*)Ys, (float*)AX, ldax, (float*)YtA, ldya,
                               (char*)split_ws, s);
   }
+  if (mode == GN_MODE_F32 && srht) {
+    const gn_status st = launch_f32_srht_narrow(m, n, r, rl, (const float*)A, lda, (const float*)Ys,
+                                                signs, idx, (float*)AX, ldax, (float*)YtA, ldya,
+                                                split_ws, split_bytes, s);
+    if (st != GN_ERR_UNSUPPORTED) return st;
+  }
   if (mode == GN_MODE_F32)
     return launch_f32_cfg<F32Pass>(srht, kSrhtFirst, kSrhtRows, m, n, r, rl, (const float*)A, lda,
                                    (const float*)Xs, (const float*)Ys, sr, (float*)AX, ldax,
@@ -564,7 +529,8 @@ gn_status launch_srht_right(int64_t rows, int64_t n, int64_t r, const float* B, 
 
 size_t pass_split_ws_bytes(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_t r,
                            int64_t rl) {
-  if (mode != GN_MODE_F32 || kind_x == GN_SKETCH_SRHT) return 0;
+  if (mode != GN_MODE_F32) return 0;
+  if (kind_x == GN_SKETCH_SRHT) return narrow_srht_ws_bytes(m, n, r, rl);
   return pass_split(m, n, r, rl).bytes;
 }
 

@@ -79,6 +79,11 @@ SMALL = Workload("small_2000x1000_f64", 2000, 1000, 50, 25, "gaussian", "gaussia
 SRHT32K = Workload("srht_32768x32768_f32", 32768, 32768, 1000, 500, "srht", "gaussian",
                    "f32", seed=2, spectrum="poly2", rank=4096, noise=1e-6,
                    eps_rel=10 * U_F32)
+# small r: the pass moves 4 bytes of A per 2(r+l) + log2 n' = 45 flops, below the
+# FP32 ridge (19.7 flop/B), so it is bound by HBM bandwidth, not the matrix cores
+SRHT32K_R10 = Workload("srht_32768x32768_f32_r10", 32768, 32768, 10, 5, "srht", "gaussian",
+                       "f32", seed=2, spectrum="poly2", rank=4096, noise=1e-6,
+                       eps_rel=10 * U_F32)
 BF16_32K = Workload("bf16bs_32768x32768", 32768, 32768, 2000, 1000, "gaussian",
                     "gaussian", "bf16", seed=3, spectrum="poly2", rank=4096, noise=1e-6,
                     eps_rel=10 * U_F32)
@@ -89,7 +94,7 @@ GRAD8K = Workload("grad_8192x4096_f32", 8192, 4096, 256, 128, "gaussian", "gauss
                   "f32", seed=5, spectrum="poly1.5", rank=4096, noise=0.0,
                   eps_rel=10 * U_F32)
 
-ALL = {w.name: w for w in (SMALL, SRHT32K, BF16_32K, F32_32K, GRAD8K)}
+ALL = {w.name: w for w in (SMALL, SRHT32K, SRHT32K_R10, BF16_32K, F32_32K, GRAD8K)}
 
 
 @dataclass(frozen=True)

@@ -234,6 +234,28 @@ def test_pass_srht_integer_inputs_exact(G):
     assert np.array_equal(host(AX), A.astype(np.float64) @ X)   # integers: exact
 
 
+# r + l <= 16 with an SRHT X: the single-read narrow pass (one 256-column chunk per
+# wave, the Walsh-Hadamard transform and the Y^T A product from the same registers,
+# partial sums added in a fixed order).  Integer A: AX exact; Y^T A within gamma_m.
+# Ragged row counts, n not a power of two (chunks past n), r + l = 1 and 16, and
+# n % 4 != 0 (which takes the fused 256 x 256 kernel instead).
+@pytest.mark.parametrize("m,n,r,l", [(1001, 3000, 7, 5), (4096, 4096, 10, 6), (37, 1024, 1, 0),
+                                     (2050, 8192, 16, 0), (500, 2048, 3, 2), (300, 1234, 5, 3)])
+def test_pass_srht_narrow(G, m, n, r, l):
+    A = W.integer_matrix(m, n, 43).astype(np.float32)
+    p = G.Problem(m, n, r, l, kind_x="srht", seed=8, mode="f32")
+    AX, YtA, signs, idx = G.gn_sketch(p, dev(A, torch.float32), want_srht=True)
+    npad = OP.next_pow2(n)
+    assert np.array_equal(signs.cpu().numpy(), OP.srht_signs(8, npad))
+    assert np.array_equal(idx.cpu().numpy(), OP.srht_sample(8, npad, r))
+    A64 = A.astype(np.float64)
+    assert np.array_equal(host(AX), A64 @ OP.srht_matrix(8, n, r))   # integers: exact
+    Y = OG.round_mode(OP.gaussian(8, OP.STREAM_Y, m, r + l), "f32")
+    ya, ref = host(YtA), Y.T @ A64
+    assert np.all(np.abs(ya - ref) <= gamma(m) * (np.abs(Y.T) @ np.abs(A64)))
+    assert relerr(ya, ref) <= 5e-6
+
+
 def test_pass_srht_f64_matches_oracle(G):
     m, n, r = 300, 700, 90
     A = W.spectrum_matrix(m, n, 0.9 ** np.arange(1, 301), seed=12)
