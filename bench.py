@@ -92,9 +92,12 @@ def optimum_estimate(w):
 class Runner:
     """Preallocated buffers and one timed solve for a workload."""
 
-    def __init__(self, gn, w, A, scales=None, kc=16):
+    def __init__(self, gn, w, A, scales=None, kc=16, A_ref=None):
         import torch
         self.gn, self.w, self.A, self.scales = gn, w, A, scales
+        # the matrix the error is measured against: the unquantized FP32 matrix for
+        # the block-scaled BF16 variant, A itself otherwise
+        self.A_ref = A if A_ref is None else A_ref
         self.p = gn.Problem(w.m, w.n, w.r, w.l, kind_x=w.kind_x, kind_y=w.kind_y, seed=w.seed,
                             mode=w.mode, eps=w.eps)
         acc = gn.ACCUM_TORCH[w.mode]
@@ -143,14 +146,16 @@ class Runner:
         return mean
 
     def error(self):
-        """||A - A_hat||_F / ||A||_F on the device, tile by tile, and the kept rank."""
+        """||A - A_hat||_F / ||A||_F on the device, tile by tile, and the kept rank.
+        A is the original matrix (for BF16, the FP32 matrix before quantization)."""
         import torch
         gn = self.gn
         F, G = gn.gn_factors(self.p, self.AX, self.YtA, self.core)
-        ss = float(gn.gn_residual(self.A, F, G, scales=self.scales).item())
+        sc = self.scales if self.A_ref is self.A else None
+        ss = float(gn.gn_residual(self.A_ref, F, G, scales=sc).item())
         z = torch.zeros(self.w.m, 1, dtype=torch.float64, device="cuda")
         zg = torch.zeros(1, self.w.n, dtype=torch.float64, device="cuda")
-        na = float(gn.gn_residual(self.A, z, zg, k=0, scales=self.scales).item())
+        na = float(gn.gn_residual(self.A_ref, z, zg, k=0, scales=sc).item())
         del F, G
         return math.sqrt(ss), math.sqrt(na), self.core.rank(), self.core.flags()
 
@@ -315,41 +320,75 @@ def stabilize_bench(gn, run, steps=3, warmup=1):
     return out
 
 
-def cpu_baseline(A_dev, w, target_s=12.0):
-    """The FP64 oracle's sketch pass on a bounded block of rows of the same A."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
+def host_threads():
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
-    from oracle import philox as OP
 
-    npad = OP.next_pow2(w.n)
+def oracle_sketches(w, workers):
+    """The oracle's X and Y for workload w, holding the values the working
+    precision stores (an SRHT X is the explicit +-1 matrix)."""
+    from oracle import gn as OG, philox as OP
+    mode = "f64" if w.mode == "f64" else w.mode
     if w.kind_x == "srht":
         X = OP.srht_matrix(w.seed, w.n, w.r)
     else:
-        X = OP.gaussian(w.seed, OP.STREAM_X, w.n, w.r)
+        X = OG.round_mode(OP.gaussian(w.seed, OP.STREAM_X, w.n, w.r, workers=workers), mode)
+    Y = OG.round_mode(OP.gaussian(w.seed, OP.STREAM_Y, w.m, w.r + w.l, workers=workers), mode)
+    return X, Y
 
-    def run(rows):
-        Ab = A_dev[:rows].double().cpu().numpy()
-        Yb = OP.gaussian(w.seed, OP.STREAM_Y, rows, w.r + w.l)
-        t0 = time.perf_counter()
-        _ = Ab @ X
-        _ = Yb.T @ Ab
-        return time.perf_counter() - t0
 
-    rows = 128
-    dt = run(rows)
-    rows = int(min(w.m, max(128, rows * target_s / max(dt, 1e-3))))
-    rows = max(128, (rows // 128) * 128)
-    dt = run(rows)
-    sub = type("S", (), {})()
-    flops = 2.0 * rows * w.n * (w.r + w.l) + (rows * w.n * math.log2(npad) if w.kind_x == "srht"
-                                               else 2.0 * rows * w.n * w.r)
+def oracle_tau(w):
+    from oracle import gn as OG
+    nx = OG.nu_srht(w.n) if w.kind_x == "srht" else OG.nu_gaussian(w.n, w.r)
+    return OG.threshold(w.eps, nx, OG.nu_gaussian(w.m, w.r + w.l))
+
+
+def cpu_baseline(A_dev, w, npad):
+    """The FP64 oracle's whole GN solve of the workload on the host cores: the
+    sketches, the sketch pass A@X and Y^T@A (timed: `value`), the core and the
+    factors (timed with the pass: `solve_seconds`), then ||A - A_hat||_F (not
+    timed) for the error ratio of the GPU solve."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import gn as OG
+
+    workers = host_threads()
+    A64 = A_dev.cpu().numpy().astype(np.float64)
+    X, Y = oracle_sketches(w, workers)
+    t0 = time.perf_counter()
+    AX, YA = OG.sketch_pass(A64, X, Y)
+    t1 = time.perf_counter()
+    c = OG.core(AX, Y, oracle_tau(w))
+    F, G = OG.factors(AX, YA, c)
+    t2 = time.perf_counter()
+    e = OG.residual_fro(A64, F, G)
+    na = float(np.linalg.norm(A64))
+    flops, _ = pass_algorithmic(w, npad)
     threads = max([d.get("num_threads", 0) for d in threadpool_info()] or [os.cpu_count() or 1])
-    del sub
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"FP64 NumPy oracle sketch pass (A@X, Y^T@A) on rows 0..{rows - 1} of the "
-                       f"same {w.m}x{w.n} matrix ({dt:.2f} s); algorithmic flops of the method"),
-            "seconds": dt}
+    dense = " (A@X as a dense product with the explicit +-1 SRHT matrix, 2mnr flops)" \
+        if w.kind_x == "srht" else ""
+    return {"value": flops / (t1 - t0) / 1e12, "unit": "TFLOP/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle, whole {w.m}x{w.n} matrix: the sketch pass A@X, "
+                       f"Y^T@A timed ({t1 - t0:.2f} s){dense}; value = the method's "
+                       f"algorithmic pass flops / that time, as for the GPU value"),
+            "seconds": t1 - t0, "solve_seconds": t2 - t0, "kept_rank": c.k,
+            "abs_err": e, "rel_err": e / na}
+
+
+def oracle_error(A_dev, w):
+    """||A - A_hat||_F of the FP64 oracle's GN on A_dev (as FP64) with workload w's
+    sketch values (not timed)."""
+    import numpy as np
+
+    from oracle import gn as OG
+
+    A64 = A_dev.cpu().numpy().astype(np.float64)
+    X, Y = oracle_sketches(w, host_threads())
+    res = OG.gn(A64, X, Y, oracle_tau(w))
+    e = OG.residual_fro(A64, res.F, res.G)
+    return e, e / float(np.linalg.norm(A64)), res.core.k
 
 
 def main():
@@ -470,7 +509,7 @@ def main():
                 Ab, sc = gn.gn_quantize_bf16_bs(A32)
             else:
                 Ab, sc = A32, None
-            rr = Runner(gn, wl, Ab, sc)
+            rr = Runner(gn, wl, Ab, sc, A_ref=A32)
             tt = rr.timed(3, 1)
             fl, by = pass_algorithmic(wl, srht_pad(wl.n))
             ent = {"pass_ms": tt["pass"], "solve_ms": tt["prepare"] + tt["pass"] + tt["core"],
@@ -478,7 +517,7 @@ def main():
                    "pass_frac_of_peak": fl / (tt["pass"] / 1e3) / 1e12 / PEAK[tag]}
             ent["solves_per_sec"] = 1e3 / ent["solve_ms"]
             e, na, k, flags = rr.error()
-            ent.update({"rel_err": e / na, "kept_rank": k, "status_flags": flags})
+            ent.update({"rel_err": e / na, "abs_err": e, "kept_rank": k, "status_flags": flags})
             cmp[tag] = ent
             del rr, Ab
             torch.cuda.empty_cache()
@@ -503,8 +542,23 @@ def main():
             f"graph {res['batched']['graph_solve_ms']:.3f} ms")
 
     if not args.no_cpu:
-        log("cpu baseline (oracle)")
-        res["cpu_baseline"] = cpu_baseline(A32 if w.mode != "f64" else A, w)
+        log("cpu baseline: the FP64 oracle's solve of the same matrix on the host")
+        cb = cpu_baseline(A32 if w.mode != "f64" else A, w, npad)
+        res["cpu_baseline"] = cb
+        log(f"oracle pass {cb['seconds']:.2f} s ({cb['value']:.3f} TFLOP/s, {cb['cores']} threads), "
+            f"rel err {cb['rel_err']:.6e}")
+        if "error" in res:
+            res["error"]["oracle_rel_err"] = cb["rel_err"]
+            res["error"]["oracle_kept_rank"] = cb["kept_rank"]
+            res["error"]["err_ratio_vs_oracle"] = res["error"]["abs_fro"] / cb["abs_err"]
+            log(f"error ratio vs the FP64 oracle: {res['error']['err_ratio_vs_oracle']:.6f}")
+        if "bf16_vs_fp32" in res:
+            log("FP64 oracle on the BF16 variant's sketch values (unquantized matrix)")
+            eo, ro, ko = oracle_error(A32, W.BF16_32K)
+            b = res["bf16_vs_fp32"]["bf16"]
+            b.update({"oracle_rel_err": ro, "oracle_kept_rank": ko,
+                      "err_ratio_vs_oracle": b["abs_err"] / eo})
+            log(f"BF16 error ratio vs the FP64 oracle: {b['err_ratio_vs_oracle']:.6f}")
     print(json.dumps(res), flush=True)
 
 

@@ -70,11 +70,13 @@ def threshold(eps: float, nu_x: float, nu_y: float) -> float:
 
 
 # ----------------------------------------------------------------------------- sketches
-def gaussian_sketches(seed: int, m: int, n: int, r: int, l: int, mode: str = "f64"):
+def gaussian_sketches(seed: int, m: int, n: int, r: int, l: int, mode: str = "f64",
+                      workers: int = 1):
     """X (n x r) on stream 1 and Y (m x (r+l)) on stream 2, as FP64 arrays holding
-    the values of the working precision ("f64", "f32" or "bf16")."""
-    X = philox.gaussian(seed, philox.STREAM_X, n, r)
-    Y = philox.gaussian(seed, philox.STREAM_Y, m, r + l)
+    the values of the working precision ("f64", "f32" or "bf16").  `workers`
+    host threads draw blocks of rows (same values)."""
+    X = philox.gaussian(seed, philox.STREAM_X, n, r, workers=workers)
+    Y = philox.gaussian(seed, philox.STREAM_Y, m, r + l, workers=workers)
     return round_mode(X, mode), round_mode(Y, mode)
 
 

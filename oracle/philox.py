@@ -30,12 +30,12 @@ Gaussian transform (Box-Muller in FP64): from words (w0, w1, w2, w3)
   z0 = sqrt(-2 ln u1) cos(2 pi u2),     z1 = sqrt(-2 ln u1) sin(2 pi u2).
 FP32 / BF16 sketches are the FP64 values rounded to nearest-even directly.
 
-Pins: the Gaussian and SRHT properties the paper relies on are checked in the CPU
-tests (moments, a Kolmogorov-Smirnov test against the normal CDF, decorrelation,
-sign balance, distinct sample indices, the Sylvester-Hadamard closed form against
-scipy.linalg.hadamard, X^T X = n' I).  The raw Philox words have no external
-known-answer vector in this repository: their parity is "unpinned" beyond the
-GPU-vs-CPU agreement and the statistical checks.
+Pins: the raw Philox4x32-10 words reproduce the generator's published
+known-answer vectors (Random123, SC'11; tests/golden/philox4x32_10_kat.json).  The
+Gaussian and SRHT properties the paper relies on are checked in the CPU tests
+(moments, a Kolmogorov-Smirnov test against the normal CDF, decorrelation, sign
+balance, distinct sample indices, the Sylvester-Hadamard closed form against
+scipy.linalg.hadamard, X^T X = n' I).
 """
 from __future__ import annotations
 
@@ -105,21 +105,36 @@ def box_muller(w0, w1, w2, w3):
 
 
 def gaussian(seed: int, stream: int, rows: int, cols: int,
-             row0: int = 0, col0: int = 0) -> np.ndarray:
-    """FP64 Gaussian sketch block G[row0:row0+rows, col0:col0+cols] (row-major)."""
+             row0: int = 0, col0: int = 0, workers: int = 1) -> np.ndarray:
+    """FP64 Gaussian sketch block G[row0:row0+rows, col0:col0+cols] (row-major).
+
+    Every element depends on its own counter only, so blocks of rows can be drawn
+    in any order: `workers` > 1 draws them on that many host threads (NumPy's
+    integer and transcendental loops release the interpreter lock); the values
+    are the same."""
     out = np.empty((rows, cols), dtype=np.float64)
     if rows == 0 or cols == 0:
         return out
     j = np.arange(col0, col0 + cols, dtype=np.int64)
     pair = (j >> 1).astype(np.uint64)
     odd = (j & 1).astype(bool)
-    chunk = max(1, (1 << 22) // max(cols, 1))
-    for r0 in range(0, rows, chunk):
+    chunk = max(1, (1 << 20) // max(cols, 1))
+
+    def block(r0):
         r1 = min(rows, r0 + chunk)
         i = np.arange(row0 + r0, row0 + r1, dtype=np.uint64)[:, None]
         w = philox4x32_10(i, pair[None, :], stream, 0, seed)
         z0, z1 = box_muller(*w)
         out[r0:r1] = np.where(odd[None, :], z1, z0)
+
+    starts = range(0, rows, chunk)
+    if workers > 1 and len(starts) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(block, starts))
+    else:
+        for r0 in starts:
+            block(r0)
     return out
 
 

@@ -2,7 +2,8 @@
 the single-problem path -- needs a GPU.
 
 A batch of the batched workload's recipe (sigma_i = 10^(-8 i / n), Gaussian X and
-Y, r + l <= 192) at reduced sizes:
+Y, r + l <= 192): ten problems at reduced sizes, r close to n, a tiny r, and two at
+the workload's largest sizes (4096 x 3000 with r = 128; 4000 x 700 with r = 100):
   * every problem's AX and Y^T A against FP64 products of the same FP32 inputs,
     entrywise within gamma_K of the magnitudes (FP32 accumulation over K terms);
   * every problem's kept rank against the oracle, and its error ||A - A_hat||_F
@@ -52,6 +53,8 @@ def batch_inputs(G):
     specs = W.batch_specs(10, seed=4, m_range=(256, 900), r_range=(8, 128))
     specs.append(W.BatchSpec(200, 130, 128, 64, (4 << 32) + 99, 40099))   # r close to n
     specs.append(W.BatchSpec(300, 140, 9, 5, (4 << 32) + 98, 40098))      # small r
+    specs.append(W.BatchSpec(4096, 3000, 128, 64, (4 << 32) + 97, 40097))  # the largest sizes
+    specs.append(W.BatchSpec(4000, 700, 100, 50, (4 << 32) + 96, 40096))   # tall, long K
     mats = [W.batch_host_matrix(b) for b in specs]
     probs = []
     for b, A in zip(specs, mats):

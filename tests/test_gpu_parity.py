@@ -75,7 +75,13 @@ def test_gaussian_f64_matches_oracle(G, layout):
     if layout == 1:
         got = got.T
     ref = OP.gaussian(11, 2, rows, cols, row0=r0, col0=c0)
-    assert np.max(ulp_diff(got, ref)) <= 8
+    # Both sides take the same 53-bit uniforms and the same rounded 2 pi u2; they
+    # differ only in the libraries' log, sqrt, cos and sin (each within about one
+    # ulp, the cosine and sine relative to their result), so z = sqrt(-2 ln u1) *
+    # cos(2 pi u2) may differ by a few ulp; 8 ulp is that sum with a margin.
+    d = ulp_diff(got, ref)
+    print(f"FP64 Gaussian: max {int(np.max(d))} ulp, {float(np.mean(d > 0)):.3f} not bit-equal")
+    assert np.max(d) <= 8
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
@@ -231,7 +237,13 @@ def test_pass_srht_integer_inputs_exact(G):
     assert np.array_equal(signs.cpu().numpy(), OP.srht_signs(4, npad))
     assert np.array_equal(idx.cpu().numpy(), OP.srht_sample(4, npad, r))
     X = OP.srht_matrix(4, n, r)
-    assert np.array_equal(host(AX), A.astype(np.float64) @ X)   # integers: exact
+    A64 = A.astype(np.float64)
+    assert np.array_equal(host(AX), A64 @ X)   # integers: exact
+    # Y^T A with the FP32 Gaussian Y: every entry within the inner-product bound
+    _, Y = OG.gaussian_sketches(4, m, n, r, 50, mode="f32")
+    ya = host(YtA)
+    assert np.all(np.abs(ya - Y.T @ A64) <= gamma(m) * (np.abs(Y.T) @ np.abs(A64)))
+    assert relerr(ya, Y.T @ A64) <= 1e-5
 
 
 # r + l <= 16 with an SRHT X: the single-read narrow pass (one 256-column chunk per

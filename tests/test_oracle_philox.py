@@ -5,12 +5,37 @@ The paper only requires i.i.d. zero-mean unit-variance Gaussian sketches
 of the oracle's generator, plus the closed form of the Sylvester-Hadamard matrix
 against scipy.linalg.hadamard and the bfloat16 rounding against torch.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.linalg as sla
 import scipy.stats as st
 
 from oracle import philox
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_philox_known_answer_vectors():
+    """The raw Philox4x32-10 words against the generator's published known-answer
+    vectors (Random123, SC'11): a wrong multiplier, Weyl constant, word order or
+    round count changes every output word."""
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.json")) as f:
+        kat = json.load(f)
+    for case in kat["cases"]:
+        c = [int(x, 16) for x in case["counter"]]
+        k0, k1 = (int(x, 16) for x in case["key"])
+        got = philox.philox4x32_10(c[0], c[1], c[2], c[3], (k1 << 32) | k0)
+        assert [int(w) for w in got] == [int(x, 16) for x in case["output"]], case
+    # vectorized: the same blocks in one call, in a different order
+    cs = np.array([[int(x, 16) for x in c["counter"]] for c in kat["cases"]][::-1], dtype=np.uint64)
+    for i, case in enumerate(kat["cases"][::-1]):
+        k0, k1 = (int(x, 16) for x in case["key"])
+        got = philox.philox4x32_10(cs[i:i + 1, 0], cs[i:i + 1, 1], cs[i:i + 1, 2], cs[i:i + 1, 3],
+                                   (k1 << 32) | k0)
+        assert [int(w[0]) for w in got] == [int(x, 16) for x in case["output"]]
 
 
 def test_gaussian_moments_and_ks():
