@@ -417,6 +417,19 @@ gn_status gn_residual(int64_t m, int64_t n, int64_t k, const void* A, int64_t ld
                       const double* G, int64_t ldg, double* out_sumsq, void* ws,
                       size_t ws_bytes, gn_stream_t stream);
 
+/* gn_residual for callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * the same result, bit for bit, with the per-tile partial sums kept in a 2 MiB
+ * device array compiled into the library (one per GPU, held until the process
+ * ends) instead of a workspace.  Limit: ceil(m/64) * ceil(n/64) <= 262144 tiles
+ * (m n <= 2^30, e.g. 32768 x 32768); larger sizes return GN_ERR_UNSUPPORTED
+ * before anything is enqueued.  Allocates nothing.  Calls that overlap in time on
+ * one GPU share the array and race: serialize them (one stream, or events). */
+gn_status gn_residual_noalloc(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
+                              int32_t a_dtype, const float* A_scales, const double* F,
+                              int64_t ldf, const double* G, int64_t ldg, double* out_sumsq,
+                              gn_stream_t stream);
+
 /* bfloat16 storage with power-of-two block scales: for each 128 x 128 block,
  * s = 2^ceil(log2 max|a|) (1 for an all-zero block), out = RNE_bf16(a / s).
  * A is m x n in a_dtype (GN_DT_F64 or GN_DT_F32); out is m x n bfloat16 bits

@@ -23,7 +23,7 @@ EXPORTED = (
     "gn_workspace_size", "gn_generate_gaussian", "gn_srht_generate", "gn_sketch_prepare",
     "gn_sketch_pass", "gn_sketch", "gn_core", "gn_core_check",
     "gn_factors", "gn_apply", "gn_backward", "gn_sketch_extend", "gn_sketch_append",
-    "gn_sketch_update", "gn_residual", "gn_quantize_bf16_bs",
+    "gn_sketch_update", "gn_residual", "gn_residual_noalloc", "gn_quantize_bf16_bs",
     "gn_batch_workspace_size", "gn_batch_prepare", "gn_batch_solve", "gn_status_string",
     "gn_version",
 )
@@ -116,6 +116,9 @@ def lib(path: str = LIB_PATH):
     L.gn_residual.argtypes = [c_int64, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
                               c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_size_t,
                               c_void_p]
+    L.gn_residual_noalloc.argtypes = [c_int64, c_int64, c_int64, c_void_p, c_int64, c_int32,
+                                      c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                      c_void_p]
     L.gn_quantize_bf16_bs.argtypes = [c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
                                       c_int64, c_void_p, c_void_p]
     for name in EXPORTED[:-2]:

@@ -265,6 +265,20 @@ def gn_residual(A: torch.Tensor, F: torch.Tensor, G: torch.Tensor, k: int | None
     return out
 
 
+def gn_residual_noalloc(A: torch.Tensor, F: torch.Tensor, G: torch.Tensor, k: int | None = None,
+                        scales=None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """gn_residual with the library's fixed device scratch array (no workspace);
+    `out` (a device double) may be given so that the call allocates nothing."""
+    m, n = A.shape
+    k = F.shape[1] if k is None else k
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=A.device)
+    C.check(C.lib().gn_residual_noalloc(m, n, k, _ptr(A), A.stride(0), DT_OF_TORCH[A.dtype],
+                                        _ptr(scales), _ptr(F), F.stride(0), _ptr(G), G.stride(0),
+                                        _ptr(out), _stream()), "gn_residual_noalloc")
+    return out
+
+
 def gn_quantize_bf16_bs(A: torch.Tensor):
     m, n = A.shape
     out = torch.empty(m, n, dtype=torch.bfloat16, device=A.device)
