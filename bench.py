@@ -30,7 +30,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}   # dense TFLOP/s (MI355X datasheet)
+PEAK = {"f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "f64": 78.6}   # dense TFLOP/s (MI355X datasheet)
 HBM_PEAK_GBS = 8000.0
 METRIC = "sketch-pass GB/s & TFLOP/s; GN solves/sec bf16 vs fp32 at equal error"
 
@@ -47,7 +47,7 @@ def srht_pad(n):
 def pass_algorithmic(w, npad):
     """(flops, bytes) the pass must do / move: A once, sketches once, outputs once."""
     m, n, r, rl = w.m, w.n, w.r, w.r + w.l
-    es = {"f64": 8, "f32": 4, "bf16": 2}[w.mode]
+    es = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[w.mode]
     acc = 8 if w.mode == "f64" else 4
     flops = 2.0 * m * n * rl
     byts = m * n * es + m * rl * es + (m * r + rl * n) * acc
@@ -57,14 +57,15 @@ def pass_algorithmic(w, npad):
     else:
         flops += 2.0 * m * n * r
         byts += n * r * es
-    if w.mode == "bf16":
+    if w.mode in ("bf16", "f16"):
         byts += 4 * ((m + 127) // 128) * ((n + 127) // 128)
     return flops, byts
 
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("pass.hip", "gemm_tiles.h", "gn_internal.h", "lane_ops.h"):
+    for f in ("pass.hip", "pass_narrow.hip", "gemm_tiles.h", "gemm_h16.h", "gn_internal.h",
+              "lane_ops.h"):
         with open(os.path.join(ROOT, "paper_2009_11392_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -320,6 +321,56 @@ def stabilize_bench(gn, run, steps=3, warmup=1):
     return out
 
 
+def r_sweep(gn, W, A32, steps=3, warmup=1,
+            rs=(4, 8, 16, 32, 64, 128, 256, 512, 1000, 2000)):
+    """The sketch pass alone on the 32768^2 matrix with Gaussian X and Y over r
+    (l = ceil(r/2)), in FP32 and in BF16 with block scales: the pass is bound by
+    HBM bandwidth at small r (about r < 16 in FP32, r < 125 in BF16) and by the
+    matrix cores above; each point reports its algorithmic bytes and flops, the
+    bound, the achieved rate and the fraction of that bound's peak."""
+    import torch
+    out = {"shape": "32768x32768, Gaussian X and Y, l = ceil(r/2)", "points": []}
+    for mode, base in (("f32", W.F32_32K), ("bf16", W.BF16_32K)):
+        if mode == "bf16":
+            A, sc = gn.gn_quantize_bf16_bs(A32)
+        else:
+            A, sc = A32, None
+        for r in rs:
+            wl = base.scaled(base.m, base.n, r=r)
+            p = gn.Problem(wl.m, wl.n, wl.r, wl.l, seed=wl.seed, mode=mode, eps=wl.eps)
+            ws = gn.workspace(p, gn.C.GN_OP_SKETCH)
+            AX = torch.empty(wl.m, wl.r, dtype=torch.float32, device="cuda")
+            YtA = torch.empty(p.rl, wl.n, dtype=torch.float32, device="cuda")
+            gn.gn_sketch_prepare(p, ws)
+            for _ in range(warmup):
+                gn.gn_sketch_pass(p, A, ws, scales=sc, AX=AX, YtA=YtA)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            for _ in range(steps):
+                gn.gn_sketch_pass(p, A, ws, scales=sc, AX=AX, YtA=YtA)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / steps
+            fl, by = pass_algorithmic(wl, srht_pad(wl.n))
+            t_hbm, t_mma = by / (HBM_PEAK_GBS * 1e9), fl / (PEAK[mode] * 1e12)
+            bound = "hbm" if t_hbm >= t_mma else "mfma"
+            ach = by / (ms / 1e3) / 1e9 if bound == "hbm" else fl / (ms / 1e3) / 1e12
+            peak = HBM_PEAK_GBS if bound == "hbm" else PEAK[mode]
+            pt = {"mode": mode, "r": r, "l": wl.l, "pass_ms": ms, "algorithmic_bytes": by,
+                  "algorithmic_flops": fl, "bound": bound, "achieved": ach,
+                  "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "peak": peak,
+                  "frac": ach / peak, "gbps": by / (ms / 1e3) / 1e9,
+                  "tflops": fl / (ms / 1e3) / 1e12}
+            out["points"].append(pt)
+            log(f"r-sweep {mode} r={r}: {ms:.3f} ms, {pt['gbps']:.0f} GB/s, "
+                f"{pt['tflops']:.1f} TFLOP/s, {bound} frac {pt['frac']:.3f}")
+            del ws, AX, YtA
+        del A, sc
+        torch.cuda.empty_cache()
+    return out
+
+
 def host_threads():
     return max(1, min(16, len(os.sched_getaffinity(0))))
 
@@ -404,6 +455,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--no-small-r", action="store_true",
                     help="skip the small-r (HBM-bound) pass measurement")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the r-sweep of the sketch pass (FP32 and BF16, r = 4 .. 2000)")
     ap.add_argument("--no-stab", action="store_true",
                     help="skip the timing of the other core stabilizations and the check")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -426,10 +479,13 @@ def main():
     w = W.ALL[args.workload]
     npad = srht_pad(w.n)
     log(f"generating {w.name} on the device")
-    A32 = W.device_matrix(w if w.mode != "bf16" else W.F32_32K, host_factors=args.host_factors)
+    A32 = W.device_matrix(w if w.mode not in ("bf16", "f16") else W.F32_32K,
+                          host_factors=args.host_factors)
     scales = None
     if w.mode == "bf16":
         A, scales = gn.gn_quantize_bf16_bs(A32)
+    elif w.mode == "f16":
+        A, scales = gn.gn_quantize_f16_bs(A32)
     elif w.mode == "f64":
         A = A32.double()
     else:
@@ -464,7 +520,7 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     res = {"metric": METRIC, "value": tflops, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": t["step"], "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": {"f32": "f32", "bf16": "bf16", "f64": "f64"}[w.mode],
+           "scaling": "weak", "vs_baseline": None, "dtype": w.mode,
            "data": "synthetic (seeded spectrum-controlled matrix generated on the device)",
            "config": {"workload": w.name, "m": w.m, "n": w.n, "r": w.r, "l": w.l,
                       "sketch_x": w.kind_x, "sketch_y": w.kind_y, "pass_precision": w.mode,
@@ -503,10 +559,12 @@ def main():
 
     if not args.no_compare and w.m == 32768 and w.n == 32768:
         cmp = {}
-        for tag, wl in (("bf16", W.BF16_32K), ("f32", W.F32_32K)):
+        for tag, wl in (("bf16", W.BF16_32K), ("f16", W.F16_32K), ("f32", W.F32_32K)):
             log(f"comparison: {wl.name}")
             if tag == "bf16":
                 Ab, sc = gn.gn_quantize_bf16_bs(A32)
+            elif tag == "f16":
+                Ab, sc = gn.gn_quantize_f16_bs(A32)
             else:
                 Ab, sc = A32, None
             rr = Runner(gn, wl, Ab, sc, A_ref=A32)
@@ -524,8 +582,15 @@ def main():
         cmp["speedup_solves_per_sec"] = cmp["bf16"]["solves_per_sec"] / cmp["f32"]["solves_per_sec"]
         cmp["speedup_pass"] = cmp["f32"]["pass_ms"] / cmp["bf16"]["pass_ms"]
         cmp["err_ratio_bf16_over_f32"] = cmp["bf16"]["rel_err"] / cmp["f32"]["rel_err"]
+        cmp["f16_speedup_solves_per_sec"] = cmp["f16"]["solves_per_sec"] / cmp["f32"]["solves_per_sec"]
+        cmp["f16_speedup_pass"] = cmp["f32"]["pass_ms"] / cmp["f16"]["pass_ms"]
+        cmp["err_ratio_f16_over_f32"] = cmp["f16"]["rel_err"] / cmp["f32"]["rel_err"]
         cmp["shape"] = "32768x32768, Gaussian X and Y, r=2000, l=1000, same matrix"
         res["bf16_vs_fp32"] = cmp
+
+    if not args.no_sweep and w.m == 32768 and w.n == 32768:
+        log("r-sweep of the sketch pass (FP32 and BF16, Gaussian X and Y)")
+        res["r_sweep"] = r_sweep(gn, W, A32)
 
     if not args.no_grad:
         log("reverse mode: grad_8192x4096_f32")
@@ -553,12 +618,13 @@ def main():
             res["error"]["err_ratio_vs_oracle"] = res["error"]["abs_fro"] / cb["abs_err"]
             log(f"error ratio vs the FP64 oracle: {res['error']['err_ratio_vs_oracle']:.6f}")
         if "bf16_vs_fp32" in res:
-            log("FP64 oracle on the BF16 variant's sketch values (unquantized matrix)")
-            eo, ro, ko = oracle_error(A32, W.BF16_32K)
-            b = res["bf16_vs_fp32"]["bf16"]
-            b.update({"oracle_rel_err": ro, "oracle_kept_rank": ko,
-                      "err_ratio_vs_oracle": b["abs_err"] / eo})
-            log(f"BF16 error ratio vs the FP64 oracle: {b['err_ratio_vs_oracle']:.6f}")
+            for tag, wl in (("bf16", W.BF16_32K), ("f16", W.F16_32K)):
+                log(f"FP64 oracle on the {tag} variant's sketch values (unquantized matrix)")
+                eo, ro, ko = oracle_error(A32, wl)
+                b = res["bf16_vs_fp32"][tag]
+                b.update({"oracle_rel_err": ro, "oracle_kept_rank": ko,
+                          "err_ratio_vs_oracle": b["abs_err"] / eo})
+                log(f"{tag} error ratio vs the FP64 oracle: {b['err_ratio_vs_oracle']:.6f}")
     print(json.dumps(res), flush=True)
 
 

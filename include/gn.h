@@ -14,7 +14,8 @@
  *                   the approximant itself,
  *   gn_backward   -- the reverse mode: dL/dA from dL/dA_hat,
  *   gn_residual   -- ||A - F G||_F^2 formed tile by tile (error measurement),
- *   gn_quantize_bf16_bs -- bfloat16 storage of A with power-of-two block scales.
+ *   gn_quantize_bf16_bs / gn_quantize_f16_bs -- bfloat16 or binary16 storage of
+ *                   A with power-of-two block scales.
  *
  * Conventions (every entry point):
  *   * Pointers are device pointers unless marked (host).  All matrices are
@@ -69,11 +70,14 @@ typedef enum { GN_SKETCH_GAUSSIAN = 0, GN_SKETCH_SRHT = 1, GN_SKETCH_USER = 2 } 
 typedef enum {
   GN_MODE_F64 = 0,     /* A, X, Y double; AX, Y^T A double (FP64 accumulation)      */
   GN_MODE_F32 = 1,     /* A, X, Y float;  AX, Y^T A float  (FP32 accumulation)      */
-  GN_MODE_BF16_BS = 2  /* A bfloat16 with one float scale per 128x128 block,
+  GN_MODE_BF16_BS = 2, /* A bfloat16 with one float scale per 128x128 block,
                           X, Y bfloat16; AX, Y^T A float (FP32 accumulation)        */
+  GN_MODE_F16_BS = 3   /* A IEEE binary16 with one float scale per 128x128 block
+                          (which keeps small entries out of the binary16 subnormal
+                          range), X, Y binary16; AX, Y^T A float (FP32 accumulation) */
 } gn_mode;
 
-typedef enum { GN_DT_F64 = 0, GN_DT_F32 = 1, GN_DT_BF16 = 2 } gn_dtype;
+typedef enum { GN_DT_F64 = 0, GN_DT_F32 = 1, GN_DT_BF16 = 2, GN_DT_F16 = 3 } gn_dtype;
 
 /* How gn_core stabilizes the core pseudoinverse (Section 5.1.1).  tau is the
  * threshold of gn_problem; the perturbations (LIFT_*) need eps > 0.
@@ -190,7 +194,7 @@ gn_status gn_srht_generate(uint64_t seed, int64_t n, int64_t r, int8_t* signs, i
 /* Sketches for the pass (Algorithm 2.1, step 1), written into the workspace
  * ws (gn_workspace_size(GN_OP_SKETCH) bytes), which gn_sketch_pass then reads:
  * Gaussian X (stream 1) and Y (stream 2) drawn on the device from `seed` in the
- * mode's sketch dtype (double, float or bfloat16), or the USER matrices
+ * mode's sketch dtype (double, float, bfloat16 or binary16), or the USER matrices
  * X_user (n x r, ld ldx) / Y_user (m x (r+l), ld ldy) in that dtype, or for an
  * SRHT X its signs and sample (copied to signs_out / idx_out when non-NULL, as
  * in gn_srht_generate).  One prepared workspace serves any number of passes
@@ -201,9 +205,10 @@ gn_status gn_sketch_prepare(const gn_problem* p, const void* X_user, int64_t ldx
 
 /* The sketch pass (Algorithm 2.1, step 2): AX (m x r) and Y^T A ((r+l) x n)
  * from A (m x n, row stride lda >= n), with the sketches of a prepared ws.
- * In FP32 and BF16 modes this is one kernel launch.
- *   A        : mode dtype (double, float, or bfloat16 bits for BF16_BS).
- *   A_scales : BF16_BS only: float[ceil(m/128) * ceil(n/128)], row-major, the
+ * In FP32, BF16 and F16 modes this is one kernel launch.
+ *   A        : mode dtype (double, float, or bfloat16 / binary16 bits for
+ *              BF16_BS / F16_BS).
+ *   A_scales : BF16_BS and F16_BS only: float[ceil(m/128) * ceil(n/128)], row-major, the
  *              scale of each 128 x 128 block (A = scale * stored value).
  *   AX, YtA  : outputs in the accumulation dtype (double for F64, float else),
  *              row strides ldax >= r and ldya >= n.
@@ -230,7 +235,7 @@ gn_status gn_sketch(const gn_problem* p, const void* A, int64_t lda, const float
  * followed by two QRs (LIFT_RRQR); or R's diagonal raised (LIFT_DIAG).  See
  * gn_core_out for what each leaves in `out`.  AX as produced by gn_sketch (ld
  * ldax).  YtA (ld ldya >= n, 16-byte aligned) may be NULL; when it is given
- * with an SRHT X in FP32 or BF16 mode, C is formed as (Y^T A) X instead: the
+ * with an SRHT X in FP32, BF16 or F16 mode, C is formed as (Y^T A) X instead: the
  * r + l rows of Y^T A sign-flipped, Walsh-Hadamard transformed and sampled in
  * FP64 (Section 2.3 costs the core this way, O(n (r + l) log n) instead of the
  * O(m r (r + l)) product; Y is then not regenerated), and in every other case it
@@ -310,7 +315,7 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
  * entries at new indices of the same streams: the updated AX and Y^T A equal the
  * products a fresh gn_sketch of the enlarged problem would give (up to rounding).
  * The core is then recomputed with gn_core on the enlarged problem (O(r^3)).
- * FP64 and FP32 modes, Gaussian Y; X Gaussian or SRHT except where noted; BF16
+ * FP64 and FP32 modes, Gaussian Y; X Gaussian or SRHT except where noted; BF16, F16
  * and USER sketches return GN_ERR_UNSUPPORTED.  Workspace:
  * gn_workspace_size(<enlarged problem>, GN_OP_UPDATE). */
 
@@ -410,7 +415,7 @@ gn_status gn_batch_solve(const gn_batch_plan* plan /*host*/, int32_t stages, voi
 
 /* ||A - F G||_F^2 accumulated in FP64, tile by tile (no Gram-matrix shortcut),
  * written to *out_sumsq (device double).  A is m x n in `a_dtype` (for
- * GN_DT_BF16, A_scales as in gn_sketch, else NULL); F m x k (ld ldf), G k x n
+ * GN_DT_BF16 and GN_DT_F16, A_scales as in gn_sketch, else NULL); F m x k (ld ldf), G k x n
  * (ld ldg), both double.  The reduction order is fixed (deterministic). */
 gn_status gn_residual(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
                       int32_t a_dtype, const float* A_scales, const double* F, int64_t ldf,
@@ -436,6 +441,11 @@ gn_status gn_residual_noalloc(int64_t m, int64_t n, int64_t k, const void* A, in
  * (ld ldo); scales float[ceil(m/128) * ceil(n/128)]. */
 gn_status gn_quantize_bf16_bs(int64_t m, int64_t n, const void* A, int64_t lda, int32_t a_dtype,
                               uint16_t* out, int64_t ldo, float* scales, gn_stream_t stream);
+
+/* binary16 storage with power-of-two block scales (GN_MODE_F16_BS): the same
+ * blocks and scales as gn_quantize_bf16_bs, out = RNE_binary16(a / s) (bits). */
+gn_status gn_quantize_f16_bs(int64_t m, int64_t n, const void* A, int64_t lda, int32_t a_dtype,
+                             uint16_t* out, int64_t ldo, float* scales, gn_stream_t stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* gn_status_string(int32_t s);

@@ -87,7 +87,45 @@ def round_mode(x: np.ndarray, mode: str) -> np.ndarray:
         return philox.round_fp32(x).astype(np.float64)
     if mode == "bf16":
         return philox.round_bf16(x)
+    if mode == "f16":
+        return philox.round_f16(x)
     raise ValueError(mode)
+
+
+def block_scales(A: np.ndarray, block: int = 128) -> np.ndarray:
+    """s = 2**ceil(log2 max|a|) for each block x block tile of A (1 for an
+    all-zero tile), as FP64 ceil(m/block) x ceil(n/block)."""
+    A = np.asarray(A, np.float64)
+    m, n = A.shape
+    mb, nb = -(-m // block), -(-n // block)
+    scales = np.ones((mb, nb), np.float64)
+    for bi in range(mb):
+        for bj in range(nb):
+            t = A[bi * block:(bi + 1) * block, bj * block:(bj + 1) * block]
+            mx = float(np.max(np.abs(t))) if t.size else 0.0
+            if mx > 0.0:
+                f, e = math.frexp(mx)          # mx = f * 2**e, f in [0.5, 1)
+                scales[bi, bj] = math.ldexp(1.0, e - 1 if f == 0.5 else e)
+    return scales
+
+
+def block_quantize_f16(A: np.ndarray, block: int = 128):
+    """Per-block power-of-two scaling and IEEE binary16 storage of A: the scales
+    of block_scales and the stored value RNE_binary16(a / s).  Returns (bits
+    uint16 m x n, scales float32).  The scale puts each block's largest entry in
+    [0.5, 1], so entries down to 2^-14 of it stay out of the subnormal range."""
+    A = np.asarray(A, np.float64)
+    m, n = A.shape
+    scales = block_scales(A, block)
+    s_full = np.repeat(np.repeat(scales, block, 0), block, 1)[:m, :n]
+    bits = (A / s_full).astype(np.float16).view(np.uint16)
+    return bits, scales.astype(np.float32)
+
+
+def block_dequantize_f16(bits: np.ndarray, scales: np.ndarray, block: int = 128):
+    m, n = bits.shape
+    s_full = np.repeat(np.repeat(scales.astype(np.float64), block, 0), block, 1)[:m, :n]
+    return np.asarray(bits, np.uint16).view(np.float16).astype(np.float64) * s_full
 
 
 def block_quantize_bf16(A: np.ndarray, block: int = 128):

@@ -138,6 +138,12 @@ def gaussian(seed: int, stream: int, rows: int, cols: int,
     return out
 
 
+def round_f16(x: np.ndarray) -> np.ndarray:
+    """Round FP64 to IEEE binary16, nearest-even, in one step (NumPy converts
+    double to half directly, subnormals included), returned as FP64."""
+    return np.asarray(x, np.float64).astype(np.float16).astype(np.float64)
+
+
 def round_fp32(x: np.ndarray) -> np.ndarray:
     """Round FP64 to FP32, nearest-even (returned as float32)."""
     return np.asarray(x, np.float64).astype(np.float32)

@@ -12,9 +12,9 @@ LIB_PATH = os.path.join(HERE, "libgn.so")
 GN_OK, GN_ERR_ARG, GN_ERR_SHAPE, GN_ERR_DTYPE, GN_ERR_ALIGN = 0, 1, 2, 3, 4
 GN_ERR_WORKSPACE, GN_ERR_HIP, GN_ERR_NUMERIC, GN_ERR_UNSUPPORTED = 5, 6, 7, 8
 GN_SKETCH_GAUSSIAN, GN_SKETCH_SRHT, GN_SKETCH_USER = 0, 1, 2
-GN_MODE_F64, GN_MODE_F32, GN_MODE_BF16_BS = 0, 1, 2
+GN_MODE_F64, GN_MODE_F32, GN_MODE_BF16_BS, GN_MODE_F16_BS = 0, 1, 2, 3
 GN_BATCH_PASS, GN_BATCH_CORE, GN_BATCH_ALL = 1, 2, 3
-GN_DT_F64, GN_DT_F32, GN_DT_BF16 = 0, 1, 2
+GN_DT_F64, GN_DT_F32, GN_DT_BF16, GN_DT_F16 = 0, 1, 2, 3
 (GN_OP_SKETCH, GN_OP_CORE, GN_OP_FACTORS, GN_OP_APPLY, GN_OP_RESIDUAL, GN_OP_SRHT,
  GN_OP_BACKWARD, GN_OP_MATERIALIZE, GN_OP_UPDATE, GN_OP_CHECK) = range(10)
 (GN_CORE_QR, GN_CORE_SVD, GN_CORE_LIFT_SVD, GN_CORE_LIFT_RRQR, GN_CORE_LIFT_DIAG) = range(5)
@@ -24,6 +24,7 @@ EXPORTED = (
     "gn_sketch_pass", "gn_sketch", "gn_core", "gn_core_check",
     "gn_factors", "gn_apply", "gn_backward", "gn_sketch_extend", "gn_sketch_append",
     "gn_sketch_update", "gn_residual", "gn_residual_noalloc", "gn_quantize_bf16_bs",
+    "gn_quantize_f16_bs",
     "gn_batch_workspace_size", "gn_batch_prepare", "gn_batch_solve", "gn_status_string",
     "gn_version",
 )
@@ -121,6 +122,8 @@ def lib(path: str = LIB_PATH):
                                       c_void_p]
     L.gn_quantize_bf16_bs.argtypes = [c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
                                       c_int64, c_void_p, c_void_p]
+    L.gn_quantize_f16_bs.argtypes = [c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
+                                     c_int64, c_void_p, c_void_p]
     for name in EXPORTED[:-2]:
         getattr(L, name).restype = c_int32
     L.gn_status_string.argtypes = [c_int32]

@@ -64,7 +64,7 @@ gn_status side_stream(SideStream** out) {
 gn_status make_plan(const gn_problem* p, Plan& P) {
   if (!p) return GN_ERR_ARG;
   if (p->core_method < GN_CORE_QR || p->core_method > GN_CORE_LIFT_DIAG) return GN_ERR_ARG;
-  if (p->mode < GN_MODE_F64 || p->mode > GN_MODE_BF16_BS) return GN_ERR_ARG;
+  if (p->mode < GN_MODE_F64 || p->mode > GN_MODE_F16_BS) return GN_ERR_ARG;
   if (p->kind_x < GN_SKETCH_GAUSSIAN || p->kind_x > GN_SKETCH_USER) return GN_ERR_ARG;
   if (p->kind_y != GN_SKETCH_GAUSSIAN && p->kind_y != GN_SKETCH_USER) return GN_ERR_ARG;
   if (!isfinite(p->eps) || !isfinite(p->nu_x) || !isfinite(p->nu_y)) return GN_ERR_ARG;
@@ -142,7 +142,7 @@ CoreWs core_ws(const Plan& P) {
   // unless USER); widened to float in F32 / BF16 modes.
   if (P.mode == GN_MODE_F64) {
     if (P.ky == GN_SKETCH_GAUSSIAN) off += align_up((size_t)P.rl * P.m * 8);
-  } else if (P.ky == GN_SKETCH_GAUSSIAN || P.mode == GN_MODE_BF16_BS) {
+  } else if (P.ky == GN_SKETCH_GAUSSIAN || is_h16_mode(P.mode)) {
     off += align_up((size_t)P.rl * P.m * 4);
   }
   w.c = off;
@@ -309,6 +309,8 @@ __global__ void __launch_bounds__(256) widen_gated(int64_t rows, int64_t cols, c
     v = reinterpret_cast<const double*>(src)[i * lds + j];
   else if (dt == GN_DT_F32)
     v = (double)reinterpret_cast<const float*>(src)[i * lds + j];
+  else if (dt == GN_DT_F16)
+    v = (double)f16_bits_to_f32(reinterpret_cast<const uint16_t*>(src)[i * lds + j]);
   else
     v = (double)bf16_bits_to_f32(reinterpret_cast<const uint16_t*>(src)[i * lds + j]);
   dst[i * ldd + j] = v;
@@ -373,7 +375,7 @@ gn_status gn_generate_gaussian(uint64_t seed, int32_t stream, int64_t row0, int6
                                int64_t rows, int64_t cols, int32_t dtype, int32_t layout, void* out,
                                int64_t ld, gn_stream_t stream_) {
   if (!out) return GN_ERR_ARG;
-  if (dtype < GN_DT_F64 || dtype > GN_DT_BF16 || (layout != 0 && layout != 1)) return GN_ERR_ARG;
+  if (dtype < GN_DT_F64 || dtype > GN_DT_F16 || (layout != 0 && layout != 1)) return GN_ERR_ARG;
   if (rows < 0 || cols < 0 || row0 < 0 || col0 < 0) return GN_ERR_SHAPE;
   if (row0 + rows > ((int64_t)1 << 32) || ((col0 + cols) >> 1) > ((int64_t)1 << 32))
     return GN_ERR_UNSUPPORTED;
@@ -411,7 +413,7 @@ gn_status gn_sketch_prepare(const gn_problem* p, const void* X_user, int64_t ldx
   char* base = (char*)ws;
   // Algorithm 2.1, step 1: the sketches.  FP64/FP32 passes read X (n x r) and
   // Y (m x (r+l)) row-major; the BF16 pass reads them transposed (k-contiguous).
-  const int lay = (P.mode == GN_MODE_BF16_BS) ? 1 : 0;
+  const int lay = is_h16_mode(P.mode) ? 1 : 0;
   const size_t es = dtype_size(P.sdt);
   if (P.ky == GN_SKETCH_GAUSSIAN) {
     GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, P.sdt, lay, base + W.yt, lay ? P.m : P.rl, s));
@@ -450,7 +452,7 @@ gn_status gn_sketch_pass(const gn_problem* p, const void* A, int64_t lda, const 
   Plan P;
   GN_TRY(make_plan(p, P));
   if (!A || !AX || !YtA || !ws) return GN_ERR_ARG;
-  if (P.mode == GN_MODE_BF16_BS && !A_scales) return GN_ERR_ARG;
+  if (is_h16_mode(P.mode) && !A_scales) return GN_ERR_ARG;
   if (lda < P.n || ldax < P.r || ldya < P.n) return GN_ERR_SHAPE;
   if (!aligned16(A) || !aligned16(AX) || !aligned16(YtA) || !aligned16(ws)) return GN_ERR_ALIGN;
   const SketchWs W = sketch_ws(P);
@@ -469,7 +471,7 @@ gn_status gn_sketch(const gn_problem* p, const void* A, int64_t lda, const float
   GN_TRY(make_plan(p, P));
   // validate the pass arguments before anything is enqueued
   if (!A || !AX || !YtA || !ws) return GN_ERR_ARG;
-  if (P.mode == GN_MODE_BF16_BS && !A_scales) return GN_ERR_ARG;
+  if (is_h16_mode(P.mode) && !A_scales) return GN_ERR_ARG;
   if (lda < P.n || ldax < P.r || ldya < P.n) return GN_ERR_SHAPE;
   if (!aligned16(A) || !aligned16(AX) || !aligned16(YtA) || !aligned16(ws)) return GN_ERR_ALIGN;
   GN_TRY(gn_sketch_prepare(p, X_user, ldx, Y_user, ldy, signs_out, idx_out, ws, ws_bytes, stream));
@@ -530,13 +532,15 @@ gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void*
     const float* Yf;
     int64_t ldyf;
     if (P.ky == GN_SKETCH_GAUSSIAN) {
-      const int32_t gdt = (P.mode == GN_MODE_BF16_BS) ? kDtBf16AsF32 : GN_DT_F32;
+      const int32_t gdt = (P.mode == GN_MODE_BF16_BS)   ? kDtBf16AsF32
+                          : (P.mode == GN_MODE_F16_BS) ? kDtF16AsF32
+                                                       : GN_DT_F32;
       GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, gdt, 0, base + W.yt, P.rl, s));
       Yf = (const float*)(base + W.yt);
       ldyf = P.rl;
-    } else if (P.mode == GN_MODE_BF16_BS) {
-      GN_TRY(launch_widen_bf16(P.m, P.rl, (const uint16_t*)Y_user, ldy, (float*)(base + W.yt),
-                               P.rl, s));
+    } else if (is_h16_mode(P.mode)) {
+      GN_TRY(launch_widen_h16(P.m, P.rl, (const uint16_t*)Y_user, ldy, P.mode == GN_MODE_F16_BS,
+                              (float*)(base + W.yt), P.rl, s));
       Yf = (const float*)(base + W.yt);
       ldyf = P.rl;
     } else {
@@ -1015,8 +1019,8 @@ gn_status gn_residual(int64_t m, int64_t n, int64_t k, const void* A, int64_t ld
                       int64_t ldg, double* out_sumsq, void* ws, size_t ws_bytes,
                       gn_stream_t stream_) {
   if (!A || !F || !G || !out_sumsq || !ws) return GN_ERR_ARG;
-  if (a_dtype < GN_DT_F64 || a_dtype > GN_DT_BF16) return GN_ERR_ARG;
-  if (a_dtype == GN_DT_BF16 && !A_scales) return GN_ERR_ARG;
+  if (a_dtype < GN_DT_F64 || a_dtype > GN_DT_F16) return GN_ERR_ARG;
+  if ((a_dtype == GN_DT_BF16 || a_dtype == GN_DT_F16) && !A_scales) return GN_ERR_ARG;
   if (m < 1 || n < 1 || k < 0 || lda < n || ldf < k || ldg < n) return GN_ERR_SHAPE;
   if (ws_bytes < residual_ws_bytes(m, n)) return GN_ERR_WORKSPACE;
   if (((uintptr_t)ws & 7u) != 0) return GN_ERR_ALIGN;
@@ -1030,7 +1034,15 @@ gn_status gn_quantize_bf16_bs(int64_t m, int64_t n, const void* A, int64_t lda, 
   if (!A || !out || !scales) return GN_ERR_ARG;
   if (a_dtype != GN_DT_F64 && a_dtype != GN_DT_F32) return GN_ERR_DTYPE;
   if (m < 1 || n < 1 || lda < n || ldo < n) return GN_ERR_SHAPE;
-  return launch_quantize(m, n, A, lda, a_dtype, out, ldo, scales, (hipStream_t)stream);
+  return launch_quantize(m, n, A, lda, a_dtype, out, ldo, scales, (hipStream_t)stream, false);
+}
+
+gn_status gn_quantize_f16_bs(int64_t m, int64_t n, const void* A, int64_t lda, int32_t a_dtype,
+                             uint16_t* out, int64_t ldo, float* scales, gn_stream_t stream) {
+  if (!A || !out || !scales) return GN_ERR_ARG;
+  if (a_dtype != GN_DT_F64 && a_dtype != GN_DT_F32) return GN_ERR_DTYPE;
+  if (m < 1 || n < 1 || lda < n || ldo < n) return GN_ERR_SHAPE;
+  return launch_quantize(m, n, A, lda, a_dtype, out, ldo, scales, (hipStream_t)stream, true);
 }
 
 }  // extern "C"

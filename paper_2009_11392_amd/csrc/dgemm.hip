@@ -23,6 +23,7 @@ constexpr int D_BM = 64, D_BN = 64, D_BK = 16;
 __device__ __forceinline__ double ld_elem(const void* p, int32_t dt, int64_t off) {
   if (dt == GN_DT_F64) return reinterpret_cast<const double*>(p)[off];
   if (dt == GN_DT_F32) return (double)reinterpret_cast<const float*>(p)[off];
+  if (dt == GN_DT_F16) return (double)f16_bits_to_f32(reinterpret_cast<const uint16_t*>(p)[off]);
   return (double)bf16_bits_to_f32(reinterpret_cast<const uint16_t*>(p)[off]);
 }
 
@@ -224,13 +225,15 @@ __global__ void __launch_bounds__(256) dgemm_reduce(DArgs g) {
 constexpr int NW_N = 16, NW_RW = 2, NW_T = 512, NW_KC = 256;
 constexpr int NT_T = 256, NT_KC = 16;
 
-// A's entries in their stored type (FP64, FP32, or BF16 widened to FP32 exactly).
+// A's entries in their stored type (FP64, FP32, or BF16 / binary16 widened to FP32
+// exactly).
 template <int DT> struct NwElem { using T = float; };
 template <> struct NwElem<GN_DT_F64> { using T = double; };
 template <int DT>
 __device__ __forceinline__ typename NwElem<DT>::T nw_load(const void* p, int64_t off) {
   if constexpr (DT == GN_DT_F64) return reinterpret_cast<const double*>(p)[off];
   else if constexpr (DT == GN_DT_F32) return reinterpret_cast<const float*>(p)[off];
+  else if constexpr (DT == GN_DT_F16) return f16_bits_to_f32(reinterpret_cast<const uint16_t*>(p)[off]);
   else return bf16_bits_to_f32(reinterpret_cast<const uint16_t*>(p)[off]);
 }
 
@@ -406,7 +409,8 @@ __global__ void __launch_bounds__(256) residual_kernel(DArgs g, RArgs rr) {
         d_coord(x, y, v, i0, j0, i, j);
         if (i >= g.M || j >= g.N) continue;
         double ref = ld_elem(rr.ref.p, rr.ref.dtype, i * rr.ref.rs + j * rr.ref.cs);
-        if (rr.ref.dtype == GN_DT_BF16) ref *= (double)rr.ref_scales[(i >> 7) * rr.nsb + (j >> 7)];
+        if (rr.ref.dtype == GN_DT_BF16 || rr.ref.dtype == GN_DT_F16)
+          ref *= (double)rr.ref_scales[(i >> 7) * rr.nsb + (j >> 7)];
         const double d = ref - acc[x][y][v];
         ss = fma(d, d, ss);
       }
@@ -447,7 +451,9 @@ static bool narrow_eligible(int64_t M, int64_t N, int64_t K, const MatRef& A, co
   const MatRef& wide = N <= NW_N ? A : B;
   const MatRef& thin = N <= NW_N ? B : A;
   if (thin.dtype != GN_DT_F64) return false;
-  if (wide.dtype != GN_DT_F64 && wide.dtype != GN_DT_F32 && wide.dtype != GN_DT_BF16) return false;
+  if (wide.dtype != GN_DT_F64 && wide.dtype != GN_DT_F32 && wide.dtype != GN_DT_BF16 &&
+      wide.dtype != GN_DT_F16)
+    return false;
   if (N <= NW_N) return A.cs == 1 || A.rs == 1;
   if (M <= NW_N) return B.rs == 1 || B.cs == 1;  // B^T is k- or m-contiguous
   return false;
@@ -520,6 +526,8 @@ gn_status launch_dgemm_to(int64_t M, int64_t N, int64_t K, double alpha, MatRef 
         dgemm_narrow<GN_DT_F64><<<grid, dim3(NW_T), 0, s>>>(g);
       else if (dt == GN_DT_F32)
         dgemm_narrow<GN_DT_F32><<<grid, dim3(NW_T), 0, s>>>(g);
+      else if (dt == GN_DT_F16)
+        dgemm_narrow<GN_DT_F16><<<grid, dim3(NW_T), 0, s>>>(g);
       else
         dgemm_narrow<GN_DT_BF16><<<grid, dim3(NW_T), 0, s>>>(g);
     } else {
@@ -527,6 +535,8 @@ gn_status launch_dgemm_to(int64_t M, int64_t N, int64_t K, double alpha, MatRef 
         dgemm_narrow_t<GN_DT_F64><<<grid, dim3(NT_T), 0, s>>>(g);
       else if (dt == GN_DT_F32)
         dgemm_narrow_t<GN_DT_F32><<<grid, dim3(NT_T), 0, s>>>(g);
+      else if (dt == GN_DT_F16)
+        dgemm_narrow_t<GN_DT_F16><<<grid, dim3(NT_T), 0, s>>>(g);
       else
         dgemm_narrow_t<GN_DT_BF16><<<grid, dim3(NT_T), 0, s>>>(g);
     }

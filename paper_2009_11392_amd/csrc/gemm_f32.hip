@@ -159,13 +159,14 @@ __global__ void __launch_bounds__(256) splitk_sum_f32(const float* partial, int6
   D[i * ldd + j] = (float)acc;
 }
 
-__global__ void __launch_bounds__(256) widen_bf16_kernel(int64_t rows, int64_t cols,
-                                                         const uint16_t* src, int64_t lds,
-                                                         float* dst, int64_t ldd) {
+template <bool F16>
+__global__ void __launch_bounds__(256) widen_h16_kernel(int64_t rows, int64_t cols,
+                                                        const uint16_t* src, int64_t lds,
+                                                        float* dst, int64_t ldd) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= rows * cols) return;
   const int64_t i = e / cols, j = e - i * cols;
-  dst[i * ldd + j] = bf16_bits_to_f32(src[i * lds + j]);
+  dst[i * ldd + j] = h16_to_f32<F16>(src[i * lds + j]);
 }
 
 }  // namespace
@@ -345,10 +346,13 @@ gn_status launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float* A, int64
   return GN_OK;
 }
 
-gn_status launch_widen_bf16(int64_t rows, int64_t cols, const uint16_t* src, int64_t lds, float* dst,
-                            int64_t ldd, hipStream_t s) {
-  widen_bf16_kernel<<<dim3((unsigned)cdiv(rows * cols, 256)), dim3(256), 0, s>>>(rows, cols, src,
-                                                                                 lds, dst, ldd);
+gn_status launch_widen_h16(int64_t rows, int64_t cols, const uint16_t* src, int64_t lds, bool f16,
+                           float* dst, int64_t ldd, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(rows * cols, 256)), block(256);
+  if (f16)
+    widen_h16_kernel<true><<<grid, block, 0, s>>>(rows, cols, src, lds, dst, ldd);
+  else
+    widen_h16_kernel<false><<<grid, block, 0, s>>>(rows, cols, src, lds, dst, ldd);
   GN_LAUNCH_CHECK();
   return GN_OK;
 }

@@ -17,6 +17,7 @@ namespace tiles {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ workgroup scheduling
@@ -51,6 +52,27 @@ __device__ __forceinline__ bool xcd_tile(int64_t local, int64_t tiles_inner, int
   return true;
 }
 
+// The same with the tiles of each XCD visited in blocks of bi (inner) x bo
+// (outer) tiles: the workgroups resident on one XCD at a time then cover a
+// roughly square block of the output and share both operands' panels in its L2
+// (the order within the XCD's range: block rows of bo outer tiles, blocks of bi
+// inner tiles along them, inner index fastest inside a block; partial blocks at
+// the edges).
+__device__ __forceinline__ bool xcd_tile_blocked(int64_t local, int64_t tiles_inner,
+                                                 int64_t tiles_outer, int64_t bi, int64_t bo,
+                                                 int64_t& ti, int64_t& to) {
+  const int64_t total = tiles_inner * tiles_outer;
+  const int64_t per = (total + 7) / 8;
+  const int64_t t = (local & 7) * per + (local >> 3);
+  if (t >= total) return false;
+  const int64_t row = t / (tiles_inner * bo), rem = t - row * tiles_inner * bo;
+  const int64_t h = (tiles_outer - row * bo < bo) ? tiles_outer - row * bo : bo;
+  const int64_t ib = rem / (bi * h), rem2 = rem - ib * bi * h;
+  const int64_t w = (tiles_inner - ib * bi < bi) ? tiles_inner - ib * bi : bi;
+  ti = ib * bi + rem2 % w;
+  to = row * bo + rem2 / w;
+  return true;
+}
 
 // ------------------------------------------------------------------ FP32
 // D (M x N) = A (M x K) B (K x N), FP32 in, FP32 accumulation.
@@ -345,20 +367,24 @@ __device__ __forceinline__ bf16x8 bf16_frag_tr(const uint16_t* S, int k0, int c0
   return __builtin_bit_cast(bf16x8, v);
 }
 
-template <class CF, bool A_IS_MAT, bool B_KC>
-__device__ void bf16_tile_cfg(const GemmBF16& g, int64_t local, char* smem) {
+// One 32 x 32 x 16 matrix-core step on 16-bit operands held as raw bits: bfloat16
+// (F16 = false) or IEEE binary16, FP32 accumulation.
+template <bool F16>
+__device__ __forceinline__ f32x16 mfma_32x32x16(bf16x8 a, bf16x8 b, f32x16 c) {
+  if constexpr (F16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                   __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// One BM x BN tile at (i0, j0).
+template <class CF, bool A_IS_MAT, bool B_KC, bool F16 = false>
+__device__ void bf16_tile_at(const GemmBF16& g, int64_t i0, int64_t j0, char* smem) {
   constexpr int BM = CF::BM, BN = CF::BN, BK = CF::BK, LDK = CF::LDK, LDN = CF::LDN;
   constexpr int SB = B_KC ? BN * LDK : BK * LDN;     // one B buffer
   uint16_t* sA = reinterpret_cast<uint16_t*>(smem);  // [2][BM * LDK]
   uint16_t* sB = sA + 2 * BM * LDK;                  // [2][SB]
-  const int64_t tm_n = cdiv_d(g.M, BM), tn_n = cdiv_d(g.N, BN);
-  int64_t tm, tn;
-  if (g.inner_is_m) {
-    if (!xcd_tile(local, tm_n, tn_n, tm, tn)) return;
-  } else {
-    if (!xcd_tile(local, tn_n, tm_n, tn, tm)) return;
-  }
-  const int64_t i0 = tm * BM, j0 = tn * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % CF::WM, wn = wave / CF::WM;
   const int li = lane & 31, lk = lane >> 5;
@@ -439,7 +465,7 @@ __device__ void bf16_tile_cfg(const GemmBF16& g, int64_t local, char* smem) {
       for (int x = 0; x < CF::FM; ++x)
 #pragma unroll
         for (int y = 0; y < CF::FN; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[x], bfr[y], acc[x][y], 0, 0, 0);
+          acc[x][y] = mfma_32x32x16<F16>(af[x], bfr[y], acc[x][y]);
     }
     if (kt + 1 < nk) {
       sa.store(sA + (cur ^ 1) * BM * LDK);
@@ -459,6 +485,19 @@ __device__ void bf16_tile_cfg(const GemmBF16& g, int64_t local, char* smem) {
         const int64_t col = j0 + wn * CF::TN + y * 32 + li;
         if (row < g.M && col < g.N) g.D[row * g.ldd + col] = acc[x][y][v] * s_cur;
       }
+}
+
+// The tile of XCD-mapped index `local` (tiles of one XCD walk the inner index).
+template <class CF, bool A_IS_MAT, bool B_KC, bool F16 = false>
+__device__ void bf16_tile_cfg(const GemmBF16& g, int64_t local, char* smem) {
+  const int64_t tm_n = cdiv_d(g.M, CF::BM), tn_n = cdiv_d(g.N, CF::BN);
+  int64_t tm, tn;
+  if (g.inner_is_m) {
+    if (!xcd_tile(local, tm_n, tn_n, tm, tn)) return;
+  } else {
+    if (!xcd_tile(local, tn_n, tm_n, tn, tm)) return;
+  }
+  bf16_tile_at<CF, A_IS_MAT, B_KC, F16>(g, tm * CF::BM, tn * CF::BN, smem);
 }
 
 // The production BF16 configuration: 256 x 256 tiles, 16 waves of 64 x 64, K

@@ -76,6 +76,39 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
   return __uint_as_float((uint32_t)b << 16);
 }
 
+// ---------------------------------------------------------------------------- float16
+// Round a double to IEEE binary16 to nearest, ties to even, in one step (no
+// intermediate float rounding): |x| < 2^-14 is a multiple of the subnormal unit
+// 2^-24 (the scaling by 2^24 is exact, rint rounds to even; 1024 units is the
+// smallest normal, encoded by the same bits); otherwise x = f 2^e with f in
+// [0.5, 1) keeps q = rint(f 2^11) in [1024, 2048] significant units, the carry
+// of q = 2048 running into the exponent field.  65520 and above round to
+// infinity, NaN stays NaN.
+__device__ __forceinline__ uint16_t f64_to_f16_bits(double x) {
+  const uint32_t sign = signbit(x) ? 0x8000u : 0u;
+  if (isnan(x)) return (uint16_t)(sign | 0x7e00u);
+  const double a = fabs(x);
+  if (!(a < 65520.0)) return (uint16_t)(sign | 0x7c00u);
+  if (a < 0x1.0p-14) return (uint16_t)(sign | (uint32_t)rint(a * 0x1.0p24));
+  int e;
+  const double f = frexp(a, &e);
+  const uint32_t q = (uint32_t)rint(ldexp(f, 11));
+  return (uint16_t)(sign | ((((uint32_t)(e + 14)) << 10) + (q - 1024u)));
+}
+
+__device__ __forceinline__ float f16_bits_to_f32(uint16_t b) {
+  return (float)__builtin_bit_cast(_Float16, b);
+}
+
+// A 16-bit storage element as float: bfloat16 (F16 = false) or binary16.
+template <bool F16>
+__device__ __forceinline__ float h16_to_f32(uint16_t b) {
+  if constexpr (F16)
+    return f16_bits_to_f32(b);
+  else
+    return bf16_bits_to_f32(b);
+}
+
 // ---------------------------------------------------------------------------- element traits
 template <typename T>
 __device__ __forceinline__ double to_f64(T v);
@@ -86,15 +119,22 @@ __device__ __forceinline__ double to_f64<float>(float v) { return (double)v; }
 template <>
 __device__ __forceinline__ double to_f64<uint16_t>(uint16_t v) { return (double)bf16_bits_to_f32(v); }
 
-// Internal element type: bfloat16-rounded values stored as float (the BF16
-// sketch widened exactly, for the FP32 core product).
-constexpr int32_t kDtBf16AsF32 = 3;
+// Internal element types: bfloat16- or binary16-rounded values stored as float
+// (the 16-bit sketch widened exactly, for the FP32 core product).
+constexpr int32_t kDtBf16AsF32 = 100;
+constexpr int32_t kDtF16AsF32 = 101;
 
 inline size_t dtype_size(int32_t dt) {
-  return dt == GN_DT_F64 ? 8 : ((dt == GN_DT_F32 || dt == kDtBf16AsF32) ? 4 : 2);
+  return dt == GN_DT_F64 ? 8
+         : (dt == GN_DT_F32 || dt == kDtBf16AsF32 || dt == kDtF16AsF32) ? 4
+                                                                           : 2;
 }
+inline bool is_h16_mode(int32_t mode) { return mode == GN_MODE_BF16_BS || mode == GN_MODE_F16_BS; }
 inline int32_t sketch_dtype(int32_t mode) {
-  return mode == GN_MODE_F64 ? GN_DT_F64 : (mode == GN_MODE_F32 ? GN_DT_F32 : GN_DT_BF16);
+  return mode == GN_MODE_F64   ? GN_DT_F64
+         : mode == GN_MODE_F32 ? GN_DT_F32
+         : mode == GN_MODE_F16_BS ? GN_DT_F16
+                                  : GN_DT_BF16;
 }
 inline int32_t accum_dtype(int32_t mode) { return mode == GN_MODE_F64 ? GN_DT_F64 : GN_DT_F32; }
 
@@ -193,9 +233,10 @@ gn_status launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float* A, int64
                           const float* B, int64_t ldb, bool b_kc, float* D, int64_t ldd,
                           hipStream_t s, float* split_ws = nullptr, size_t split_bytes = 0);
 size_t gemm_f32_split_ws_bytes(int64_t M, int64_t N, int64_t K);
-// widen a bfloat16 matrix (rows x cols, ld lds) to float (ld ldd)
-gn_status launch_widen_bf16(int64_t rows, int64_t cols, const uint16_t* src, int64_t lds, float* dst,
-                            int64_t ldd, hipStream_t s);
+// widen a bfloat16 (f16 = false) or binary16 matrix (rows x cols, ld lds) to
+// float (ld ldd)
+gn_status launch_widen_h16(int64_t rows, int64_t cols, const uint16_t* src, int64_t lds, bool f16,
+                           float* dst, int64_t ldd, hipStream_t s);
 
 // dgemm.hip : FP64 strided GEMM  D = alpha * op(A) op(B) + beta * D
 struct MatRef {
@@ -344,7 +385,8 @@ gn_status launch_axpy(int64_t rows, int64_t cols, double alpha, const double* X,
                       double* Y, int64_t ldy, hipStream_t s);
 
 // quant.hip
+// f16: binary16 storage instead of bfloat16
 gn_status launch_quantize(int64_t m, int64_t n, const void* A, int64_t lda, int32_t dtype,
-                          uint16_t* out, int64_t ldo, float* scales, hipStream_t s);
+                          uint16_t* out, int64_t ldo, float* scales, hipStream_t s, bool f16);
 
 }  // namespace gn

@@ -53,8 +53,8 @@ gn_status gn_residual_noalloc(int64_t m, int64_t n, int64_t k, const void* A, in
                               const double* G, int64_t ldg, double* out_sumsq,
                               gn_stream_t stream) {
   if (!A || !F || !G || !out_sumsq) return GN_ERR_ARG;
-  if (a_dtype < GN_DT_F64 || a_dtype > GN_DT_BF16) return GN_ERR_ARG;
-  if (a_dtype == GN_DT_BF16 && !A_scales) return GN_ERR_ARG;
+  if (a_dtype < GN_DT_F64 || a_dtype > GN_DT_F16) return GN_ERR_ARG;
+  if ((a_dtype == GN_DT_BF16 || a_dtype == GN_DT_F16) && !A_scales) return GN_ERR_ARG;
   if (m < 1 || n < 1 || k < 0 || lda < n || ldf < k || ldg < n) return GN_ERR_SHAPE;
   if (residual_ws_bytes(m, n) > kScratchBytes) return GN_ERR_UNSUPPORTED;
   double* partial = nullptr;

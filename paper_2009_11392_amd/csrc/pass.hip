@@ -18,6 +18,7 @@
 // as separate launches.
 #include <type_traits>
 
+#include "gemm_h16.h"
 #include "gemm_tiles.h"
 #include "lane_ops.h"
 
@@ -64,19 +65,20 @@ __device__ __forceinline__ void srht_load8(const SrhtArgs& a, int64_t i, int64_t
 #pragma unroll
       for (int e = 0; e < 8; ++e) x[e] = (j + e < a.n) ? row[j + e] : 0.f;
     }
-  } else {  // BF16 with block scales; j is a multiple of 8, so one 128-column block
+  } else {  // 16-bit with block scales; j is a multiple of 8, so one 128-column block
+    constexpr bool F16 = (MODE == GN_MODE_F16_BS);
     const uint16_t* row = reinterpret_cast<const uint16_t*>(a.A) + i * a.lda;
     const float sc = (j < a.n) ? a.scales[(i >> 7) * a.nsb + (j >> 7)] : 0.f;
     if (j + 7 < a.n && (a.lda % 8 == 0)) {
       const u32x4 v = *reinterpret_cast<const u32x4*>(row + j);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        x[2 * e] = __uint_as_float(v[e] << 16) * sc;
-        x[2 * e + 1] = __uint_as_float(v[e] & 0xffff0000u) * sc;
+        x[2 * e] = h16_to_f32<F16>((uint16_t)(v[e] & 0xffffu)) * sc;
+        x[2 * e + 1] = h16_to_f32<F16>((uint16_t)(v[e] >> 16)) * sc;
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) x[e] = (j + e < a.n) ? bf16_bits_to_f32(row[j + e]) * sc : 0.f;
+      for (int e = 0; e < 8; ++e) x[e] = (j + e < a.n) ? h16_to_f32<F16>(row[j + e]) * sc : 0.f;
     }
   }
 }
@@ -287,26 +289,36 @@ __global__ void __launch_bounds__(CF::T) pass_f32_srht(GemmF32 yta, SrhtArgs sr,
     f32_tile_cfg<CF, false, false, VEC>(yta, local, smem);
 }
 
-template <class CF>
+template <class CF, bool F16>
 __global__ void __launch_bounds__(CF::T) pass_bf16_gauss(GemmBF16 yta, GemmBF16 ax, int64_t gY,
                                                          int64_t gA) {
   __shared__ __attribute__((aligned(16))) char smem[CF::smem()];
   int64_t local;
   if (family_split(gY, gA, local))
-    bf16_tile_cfg<CF, false, false>(yta, local, smem);
+    bf16_tile_cfg<CF, false, false, F16>(yta, local, smem);
   else
-    bf16_tile_cfg<CF, true, true>(ax, local, smem);
+    bf16_tile_cfg<CF, true, true, F16>(ax, local, smem);
 }
 
-template <class CF, int RPL>
+// One family of the pass on the large 16-bit tile (gemm_h16.h), one 256-thread
+// workgroup per CU: Y^T A (AX_FAMILY false) or AX.  The two families run as two
+// launches: in one launch, interleaved or one after the other, the pass took
+// 19-20 ms at 32768^2, r = 2000, against 6.7 + 4.4 ms for the two alone.
+template <bool F16, bool AX_FAMILY>
+__global__ void __launch_bounds__(H16Big::T, 1) pass_h16_big(GemmBF16 g) {
+  __shared__ __attribute__((aligned(16))) char smem[H16Big::smem()];
+  h16_big_tile<AX_FAMILY, AX_FAMILY, F16>(g, blockIdx.x, smem);
+}
+
+template <class CF, int RPL, bool F16>
 __global__ void __launch_bounds__(CF::T) pass_bf16_srht(GemmBF16 yta, SrhtArgs sr, int64_t gY,
                                                         int64_t gS, int srht_first) {
   __shared__ __attribute__((aligned(16))) char smem[smax(CF::smem(), SR_SMEM_F32)];
   int64_t local;
   if (take_first(gS, gY, srht_first, local))
-    srht_rows<float, GN_MODE_BF16_BS, RPL>(sr, local, smem);
+    srht_rows<float, F16 ? GN_MODE_F16_BS : GN_MODE_BF16_BS, RPL>(sr, local, smem);
   else
-    bf16_tile_cfg<CF, false, false>(yta, local, smem);
+    bf16_tile_cfg<CF, false, false, F16>(yta, local, smem);
 }
 
 template <int RPL>
@@ -428,9 +440,9 @@ gn_status launch_f32_split(const PassSplit& ps, int64_t m, int64_t n, int64_t r,
   return launch_splitk_sum_f32(partA, ps.sA, m, r, AX, ldax, s);
 }
 
-// BF16 pass with tile configuration CF (sketches stored transposed: Xt r x n,
-// Yt rl x m).
-template <class CF>
+// BF16 / binary16 (F16) pass with tile configuration CF (sketches stored
+// transposed: Xt r x n, Yt rl x m).
+template <class CF, bool F16>
 gn_status launch_bf16_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_t m, int64_t n,
                           int64_t r, int64_t rl, const uint16_t* A, int64_t lda,
                           const float* scales, const uint16_t* Xt, const uint16_t* Yt, SrhtArgs sr,
@@ -445,15 +457,25 @@ gn_status launch_bf16_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_
     const int64_t gS = cdiv(cdiv(m, rows_per_wg), 8);
     const dim3 grid((unsigned)(8 * (gY + gS)));
     const int rpl = srht_rpl(r);
-#define GN_BFS(R) pass_bf16_srht<CF, R><<<grid, dim3(CF::T), 0, s>>>(yta, sr, gY, gS, srht_first)
+#define GN_BFS(R) pass_bf16_srht<CF, R, F16><<<grid, dim3(CF::T), 0, s>>>(yta, sr, gY, gS, srht_first)
     GN_RPL_SWITCH(rpl, GN_BFS)
 #undef GN_BFS
   } else {
     const bool vec_x = (lda % 8 == 0) && (n % 8 == 0) && ((uintptr_t)A % 16 == 0) &&
                        ((uintptr_t)Xt % 16 == 0);
     GemmBF16 ax{m, r, n, A, lda, Xt, n, scales, nsb, AX, ldax, 0, vec_x ? 1 : 0};
+    if (h16_big_eligible(yta, false) && h16_big_eligible(ax, true)) {
+      const int64_t tY = cdiv(rl, H16Big::BM) * cdiv(n, H16Big::BN);
+      const int64_t tA = cdiv(m, H16Big::BM) * cdiv(r, H16Big::BN);
+      pass_h16_big<F16, false><<<dim3((unsigned)(8 * cdiv(tY, 8))), dim3(H16Big::T), 0, s>>>(yta);
+      GN_LAUNCH_CHECK();
+      pass_h16_big<F16, true><<<dim3((unsigned)(8 * cdiv(tA, 8))), dim3(H16Big::T), 0, s>>>(ax);
+      GN_LAUNCH_CHECK();
+      return GN_OK;
+    }
     const int64_t gA = cdiv(cdiv(m, CF::BM) * cdiv(r, CF::BN), 8);
-    pass_bf16_gauss<CF><<<dim3((unsigned)(8 * (gY + gA))), dim3(CF::T), 0, s>>>(yta, ax, gY, gA);
+    pass_bf16_gauss<CF, F16><<<dim3((unsigned)(8 * (gY + gA))), dim3(CF::T), 0, s>>>(yta, ax, gY,
+                                                                                       gA);
   }
   GN_LAUNCH_CHECK();
   return GN_OK;
@@ -508,9 +530,15 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
                                    (const float*)Xs, (const float*)Ys, sr, (float*)AX, ldax,
                                    (float*)YtA, ldya, s);
 
-  return launch_bf16_cfg<BF16Pass>(srht, kSrhtFirst, kSrhtRows, m, n, r, rl,
-                                   (const uint16_t*)A, lda, scales, (const uint16_t*)Xs,
-                                   (const uint16_t*)Ys, sr, (float*)AX, ldax, (float*)YtA, ldya, s);
+  if (mode == GN_MODE_F16_BS)
+    return launch_bf16_cfg<BF16Pass, true>(srht, kSrhtFirst, kSrhtRows, m, n, r, rl,
+                                           (const uint16_t*)A, lda, scales, (const uint16_t*)Xs,
+                                           (const uint16_t*)Ys, sr, (float*)AX, ldax, (float*)YtA,
+                                           ldya, s);
+  return launch_bf16_cfg<BF16Pass, false>(srht, kSrhtFirst, kSrhtRows, m, n, r, rl,
+                                          (const uint16_t*)A, lda, scales, (const uint16_t*)Xs,
+                                          (const uint16_t*)Ys, sr, (float*)AX, ldax, (float*)YtA,
+                                          ldya, s);
 }
 
 gn_status launch_srht_right(int64_t rows, int64_t n, int64_t r, const float* B, int64_t ldb,

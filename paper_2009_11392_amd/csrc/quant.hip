@@ -1,13 +1,16 @@
-// bfloat16 storage of A with one power-of-two scale per 128 x 128 block:
-// s = 2^ceil(log2 max|a|) (1 for an all-zero block), stored value RNE_bf16(a / s).
-// Dividing by a power of two is exact, so s * stored == RNE_bf16(a).
+// 16-bit storage of A with one power-of-two scale per 128 x 128 block:
+// s = 2^ceil(log2 max|a|) (1 for an all-zero block), stored value RNE(a / s) in
+// bfloat16 or IEEE binary16.  Dividing by a power of two is exact, so for
+// bfloat16 s * stored == RNE_bf16(a); for binary16 the scale also keeps the
+// block's entries out of the binary16 subnormal range down to 2^-14 of its
+// largest magnitude.
 #include "gn_internal.h"
 
 namespace gn {
 namespace {
 
-template <typename T>
-__global__ void __launch_bounds__(256) quant_bf16_bs(int64_t m, int64_t n, const T* __restrict__ A,
+template <typename T, bool F16>
+__global__ void __launch_bounds__(256) quant_h16_bs(int64_t m, int64_t n, const T* __restrict__ A,
                                                      int64_t lda, uint16_t* __restrict__ out,
                                                      int64_t ldo, float* __restrict__ scales) {
   const int64_t nsb = (n + 127) >> 7;
@@ -37,21 +40,30 @@ __global__ void __launch_bounds__(256) quant_bf16_bs(int64_t m, int64_t n, const
   const double inv = 1.0 / sc;  // exact: sc is a power of two
   for (int e = tid; e < 128 * 128; e += 256) {
     const int64_t i = r0 + (e >> 7), j = c0 + (e & 127);
-    if (i < m && j < n) out[i * ldo + j] = f64_to_bf16_bits((double)A[i * lda + j] * inv);
+    if (i < m && j < n) {
+      const double v = (double)A[i * lda + j] * inv;
+      out[i * ldo + j] = F16 ? f64_to_f16_bits(v) : f64_to_bf16_bits(v);
+    }
   }
 }
 
 }  // namespace
 
 gn_status launch_quantize(int64_t m, int64_t n, const void* A, int64_t lda, int32_t dtype,
-                          uint16_t* out, int64_t ldo, float* scales, hipStream_t s) {
+                          uint16_t* out, int64_t ldo, float* scales, hipStream_t s, bool f16) {
   const int64_t blocks = cdiv(m, 128) * cdiv(n, 128);
-  if (dtype == GN_DT_F64)
-    quant_bf16_bs<double><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(m, n, (const double*)A, lda,
-                                                                      out, ldo, scales);
-  else
-    quant_bf16_bs<float><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(m, n, (const float*)A, lda,
-                                                                     out, ldo, scales);
+  const dim3 grid((unsigned)blocks), block(256);
+  if (dtype == GN_DT_F64) {
+    if (f16)
+      quant_h16_bs<double, true><<<grid, block, 0, s>>>(m, n, (const double*)A, lda, out, ldo, scales);
+    else
+      quant_h16_bs<double, false><<<grid, block, 0, s>>>(m, n, (const double*)A, lda, out, ldo, scales);
+  } else {
+    if (f16)
+      quant_h16_bs<float, true><<<grid, block, 0, s>>>(m, n, (const float*)A, lda, out, ldo, scales);
+    else
+      quant_h16_bs<float, false><<<grid, block, 0, s>>>(m, n, (const float*)A, lda, out, ldo, scales);
+  }
   GN_LAUNCH_CHECK();
   return GN_OK;
 }

@@ -14,6 +14,10 @@ __device__ __forceinline__ void store_elem(void* out, int64_t off, double z) {
     reinterpret_cast<float*>(out)[off] = __double2float_rn(z);
   } else if constexpr (DT == kDtBf16AsF32) {
     reinterpret_cast<float*>(out)[off] = bf16_bits_to_f32(f64_to_bf16_bits(z));
+  } else if constexpr (DT == kDtF16AsF32) {
+    reinterpret_cast<float*>(out)[off] = f16_bits_to_f32(f64_to_f16_bits(z));
+  } else if constexpr (DT == GN_DT_F16) {
+    reinterpret_cast<uint16_t*>(out)[off] = f64_to_f16_bits(z);
   } else {
     reinterpret_cast<uint16_t*>(out)[off] = f64_to_bf16_bits(z);
   }
@@ -209,6 +213,10 @@ gn_status launch_gaussian(uint64_t seed, int32_t sid, int64_t row0, int64_t col0
     GN_GAUSS(GN_DT_F32)
   } else if (dtype == kDtBf16AsF32) {
     GN_GAUSS(kDtBf16AsF32)
+  } else if (dtype == kDtF16AsF32) {
+    GN_GAUSS(kDtF16AsF32)
+  } else if (dtype == GN_DT_F16) {
+    GN_GAUSS(GN_DT_F16)
   } else {
     GN_GAUSS(GN_DT_BF16)
   }

@@ -13,13 +13,17 @@ import torch
 from . import _capi as C
 from ._capi import GNError  # noqa: F401  (re-export)
 
-MODES = {"f64": C.GN_MODE_F64, "f32": C.GN_MODE_F32, "bf16": C.GN_MODE_BF16_BS}
+MODES = {"f64": C.GN_MODE_F64, "f32": C.GN_MODE_F32, "bf16": C.GN_MODE_BF16_BS,
+         "f16": C.GN_MODE_F16_BS}
 KINDS = {"gaussian": C.GN_SKETCH_GAUSSIAN, "srht": C.GN_SKETCH_SRHT, "user": C.GN_SKETCH_USER}
 CORE_METHODS = {"qr": C.GN_CORE_QR, "svd": C.GN_CORE_SVD, "lift_svd": C.GN_CORE_LIFT_SVD,
                 "lift_rrqr": C.GN_CORE_LIFT_RRQR, "lift_diag": C.GN_CORE_LIFT_DIAG}
-SKETCH_TORCH = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
-ACCUM_TORCH = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
-DT_OF_TORCH = {torch.float64: C.GN_DT_F64, torch.float32: C.GN_DT_F32, torch.bfloat16: C.GN_DT_BF16}
+SKETCH_TORCH = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
+                "f16": torch.float16}
+ACCUM_TORCH = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32,
+               "f16": torch.float32}
+DT_OF_TORCH = {torch.float64: C.GN_DT_F64, torch.float32: C.GN_DT_F32, torch.bfloat16: C.GN_DT_BF16,
+               torch.float16: C.GN_DT_F16}
 
 
 @dataclass
@@ -286,6 +290,17 @@ def gn_quantize_bf16_bs(A: torch.Tensor):
     C.check(C.lib().gn_quantize_bf16_bs(m, n, _ptr(A), A.stride(0), DT_OF_TORCH[A.dtype], _ptr(out),
                                         out.stride(0), _ptr(scales), _stream()),
             "gn_quantize_bf16_bs")
+    return out, scales
+
+
+def gn_quantize_f16_bs(A: torch.Tensor):
+    """binary16 storage of A with the power-of-two 128 x 128 block scales."""
+    m, n = A.shape
+    out = torch.empty(m, n, dtype=torch.float16, device=A.device)
+    scales = torch.empty((m + 127) // 128, (n + 127) // 128, dtype=torch.float32, device=A.device)
+    C.check(C.lib().gn_quantize_f16_bs(m, n, _ptr(A), A.stride(0), DT_OF_TORCH[A.dtype], _ptr(out),
+                                       out.stride(0), _ptr(scales), _stream()),
+            "gn_quantize_f16_bs")
     return out, scales
 
 

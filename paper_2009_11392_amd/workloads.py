@@ -18,6 +18,7 @@ library is measured on:
              Gaussian noise; SRHT X with r = 1000, Gaussian Y with r + l = 1500.
   bf16_32k : the same matrix stored as bfloat16 with one power-of-two FP32 scale
              per 128 x 128 block; Gaussian X, Y (r = 2000, l = 1000).
+  f16_32k  : the same, stored as IEEE binary16 with the same block scales.
   grad8k   : 8192 x 4096 FP32, sigma_i = i^-1.5, Gaussian X, Y (r = 256, l = 128).
 """
 from __future__ import annotations
@@ -87,6 +88,9 @@ SRHT32K_R10 = Workload("srht_32768x32768_f32_r10", 32768, 32768, 10, 5, "srht", 
 BF16_32K = Workload("bf16bs_32768x32768", 32768, 32768, 2000, 1000, "gaussian",
                     "gaussian", "bf16", seed=3, spectrum="poly2", rank=4096, noise=1e-6,
                     eps_rel=10 * U_F32)
+F16_32K = Workload("f16bs_32768x32768", 32768, 32768, 2000, 1000, "gaussian",
+                   "gaussian", "f16", seed=3, spectrum="poly2", rank=4096, noise=1e-6,
+                   eps_rel=10 * U_F32)
 F32_32K = Workload("f32_32768x32768_gauss", 32768, 32768, 2000, 1000, "gaussian",
                    "gaussian", "f32", seed=3, spectrum="poly2", rank=4096, noise=1e-6,
                    eps_rel=10 * U_F32)
@@ -94,7 +98,7 @@ GRAD8K = Workload("grad_8192x4096_f32", 8192, 4096, 256, 128, "gaussian", "gauss
                   "f32", seed=5, spectrum="poly1.5", rank=4096, noise=0.0,
                   eps_rel=10 * U_F32)
 
-ALL = {w.name: w for w in (SMALL, SRHT32K, SRHT32K_R10, BF16_32K, F32_32K, GRAD8K)}
+ALL = {w.name: w for w in (SMALL, SRHT32K, SRHT32K_R10, BF16_32K, F16_32K, F32_32K, GRAD8K)}
 
 
 @dataclass(frozen=True)

@@ -388,3 +388,97 @@ def test_full_bf16_error_vs_oracle(full_bf16):
           f"k {core.rank()} / {ref.core.k}")
     check_rank(core.rank(), ref.core.k, np.diag(ref.core.R), tau)
     assert e_gpu <= 1.05 * e_ref
+
+
+# ----------------------------------------------------------------------------- binary16 variant
+# The same matrix stored as IEEE binary16 with the same power-of-two 128 x 128
+# block scales (which keep the small entries out of the binary16 subnormal range),
+# Gaussian X and Y in binary16 (r = 2000, l = 1000), FP32 accumulation; the core
+# product on the FP32 matrix cores with Y's binary16 values.
+@pytest.fixture(scope="module")
+def full_f16(full_bf16):
+    from paper_2009_11392_amd import gn
+    w = W.F16_32K
+    A32 = full_bf16["A32"]
+    bits, scales = gn.gn_quantize_f16_bs(A32)
+    p = gn.Problem(w.m, w.n, w.r, w.l, kind_x=w.kind_x, kind_y=w.kind_y, seed=w.seed,
+                   mode=w.mode, eps=w.eps)
+    ws = gn.workspace(p, gn.C.GN_OP_SKETCH)
+    ws_core = gn.workspace(p, gn.C.GN_OP_CORE)
+    AX = torch.empty(w.m, w.r, dtype=torch.float32, device="cuda")
+    YtA = torch.empty(p.rl, w.n, dtype=torch.float32, device="cuda")
+    core = gn.new_core(p)
+    print("\n[full-size] binary16 prepare, pass, core", flush=True)
+    gn.gn_sketch_prepare(p, ws)
+    gn.gn_sketch_pass(p, bits, ws, scales=scales, AX=AX, YtA=YtA)
+    gn.gn_core(p, AX, out=core, ws=ws_core, YtA=YtA)
+    torch.cuda.synchronize()
+    return dict(w=w, p=p, A32=A32, bits=bits, scales=scales, AX=AX, YtA=YtA, core=core)
+
+
+def test_full_f16_quantization_sampled_blocks(full_f16):
+    A32, bits, scales = full_f16["A32"], full_f16["bits"], full_f16["scales"]
+    nb = scales.shape[0]
+    sc = scales.cpu().numpy()
+    for bi, bj in ((0, 0), (nb - 1, nb - 1), (17, 200), (255, 3), (100, 100)):
+        blk = host(A32[bi * 128:(bi + 1) * 128, bj * 128:(bj + 1) * 128])
+        rb, rs = OG.block_quantize_f16(blk)
+        got = _bits_host(bits[bi * 128:(bi + 1) * 128, bj * 128:(bj + 1) * 128])
+        assert np.array_equal(got, rb), (bi, bj)
+        assert sc[bi, bj] == rs[0, 0], (bi, bj)
+
+
+def test_full_f16_pass_sampled(full_f16):
+    w, p = full_f16["w"], full_f16["p"]
+    rng = np.random.default_rng(13)
+    cols = np.unique(np.concatenate([[0, 1, 255, 256, w.r - 1], rng.integers(0, w.r, 11)]))
+    sel = np.unique(np.concatenate([[0, 1, 255, 256, 2047, 2048, p.rl - 1],
+                                    rng.integers(0, p.rl, 9)]))
+    Xs = np.concatenate([OG.round_mode(OP.gaussian(w.seed, OP.STREAM_X, w.n, 1, col0=int(c)), "f16")
+                         for c in cols], axis=1)
+    Ys = np.concatenate([OG.round_mode(OP.gaussian(w.seed, OP.STREAM_Y, w.m, 1, col0=int(a)), "f16")
+                         for a in sel], axis=1)
+    sc = full_f16["scales"].cpu().numpy()
+    ax_ref = np.zeros((w.m, len(cols)))
+    ax_mag = np.zeros((w.m, len(cols)))
+    ya_ref = np.zeros((len(sel), w.n))
+    ya_mag = np.zeros((len(sel), w.n))
+    step = 2048
+    for i0 in range(0, w.m, step):
+        Ab = OG.block_dequantize_f16(_bits_host(full_f16["bits"][i0:i0 + step]),
+                                     sc[i0 // 128:(i0 + step) // 128])
+        ax_ref[i0:i0 + step] = Ab @ Xs
+        ax_mag[i0:i0 + step] = np.abs(Ab) @ np.abs(Xs)
+        yb = Ys[i0:i0 + step]
+        ya_ref += yb.T @ Ab
+        ya_mag += np.abs(yb).T @ np.abs(Ab)
+    ax = host(full_f16["AX"].index_select(1, torch.from_numpy(cols).cuda()))
+    ya = host(full_f16["YtA"].index_select(0, torch.from_numpy(sel).cuda()))
+    assert np.all(np.abs(ax - ax_ref) <= gamma(w.n) * ax_mag)
+    assert np.all(np.abs(ya - ya_ref) <= gamma(w.m) * ya_mag)
+    e_ax, e_ya = relerr(ax, ax_ref), relerr(ya, ya_ref)
+    print(f"binary16 AX sampled columns: rel err {e_ax:.3e}; Y^T A sampled rows: rel err {e_ya:.3e}")
+    assert e_ax <= 2e-5 and e_ya <= 2e-5
+
+
+@pytest.mark.timeout(900)
+def test_full_f16_error_vs_oracle(full_f16):
+    """eq. (4) for the binary16 variant, against the unquantized matrix: the FP64
+    oracle runs GN on the FP32 matrix with the same binary16-valued X and Y."""
+    from paper_2009_11392_amd import gn
+    w, p, core = full_f16["w"], full_f16["p"], full_f16["core"]
+    assert (core.flags() & 3) == 0
+    F, Gm = gn.gn_factors(p, full_f16["AX"], full_f16["YtA"], core)
+    e_gpu = math.sqrt(float(gn.gn_residual(full_f16["A32"], F, Gm).item()))
+    del F, Gm
+    torch.cuda.empty_cache()
+    print("\n[full-size] FP64 oracle solve (binary16 sketch values) on the host", flush=True)
+    A64 = full_f16["A32"].cpu().numpy().astype(np.float64)
+    X, Y = OG.gaussian_sketches(w.seed, w.m, w.n, w.r, w.l, mode="f16", workers=host_threads())
+    tau = OG.threshold(p.eps, OG.nu_gaussian(p.n, p.r), OG.nu_gaussian(p.m, p.rl))
+    e_ref, ref = oracle_error(A64, X, Y, tau)
+    na = float(np.linalg.norm(A64))
+    print(f"binary16 error: GPU {e_gpu / na:.6e}, oracle {e_ref / na:.6e}, "
+          f"ratio {e_gpu / e_ref:.6f}, k {core.rank()} / {ref.core.k}")
+    check_rank(core.rank(), ref.core.k, np.diag(ref.core.R), tau)
+    assert e_gpu <= 1.05 * e_ref

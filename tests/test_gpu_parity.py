@@ -84,20 +84,37 @@ def test_gaussian_f64_matches_oracle(G, layout):
     assert np.max(d) <= 8
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_gaussian_rounded_equal_except_ties(G, dtype):
     rows, cols = 1000, 333
-    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[dtype]
     got = host(G.gn_generate_gaussian(5, 1, rows, cols, tdt))
     z = OP.gaussian(5, 1, rows, cols)
-    ref = OP.round_fp32(z).astype(np.float64) if dtype == "f32" else OP.round_bf16(z)
+    ref = OG.round_mode(z, dtype)
     bad = got != ref
     assert bad.mean() <= 1e-5
     if bad.any():   # only rounding ties: neighbours in the target format
         ulp = np.spacing(np.abs(ref[bad]).astype(np.float32)).astype(np.float64)
         if dtype == "bf16":
             ulp = ulp * 2.0 ** 16
+        elif dtype == "f16":
+            ulp = np.spacing(np.abs(ref[bad]).astype(np.float16)).astype(np.float64)
         assert np.all(np.abs(got[bad] - ref[bad]) <= ulp * 1.0001)
+
+
+def test_gaussian_f16_subnormals_and_ties(G):
+    """binary16 rounding of the sketch values straight from FP64: a large block so
+    that values below 2^-14 (subnormal in binary16) occur, each compared with the
+    oracle's direct double-to-half rounding."""
+    rows, cols = 4096, 1024
+    got = host(G.gn_generate_gaussian(23, 2, rows, cols, torch.float16))
+    z = OP.gaussian(23, 2, rows, cols, workers=8)
+    ref = OG.round_mode(z, "f16")
+    sub = np.abs(z) < 2.0 ** -14
+    print(f"binary16 sketch: {int(sub.sum())} subnormal values")
+    assert sub.sum() > 0
+    assert np.array_equal(got[sub], ref[sub])
+    assert np.mean(got != ref) <= 1e-5
 
 
 @pytest.mark.parametrize("n,r", [(1000, 10), (4096, 1000), (100, 64), (1, 1), (32768, 1000)])
@@ -276,27 +293,77 @@ def test_pass_srht_f64_matches_oracle(G):
     assert relerr(host(AX), A @ OP.srht_matrix(6, n, r)) <= 1e-13
 
 
-def test_quantize_bf16_bit_exact(G):
+def quantize(G, mode, A):
+    return G.gn_quantize_f16_bs(A) if mode == "f16" else G.gn_quantize_bf16_bs(A)
+
+
+def quantize_oracle(mode, A):
+    if mode == "f16":
+        rb, rs = OG.block_quantize_f16(A)
+        return rb, rs, OG.block_dequantize_f16(rb, rs)
+    rb, rs = OG.block_quantize_bf16(A)
+    return rb, rs, OG.block_dequantize_bf16(rb, rs)
+
+
+@pytest.mark.parametrize("mode", ["bf16", "f16"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_quantize_bit_exact(G, mode, dtype):
     A = W.spectrum_matrix(300, 260, 0.9 ** np.arange(1, 261), seed=9)
     A[:128, :128] = 0.0
-    bits, scales = G.gn_quantize_bf16_bs(dev(A))
-    rb, rs = OG.block_quantize_bf16(A)
+    A[130:140, 200:210] *= 1e-4       # tiny entries: binary16 subnormals after scaling
+    A = A.astype(np.float32).astype(np.float64) if dtype == torch.float32 else A
+    bits, scales = quantize(G, mode, dev(A, dtype))
+    rb, rs, _ = quantize_oracle(mode, A)
     assert np.array_equal(bits.view(torch.int16).cpu().numpy().view(np.uint16), rb)
     assert np.array_equal(scales.cpu().numpy(), rs)
 
 
-def test_pass_bf16_block_scaled(G):
+@pytest.mark.parametrize("mode", ["bf16", "f16"])
+def test_pass_h16_block_scaled(G, mode):
     m, n, r, l = 300, 260, 40, 20
     A = W.spectrum_matrix(m, n, 0.9 ** np.arange(1, 261), seed=13)
-    bits, scales = G.gn_quantize_bf16_bs(dev(A))
-    p = G.Problem(m, n, r, l, seed=3, mode="bf16")
+    bits, scales = quantize(G, mode, dev(A))
+    p = G.Problem(m, n, r, l, seed=3, mode=mode)
     AX, YtA, _, _ = G.gn_sketch(p, bits, scales=scales)
-    rb, rs = OG.block_quantize_bf16(A)
-    Aq = OG.block_dequantize_bf16(rb, rs)
-    X, Y = OG.gaussian_sketches(3, m, n, r, l, mode="bf16")
+    _, _, Aq = quantize_oracle(mode, A)
+    X, Y = OG.gaussian_sketches(3, m, n, r, l, mode=mode)
     ax, ya = host(AX), host(YtA)
     assert np.all(np.abs(ax - Aq @ X) <= gamma(n) * (np.abs(Aq) @ np.abs(X)))
     assert np.all(np.abs(ya - Y.T @ Aq) <= gamma(m) * (np.abs(Y.T) @ np.abs(Aq)))
+
+
+# The large 16-bit tile (256 x 256 per workgroup, direct-to-LDS staging; taken
+# when m and n are multiples of 8): ragged output tiles in both families, K not
+# a multiple of the 32-deep stage, a tiny r, and three kinds of block scales --
+# uniform along each 128-row / 128-column stripe, mixed (some blocks 2^-3 or 2^-6
+# smaller: the non-matrix fragments are scaled by powers of two), and wide (one
+# block 2^-12 smaller for binary16, 2^-40 for bfloat16: beyond the scaled range,
+# so those tiles take the general tile).  Every entry within the FP32
+# inner-product bound of the oracle's product of the dequantized matrix and the
+# sketches' 16-bit values.
+@pytest.mark.parametrize("mode", ["bf16", "f16"])
+@pytest.mark.parametrize("scales_kind", ["uniform", "mixed", "wide"])
+@pytest.mark.parametrize("m,n,r,l", [(1000, 1032, 300, 150), (776, 1000, 8, 4)])
+def test_pass_h16_large_tile(G, mode, scales_kind, m, n, r, l):
+    A = W.spectrum_matrix(m, n, np.arange(1, min(m, n) + 1, dtype=np.float64) ** -1.0, seed=31)
+    if scales_kind != "uniform":
+        A[128:256, 256:384] *= 2.0 ** -3
+        A[512:640, 0:128] *= 2.0 ** -6
+    if scales_kind == "wide":
+        A[0:128, 640:768] *= 2.0 ** (-12 if mode == "f16" else -40)
+    bits, scales = quantize(G, mode, dev(A))
+    p = G.Problem(m, n, r, l, seed=8, mode=mode)
+    AX, YtA, _, _ = G.gn_sketch(p, bits, scales=scales)
+    _, _, Aq = quantize_oracle(mode, A)
+    X, Y = OG.gaussian_sketches(8, m, n, r, l, mode=mode)
+    ax, ya = host(AX), host(YtA)
+    ref_ax, ref_ya = Aq @ X, Y.T @ Aq
+    bad_ax = np.abs(ax - ref_ax) > gamma(n) * (np.abs(Aq) @ np.abs(X))
+    bad_ya = np.abs(ya - ref_ya) > gamma(m) * (np.abs(Y.T) @ np.abs(Aq))
+    print(f"{mode} {scales_kind} {m}x{n} r={r}: AX rel err {relerr(ax, ref_ax):.2e}, "
+          f"Y^T A rel err {relerr(ya, ref_ya):.2e}, outside bound {int(bad_ax.sum())}, "
+          f"{int(bad_ya.sum())}")
+    assert not bad_ax.any() and not bad_ya.any()
 
 
 # ----------------------------------------------------------------------------- edge cases
@@ -316,7 +383,8 @@ def _noisy(m, n, seed):
 
 
 @pytest.mark.parametrize("mode,kind_x", [("f32", "gaussian"), ("f32", "srht"),
-                                         ("bf16", "gaussian"), ("bf16", "srht")])
+                                         ("bf16", "gaussian"), ("bf16", "srht"),
+                                         ("f16", "gaussian"), ("f16", "srht")])
 def test_low_precision_solve_within_5pct_of_oracle(G, mode, kind_x):
     """FP32 / BF16 pass + FP64 core: ||A - A_hat||_F <= 1.05 x the FP64 oracle's
     error with the same sketches (the error is measured against the FP64 A)."""
@@ -327,7 +395,7 @@ def test_low_precision_solve_within_5pct_of_oracle(G, mode, kind_x):
     if mode == "f32":
         Ad, sc = dev(A, torch.float32), None
     else:
-        Ad, sc = G.gn_quantize_bf16_bs(dev(A))
+        Ad, sc = quantize(G, mode, dev(A))
     AX, YtA, _, _ = G.gn_sketch(p, Ad, scales=sc)
     core = G.gn_core(p, AX)
     assert (core.flags() & 3) == 0

@@ -134,3 +134,44 @@ def test_srht_matches_scipy_hadamard():
         assert np.array_equal(X, d[:, None] * H[:n, idx])
     X = philox.srht_matrix(9, 256, 256)
     assert np.array_equal(X.T @ X, 256.0 * np.eye(256))
+
+
+def _half_values():
+    """Every finite non-negative binary16 value, exactly, built from its
+    definition: (m / 1024) 2^-14 for the subnormals, (1 + m / 1024) 2^(e-15)
+    for biased exponents e = 1..30."""
+    from fractions import Fraction
+    vals = [Fraction(m, 1024) * Fraction(1, 2 ** 14) for m in range(1024)]
+    for e in range(1, 31):
+        vals += [(1 + Fraction(m, 1024)) * Fraction(2) ** (e - 15) for m in range(1024)]
+    return vals
+
+
+def test_f16_rounding_brute_force():
+    """round_f16 (one-step double -> binary16, nearest-even) against a brute-force
+    search over every binary16 value in exact rational arithmetic: random doubles
+    across the normal and subnormal ranges, exact ties (half-way points), points
+    one double away from a tie, and the overflow threshold."""
+    from fractions import Fraction
+    vals = _half_values()
+    rng = np.random.default_rng(5)
+    xs = list(rng.standard_normal(300) * 10.0 ** rng.uniform(-9, 4.5, 300))
+    for k in (3, 517, 1023, 1024, 1500, 20000, 30000):            # ties between neighbours
+        a, b = vals[k], vals[k + 1]
+        mid = float((a + b) / 2)
+        xs += [mid, np.nextafter(mid, np.inf), np.nextafter(mid, -np.inf)]
+    xs += [65504.0, 65519.99, 2.0 ** -24 * 0.5, 2.0 ** -24 * 1.5, 2.0 ** -25 + 2.0 ** -60]
+    import bisect
+    got = philox.round_f16(np.array(xs))
+    for x, g in zip(xs, got):
+        ax = Fraction(abs(float(x)))
+        if ax >= 65520:          # half-way from 65504 to the next (absent) value: infinity
+            assert np.isinf(g)
+            continue
+        # nearest value; on a tie the one with an even last significand bit (the
+        # index of a value in the list has the parity of its significand)
+        j = bisect.bisect_left(vals, ax)
+        cand = [t for t in (j - 1, j) if 0 <= t < len(vals)]
+        i = min(cand, key=lambda t: (abs(vals[t] - ax), t % 2))
+        want = float(vals[i]) * (1 if x >= 0 else -1)
+        assert g == want, (x, g, want)

@@ -271,6 +271,32 @@ def test_block_quantize_bf16_exact_scaling():
     assert np.array_equal(deq, philox.round_bf16(A))
 
 
+def test_block_quantize_f16_scaling_and_rounding():
+    """binary16 block storage: the same power-of-two scales as the bfloat16 one;
+    every stored value is the binary16 value nearest a / s (neither neighbour is
+    closer), within half a binary16 unit in the last place of a / s (2^-25 in the
+    subnormal range), including entries small enough to be subnormal."""
+    A = W.spectrum_matrix(300, 260, 0.9 ** np.arange(1, 261), seed=9)
+    A[:128, :128] = 0.0
+    A[130:140, 200:210] *= 1e-4
+    bits, s = G.block_quantize_f16(A)
+    _, s_bf = G.block_quantize_bf16(A)
+    assert np.array_equal(s, s_bf)
+    s_full = np.repeat(np.repeat(s.astype(np.float64), 128, 0), 128, 1)[:300, :260]
+    v = bits.view(np.float16)
+    q = v.astype(np.float64)
+    t = A / s_full
+    assert np.all(np.abs(q) <= 1.0)
+    ulp = np.spacing(np.abs(v)).astype(np.float64)
+    assert np.all(np.abs(q - t) <= 0.5 * ulp)
+    up = np.nextafter(v, np.float16(np.inf)).astype(np.float64)
+    dn = np.nextafter(v, np.float16(-np.inf)).astype(np.float64)
+    assert np.all(np.abs(q - t) <= np.abs(up - t)) and np.all(np.abs(q - t) <= np.abs(dn - t))
+    sub = (np.abs(t) < 2.0 ** -14) & (t != 0)
+    assert sub.sum() > 0 and np.all(np.abs(q[sub] - t[sub]) <= 2.0 ** -25)
+    assert np.array_equal(G.block_dequantize_f16(bits, s), q * s_full)
+
+
 def test_default_l_and_thresholds():
     assert G.default_l(50) == 25 and G.default_l(7) == 4 and G.default_l(1) == 1
     assert math.isclose(G.nu_srht(1000), math.sqrt(1024))
