@@ -34,6 +34,8 @@
 
 #include "gemm_tiles.h"
 
+#include <type_traits>
+
 namespace gn {
 namespace tiles {
 
@@ -182,25 +184,27 @@ __device__ __forceinline__ void h16_stage_barrier() {
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// The non-matrix operand's fragment times 2^e (f = 2^e, e <= 0, wave-uniform):
-// for bfloat16 through float (the products stay bfloat16 values, so the
-// truncation back is exact), for binary16 one packed multiply per register.
+// One register (two values) of the non-matrix operand's fragment times f = 2^e
+// (e <= 0, wave-uniform): for bfloat16 through float (the products stay bfloat16
+// values, so taking their high halves is exact), for binary16 one packed
+// multiply.
+template <bool F16>
+__device__ __forceinline__ uint32_t h16_scale_word(uint32_t w, float f) {
+  if constexpr (F16) {
+    typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, w) * (_Float16)f);
+  } else {
+    const float lo = __uint_as_float(w << 16) * f;
+    const float hi = __uint_as_float(w & 0xffff0000u) * f;
+    return __builtin_amdgcn_perm(__float_as_uint(hi), __float_as_uint(lo), 0x07060302u);
+  }
+}
 template <bool F16>
 __device__ __forceinline__ bf16x8 h16_scale_frag(bf16x8 v, float f) {
-  if constexpr (F16) {
-    const f16x8 h = __builtin_bit_cast(f16x8, v) * (_Float16)f;
-    return __builtin_bit_cast(bf16x8, h);
-  } else {
-    const u32x4 u = __builtin_bit_cast(u32x4, v);
-    u32x4 o;
+  u32x4 u = __builtin_bit_cast(u32x4, v);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float lo = __uint_as_float(u[i] << 16) * f;
-      const float hi = __uint_as_float(u[i] & 0xffff0000u) * f;
-      o[i] = (__float_as_uint(hi) & 0xffff0000u) | (__float_as_uint(lo) >> 16);
-    }
-    return __builtin_bit_cast(bf16x8, o);
-  }
+  for (int i = 0; i < 4; ++i) u[i] = h16_scale_word<F16>(u[i], f);
+  return __builtin_bit_cast(bf16x8, u);
 }
 
 // Largest and smallest entry of a stripe's block scales held in LDS (nkb
@@ -274,7 +278,7 @@ __device__ void h16_big_tile_at(const GemmBF16& g, int64_t i0, int64_t j0, char*
     return;
   }
   const int my = A_IS_MAT ? wm : wn;  // this wave's stripe
-  const float s_ref = my ? mx1 : mx0;
+  const float s_ref = my ? mx1 : mx0, my_mn = my ? mn1 : mn0;
   const float inv_ref = 1.f / s_ref;  // exact: a power of two
   const float* my_sc = sc_lds + my * CF::MAX_KB;
   auto scale_of = [&](int64_t kb) -> float { return my_sc[kb]; };
@@ -283,7 +287,6 @@ __device__ void h16_big_tile_at(const GemmBF16& g, int64_t i0, int64_t j0, char*
   H16Dma db = B_KC ? h16_dma_kc_init(g.B, g.ldb, g.N, j0, lane, wave)
                    : h16_dma_jc_init(g.B, g.ldb, g.N, j0, lane, wave);
   const uint32_t ring_lds = lds_addr(smem);
-  // stages are issued in order, st = 0, 1, 2, ...; past the end they load zeros
   // Stage loads: issue_half(st, h) issues this thread's chunks h of stage st
   // (h = 0, 1: operand A; 2, 3: operand B; two chunks each), so that the eight
   // loads of a stage can be spread between the matrix-core instructions.
@@ -316,17 +319,6 @@ __device__ void h16_big_tile_at(const GemmBF16& g, int64_t i0, int64_t j0, char*
     else
       return h16_frag_jc(S, wn * 128 + 32 * y, kk, lane);
   };
-  // the non-matrix operand: X (the B fragments) for AX, Y^T (the A fragments) for Y^T A
-  auto scale_frags = [&](bf16x8 (&fa)[4], bf16x8 (&fb)[4], float f) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if constexpr (A_IS_MAT)
-        fb[q] = h16_scale_frag<F16>(fb[q], f);
-      else
-        fa[q] = h16_scale_frag<F16>(fa[q], f);
-    }
-  };
-
   f32x16 acc[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
@@ -334,66 +326,100 @@ __device__ void h16_big_tile_at(const GemmBF16& g, int64_t i0, int64_t j0, char*
     for (int y = 0; y < 4; ++y)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.f;
-  // one row of matrix-core blocks (4 instructions), pinned in place so that the
-  // loads placed between rows issue while the matrix cores work
-  auto mma_row = [&](int x, const bf16x8 (&fa)[4], const bf16x8 (&fb)[4]) {
+  // The sketch operand (X, the B fragments, for AX; Y^T, the A fragments, for
+  // Y^T A) carries the block scales: S[g] is its fragment g and O the other
+  // operand's four.  A half stage's products are issued in four groups, group g
+  // multiplying S[g] with O[0 .. 3].  When the wave's stripe holds more than one
+  // scale, group g also scales the fragment that the following group needs, its
+  // instructions placed between the group's matrix-core instructions so that they
+  // issue while those execute.
+  auto group = [&](auto scaled, int g, const bf16x8 (&S)[4], const bf16x8 (&O)[4], bf16x8& next,
+                   float fn) {
+    constexpr bool SC = decltype(scaled)::value;
+    u32x4 nx = __builtin_bit_cast(u32x4, next);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = mfma_32x32x16<F16>(fa[x], fb[y], acc[x][y]);
+    for (int o = 0; o < 4; ++o) {
+      if constexpr (A_IS_MAT)
+        acc[o][g] = mfma_32x32x16<F16>(O[o], S[g], acc[o][g]);
+      else
+        acc[g][o] = mfma_32x32x16<F16>(S[g], O[o], acc[g][o]);
+      if constexpr (SC) {  // one register of `next` after each product, pinned there
+        __builtin_amdgcn_sched_barrier(0);
+        nx[o] = h16_scale_word<F16>(nx[o], fn);
+        asm volatile("" : "+v"(nx[o]));  // computed here, not sunk to its use
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (SC) next = __builtin_bit_cast(bf16x8, nx);
   };
 
-  // prologue: stages 0 .. 3 in flight, stage 0 landed
+  // the K loop; `scaled` (std::true_type or std::false_type) says whether the
+  // wave's stripe needs the scaling
+  auto run = [&](auto scaled) {
+    constexpr bool SC = decltype(scaled)::value;
+    // prologue: stages 0 .. 3 in flight, stage 0 landed
 #pragma unroll
-  for (int st = 0; st < CF::NS; ++st)
+    for (int st = 0; st < CF::NS; ++st)
 #pragma unroll
-    for (int h = 0; h < 4; ++h) issue_half(st, h);
-  // f: the factor of the K block of the stage being multiplied; s_next: the
-  // scale of the following K block
-  float f = scale_of(0) * inv_ref;
-  float s_next = nkb > 1 ? scale_of(1) : s_ref;
-  asm volatile("s_waitcnt vmcnt(24)\n\ts_barrier" ::: "memory");
-  bf16x8 fa0[4], fb0[4], fa1[4], fb1[4];
+      for (int h = 0; h < 4; ++h) issue_half(st, h);
+    // f: the factor of the K block of the stage being multiplied; s_next: the
+    // scale of the following K block
+    float f = scale_of(0) * inv_ref;
+    float s_next = nkb > 1 ? scale_of(1) : s_ref;
+    asm volatile("s_waitcnt vmcnt(24)\n\ts_barrier" ::: "memory");
+    bf16x8 fa0[4], fb0[4], fa1[4], fb1[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    fb0[q] = frag_b(0, 0, q);
-    fa0[q] = frag_a(0, 0, q);
-  }
+    for (int q = 0; q < 4; ++q) {
+      fb0[q] = frag_b(0, 0, q);
+      fa0[q] = frag_a(0, 0, q);
+    }
+    bf16x8(&S0)[4] = A_IS_MAT ? fb0 : fa0;
+    bf16x8(&O0)[4] = A_IS_MAT ? fa0 : fb0;
+    bf16x8(&S1)[4] = A_IS_MAT ? fb1 : fa1;
+    bf16x8(&O1)[4] = A_IS_MAT ? fa1 : fb1;
+    if constexpr (SC) S0[0] = h16_scale_frag<F16>(S0[0], f);
 
-  for (int64_t t = 0; t < nst; ++t) {
-    if (f != 1.f) scale_frags(fa0, fb0, f);
-    // phase 1: the products of stage t's first 16-deep half (fa0, fb0), with the
-    // second half's fragments read in between
+    for (int64_t t = 0; t < nst; ++t) {
+      // phase 1: the products of stage t's first 16-deep half, with the second
+      // half's fragments read in between
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      fb1[x] = frag_b(t, 16, x);
-      fa1[x] = frag_a(t, 16, x);
-      mma_row(x, fa0, fb0);
-    }
-    h16_stage_barrier<16>();  // stage t + 1 landed; every wave is done with stage t
-    if (f != 1.f) scale_frags(fa1, fb1, f);
-    if (((t + 1) & 3) == 0) {  // stage t + 1 starts a new 128-deep K block
-      f = s_next * inv_ref;
-      const int64_t kb = ((t + 1) >> 2) + 1;
-      if (kb < nkb) s_next = scale_of(kb);
-    }
-    // phase 2: the second half's products, with stage t + 4's loads and stage
-    // t + 1's first-half fragments (B first: the next phase needs all of them
-    // for its first row) issued in between; past the last stage the fragments
-    // come from a zero stage and are not used
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      issue_half(t + CF::NS, x);
-      if (x < 2) {
-        fb0[2 * x] = frag_b(t + 1, 0, 2 * x);
-        fb0[2 * x + 1] = frag_b(t + 1, 0, 2 * x + 1);
-      } else {
-        fa0[2 * x - 4] = frag_a(t + 1, 0, 2 * x - 4);
-        fa0[2 * x - 3] = frag_a(t + 1, 0, 2 * x - 3);
+      for (int x = 0; x < 4; ++x) {
+        fb1[x] = frag_b(t, 16, x);
+        fa1[x] = frag_a(t, 16, x);
+        group(scaled, x, S0, O0, x < 3 ? S0[x + 1] : S1[0], f);
       }
-      mma_row(x, fa1, fb1);
+      h16_stage_barrier<16>();  // stage t + 1 landed; every wave is done with stage t
+      float fn = f;
+      if (((t + 1) & 3) == 0) {  // stage t + 1 starts a new 128-deep K block
+        fn = s_next * inv_ref;
+        const int64_t kb = ((t + 1) >> 2) + 1;
+        if (kb < nkb) s_next = scale_of(kb);
+      }
+      // phase 2: the second half's products, with stage t + 4's loads and stage
+      // t + 1's first-half fragments (B first: the next phase needs all of them
+      // for its first group) issued in between; past the last stage the
+      // fragments come from a zero stage and are not used
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        issue_half(t + CF::NS, x);
+        if (x < 2) {
+          fb0[2 * x] = frag_b(t + 1, 0, 2 * x);
+          fb0[2 * x + 1] = frag_b(t + 1, 0, 2 * x + 1);
+        } else {
+          fa0[2 * x - 4] = frag_a(t + 1, 0, 2 * x - 4);
+          fa0[2 * x - 3] = frag_a(t + 1, 0, 2 * x - 3);
+        }
+        group(scaled, x, S1, O1, x < 3 ? S1[x + 1] : S0[0], x < 3 ? f : fn);
+      }
+      f = fn;
     }
-  }
+  };
+  if (my_mn == s_ref)
+    run(std::false_type{});
+  else
+    run(std::true_type{});
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // no load may land after the tile
 
   // 32 x 32 accumulator: register v of lane l holds row 8 (v / 4) + 4 (l / 32) + v % 4,
