@@ -36,10 +36,10 @@ def load_policy(key: str = "batch_f32"):
     return None if ent is None else list(ent["policy"])
 
 
-def build_batch_problems(gn, W, count: int):
+def build_batch_problems(gn, W, count: int, host_factors: bool = False):
     probs = []
     for b in W.batch_specs(count):
-        A = W.batch_device_matrix(b)
+        A = W.batch_device_matrix(b, host_factors=host_factors)
         p = gn.Problem(b.m, b.n, b.r, b.l, seed=b.seed, mode="f32",
                        eps=10 * 2.0 ** -24 * float(b.sigma()[0]))
         probs.append((p, A))

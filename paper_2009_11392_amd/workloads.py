@@ -134,18 +134,23 @@ def batch_host_matrix(b: BatchSpec) -> np.ndarray:
     return spectrum_matrix(b.m, b.n, b.sigma(), b.input_seed)
 
 
-def batch_device_matrix(b: BatchSpec, device="cuda"):
+def batch_device_matrix(b: BatchSpec, device="cuda", host_factors: bool = False):
     """A of problem b built on the device in FP32 (torch generator seeded with the
-    input seed; U, V Q factors of Gaussians), row stride a multiple of 4."""
+    input seed; U, V Q factors of Gaussians), row stride a multiple of 4.  With
+    `host_factors` the matrix is built on the host (`batch_host_matrix`) and copied
+    over, so that no library kernel runs on the device."""
     import torch
+    ld = (b.n + 3) // 4 * 4
+    A = torch.zeros(b.m, ld, dtype=torch.float32, device=device)
+    if host_factors:
+        A[:, :b.n] = torch.from_numpy(batch_host_matrix(b).astype(np.float32)).to(device)
+        return A[:, :b.n]
     g = torch.Generator(device=device)
     g.manual_seed(b.input_seed)
     k = b.n
     sig = torch.tensor(b.sigma(), dtype=torch.float64, device=device)
     U, _ = torch.linalg.qr(torch.randn(b.m, k, generator=g, device=device, dtype=torch.float64))
     V, _ = torch.linalg.qr(torch.randn(b.n, k, generator=g, device=device, dtype=torch.float64))
-    ld = (b.n + 3) // 4 * 4
-    A = torch.zeros(b.m, ld, dtype=torch.float32, device=device)
     A[:, :b.n] = ((U * sig[None, :]) @ V.T).to(torch.float32)
     return A[:, :b.n]
 
