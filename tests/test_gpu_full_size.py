@@ -157,6 +157,51 @@ def test_full_pass_yta_sampled_rows(full):
     assert e <= 2e-5
 
 
+@pytest.fixture(scope="module")
+def full_r10(full):
+    """The same resident matrix at r = 10, l = 5: the single-read narrow pass
+    (SRHT X with r + l <= 16), launched as the benchmark's small-r entry is."""
+    gn, A = full["gn"], full["A"]
+    w = W.SRHT32K_R10
+    p = gn.Problem(w.m, w.n, w.r, w.l, kind_x=w.kind_x, kind_y=w.kind_y, seed=w.seed,
+                   mode=w.mode, eps=w.eps)
+    ws = gn.workspace(p, gn.C.GN_OP_SKETCH)
+    AX = torch.empty(w.m, w.r, dtype=torch.float32, device="cuda")
+    YtA = torch.empty(p.rl, w.n, dtype=torch.float32, device="cuda")
+    print("\n[full-size] r = 10 narrow pass", flush=True)
+    gn.gn_sketch_prepare(p, ws, want_srht=True)
+    gn.gn_sketch_pass(p, A, ws, AX=AX, YtA=YtA)
+    torch.cuda.synchronize()
+    return dict(w=w, p=p, A=A, AX=AX, YtA=YtA, X=OP.srht_matrix(w.seed, w.n, w.r))
+
+
+def test_full_r10_narrow_pass(full_r10):
+    w, p, A, X = full_r10["w"], full_r10["p"], full_r10["A"], full_r10["X"]
+    rng = np.random.default_rng(9)
+    rows = np.unique(np.concatenate([[0, 3, 4, 1023, 1024, w.m - 5, w.m - 1],
+                                     rng.integers(0, w.m, 25)]))
+    Ar = host(A.index_select(0, torch.from_numpy(rows).cuda()))
+    ref = Ar @ X
+    got = host(full_r10["AX"].index_select(0, torch.from_numpy(rows).cuda()))
+    assert np.all(np.abs(got - ref) <= gamma(w.n) * (np.abs(Ar) @ np.abs(X)))
+    e_ax = relerr(got, ref)
+    # every row of Y^T A (all r + l = 15), summed over row blocks of A on the host
+    Y = OG.round_mode(OP.gaussian(w.seed, OP.STREAM_Y, w.m, p.rl), "f32")
+    ref = np.zeros((p.rl, w.n))
+    mag = np.zeros((p.rl, w.n))
+    step = 2048
+    for i0 in range(0, w.m, step):
+        Ab = host(A[i0:i0 + step])
+        yb = Y[i0:i0 + step]
+        ref += yb.T @ Ab
+        mag += np.abs(yb).T @ np.abs(Ab)
+    got = host(full_r10["YtA"])
+    assert np.all(np.abs(got - ref) <= gamma(w.m) * mag)
+    e_ya = relerr(got, ref)
+    print(f"r = 10 narrow pass: AX sampled rows rel err {e_ax:.3e}, Y^T A rel err {e_ya:.3e}")
+    assert e_ax <= 2e-5 and e_ya <= 2e-5
+
+
 def test_full_core_properties(full):
     w, p, core, X = full["w"], full["p"], full["core"], full["X"]
     k, r = core.rank(), w.r

@@ -126,10 +126,14 @@ def test_append_cols_f64(G):
     assert relerr(host(AX), host(AXf)) <= 1e-13 and relerr(host(YtA), host(YAf)) <= 1e-13
 
 
-@pytest.mark.parametrize("mode,kind_x", [("f64", "gaussian"), ("f64", "srht"), ("f32", "gaussian"),
-                                         ("f32", "srht")])
-def test_perturbation_update(G, mode, kind_x):
-    m, n, r = 333, 250, 24
+# the last case runs the single-read narrow pass (FP32, SRHT X, r + l <= 16, padded
+# n >= 1024) over E
+@pytest.mark.parametrize("mode,kind_x,m,n,r", [("f64", "gaussian", 333, 250, 24),
+                                               ("f64", "srht", 333, 250, 24),
+                                               ("f32", "gaussian", 333, 250, 24),
+                                               ("f32", "srht", 333, 250, 24),
+                                               ("f32", "srht", 700, 2048, 10)])
+def test_perturbation_update(G, mode, kind_x, m, n, r):
     A = _mat(m, n, 4)
     E = 1e-3 * np.random.default_rng(5).standard_normal((m, n))
     dt = torch.float64 if mode == "f64" else torch.float32
@@ -149,3 +153,51 @@ def test_perturbation_update(G, mode, kind_x):
         bya = g(m) * (np.abs(Y.T) @ (np.abs(A32) + np.abs(E32)))
         assert np.all(np.abs(host(AX) - (A32 + E32) @ X) <= bax + 1e-30)
         assert np.all(np.abs(host(YtA) - Y.T @ (A32 + E32)) <= bya + 1e-30)
+
+
+def _check_f32(AX, YtA, A32, X, Y, adds=1):
+    """FP32 sketches against the exact products of the FP32-rounded operands:
+    entrywise within the bound of `adds` + 1 accumulations."""
+    g = lambda K: (adds + 1) * K * U32 / (1 - (adds + 1) * K * U32)
+    m, n = A32.shape
+    assert np.all(np.abs(host(AX) - A32 @ X) <= g(n) * (np.abs(A32) @ np.abs(X)) + 1e-30)
+    assert np.all(np.abs(host(YtA) - Y.T @ A32) <= g(m) * (np.abs(Y.T) @ np.abs(A32)) + 1e-30)
+
+
+def test_extend_rank_narrow_f32(G):
+    """Section 6 rank extension through the narrow pass: r = 6 -> 10 (r + l = 9 -> 15)
+    with an SRHT X on 2048 columns; the new columns and rows come from a pass of
+    r = 4, r + l = 6 with the sample offset by the old r."""
+    m, n, r, dr = 700, 2048, 6, 4
+    A = _mat(m, n, 6)
+    A32 = A.astype(np.float32).astype(np.float64)
+    po = G.Problem(m, n, r, 3, kind_x="srht", seed=SEED, mode="f32")
+    pn = G.Problem(m, n, r + dr, 5, kind_x="srht", seed=SEED, mode="f32")
+    Ad = dev(A, torch.float32)
+    AXo, YAo = _sketch(G, po, Ad)
+    AX = torch.zeros(m, pn.r, dtype=torch.float32, device="cuda")
+    YtA = torch.zeros(pn.rl, n, dtype=torch.float32, device="cuda")
+    AX[:, :r] = AXo
+    YtA[:po.rl] = YAo
+    G.gn_sketch_extend(po, pn, Ad, AX, YtA)
+    X = OG.round_mode(_X(pn), "f32")
+    Y = OG.round_mode(OP.gaussian(SEED, OP.STREAM_Y, m, pn.rl), "f32")
+    _check_f32(AX, YtA, A32, X, Y, adds=0)
+
+
+def test_append_rows_narrow_f32(G):
+    """Section 6 row append through the narrow pass: the new rows' AX and their
+    Y^T B added to Y^T A (r = 10, l = 5, SRHT X on 2048 columns)."""
+    m, mb, n, r = 600, 100, 2048, 10
+    Afull = _mat(m + mb, n, 7)
+    A32 = Afull.astype(np.float32).astype(np.float64)
+    po = G.Problem(m, n, r, 5, kind_x="srht", seed=SEED, mode="f32")
+    pn = G.Problem(m + mb, n, r, 5, kind_x="srht", seed=SEED, mode="f32")
+    AXo, YAo = _sketch(G, po, dev(Afull[:m], torch.float32))
+    AX = torch.zeros(m + mb, r, dtype=torch.float32, device="cuda")
+    AX[:m] = AXo
+    YtA = YAo.clone()
+    G.gn_sketch_append(pn, 0, m, dev(Afull[m:], torch.float32), AX, YtA)
+    X = OG.round_mode(_X(pn), "f32")
+    Y = OG.round_mode(OP.gaussian(SEED, OP.STREAM_Y, m + mb, pn.rl), "f32")
+    _check_f32(AX, YtA, A32, X, Y, adds=1)
