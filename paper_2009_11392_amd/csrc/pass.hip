@@ -394,6 +394,112 @@ gn_status launch_f32_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_t
   return GN_OK;
 }
 
+// FP32 Gaussian pass for small r and r + l (at most 128 and 192): tiles of 64
+// sketch rows (Y^T A) or columns (AX) by 256, four waves of 64 x 64 each, so the
+// narrow side is padded to 64 instead of 256 (at 32768^2, r = 16, l = 8 the
+// 256 x 256 tile did ten times the useful matrix-core work).
+using F32NarrowY = F32Cfg<64, 256, 16, 1, 4, 32>;   // Y^T A: rl x n
+using F32NarrowA = F32Cfg<256, 64, 16, 4, 1, 32>;   // AX:    m x r
+static_assert(F32NarrowY::T == F32NarrowA::T, "one workgroup size for both families");
+constexpr int64_t kNarrowMaxR = 128, kNarrowMaxRL = 192, kNarrowMinTiles = 128;
+
+int64_t f32_narrow_tiles(int64_t m, int64_t n, int64_t r, int64_t rl) {
+  return cdiv(rl, F32NarrowY::BM) * cdiv(n, F32NarrowY::BN) +
+         cdiv(m, F32NarrowA::BM) * cdiv(r, F32NarrowA::BN);
+}
+bool use_f32_narrow_tiles(int64_t m, int64_t n, int64_t r, int64_t rl) {
+  return r <= kNarrowMaxR && rl <= kNarrowMaxRL && f32_narrow_tiles(m, n, r, rl) >= kNarrowMinTiles;
+}
+
+// K split into slices (blockIdx.y) so that about three workgroups run per CU:
+// slice s of Y^T A covers rows [s kslY, ...) of A and slice s of AX its columns
+// [s kslA, ...), each writing its own partial, summed afterwards in slice order.
+struct NarrowSplit {
+  int64_t sY, kslY, sA, kslA;
+  size_t bytes;  // partials (0: one slice)
+};
+NarrowSplit narrow_split(int64_t tiles, int64_t m, int64_t n, int64_t r, int64_t rl,
+                         int64_t kgran, size_t elem) {
+  int64_t sl = cdiv(768, tiles);
+  if (sl > 16) sl = 16;
+  NarrowSplit ns{1, m, 1, n, 0};
+  if (sl <= 1) return ns;
+  ns.kslY = cdiv(cdiv(m, sl), kgran) * kgran;
+  ns.kslA = cdiv(cdiv(n, sl), kgran) * kgran;
+  if (ns.kslY < 1024 || ns.kslA < 1024) return NarrowSplit{1, m, 1, n, 0};
+  ns.sY = cdiv(m, ns.kslY);
+  ns.sA = cdiv(n, ns.kslA);
+  ns.bytes = align_up((size_t)ns.sY * rl * n * elem) + align_up((size_t)ns.sA * m * r * elem);
+  return ns;
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(F32NarrowY::T) pass_f32_gauss_nt(GemmF32 yta, GemmF32 ax,
+                                                                   int64_t gY, int64_t gA,
+                                                                   NarrowSplit ns, float* partY,
+                                                                   float* partA) {
+  __shared__ __attribute__((aligned(16))) char smem[smax(
+      F32NarrowY::template smem<false, false>(), F32NarrowA::template smem<true, false>())];
+  const int64_t sl = blockIdx.y;
+  int64_t local;
+  if (family_split(gY, gA, local)) {
+    if (sl >= ns.sY) return;
+    GemmF32 g = yta;
+    if (partY) {
+      const int64_t k0 = sl * ns.kslY;
+      g.A = yta.A + k0 * yta.lda;  // Y (m x rl): A(i, k) = Y[k * rl + i]
+      g.B = yta.B + k0 * yta.ldb;  // A (m x n):  B(k, j) = A[k * lda + j]
+      g.K = (k0 + ns.kslY < yta.K) ? ns.kslY : yta.K - k0;
+      g.D = partY + sl * yta.M * yta.N;
+      g.ldd = yta.N;
+    }
+    f32_tile_cfg<F32NarrowY, false, false, VEC>(g, local, smem);
+  } else {
+    if (sl >= ns.sA) return;
+    GemmF32 g = ax;
+    if (partA) {
+      const int64_t k0 = sl * ns.kslA;
+      g.A = ax.A + k0;             // A (m x n):  A(i, k) = A[i * lda + k]
+      g.B = ax.B + k0 * ax.ldb;    // X (n x r):  B(k, j) = X[k * r + j]
+      g.K = (k0 + ns.kslA < ax.K) ? ns.kslA : ax.K - k0;
+      g.D = partA + sl * ax.M * ax.N;
+      g.ldd = ax.N;
+    }
+    f32_tile_cfg<F32NarrowA, true, false, VEC>(g, local, smem);
+  }
+}
+
+NarrowSplit f32_narrow_split(int64_t m, int64_t n, int64_t r, int64_t rl) {
+  return narrow_split(f32_narrow_tiles(m, n, r, rl), m, n, r, rl, F32NarrowY::BK, sizeof(float));
+}
+
+gn_status launch_f32_gauss_nt(int64_t m, int64_t n, int64_t r, int64_t rl, const float* A,
+                              int64_t lda, const float* X, const float* Y, float* AX,
+                              int64_t ldax, float* YtA, int64_t ldya, void* ws, size_t ws_bytes,
+                              hipStream_t s) {
+  GemmF32 yta{rl, n, m, Y, rl, A, lda, YtA, ldya, 1};
+  GemmF32 ax{m, r, n, A, lda, X, r, AX, ldax, 0};
+  const int64_t gY = cdiv(cdiv(rl, F32NarrowY::BM) * cdiv(n, F32NarrowY::BN), 8);
+  const int64_t gA = cdiv(cdiv(m, F32NarrowA::BM) * cdiv(r, F32NarrowA::BN), 8);
+  const bool vec = (lda % 4 == 0) && (rl % 4 == 0) && (r % 4 == 0) && ((uintptr_t)A % 16 == 0) &&
+                   ((uintptr_t)Y % 16 == 0) && ((uintptr_t)X % 16 == 0);
+  NarrowSplit ns = f32_narrow_split(m, n, r, rl);
+  if (ns.bytes == 0 || !ws || ws_bytes < ns.bytes) ns = NarrowSplit{1, m, 1, n, 0};
+  float* partY = ns.bytes ? (float*)ws : nullptr;
+  float* partA = ns.bytes ? (float*)((char*)ws + align_up((size_t)ns.sY * rl * n * 4)) : nullptr;
+  const int64_t sl = ns.sY > ns.sA ? ns.sY : ns.sA;
+  const dim3 grid((unsigned)(8 * (gY + gA)), (unsigned)sl);
+  if (vec)
+    pass_f32_gauss_nt<true><<<grid, dim3(F32NarrowY::T), 0, s>>>(yta, ax, gY, gA, ns, partY, partA);
+  else
+    pass_f32_gauss_nt<false><<<grid, dim3(F32NarrowY::T), 0, s>>>(yta, ax, gY, gA, ns, partY,
+                                                                  partA);
+  GN_LAUNCH_CHECK();
+  if (!ns.bytes) return GN_OK;
+  GN_TRY(launch_splitk_sum_f32(partY, ns.sY, rl, n, YtA, ldya, s));
+  return launch_splitk_sum_f32(partA, ns.sA, m, r, AX, ldax, s);
+}
+
 struct PassSplit {
   int64_t sY, kslY, sA, kslA;
   size_t bytes;
@@ -440,13 +546,73 @@ gn_status launch_f32_split(const PassSplit& ps, int64_t m, int64_t n, int64_t r,
   return launch_splitk_sum_f32(partA, ps.sA, m, r, AX, ldax, s);
 }
 
+// 16-bit Gaussian pass for small r and r + l (at most 64 and 96): the general
+// 16-bit tile with 64 sketch rows (Y^T A) or columns (AX) by 256, four waves of
+// 64 x 64 each, K staged 32 deep (the large tile padded r + l = 24 to 256).
+constexpr int64_t kH16NarrowMaxR = 64, kH16NarrowMaxRL = 96;
+using H16NarrowY = BF16Cfg<64, 256, 32, 1, 4>;
+using H16NarrowA = BF16Cfg<256, 64, 32, 4, 1>;
+static_assert(H16NarrowY::T == H16NarrowA::T, "one workgroup size for both families");
+
+template <bool F16>
+__global__ void __launch_bounds__(H16NarrowY::T) pass_bf16_gauss_nt(GemmBF16 yta, GemmBF16 ax,
+                                                                    int64_t gY, int64_t gA,
+                                                                    NarrowSplit ns, float* partY,
+                                                                    float* partA) {
+  __shared__ __attribute__((aligned(16))) char smem[smax(H16NarrowY::smem(), H16NarrowA::smem())];
+  const int64_t sl = blockIdx.y;
+  int64_t local;
+  // K slices are multiples of 128, so a slice starts on a block-scale boundary
+  if (family_split(gY, gA, local)) {
+    if (sl >= ns.sY) return;
+    GemmBF16 g = yta;
+    if (partY) {
+      const int64_t k0 = sl * ns.kslY;
+      g.A = yta.A + k0;                   // Y^T (rl x m, k-contiguous)
+      g.B = yta.B + k0 * yta.ldb;         // the matrix, row k0 on
+      g.scales = yta.scales + (k0 >> 7) * yta.nsb;
+      g.K = (k0 + ns.kslY < yta.K) ? ns.kslY : yta.K - k0;
+      g.D = partY + sl * yta.M * yta.N;
+      g.ldd = yta.N;
+    }
+    bf16_tile_cfg<H16NarrowY, false, false, F16>(g, local, smem);
+  } else {
+    if (sl >= ns.sA) return;
+    GemmBF16 g = ax;
+    if (partA) {
+      const int64_t k0 = sl * ns.kslA;
+      g.A = ax.A + k0;                    // the matrix, column k0 on
+      g.B = ax.B + k0;                    // X^T (r x n, k-contiguous)
+      g.scales = ax.scales + (k0 >> 7);
+      g.K = (k0 + ns.kslA < ax.K) ? ns.kslA : ax.K - k0;
+      g.D = partA + sl * ax.M * ax.N;
+      g.ldd = ax.N;
+    }
+    bf16_tile_cfg<H16NarrowA, true, true, F16>(g, local, smem);
+  }
+}
+
+int64_t h16_narrow_tiles(int64_t m, int64_t n, int64_t r, int64_t rl) {
+  return cdiv(rl, H16NarrowY::BM) * cdiv(n, H16NarrowY::BN) +
+         cdiv(m, H16NarrowA::BM) * cdiv(r, H16NarrowA::BN);
+}
+// (at r = 128, r + l = 192 the large tile was as fast: 1.91 against 2.02 ms at 32768^2)
+bool use_h16_narrow_tiles(int64_t m, int64_t n, int64_t r, int64_t rl) {
+  return r <= kH16NarrowMaxR && rl <= kH16NarrowMaxRL &&
+         h16_narrow_tiles(m, n, r, rl) >= kNarrowMinTiles;
+}
+NarrowSplit h16_narrow_split(int64_t m, int64_t n, int64_t r, int64_t rl) {
+  return narrow_split(h16_narrow_tiles(m, n, r, rl), m, n, r, rl, 128, sizeof(float));
+}
+
 // BF16 / binary16 (F16) pass with tile configuration CF (sketches stored
 // transposed: Xt r x n, Yt rl x m).
 template <class CF, bool F16>
 gn_status launch_bf16_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_t m, int64_t n,
                           int64_t r, int64_t rl, const uint16_t* A, int64_t lda,
                           const float* scales, const uint16_t* Xt, const uint16_t* Yt, SrhtArgs sr,
-                          float* AX, int64_t ldax, float* YtA, int64_t ldya, hipStream_t s) {
+                          float* AX, int64_t ldax, float* YtA, int64_t ldya, hipStream_t s,
+                          void* ws, size_t ws_bytes) {
   const int64_t nsb = cdiv(n, 128);
   const bool vec_y = (lda % 8 == 0) && (m % 8 == 0) && ((uintptr_t)A % 16 == 0) &&
                      ((uintptr_t)Yt % 16 == 0);
@@ -464,6 +630,21 @@ gn_status launch_bf16_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_
     const bool vec_x = (lda % 8 == 0) && (n % 8 == 0) && ((uintptr_t)A % 16 == 0) &&
                        ((uintptr_t)Xt % 16 == 0);
     GemmBF16 ax{m, r, n, A, lda, Xt, n, scales, nsb, AX, ldax, 0, vec_x ? 1 : 0};
+    if (use_h16_narrow_tiles(m, n, r, rl)) {
+      const int64_t gYn = cdiv(cdiv(rl, H16NarrowY::BM) * cdiv(n, H16NarrowY::BN), 8);
+      const int64_t gAn = cdiv(cdiv(m, H16NarrowA::BM) * cdiv(r, H16NarrowA::BN), 8);
+      NarrowSplit ns = h16_narrow_split(m, n, r, rl);
+      if (ns.bytes == 0 || !ws || ws_bytes < ns.bytes) ns = NarrowSplit{1, m, 1, n, 0};
+      float* partY = ns.bytes ? (float*)ws : nullptr;
+      float* partA = ns.bytes ? (float*)((char*)ws + align_up((size_t)ns.sY * rl * n * 4)) : nullptr;
+      const int64_t sl = ns.sY > ns.sA ? ns.sY : ns.sA;
+      pass_bf16_gauss_nt<F16><<<dim3((unsigned)(8 * (gYn + gAn)), (unsigned)sl),
+                                dim3(H16NarrowY::T), 0, s>>>(yta, ax, gYn, gAn, ns, partY, partA);
+      GN_LAUNCH_CHECK();
+      if (!ns.bytes) return GN_OK;
+      GN_TRY(launch_splitk_sum_f32(partY, ns.sY, rl, n, YtA, ldya, s));
+      return launch_splitk_sum_f32(partA, ns.sA, m, r, AX, ldax, s);
+    }
     if (h16_big_eligible(yta, false) && h16_big_eligible(ax, true)) {
       const int64_t tY = cdiv(rl, H16Big::BM) * cdiv(n, H16Big::BN);
       const int64_t tA = cdiv(m, H16Big::BM) * cdiv(r, H16Big::BN);
@@ -513,6 +694,10 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
   }
 
   if (mode == GN_MODE_F32 && !srht) {
+    if (use_f32_narrow_tiles(m, n, r, rl))
+      return launch_f32_gauss_nt(m, n, r, rl, (const float*)A, lda, (const float*)Xs,
+                                 (const float*)Ys, (float*)AX, ldax, (float*)YtA, ldya, split_ws,
+                                 split_bytes, s);
     const PassSplit ps = pass_split(m, n, r, rl);
     if (ps.bytes > 0 && split_ws && split_bytes >= ps.bytes)
       return launch_f32_split(ps, m, n, r, rl, (const float*)A, lda, (const float*)Xs,
@@ -534,11 +719,11 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
     return launch_bf16_cfg<BF16Pass, true>(srht, kSrhtFirst, kSrhtRows, m, n, r, rl,
                                            (const uint16_t*)A, lda, scales, (const uint16_t*)Xs,
                                            (const uint16_t*)Ys, sr, (float*)AX, ldax, (float*)YtA,
-                                           ldya, s);
+                                           ldya, s, split_ws, split_bytes);
   return launch_bf16_cfg<BF16Pass, false>(srht, kSrhtFirst, kSrhtRows, m, n, r, rl,
                                           (const uint16_t*)A, lda, scales, (const uint16_t*)Xs,
                                           (const uint16_t*)Ys, sr, (float*)AX, ldax, (float*)YtA,
-                                          ldya, s);
+                                          ldya, s, split_ws, split_bytes);
 }
 
 gn_status launch_srht_right(int64_t rows, int64_t n, int64_t r, const float* B, int64_t ldb,
@@ -557,8 +742,13 @@ gn_status launch_srht_right(int64_t rows, int64_t n, int64_t r, const float* B, 
 
 size_t pass_split_ws_bytes(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_t r,
                            int64_t rl) {
+  if (mode == GN_MODE_BF16_BS || mode == GN_MODE_F16_BS)
+    return (kind_x == GN_SKETCH_GAUSSIAN && use_h16_narrow_tiles(m, n, r, rl))
+               ? h16_narrow_split(m, n, r, rl).bytes
+               : 0;
   if (mode != GN_MODE_F32) return 0;
   if (kind_x == GN_SKETCH_SRHT) return narrow_srht_ws_bytes(m, n, r, rl);
+  if (use_f32_narrow_tiles(m, n, r, rl)) return f32_narrow_split(m, n, r, rl).bytes;
   return pass_split(m, n, r, rl).bytes;
 }
 

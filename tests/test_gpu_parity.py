@@ -245,6 +245,27 @@ def test_pass_f32_gaussian_ragged(G):
     assert relerr(ax, A64 @ X) <= 1e-5 and relerr(ya, Y.T @ A64) <= 1e-5
 
 
+# Small r (at most 128) and r + l (at most 192) on wide or tall matrices: tiles of
+# 64 sketch rows (Y^T A) or columns (AX) by 256, so the narrow side is padded to
+# 64 instead of 256, with K split into slices summed in order.  Ragged m and n,
+# vector (r, r + l, lda multiples of 4) and scalar loads, and the limits r = 128,
+# r + l = 192.
+@pytest.mark.parametrize("m,n,r,l", [(3001, 33024, 16, 8), (4196, 30000, 20, 10),
+                                     (5000, 8200, 128, 64), (2500, 32770, 4, 2)])
+def test_pass_f32_gaussian_narrow_tiles(G, m, n, r, l):
+    A = np.random.default_rng(m + n).standard_normal((m, n)).astype(np.float32)
+    p = G.Problem(m, n, r, l, seed=11, mode="f32")
+    AX, YtA, _, _ = G.gn_sketch(p, dev(A, torch.float32))
+    X, Y = OG.gaussian_sketches(11, m, n, r, l, mode="f32")
+    A64 = A.astype(np.float64)
+    ax, ya = host(AX), host(YtA)
+    ref_ax, ref_ya = A64 @ X, Y.T @ A64
+    Aa = np.abs(A64)
+    assert np.all(np.abs(ax - ref_ax) <= gamma(n) * (Aa @ np.abs(X)))
+    assert np.all(np.abs(ya - ref_ya) <= gamma(m) * (np.abs(Y.T) @ Aa))
+    assert relerr(ax, ref_ax) <= 1e-5 and relerr(ya, ref_ya) <= 1e-5
+
+
 def test_pass_srht_integer_inputs_exact(G):
     m, n, r = 170, 1000, 100         # n' = 1024: two 512-column chunks, ragged tail
     A = W.integer_matrix(m, n, 41).astype(np.float32)
@@ -364,6 +385,30 @@ def test_pass_h16_large_tile(G, mode, scales_kind, m, n, r, l):
           f"Y^T A rel err {relerr(ya, ref_ya):.2e}, outside bound {int(bad_ax.sum())}, "
           f"{int(bad_ya.sum())}")
     assert not bad_ax.any() and not bad_ya.any()
+
+
+# Small r (at most 64) and r + l (at most 96) in the 16-bit modes: the general
+# 16-bit tile with 64 sketch rows / columns by 256, K split into slices that
+# start on block-scale boundaries.  Block scales mixed (some 128 x 128 blocks
+# 2^-5 smaller), ragged m and n, m not a multiple of 8 (scalar loads of Y^T), and
+# the limits r = 64, r + l = 96.
+@pytest.mark.parametrize("mode", ["bf16", "f16"])
+@pytest.mark.parametrize("m,n,r,l", [(3000, 30000, 16, 8), (2999, 33000, 5, 3),
+                                     (4104, 16384, 64, 32)])
+def test_pass_h16_narrow_tiles(G, mode, m, n, r, l):
+    A = np.random.default_rng(m + n + r).standard_normal((m, n))
+    A[128:256, 256:384] *= 2.0 ** -5
+    A[512:640, 0:128] *= 2.0 ** -5
+    bits, scales = quantize(G, mode, dev(A))
+    p = G.Problem(m, n, r, l, seed=8, mode=mode)
+    AX, YtA, _, _ = G.gn_sketch(p, bits, scales=scales)
+    _, _, Aq = quantize_oracle(mode, A)
+    X, Y = OG.gaussian_sketches(8, m, n, r, l, mode=mode)
+    ax, ya = host(AX), host(YtA)
+    ref_ax, ref_ya = Aq @ X, Y.T @ Aq
+    Aa = np.abs(Aq)
+    assert np.all(np.abs(ax - ref_ax) <= gamma(n) * (Aa @ np.abs(X)))
+    assert np.all(np.abs(ya - ref_ya) <= gamma(m) * (np.abs(Y.T) @ Aa))
 
 
 # ----------------------------------------------------------------------------- edge cases
