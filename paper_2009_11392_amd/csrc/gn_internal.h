@@ -209,6 +209,18 @@ gn_status launch_f32_srht_narrow(int64_t m, int64_t n, int64_t r, int64_t rl, co
                                  const int32_t* idx, float* AX, int64_t ldax, float* YtA,
                                  int64_t ldya, void* ws, size_t ws_bytes, hipStream_t s);
 
+// The same single read of A for a Gaussian (dense) X, n x r with ld r, when
+// r + l <= 16, n % 4 == 0, n >= 1024 and A is 16-byte aligned with lda % 4 == 0:
+// Y^T A on the matrix cores as above, AX from the same loaded values staged
+// through LDS (16 rows at a time) on the matrix cores; partials in ws
+// (narrow_gauss_ws_bytes) added in a fixed order.  GN_ERR_UNSUPPORTED (nothing
+// enqueued) when the shape or ws does not fit.
+size_t narrow_gauss_ws_bytes(int64_t m, int64_t n, int64_t r, int64_t rl);
+gn_status launch_f32_gauss_narrow(int64_t m, int64_t n, int64_t r, int64_t rl, const float* A,
+                                  int64_t lda, const float* X, const float* Y, float* AX,
+                                  int64_t ldax, float* YtA, int64_t ldya, void* ws,
+                                  size_t ws_bytes, hipStream_t s);
+
 gn_status launch_splitk_sum_f32(const float* partial, int64_t nslice, int64_t M, int64_t N,
                                 float* D, int64_t ldd, hipStream_t s);
 

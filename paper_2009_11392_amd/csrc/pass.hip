@@ -694,6 +694,12 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
   }
 
   if (mode == GN_MODE_F32 && !srht) {
+    if (rl <= 16) {
+      const gn_status st = launch_f32_gauss_narrow(m, n, r, rl, (const float*)A, lda,
+                                                   (const float*)Xs, (const float*)Ys, (float*)AX,
+                                                   ldax, (float*)YtA, ldya, split_ws, split_bytes, s);
+      if (st != GN_ERR_UNSUPPORTED) return st;
+    }
     if (use_f32_narrow_tiles(m, n, r, rl))
       return launch_f32_gauss_nt(m, n, r, rl, (const float*)A, lda, (const float*)Xs,
                                  (const float*)Ys, (float*)AX, ldax, (float*)YtA, ldya, split_ws,
@@ -748,6 +754,8 @@ size_t pass_split_ws_bytes(int32_t mode, int32_t kind_x, int64_t m, int64_t n, i
                : 0;
   if (mode != GN_MODE_F32) return 0;
   if (kind_x == GN_SKETCH_SRHT) return narrow_srht_ws_bytes(m, n, r, rl);
+  const size_t gb = narrow_gauss_ws_bytes(m, n, r, rl);
+  if (gb) return gb;
   if (use_f32_narrow_tiles(m, n, r, rl)) return f32_narrow_split(m, n, r, rl).bytes;
   return pass_split(m, n, r, rl).bytes;
 }

@@ -266,6 +266,27 @@ def test_pass_f32_gaussian_narrow_tiles(G, m, n, r, l):
     assert relerr(ax, ref_ax) <= 1e-5 and relerr(ya, ref_ya) <= 1e-5
 
 
+# r + l <= 16 with a Gaussian X: the single-read narrow pass (one 256-column chunk
+# per wave; Y^T A from the loaded registers, AX from the same values staged in
+# LDS 16 rows at a time, both on the matrix cores; partials added in order).
+# Ragged rows (not a multiple of 16), a ragged last chunk, padding chunks past n
+# (n = 1236: 5 chunks rounded up to 8), r + l = 1 and 16.
+@pytest.mark.parametrize("m,n,r,l", [(1001, 3000, 7, 5), (4096, 4096, 10, 6), (37, 1024, 1, 0),
+                                     (2050, 8192, 16, 0), (300, 1236, 5, 3)])
+def test_pass_f32_gaussian_single_read(G, m, n, r, l):
+    A = np.random.default_rng(m * n).standard_normal((m, n)).astype(np.float32)
+    p = G.Problem(m, n, r, l, seed=12, mode="f32")
+    AX, YtA, _, _ = G.gn_sketch(p, dev(A, torch.float32))
+    X, Y = OG.gaussian_sketches(12, m, n, r, l, mode="f32")
+    A64 = A.astype(np.float64)
+    ax, ya = host(AX), host(YtA)
+    ref_ax, ref_ya = A64 @ X, Y.T @ A64
+    Aa = np.abs(A64)
+    assert np.all(np.abs(ax - ref_ax) <= gamma(n) * (Aa @ np.abs(X)))
+    assert np.all(np.abs(ya - ref_ya) <= gamma(m) * (np.abs(Y.T) @ Aa))
+    assert relerr(ax, ref_ax) <= 1e-5 and relerr(ya, ref_ya) <= 1e-5
+
+
 def test_pass_srht_integer_inputs_exact(G):
     m, n, r = 170, 1000, 100         # n' = 1024: two 512-column chunks, ragged tail
     A = W.integer_matrix(m, n, 41).astype(np.float32)

@@ -126,13 +126,14 @@ def test_append_cols_f64(G):
     assert relerr(host(AX), host(AXf)) <= 1e-13 and relerr(host(YtA), host(YAf)) <= 1e-13
 
 
-# the last case runs the single-read narrow pass (FP32, SRHT X, r + l <= 16, padded
-# n >= 1024) over E
+# the last two cases run the single-read narrow passes (FP32, r + l <= 16,
+# n >= 1024; SRHT and Gaussian X) over E
 @pytest.mark.parametrize("mode,kind_x,m,n,r", [("f64", "gaussian", 333, 250, 24),
                                                ("f64", "srht", 333, 250, 24),
                                                ("f32", "gaussian", 333, 250, 24),
                                                ("f32", "srht", 333, 250, 24),
-                                               ("f32", "srht", 700, 2048, 10)])
+                                               ("f32", "srht", 700, 2048, 10),
+                                               ("f32", "gaussian", 700, 2048, 10)])
 def test_perturbation_update(G, mode, kind_x, m, n, r):
     A = _mat(m, n, 4)
     E = 1e-3 * np.random.default_rng(5).standard_normal((m, n))
