@@ -158,7 +158,7 @@ CoreWs core_ws(const Plan& P) {
     off += dgemm_split_ws_bytes(P.rl, P.r, P.m);
   } else {
     const size_t a = core_product_ws_bytes(P.m, P.rl, P.r);
-    const size_t b = (P.mode == GN_MODE_BF16_BS) ? core_product_bf16_ws_bytes(P.m, P.rl, P.r) : 0;
+    const size_t b = is_h16_mode(P.mode) ? core_product_bf16_ws_bytes(P.m, P.rl, P.r) : 0;
     off += a > b ? a : b;
   }
   // the QR's Q before the SVD / pivoting turns it into Q1, and that method's scratch
@@ -498,9 +498,9 @@ gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void*
   double* Z = (double*)(base + W.z);
 
   // C = Y^T (AX) (the order of the Section 5.1 evaluation): FP64 in F64 mode;
-  // in F32 mode (and BF16 mode with a user Y) on the FP32 matrix cores (the pass
-  // precision), in BF16 mode on the BF16 matrix cores, the K slices summed in
-  // FP64.  With an SRHT X and Y^T A given (F32 / BF16 modes), C = (Y^T A) X
+  // in F32 mode (and the 16-bit modes with a user Y) on the FP32 matrix cores (the
+  // pass precision), in BF16 / FP16 modes on the matrix cores of that format, the
+  // K slices summed in FP64.  With an SRHT X and Y^T A given (F32 / BF16 modes), C = (Y^T A) X
   // instead, the order Section 2.3 costs: the r + l rows of Y^T A sign-flipped,
   // Walsh-Hadamard transformed and sampled in FP64, with the signs and columns
   // regenerated from the seed (bit-identical to the pass's).
@@ -521,13 +521,15 @@ gn_status gn_core(const gn_problem* p, const void* AX, int64_t ldax, const void*
     MatRef ax{AX, P.adt, ldax, 1};
     GN_TRY(launch_dgemm(P.rl, P.r, P.m, 1.0, yt, ax, 0.0, C, P.r, 1, nullptr, false, s, nullptr,
                         0, true, (double*)(base + W.split), W.total - W.split));
-  } else if (P.mode == GN_MODE_BF16_BS && P.ky == GN_SKETCH_GAUSSIAN) {
-    // BF16 mode: Y's bfloat16 values (transposed, as the pass reads them) on the
-    // BF16 matrix cores, AX in two bfloat16 terms
+  } else if (is_h16_mode(P.mode) && P.ky == GN_SKETCH_GAUSSIAN) {
+    // BF16 / FP16 modes: Y's 16-bit values (transposed, as the pass reads them) on
+    // the 16-bit matrix cores, AX in two terms of the same format
+    const bool f16 = (P.mode == GN_MODE_F16_BS);
     uint16_t* Yt = (uint16_t*)(base + W.yt);
-    GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, GN_DT_BF16, 1, Yt, P.m, s));
-    GN_TRY(launch_core_product_bf16(P.m, P.rl, P.r, Yt, (const float*)AX, ldax, base + W.split, C,
-                                    s));
+    GN_TRY(launch_gaussian(p->seed, 2, 0, 0, P.m, P.rl, f16 ? GN_DT_F16 : GN_DT_BF16, 1, Yt, P.m,
+                           s));
+    GN_TRY(launch_core_product_h16(P.m, P.rl, P.r, Yt, f16, (const float*)AX, ldax,
+                                   base + W.split, C, s));
   } else {
     const float* Yf;
     int64_t ldyf;

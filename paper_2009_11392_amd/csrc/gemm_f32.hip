@@ -66,6 +66,7 @@ __global__ void __launch_bounds__(256) fill_f32(float* p, int64_t n, float v) {
 
 // slice blockIdx.y of K (length kslice), term blockIdx.z (0: hi, 1: lo) to
 // partial + (2 slice + term) M N
+template <bool F16>
 __global__ void __launch_bounds__(BF16Pass::T) core_product_bf16(GemmBF16 g, int64_t kslice,
                                                                  const uint16_t* hi,
                                                                  const uint16_t* lo,
@@ -79,7 +80,71 @@ __global__ void __launch_bounds__(BF16Pass::T) core_product_bf16(GemmBF16 g, int
   gs.A = g.A + k0;
   gs.B = (term ? lo : hi) + k0 * g.ldb;
   gs.D = partial + (2 * sl + term) * g.M * g.N;
-  bf16_tile_cfg<BF16Pass, true, false>(gs, blockIdx.x, smem);
+  bf16_tile_cfg<BF16Pass, true, false, F16>(gs, blockIdx.x, smem);
+}
+
+// ------------------------------------------------------------------ FP16 core product
+// In FP16 mode Y holds binary16 values: the same two-term product on the f16
+// matrix cores, with each column j of AX first divided by s_j, the power of two
+// just above its largest magnitude, so that hi = f16(AX / s) and lo =
+// f16(AX / s - hi) stay in binary16's range (22 significant bits for entries
+// within 2^-14 of the column's largest; smaller ones keep an absolute error
+// below 2^-25 s_j, under the FP16 pass's own).  C = (Y^T hi + Y^T lo) diag(s),
+// the factor exact.
+
+// cmax[j] = bits of max_i |AX[i][j]| (non-negative floats order as integers;
+// cmax starts at zero).  Block (column group of 64, row group of 1024).
+__global__ void __launch_bounds__(256) colmax_abs(const float* __restrict__ AX, int64_t ldax,
+                                                  int64_t m, int64_t r, uint32_t* cmax) {
+  __shared__ float red[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + tx;
+  const int64_t i0 = (int64_t)blockIdx.y * 1024;
+  float mx = 0.f;
+  if (j < r) {
+    const int64_t i1 = (i0 + 1024 < m) ? i0 + 1024 : m;
+    for (int64_t i = i0 + ty; i < i1; i += 4) mx = fmaxf(mx, fabsf(AX[i * ldax + j]));
+  }
+  red[ty][tx] = mx;
+  __syncthreads();
+  if (ty == 0 && j < r) {
+    mx = fmaxf(fmaxf(red[0][tx], red[1][tx]), fmaxf(red[2][tx], red[3][tx]));
+    atomicMax(cmax + j, __float_as_uint(mx));
+  }
+}
+
+// s_j = 2^e with max |AX[:, j]| = f 2^e, f in [0.5, 1) (1 for a zero column)
+__device__ __forceinline__ float col_scale(uint32_t bits) {
+  const float mx = __uint_as_float(bits);
+  if (!(mx > 0.f)) return 1.f;
+  int e;
+  frexpf(mx, &e);
+  return ldexpf(1.f, e);
+}
+
+__global__ void __launch_bounds__(256) split_f16x2(const float* __restrict__ AX, int64_t ldax,
+                                                   int64_t m, int64_t r, const uint32_t* cmax,
+                                                   uint16_t* __restrict__ hi,
+                                                   uint16_t* __restrict__ lo) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= m * r) return;
+  const int64_t i = e / r, j = e - i * r;
+  const float x = AX[i * ldax + j] * (1.f / col_scale(cmax[j]));  // exact: a power of two
+  const _Float16 h = (_Float16)x;
+  hi[e] = __builtin_bit_cast(uint16_t, h);
+  lo[e] = __builtin_bit_cast(uint16_t, (_Float16)(x - (float)h));  // the difference is exact
+}
+
+__global__ void __launch_bounds__(256) core_product_sum2_scaled(const float* partial,
+                                                                int64_t nslice, int64_t mn,
+                                                                int64_t r, const uint32_t* cmax,
+                                                                double* C) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mn) return;
+  double acc = 0.0;
+  for (int64_t q = 0; q < nslice; ++q)
+    acc += (double)partial[2 * q * mn + e] + (double)partial[(2 * q + 1) * mn + e];
+  C[e] = acc * (double)col_scale(cmax[e % r]);
 }
 
 __global__ void __launch_bounds__(256) core_product_sum2(const float* partial, int64_t nslice,
@@ -222,7 +287,7 @@ size_t core_product_ws_bytes(int64_t m, int64_t rl, int64_t r) {
 // at least 1024 long and a multiple of 128, at most 16.
 struct Bf16CoreLayout {
   int64_t kslice, nslice, nsb;
-  size_t hi, lo, ones, partial, total;
+  size_t hi, lo, ones, partial, cmax, total;
 };
 static Bf16CoreLayout bf16_core_layout(int64_t m, int64_t rl, int64_t r) {
   Bf16CoreLayout L{};
@@ -243,6 +308,8 @@ static Bf16CoreLayout bf16_core_layout(int64_t m, int64_t rl, int64_t r) {
   off += align_up((size_t)cdiv(rl, 128) * L.nsb * 4);
   L.partial = off;
   off += align_up((size_t)2 * L.nslice * rl * r * 4);
+  L.cmax = off;
+  off += align_up((size_t)r * 4);
   L.total = off;
   return L;
 }
@@ -251,16 +318,27 @@ size_t core_product_bf16_ws_bytes(int64_t m, int64_t rl, int64_t r) {
   return bf16_core_layout(m, rl, r).total;
 }
 
-gn_status launch_core_product_bf16(int64_t m, int64_t rl, int64_t r, const uint16_t* Yt,
-                                   const float* AX, int64_t ldax, void* ws, double* C,
-                                   hipStream_t s) {
+gn_status launch_core_product_h16(int64_t m, int64_t rl, int64_t r, const uint16_t* Yt, bool f16,
+                                  const float* AX, int64_t ldax, void* ws, double* C,
+                                  hipStream_t s) {
   const Bf16CoreLayout L = bf16_core_layout(m, rl, r);
   char* base = (char*)ws;
   uint16_t* hi = (uint16_t*)(base + L.hi);
   uint16_t* lo = (uint16_t*)(base + L.lo);
   float* ones = (float*)(base + L.ones);
   float* partial = (float*)(base + L.partial);
-  split_bf16x2<<<dim3((unsigned)cdiv(m * r, 256)), dim3(256), 0, s>>>(AX, ldax, m, r, hi, lo);
+  uint32_t* cmax = (uint32_t*)(base + L.cmax);
+  if (f16) {
+    fill_f32<<<dim3((unsigned)cdiv(r, 256)), dim3(256), 0, s>>>((float*)cmax, r, 0.0f);
+    GN_LAUNCH_CHECK();
+    colmax_abs<<<dim3((unsigned)cdiv(r, 64), (unsigned)cdiv(m, 1024)), dim3(256), 0, s>>>(
+        AX, ldax, m, r, cmax);
+    GN_LAUNCH_CHECK();
+    split_f16x2<<<dim3((unsigned)cdiv(m * r, 256)), dim3(256), 0, s>>>(AX, ldax, m, r, cmax, hi,
+                                                                        lo);
+  } else {
+    split_bf16x2<<<dim3((unsigned)cdiv(m * r, 256)), dim3(256), 0, s>>>(AX, ldax, m, r, hi, lo);
+  }
   GN_LAUNCH_CHECK();
   const int64_t nones = cdiv(rl, 128) * L.nsb;
   fill_f32<<<dim3((unsigned)cdiv(nones, 256)), dim3(256), 0, s>>>(ones, nones, 1.0f);
@@ -270,10 +348,17 @@ gn_status launch_core_product_bf16(int64_t m, int64_t rl, int64_t r, const uint1
   const GemmBF16 g{rl, r, m, Yt, m, hi, r, ones, L.nsb, partial, r, 1, vec};
   const int64_t tiles = cdiv(rl, BF16Pass::BM) * cdiv(r, BF16Pass::BN);
   const dim3 grid((unsigned)(8 * cdiv(tiles, 8)), (unsigned)L.nslice, 2u);
-  core_product_bf16<<<grid, dim3(BF16Pass::T), 0, s>>>(g, L.kslice, hi, lo, partial);
+  if (f16)
+    core_product_bf16<true><<<grid, dim3(BF16Pass::T), 0, s>>>(g, L.kslice, hi, lo, partial);
+  else
+    core_product_bf16<false><<<grid, dim3(BF16Pass::T), 0, s>>>(g, L.kslice, hi, lo, partial);
   GN_LAUNCH_CHECK();
-  core_product_sum2<<<dim3((unsigned)cdiv(rl * r, 256)), dim3(256), 0, s>>>(partial, L.nslice,
-                                                                          rl * r, C);
+  if (f16)
+    core_product_sum2_scaled<<<dim3((unsigned)cdiv(rl * r, 256)), dim3(256), 0, s>>>(
+        partial, L.nslice, rl * r, r, cmax, C);
+  else
+    core_product_sum2<<<dim3((unsigned)cdiv(rl * r, 256)), dim3(256), 0, s>>>(partial, L.nslice,
+                                                                            rl * r, C);
   GN_LAUNCH_CHECK();
   return GN_OK;
 }

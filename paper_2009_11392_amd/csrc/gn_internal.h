@@ -231,11 +231,13 @@ gn_status launch_core_product_f32(int64_t m, int64_t rl, int64_t r, const float*
                                   const float* AX, int64_t ldax, float* partial, double* C,
                                   hipStream_t s);
 size_t core_product_ws_bytes(int64_t m, int64_t rl, int64_t r);
-// BF16 mode: C (rl x r, FP64) = Y^T (AX) with Yt (rl x m, bfloat16 bits, ld m) on the
-// BF16 matrix cores, AX split into two bfloat16 terms; ws: core_product_bf16_ws_bytes.
-gn_status launch_core_product_bf16(int64_t m, int64_t rl, int64_t r, const uint16_t* Yt,
-                                   const float* AX, int64_t ldax, void* ws, double* C,
-                                   hipStream_t s);
+// BF16 / FP16 modes: C (rl x r, FP64) = Y^T (AX) with Yt (rl x m, bfloat16 or
+// binary16 bits (f16), ld m) on the 16-bit matrix cores, AX split into two terms
+// of that format (for binary16 after each column is divided by a power of two);
+// ws: core_product_bf16_ws_bytes.
+gn_status launch_core_product_h16(int64_t m, int64_t rl, int64_t r, const uint16_t* Yt, bool f16,
+                                  const float* AX, int64_t ldax, void* ws, double* C,
+                                  hipStream_t s);
 size_t core_product_bf16_ws_bytes(int64_t m, int64_t rl, int64_t r);
 // D (M x N, FP32) = A (M x K) B (K x N), FP32 MFMA with FP32 accumulation.
 // a_kc: A(i,k) = A[i*lda + k], else A[k*lda + i]; b_kc: B(k,j) = B[j*ldb + k],

@@ -335,6 +335,9 @@ def test_pass_srht_f64_matches_oracle(G):
     assert relerr(host(AX), A @ OP.srht_matrix(6, n, r)) <= 1e-13
 
 
+SKETCH_DT = {"bf16": torch.bfloat16, "f16": torch.float16}
+
+
 def quantize(G, mode, A):
     return G.gn_quantize_f16_bs(A) if mode == "f16" else G.gn_quantize_bf16_bs(A)
 
@@ -486,22 +489,42 @@ def test_low_precision_solve_within_5pct_of_oracle(G, mode, kind_x):
 # Y (the same Y given as user values).  Both carry FP32 accumulation error; the
 # two-term split adds at most 2^-17 relative per entry of AX, so the BF16 product
 # may not be more than a few times further from the oracle than the FP32 one.
-def test_core_bf16_product(G):
+@pytest.mark.parametrize("mode", ["bf16", "f16"])
+def test_core_bf16_product(G, mode):
     m, n, r, l = 3000, 2000, 200, 100
     A = _noisy(m, n, 21)
-    p = G.Problem(m, n, r, l, seed=17, mode="bf16", eps=10 * U32)
-    Ad, sc = G.gn_quantize_bf16_bs(dev(A))
+    p = G.Problem(m, n, r, l, seed=17, mode=mode, eps=10 * U32)
+    Ad, sc = quantize(G, mode, dev(A))
     AX, YtA, _, _ = G.gn_sketch(p, Ad, scales=sc)
     core = G.gn_core(p, AX)
-    Yb = G.gn_generate_gaussian(17, 2, m, p.rl, dtype=torch.bfloat16)
+    Yb = G.gn_generate_gaussian(17, 2, m, p.rl, dtype=SKETCH_DT[mode])
     pu = dataclasses.replace(p, kind_y="user", nu_y=OG.nu_gaussian(m, p.rl))
     core32 = G.gn_core(pu, AX, Y_user=Yb)
-    Y = OG.round_mode(OP.gaussian(17, OP.STREAM_Y, m, p.rl), "bf16")
+    Y = OG.round_mode(OP.gaussian(17, OP.STREAM_Y, m, p.rl), mode)
     assert np.array_equal(Yb.float().cpu().numpy().astype(np.float64), Y)
     ref = OG.core(host(AX), Y, 0.0)
     e16, e32 = relerr(host(core.R), ref.R), relerr(host(core32.R), ref.R)
     assert e16 <= 1e-5 and e32 <= 1e-5, (e16, e32)
     assert core.rank() == core32.rank()
+
+
+# The FP16 core product divides each column of AX by a power of two before the
+# two-term binary16 split: columns spread over 10^-8 .. 10^8 (far outside
+# binary16's range unscaled) must each come out of the product to FP32-like
+# relative accuracy.  Householder QR is columnwise backward stable, so Q1 R
+# reproduces every column of C = Y^T (AX) to that accuracy.
+def test_core_f16_product_wide_columns(G):
+    m, r, l = 2048, 64, 32
+    rng = np.random.default_rng(5)
+    AXh = (rng.standard_normal((m, r)) * 10.0 ** rng.uniform(-8, 8, r)).astype(np.float32)
+    p = G.Problem(m, 4 * r, r, l, seed=23, mode="f16")
+    core = G.gn_core(p, dev(AXh, torch.float32))
+    Y = OG.round_mode(OP.gaussian(23, OP.STREAM_Y, m, p.rl), "f16")
+    C = Y.T @ AXh.astype(np.float64)
+    QR = host(core.Q1) @ host(core.R)
+    err = np.linalg.norm(QR - C, axis=0) / np.linalg.norm(C, axis=0)
+    print(f"FP16 core product, wide columns: worst column rel err {err.max():.2e}")
+    assert core.rank() == r and err.max() <= 1e-5
 
 
 # ----------------------------------------------------------------------------- products, several blocks
