@@ -686,11 +686,14 @@ gn_status launch_pass(int32_t mode, int32_t kind_x, int64_t m, int64_t n, int64_
 #undef GN_F64S
       GN_LAUNCH_CHECK();
     } else {
+      // products with few output tiles split K through the workspace (slice sums in order)
       GN_TRY(launch_dgemm(m, r, n, 1.0, MatRef{A, GN_DT_F64, lda, 1}, MatRef{Xs, GN_DT_F64, r, 1},
-                          0.0, (double*)AX, ldax, 1, nullptr, false, s));
+                          0.0, (double*)AX, ldax, 1, nullptr, false, s, nullptr, 0, true,
+                          (double*)split_ws, split_bytes));
     }
     return launch_dgemm(rl, n, m, 1.0, MatRef{Ys, GN_DT_F64, 1, rl}, MatRef{A, GN_DT_F64, lda, 1},
-                        0.0, (double*)YtA, ldya, 1, nullptr, false, s);
+                        0.0, (double*)YtA, ldya, 1, nullptr, false, s, nullptr, 0, true,
+                        (double*)split_ws, split_bytes);
   }
 
   if (mode == GN_MODE_F32 && !srht) {
@@ -752,6 +755,11 @@ size_t pass_split_ws_bytes(int32_t mode, int32_t kind_x, int64_t m, int64_t n, i
     return (kind_x == GN_SKETCH_GAUSSIAN && use_h16_narrow_tiles(m, n, r, rl))
                ? h16_narrow_split(m, n, r, rl).bytes
                : 0;
+  if (mode == GN_MODE_F64) {
+    const size_t y = dgemm_split_ws_bytes(rl, n, m);
+    const size_t x = (kind_x == GN_SKETCH_SRHT) ? 0 : dgemm_split_ws_bytes(m, r, n);
+    return x > y ? x : y;
+  }
   if (mode != GN_MODE_F32) return 0;
   if (kind_x == GN_SKETCH_SRHT) return narrow_srht_ws_bytes(m, n, r, rl);
   const size_t gb = narrow_gauss_ws_bytes(m, n, r, rl);

@@ -73,9 +73,12 @@ def test_backward_f64_matches_oracle(G, m, n, r, l):
     assert core.rank() == r
     dA = G.gn_backward(p, dev(Gb), YtA, core, AX=AX)
     assert relerr(host(dA), ref) <= 1e-10
-    # AX recomputed from A inside gn_backward
+    # AX recomputed from A inside gn_backward: the same FP64 criterion against the
+    # oracle; against the first result it differs only in the order of the AX sums
+    # (the pass splits K, the recomputation reads X transposed)
     dA2 = G.gn_backward(p, dev(Gb), YtA, core, A=Ad)
-    assert relerr(host(dA2), host(dA)) <= 1e-13
+    assert relerr(host(dA2), ref) <= 1e-10
+    assert relerr(host(dA2), host(dA)) <= 1e-11
     # AX passed with a row stride larger than r
     AXw = torch.zeros(m, r + 5, dtype=torch.float64, device="cuda")
     AXw[:, :r] = AX
