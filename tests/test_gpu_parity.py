@@ -267,12 +267,14 @@ def test_pass_f32_gaussian_narrow_tiles(G, m, n, r, l):
 
 
 # r + l <= 16 with a Gaussian X: the single-read narrow pass (one 256-column chunk
-# per wave; Y^T A from the loaded registers, AX from the same values staged in
-# LDS 16 rows at a time, both on the matrix cores; partials added in order).
-# Ragged rows (not a multiple of 16), a ragged last chunk, padding chunks past n
-# (n = 1236: 5 chunks rounded up to 8), r + l = 1 and 16.
+# per wave; Y^T A from the loaded registers, AX from the same values staged in LDS
+# 16 rows at a time, both on the matrix cores; partials added in order).  Ragged
+# rows (not a multiple of 16), a ragged last chunk, padding chunks past n (n =
+# 1236: 5 chunks rounded up to 8), r + l = 1 and 16; and just past the limit (r +
+# l = 17, 24, 32), where the narrow tiles take over.
 @pytest.mark.parametrize("m,n,r,l", [(1001, 3000, 7, 5), (4096, 4096, 10, 6), (37, 1024, 1, 0),
-                                     (2050, 8192, 16, 0), (300, 1236, 5, 3)])
+                                     (2050, 8192, 16, 0), (300, 1236, 5, 3), (1001, 3000, 12, 5),
+                                     (700, 1024, 16, 8), (2050, 8192, 21, 11), (517, 2000, 4, 13)])
 def test_pass_f32_gaussian_single_read(G, m, n, r, l):
     A = np.random.default_rng(m * n).standard_normal((m, n)).astype(np.float32)
     p = G.Problem(m, n, r, l, seed=12, mode="f32")
