@@ -205,18 +205,21 @@ gn_status gn_sketch_prepare(const gn_problem* p, const void* X_user, int64_t ldx
 
 /* The sketch pass (Algorithm 2.1, step 2): AX (m x r) and Y^T A ((r+l) x n)
  * from A (m x n, row stride lda >= n), with the sketches of a prepared ws.
- * In FP32, BF16 and F16 modes this is one kernel launch.
+ * In FP32 mode both products run in one kernel launch; in BF16 and F16 modes the
+ * large-r Gaussian pass is one launch per product.  For small r the pass reads A
+ * once (r + l <= 16, FP32: SRHT or Gaussian X) or takes narrow tiles (FP32
+ * r <= 128, 16-bit r <= 64, Gaussian X).
  *   A        : mode dtype (double, float, or bfloat16 / binary16 bits for
  *              BF16_BS / F16_BS).
  *   A_scales : BF16_BS and F16_BS only: float[ceil(m/128) * ceil(n/128)], row-major, the
  *              scale of each 128 x 128 block (A = scale * stored value).
  *   AX, YtA  : outputs in the accumulation dtype (double for F64, float else),
  *              row strides ldax >= r and ldya >= n.
- * All pointers 16-byte aligned.  When the problem has too few 256 x 256 output
- * tiles to fill the GPU (FP32 mode, Gaussian or user X), the pass splits the
- * contraction length into slices whose partial products go to a scratch region
- * at the end of ws and are summed in slice order (deterministic): passes that
- * run concurrently need separate workspaces. */
+ * All pointers 16-byte aligned.  When the problem has too few output tiles to
+ * fill the GPU (FP64 and FP32 modes, the narrow tiles of the 16-bit modes), and
+ * on the single-read paths (per-chunk and per-row-range partials), partial
+ * products go to a scratch region at the end of ws and are summed in a fixed
+ * order (deterministic): passes that run concurrently need separate workspaces. */
 gn_status gn_sketch_pass(const gn_problem* p, const void* A, int64_t lda, const float* A_scales,
                          void* AX, int64_t ldax, void* YtA, int64_t ldya, void* ws,
                          size_t ws_bytes, gn_stream_t stream);
