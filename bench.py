@@ -13,7 +13,7 @@ pass's algorithmic TFLOP/s.  After timing: the error ||A - A_hat||_F (tile-wise
 on the device), a bounded CPU-oracle baseline, and the BF16-vs-FP32 comparison
 on the 32768^2, r = 2000, l = 1000 shape (same matrix), the reverse mode on the
 8192 x 4096 gradient workload (forward, backward, backward with AX recomputed),
-the 512-problem batched workload (persistent pass, whole solve, graph replay),
+the 512-problem batched workload (pass launch, whole solve, graph replay),
 and the core under each Section 5.1.1 stabilization with the Section 5.1.2 check.
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -248,7 +248,7 @@ def grad_bench(gn, W, steps=5, warmup=2, host_factors=False):
 def batch_bench(gn, W, steps=5, warmup=2, count=512, host_factors=False):
     """The batched workload: 512 FP32 problems (m ~ U[256,4096], n ~ U[128,m],
     r ~ U[8,128], l = ceil(r/2), sigma_i = 10^(-8i/n), Gaussian X and Y) solved by
-    gn_batch_solve: the persistent pass launch alone, the whole solve, and the
+    gn_batch_solve: the pass launch alone, the whole solve, and the
     whole solve replayed from a captured HIP graph."""
     import torch
     from paper_2009_11392_amd.autotune import build_batch_problems
@@ -289,7 +289,7 @@ def batch_bench(gn, W, steps=5, warmup=2, count=512, host_factors=False):
            "pass_frac_of_fp32_peak": flops / (t_pass / 1e3) / 1e12 / PEAK["f32"],
            "roofline_ms": max(flops / (PEAK["f32"] * 1e12), byts / (HBM_PEAK_GBS * 1e9)) * 1e3,
            "work_items": plan.n_pass_items, "core_items": plan.n_core_items,
-           "persistent_workgroups": plan.grid, "tile_policy": list(plan.tile_policy),
+           "pass_workgroups": plan.grid, "tile_policy": list(plan.tile_policy),
            "truncated_problems": sum(1 for k, p in zip(ks, batch.problems) if k < p.r),
            "solves_per_sec": count * 1e3 / t_graph}
     del batch, probs, graph

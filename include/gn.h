@@ -372,7 +372,7 @@ typedef struct {
   int32_t count;               /* problems */
   int32_t n_pass_items;        /* (problem, product, tile) work items of the pass */
   int32_t n_core_items;        /* work items of the core products Y^T (AX) */
-  int32_t grid;                /* persistent workgroups per launch */
+  int32_t grid;                /* workgroups of the pass launch (one per work item) */
   int64_t max_m, max_n, max_r, max_rl;
   size_t ws_bytes;             /* workspace the plan was laid out in */
   size_t off_desc, off_items, off_qr, off_qr2, off_trunc, off_widen;
@@ -406,9 +406,9 @@ gn_status gn_batch_prepare(const gn_batch_problem* probs /*host*/, int32_t count
 typedef enum { GN_BATCH_PASS = 1, GN_BATCH_CORE = 2, GN_BATCH_ALL = 3 } gn_batch_stage;
 
 /* The sketch passes and cores of every problem of a prepared batch (Algorithm 2.1
- * steps 2-3 and Section 5.1.1 for each).  stages & GN_BATCH_PASS: one persistent
- * launch over the pass's work items (AX, Y^T A of every problem); stages &
- * GN_BATCH_CORE: one persistent launch over the core products C = Y^T (AX)
+ * steps 2-3 and Section 5.1.1 for each).  stages & GN_BATCH_PASS: one launch
+ * over the pass's work items (AX, Y^T A of every problem; one workgroup per item,
+ * largest first); stages & GN_BATCH_CORE: one launch over the core products C = Y^T (AX)
  * (reading the AX of an earlier pass), then the batched FP64 Householder QR,
  * truncation and second QR.  Every parameter is read from ws and `plan`: nothing
  * is allocated, copied from the host or synchronized, so the call can be captured

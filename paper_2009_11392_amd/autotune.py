@@ -3,7 +3,7 @@
     python -m paper_2009_11392_amd.autotune [--count 512] [--out tile_table.json]
 
 Builds the batched workload (the same seeded problems the benchmark uses), times
-the persistent sketch-pass launch of gn_batch_solve for every candidate tile
+the sketch-pass launch of gn_batch_solve for every candidate tile
 policy (which 256-thread MFMA tile each product uses: Y^T A with r + l <= 64 or
 > 64, AX with r <= 64 or > 64) and writes the fastest to the table that
 gn.Batch reads by default.  Timing only: every policy computes the same products.

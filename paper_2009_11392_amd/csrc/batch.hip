@@ -2,14 +2,16 @@
 // Y): Algorithm 2.1 steps 2-3 and the Section 5.1.1 truncation for every problem
 // of a batch in a fixed, small number of launches.
 //
-// The sketch passes of all problems are one persistent launch over a table of
-// work items (problem, product, tile configuration, tile).  Each item is one
+// The sketch passes of all problems are one launch over a table of work items
+// (problem, product, tile configuration, tile), one workgroup per item.  Each item is one
 // output tile of Y^T A or AX on the FP32 matrix cores with one of three
 // tile shapes (256 threads: 64 x 256, 128 x 128, 256 x 64; 512 threads: 128 x 256,
 // 256 x 128), chosen per product from the size of its
 // narrow side by a tile policy that the autotuner can replace);
-// items are ordered by decreasing cost and taken round-robin by the persistent
-// workgroups.  The core products C = Y^T (AX) are a second persistent launch of
+// items are ordered by decreasing cost, so the dispatcher starts the largest
+// first and hands the small ones to whichever CU frees up (no static round-robin,
+// and no loop whose hoisted per-thread offsets of every tile shape stay live: the
+// kernel fits three waves per SIMD).  The core products C = Y^T (AX) are a second launch of
 // the same kernel, and the FP64 Householder QR, truncation scan and second QR run
 // batched over the problems (one grid dimension per problem).  Every table lives
 // in the workspace, so a solve is replayable inside a HIP graph.
@@ -48,9 +50,6 @@ constexpr size_t kSmem256 = cmax(cmax(cfg_smem<BC0>(), cfg_smem<BC1>()), cfg_sme
 constexpr size_t kSmem512 = cmax(cfg_smem<BC3>(), cfg_smem<BC4>());
 
 constexpr int kMaxCoreRows = 512;   // r + l: one QR row per thread
-constexpr int kWGPerCU256 = 2;      // resident workgroups per CU (registers)
-constexpr int kWGPerCU512 = 1;
-constexpr int kCUs = 256;
 
 struct BatchDesc {
   int64_t m, n, r, rl;
@@ -81,38 +80,37 @@ __device__ __forceinline__ void batch_tile(const GemmF32& g, int fam, int tm, in
     f32_tile_at<CF, false, false, true>(g, (int64_t)tm * CF::BM, (int64_t)tn * CF::BN, smem);
 }
 
-// The register budget of either instantiation (about 170 VGPRs) leaves 2 waves
-// per SIMD: 2 workgroups of 4 waves, or 1 of 8 waves, resident per CU; the
-// persistent grid is sized for exactly that (a tighter budget spills).
+// One work item per workgroup (item blockIdx.x).  The 256-thread instantiation
+// takes 69 VGPRs and 64 accumulation registers (three waves per SIMD, three
+// workgroups of 4 waves per CU), the 512-thread one 118 VGPRs (two waves per SIMD).
 template <int NT, size_t SMEM>
 __global__ void __launch_bounds__(NT) batch_pass(const BatchDesc* __restrict__ probs,
                                                  const PassItem* __restrict__ items,
                                                  int64_t n_items) {
   __shared__ __attribute__((aligned(16))) char smem[SMEM];
-  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const PassItem w = items[it];
-    const BatchDesc d = probs[w.prob];
-    GemmF32 g;
-    if (w.fam == 0)
-      g = GemmF32{d.rl, d.n, d.m, d.Y, d.ldy, d.A, d.lda, d.YtA, d.ldya, 1};
-    else if (w.fam == 1)
-      g = GemmF32{d.m, d.r, d.n, d.A, d.lda, d.X, d.ldx, d.AX, d.ldax, 0};
+  const int64_t it = blockIdx.x;
+  if (it >= n_items) return;
+  const PassItem w = items[it];
+  const BatchDesc d = probs[w.prob];
+  GemmF32 g;
+  if (w.fam == 0)
+    g = GemmF32{d.rl, d.n, d.m, d.Y, d.ldy, d.A, d.lda, d.YtA, d.ldya, 1};
+  else if (w.fam == 1)
+    g = GemmF32{d.m, d.r, d.n, d.A, d.lda, d.X, d.ldx, d.AX, d.ldax, 0};
+  else
+    g = GemmF32{d.rl, d.r, d.m, d.Y, d.ldy, d.AX, d.ldax, d.Cf, d.r, 1};
+  if constexpr (NT == 256) {
+    if (w.cfg == 0)
+      batch_tile<BC0>(g, w.fam, w.tm, w.tn, smem);
+    else if (w.cfg == 1)
+      batch_tile<BC1>(g, w.fam, w.tm, w.tn, smem);
     else
-      g = GemmF32{d.rl, d.r, d.m, d.Y, d.ldy, d.AX, d.ldax, d.Cf, d.r, 1};
-    if constexpr (NT == 256) {
-      if (w.cfg == 0)
-        batch_tile<BC0>(g, w.fam, w.tm, w.tn, smem);
-      else if (w.cfg == 1)
-        batch_tile<BC1>(g, w.fam, w.tm, w.tn, smem);
-      else
-        batch_tile<BC2>(g, w.fam, w.tm, w.tn, smem);
-    } else {
-      if (w.cfg == 3)
-        batch_tile<BC3>(g, w.fam, w.tm, w.tn, smem);
-      else
-        batch_tile<BC4>(g, w.fam, w.tm, w.tn, smem);
-    }
-    __syncthreads();  // the next item restages LDS
+      batch_tile<BC2>(g, w.fam, w.tm, w.tn, smem);
+  } else {
+    if (w.cfg == 3)
+      batch_tile<BC3>(g, w.fam, w.tm, w.tn, smem);
+    else
+      batch_tile<BC4>(g, w.fam, w.tm, w.tn, smem);
   }
 }
 
@@ -322,8 +320,7 @@ gn_status gn_batch_prepare(const gn_batch_problem* probs, int32_t count, const i
                            (double)b.m * b.r + (double)rl * b.n);
   }
   P.pass_threads = kCfgThreads[pol[0]];
-  const int64_t per_cu = (P.pass_threads == 256) ? kWGPerCU256 : kWGPerCU512;
-  P.grid = (int32_t)std::min<int64_t>((int64_t)kCUs * per_cu, std::max<int64_t>(n_pass, 1));
+  P.grid = (int32_t)std::max<int64_t>(n_pass, 1);
   P.ws_bytes = L.total;
   P.off_desc = L.desc;
   P.off_items = L.items;
@@ -374,8 +371,7 @@ gn_status gn_batch_solve(const gn_batch_plan* plan, int32_t stages, void* ws, si
     GN_LAUNCH_CHECK();
   }
   if (!(stages & GN_BATCH_CORE)) return GN_OK;
-  const int64_t gcore =
-      std::min<int64_t>((int64_t)kCUs * kWGPerCU256, std::max<int64_t>(plan->n_core_items, 1));
+  const int64_t gcore = std::max<int64_t>(plan->n_core_items, 1);
   batch_pass<256, kSmem256><<<dim3((unsigned)gcore), dim3(256), 0, s>>>(desc, items + plan->n_pass_items,
                                                          plan->n_core_items);
   GN_LAUNCH_CHECK();
