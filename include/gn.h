@@ -208,7 +208,7 @@ gn_status gn_sketch_prepare(const gn_problem* p, const void* X_user, int64_t ldx
  * In FP32 mode both products run in one kernel launch; in BF16 and F16 modes the
  * large-r Gaussian pass is one launch per product.  For small r the pass reads A
  * once (r + l <= 16, FP32: SRHT or Gaussian X) or takes narrow tiles (FP32
- * r <= 128, 16-bit r <= 64, Gaussian X).
+ * r <= 512 and r + l <= 768, 16-bit r <= 64, Gaussian X).
  *   A        : mode dtype (double, float, or bfloat16 / binary16 bits for
  *              BF16_BS / F16_BS).
  *   A_scales : BF16_BS and F16_BS only: float[ceil(m/128) * ceil(n/128)], row-major, the

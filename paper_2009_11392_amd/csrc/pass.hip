@@ -394,14 +394,17 @@ gn_status launch_f32_cfg(bool srht, int srht_first, int64_t rows_per_wg, int64_t
   return GN_OK;
 }
 
-// FP32 Gaussian pass for small r and r + l (at most 128 and 192): tiles of 64
-// sketch rows (Y^T A) or columns (AX) by 256, four waves of 64 x 64 each, so the
-// narrow side is padded to 64 instead of 256 (at 32768^2, r = 16, l = 8 the
-// 256 x 256 tile did ten times the useful matrix-core work).
+// FP32 Gaussian pass for r and r + l up to 512 and 768: tiles of 64 sketch rows
+// (Y^T A) or columns (AX) by 256, four waves of 64 x 64 each, so the narrow side
+// is padded to 64 instead of 256 (at 32768^2, r = 16, l = 8 the 256 x 256 tile
+// did ten times the useful matrix-core work) and the many small tiles fill the
+// CUs evenly where the 256 x 256 tiles leave a partial last round (r = 256, 384,
+// 512 at 32768^2: 384, 640, 640 large tiles on 256 CUs).  Above that the large
+// tile's higher reuse wins.
 using F32NarrowY = F32Cfg<64, 256, 16, 1, 4, 32>;   // Y^T A: rl x n
 using F32NarrowA = F32Cfg<256, 64, 16, 4, 1, 32>;   // AX:    m x r
 static_assert(F32NarrowY::T == F32NarrowA::T, "one workgroup size for both families");
-constexpr int64_t kNarrowMaxR = 128, kNarrowMaxRL = 192, kNarrowMinTiles = 128;
+constexpr int64_t kNarrowMaxR = 512, kNarrowMaxRL = 768, kNarrowMinTiles = 128;
 
 int64_t f32_narrow_tiles(int64_t m, int64_t n, int64_t r, int64_t rl) {
   return cdiv(rl, F32NarrowY::BM) * cdiv(n, F32NarrowY::BN) +

@@ -245,13 +245,15 @@ def test_pass_f32_gaussian_ragged(G):
     assert relerr(ax, A64 @ X) <= 1e-5 and relerr(ya, Y.T @ A64) <= 1e-5
 
 
-# Small r (at most 128) and r + l (at most 192) on wide or tall matrices: tiles of
-# 64 sketch rows (Y^T A) or columns (AX) by 256, so the narrow side is padded to
-# 64 instead of 256, with K split into slices summed in order.  Ragged m and n,
-# vector (r, r + l, lda multiples of 4) and scalar loads, and the limits r = 128,
-# r + l = 192.
+# r up to 512 and r + l up to 768 on wide or tall matrices: tiles of 64 sketch
+# rows (Y^T A) or columns (AX) by 256, so the narrow side is padded to 64 instead
+# of 256, with K split into slices summed in order where the tiles are few.
+# Ragged m and n, vector (r, r + l, lda multiples of 4) and scalar loads, r and
+# r + l not multiples of 64, and the limits r = 512, r + l = 768.
 @pytest.mark.parametrize("m,n,r,l", [(3001, 33024, 16, 8), (4196, 30000, 20, 10),
-                                     (5000, 8200, 128, 64), (2500, 32770, 4, 2)])
+                                     (5000, 8200, 128, 64), (2500, 32770, 4, 2),
+                                     (3000, 8192, 256, 128), (1500, 5001, 449, 223),
+                                     (1030, 4100, 512, 256), (8192, 4100, 300, 150)])
 def test_pass_f32_gaussian_narrow_tiles(G, m, n, r, l):
     A = np.random.default_rng(m + n).standard_normal((m, n)).astype(np.float32)
     p = G.Problem(m, n, r, l, seed=11, mode="f32")
