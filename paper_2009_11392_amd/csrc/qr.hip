@@ -169,15 +169,33 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ C, int64_t ld
   __shared__ double part[2][NT / 64][NB];
   __shared__ double prow[2][NB];
   __shared__ double T[NB][NB + 1];
+  // the panel moves between memory and the thread-per-row registers through LDS,
+  // NT rows at a time: in memory consecutive lanes take consecutive columns of a
+  // row (a wave covers 64 / NB whole rows, one cache line each) instead of one row
+  // per lane (64 lines per instruction).  Register row q first holds the thread's
+  // share of that row-contiguous layout, is exchanged through LDS, then holds the
+  // thread's own row.  LDS rows are padded to NB + 1 doubles so that a thread's
+  // own row is read without bank conflicts.
+  __shared__ double stage[NT][NB + 1];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t Mp = M - j0;
+  constexpr int kRowsPerPass = NT / NB;  // rows covered by one load of every thread
+  const int cr = t / NB, ccol = t % NB;  // row offset and column of the thread's elements
+  const bool col_ok = ccol < nbw;
   double p[RPT][NB];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t row = t + (int64_t)NT * q;
+    const int64_t r0 = (int64_t)NT * q + cr;
+    const double* src = C + (j0 + r0) * ldc + j0 + ccol;
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-      p[q][c] = (row < Mp && c < nbw) ? C[(j0 + row) * ldc + j0 + c] : 0.0;
+    for (int k = 0; k < NB; ++k)
+      p[q][k] = (col_ok && r0 + kRowsPerPass * k < Mp) ? src[(int64_t)kRowsPerPass * k * ldc] : 0.0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) stage[cr + kRowsPerPass * k][ccol] = p[q][k];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NB; ++c) p[q][c] = stage[t][c];
+    __syncthreads();
   }
   if (t < NB) {
     for (int l = 0; l < NB; ++l) T[t][l] = 0.0;  // row t of T is only touched by thread t
@@ -187,11 +205,16 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ C, int64_t ld
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t row = t + (int64_t)NT * q;
-    if (row >= Mp) continue;
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-      if (c < nbw) C[(j0 + row) * ldc + j0 + c] = p[q][c];
+    for (int c = 0; c < NB; ++c) stage[t][c] = p[q][c];
+    __syncthreads();
+    const int64_t r0 = (int64_t)NT * q + cr;
+    double* dst = C + (j0 + r0) * ldc + j0 + ccol;
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      if (col_ok && r0 + kRowsPerPass * k < Mp)
+        dst[(int64_t)kRowsPerPass * k * ldc] = stage[cr + kRowsPerPass * k][ccol];
+    __syncthreads();
   }
   for (int e = t; e < NB * NB; e += NT) Tout[(e / NB) * QR_NB + (e % NB)] = T[e / NB][e % NB];  // stride QR_NB
 }
