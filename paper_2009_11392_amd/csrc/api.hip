@@ -207,7 +207,7 @@ ApplyWs apply_ws(const Plan& P, int64_t kc) {
 // ((r+l) x n), S^T (n x (r+l)), AX (m x r, when recomputed or re-strided),
 // G1 (m x (r+l)) and G2 (r x n); FP64 buffers for H and the core adjoint.
 struct BackWs {
-  size_t lcat, rcat, st, p, g1, g2, h, m0, m1, c, bbar, x2, z, y5, t1, t2, t3, t4, psplit,
+  size_t lcat, rcat, st, p, g1, g2, h, m0, m1, c, bbar, x2, z, y5, t1, t2, t3, t4, t5, psplit,
       psplit_bytes, gsplit, gsplit_bytes, dsplit, dsplit_bytes, split, total;
 };
 BackWs back_ws(const Plan& P) {
@@ -238,6 +238,7 @@ BackWs back_ws(const Plan& P) {
   w.t2 = take(r * r * 8);
   w.t3 = take(r * r * 8);
   w.t4 = take(r * r * 8);
+  w.t5 = take(r * r * 8);
   w.psplit_bytes = pass_split_ws_bytes(P.mode, GN_SKETCH_GAUSSIAN, P.m, P.n, P.rl, P.r);
   w.psplit = take(w.psplit_bytes);
   w.gsplit_bytes = (P.mode == GN_MODE_F32) ? gemm_f32_split_ws_bytes(P.m, P.r, P.n) : 0;
@@ -790,8 +791,41 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
   double* T2 = (double*)(base + W.t2);
   double* T3 = (double*)(base + W.t3);
   double* T4 = (double*)(base + W.t4);
+  double* T5 = (double*)(base + W.t5);
   const int32_t* kd = core->k;
   constexpr int32_t F64 = GN_DT_F64;
+  double* DS = (double*)(base + W.dsplit);  // split-contraction scratch of the FP64 products
+  const size_t DSB = W.dsplit_bytes;
+  const MatRef Q1r{core->Q1, F64, r, 1}, Q1t{core->Q1, F64, 1, r};
+  const MatRef Q2r{core->Q2, F64, r, 1}, Q2t{core->Q2, F64, 1, r};
+  auto sq = [&](double* T) { return MatRef{T, F64, r, 1}; };  // ld r (r x r and rl x r)
+
+  // The parts of the core adjoint that need only the forward's core run on the
+  // side stream while this stream draws the sketches and makes the pass over
+  // Gbar; the two meet before Bbar.  The side stream alone uses M0, M, C, Z, T5
+  // and the DS scratch until then.
+  std::lock_guard<std::mutex> side_lock(g_side_mu);
+  SideStream* ss = nullptr;
+  GN_TRY(side_stream(&ss));
+  const hipStream_t s2 = ss->s;
+  if (hipEventRecord(ss->fork, s) != hipSuccess || hipStreamWaitEvent(s2, ss->fork, 0) != hipSuccess)
+    return GN_ERR_HIP;
+  // M = R^{-1} Q1^T (k == r) or Q2 R2^{-T} Q1[:, :k]^T (k < r)
+  GN_TRY(launch_transpose_rows_masked(rl, r, core->Q1, r, kd, M0, rl, s2));
+  GN_TRY(launch_trsm_core(rl, r, core->R, core->R2, r, kd, M0, 1, rl, true, true, s2));
+  GN_TRY(widen(r, rl, M0, F64, rl, M, rl, kd, r, s2));
+  GN_TRY(launch_dgemm(r, rl, r, 1.0, Q2r, MatRef{M0, F64, rl, 1}, 0.0, M, rl, 1, nullptr, false, s2,
+                      kd, r, true, DS, DSB));
+  // C = Q1 R
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, Q1r, MatRef{core->R, F64, r, 1}, 0.0, Cm, r, 1, nullptr,
+                      false, s2, nullptr, 0, true, DS, DSB));
+  // Z = Q1k R11^{-T} (columns >= k zero), then T5 = C^T Z
+  if (hipMemcpyAsync(Z, core->Q1, (size_t)rl * r * 8, hipMemcpyDeviceToDevice, s2) != hipSuccess)
+    return GN_ERR_HIP;
+  GN_TRY(launch_trsm_core(rl, r, core->R, core->R2, r, kd, Z, r, 1, true, true, s2, true));
+  GN_TRY(launch_dgemm(r, r, rl, 1.0, MatRef{Cm, F64, 1, r}, sq(Z), 0.0, T5, r, 1, nullptr, false,
+                      s2, nullptr, 0, true, DS, DSB));
+  if (hipEventRecord(ss->join, s2) != hipSuccess) return GN_ERR_HIP;
 
   // sketches, as the forward pass drew them: X^T in rows [0, r) of rcat, Y in
   // columns [r, r + rl) of lcat
@@ -828,24 +862,12 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
                         nullptr, false, s, nullptr, 0, true, (double*)(base + W.split),
                         W.total - W.split));
 
-  // ---- the core adjoint in FP64 (k from the forward pass, on the device); the
-  // small products split their contraction through the DS scratch region
-  double* DS = (double*)(base + W.dsplit);
-  const size_t DSB = W.dsplit_bytes;
+  // ---- the rest of the core adjoint in FP64 (k from the forward pass, on the
+  // device), after the side stream's M, C, Z and C^T Z; the small products split
+  // their contraction through the DS scratch region
+  if (hipStreamWaitEvent(s, ss->join, 0) != hipSuccess) return GN_ERR_HIP;
   const MatRef Mr{M, F64, rl, 1}, Mt{M, F64, 1, rl};
   const MatRef Hr{H, F64, rl, 1}, Ht{H, F64, 1, rl};
-  const MatRef Q1r{core->Q1, F64, r, 1}, Q1t{core->Q1, F64, 1, r};
-  const MatRef Q2r{core->Q2, F64, r, 1}, Q2t{core->Q2, F64, 1, r};
-  auto sq = [&](double* T) { return MatRef{T, F64, r, 1}; };  // ld r (r x r and rl x r)
-  // M = R^{-1} Q1^T (k == r) or Q2 R2^{-T} Q1[:, :k]^T (k < r)
-  GN_TRY(launch_transpose_rows_masked(rl, r, core->Q1, r, kd, M0, rl, s));
-  GN_TRY(launch_trsm_core(rl, r, core->R, core->R2, r, kd, M0, 1, rl, true, true, s));
-  GN_TRY(widen(r, rl, M0, F64, rl, M, rl, kd, r, s));
-  GN_TRY(launch_dgemm(r, rl, r, 1.0, Q2r, MatRef{M0, F64, rl, 1}, 0.0, M, rl, 1, nullptr, false, s,
-                      kd, r, true, DS, DSB));
-  // C = Q1 R
-  GN_TRY(launch_dgemm(rl, r, r, 1.0, Q1r, MatRef{core->R, F64, r, 1}, 0.0, Cm, r, 1, nullptr,
-                      false, s, nullptr, 0, true, DS, DSB));
   // Bbar = -M^T H M^T
   GN_TRY(launch_dgemm(r, r, rl, 1.0, Hr, Mt, 0.0, T1, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
   GN_TRY(launch_dgemm(rl, r, r, -1.0, Mt, sq(T1), 0.0, Bb, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
@@ -860,16 +882,10 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
   GN_TRY(launch_dgemm(r, r, r, 1.0, sq(T1), Q2r, 0.0, T4, r, 1, kd, false, s, kd, r, true, DS, DSB));
   GN_TRY(launch_dgemm(r, r, r, -1.0, sq(T4), Q2t, 1.0, T1, r, 1, nullptr, false, s, kd, r, true, DS, DSB));
   GN_TRY(launch_dgemm(rl, r, r, 1.0, Mt, sq(T1), 1.0, Bb, r, 1, nullptr, false, s, kd, r, true, DS, DSB));
-  // Z = Q1k R11^{-T} (columns >= k zero)
-  if (hipMemcpyAsync(Z, core->Q1, (size_t)rl * r * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return GN_ERR_HIP;
-  GN_TRY(launch_trsm_core(rl, r, core->R, core->R2, r, kd, Z, r, 1, true, true, s, true));
-  // Y5 = Bbar (C^T Z) + C (Bbar^T Z)
-  GN_TRY(launch_dgemm(r, r, rl, 1.0, MatRef{Cm, F64, 1, r}, sq(Z), 0.0, T2, r, 1, nullptr, false,
-                      s, nullptr, 0, true, DS, DSB));
+  // Y5 = Bbar (C^T Z) + C (Bbar^T Z), C^T Z = T5 from the side stream
   GN_TRY(launch_dgemm(r, r, rl, 1.0, MatRef{Bb, F64, 1, r}, sq(Z), 0.0, T3, r, 1, nullptr, false,
                       s, nullptr, 0, true, DS, DSB));
-  GN_TRY(launch_dgemm(rl, r, r, 1.0, sq(Bb), sq(T2), 0.0, Y5, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
+  GN_TRY(launch_dgemm(rl, r, r, 1.0, sq(Bb), sq(T5), 0.0, Y5, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
   GN_TRY(launch_dgemm(rl, r, r, 1.0, sq(Cm), sq(T3), 1.0, Y5, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
   // Cbar = Y5 + Q1k Q1k^T (Bbar - Y5)   (kept in Y5)
   GN_TRY(launch_dgemm(r, r, rl, 1.0, Q1t, sq(Bb), 0.0, T4, r, 1, kd, true, s, nullptr, 0, true, DS, DSB));
