@@ -6,6 +6,100 @@
 namespace gn {
 namespace {
 
+// ---------------------------------------------------------------- Box-Muller in FP64
+// The map of two 53-bit uniforms to two standard normals, z = sqrt(-2 ln u1) (cos t,
+// sin t) with t the double nearest 2 pi u2, evaluated for exactly this domain
+// (u1 in [2^-53, 1], t in [0, 2 pi)) with a few FMAs: the generic library log, sin
+// and cos spent most of the generator's time on their range checks and on
+// reductions for arguments that never occur here.  Each result is within about one
+// ulp of the correctly rounded value (a CPU model of these steps measured at most
+// 1 ulp for the log, sine and cosine and 3 ulp for z against the C library).
+
+// ln x for x in [2^-53, 1]: x = 2^e m with m in (sqrt(2)/2, sqrt(2)], f = m - 1
+// (exact), s = f / (2 + f), ln m = 2 atanh(s) = f - (f^2/2 - s (f^2/2 + R)) with
+// R = sum_k 2 s^(2k) / (2k + 1) (k = 1 .. 12: the first omitted term is below
+// 2^-60 of ln m), and e ln 2 added through FMAs with ln 2 in two parts.
+__device__ __forceinline__ double bm_log(double x) {
+#pragma clang fp contract(off)
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  int e = (int)(b >> 52) - 1023;
+  double m = __longlong_as_double((long long)((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+  if (m > 0x1.6a09e667f3bcdp+0) {
+    m *= 0.5;
+    e += 1;
+  }
+  const double f = m - 1.0;
+  const double s = f / (2.0 + f);
+  const double z = s * s;
+  double p = 2.0 / 25.0;
+  p = __builtin_fma(p, z, 2.0 / 23.0);
+  p = __builtin_fma(p, z, 2.0 / 21.0);
+  p = __builtin_fma(p, z, 2.0 / 19.0);
+  p = __builtin_fma(p, z, 2.0 / 17.0);
+  p = __builtin_fma(p, z, 2.0 / 15.0);
+  p = __builtin_fma(p, z, 2.0 / 13.0);
+  p = __builtin_fma(p, z, 2.0 / 11.0);
+  p = __builtin_fma(p, z, 2.0 / 9.0);
+  p = __builtin_fma(p, z, 2.0 / 7.0);
+  p = __builtin_fma(p, z, 2.0 / 5.0);
+  p = __builtin_fma(p, z, 2.0 / 3.0);
+  const double R = z * p;
+  const double hfsq = 0.5 * f * f;
+  const double lm = f - (hfsq - s * (hfsq + R));
+  const double de = (double)e;
+  return __builtin_fma(de, 0x1.62e42fefa39efp-1, __builtin_fma(de, 0x1.abc9e3b39803fp-56, lm));
+}
+
+// sin t and cos t for t in [0, 2 pi): k = nearest integer to t / (pi/2), y = t - k pi/2
+// with pi/2 in three parts (the products exact inside the FMAs, so y is accurate
+// to far below its ulp even next to a multiple of pi/2), |y| <= pi/4, then the
+// Taylor series of sin y to y^17 and of cos y to y^16 (omitted terms below 2^-60)
+// and the quadrant of k.
+__device__ __forceinline__ void bm_sincos(double t, double& sn, double& cs) {
+#pragma clang fp contract(off)
+  const double k = __builtin_rint(t * 0x1.45f306dc9c883p-1);
+  double y = __builtin_fma(-k, 0x1.921fb54442d18p+0, t);
+  y = __builtin_fma(-k, 0x1.1a62633145c07p-54, y);
+  y = __builtin_fma(-k, -0x1.f1976b7ed8fbcp-110, y);
+  const double z = y * y;
+  double ps = 1.0 / 355687428096000.0;                // 1/17!
+  ps = __builtin_fma(ps, z, -1.0 / 1307674368000.0);  // 1/15!
+  ps = __builtin_fma(ps, z, 1.0 / 6227020800.0);      // 1/13!
+  ps = __builtin_fma(ps, z, -1.0 / 39916800.0);       // 1/11!
+  ps = __builtin_fma(ps, z, 1.0 / 362880.0);          // 1/9!
+  ps = __builtin_fma(ps, z, -1.0 / 5040.0);           // 1/7!
+  ps = __builtin_fma(ps, z, 1.0 / 120.0);             // 1/5!
+  ps = __builtin_fma(ps, z, -1.0 / 6.0);              // 1/3!
+  const double sy = __builtin_fma(y * z, ps, y);
+  double pc = 1.0 / 20922789888000.0;                 // 1/16!
+  pc = __builtin_fma(pc, z, -1.0 / 87178291200.0);    // 1/14!
+  pc = __builtin_fma(pc, z, 1.0 / 479001600.0);       // 1/12!
+  pc = __builtin_fma(pc, z, -1.0 / 3628800.0);        // 1/10!
+  pc = __builtin_fma(pc, z, 1.0 / 40320.0);           // 1/8!
+  pc = __builtin_fma(pc, z, -1.0 / 720.0);            // 1/6!
+  pc = __builtin_fma(pc, z, 1.0 / 24.0);              // 1/4!
+  pc = __builtin_fma(pc, z, -0.5);                    // 1/2!
+  const double cy = __builtin_fma(z, pc, 1.0);
+  const int q = ((int)k) & 3;
+  sn = (q == 0) ? sy : (q == 1) ? cy : (q == 2) ? -sy : -cy;
+  cs = (q == 0) ? cy : (q == 1) ? -sy : (q == 2) ? -cy : sy;
+}
+
+// Two standard normals from one Philox block: 53-bit uniforms u1 in (0,1],
+// u2 in [0,1) and the Box-Muller map, all in double precision.
+__device__ __forceinline__ void bm_normal_pair(U4 w, double& z0, double& z1) {
+#pragma clang fp contract(off)
+  const uint64_t ka = ((uint64_t)(w.a >> 5) << 26) | (uint64_t)(w.b >> 6);
+  const uint64_t kb = ((uint64_t)(w.c >> 5) << 26) | (uint64_t)(w.d >> 6);
+  const double u1 = 1.0 - (double)ka * 0x1.0p-53;
+  const double u2 = (double)kb * 0x1.0p-53;
+  const double rad = sqrt(-2.0 * bm_log(u1));
+  double sn, cs;
+  bm_sincos(6.283185307179586 * u2, sn, cs);
+  z0 = rad * cs;
+  z1 = rad * sn;
+}
+
 template <int DT>
 __device__ __forceinline__ void store_elem(void* out, int64_t off, double z) {
   if constexpr (DT == GN_DT_F64) {
@@ -35,7 +129,7 @@ __global__ void __launch_bounds__(256) gaussian_rowmajor(uint32_t k0, uint32_t k
   const int64_t p = pair0 + (t - i * npairs);
   const U4 w = philox10(U4{(uint32_t)(row0 + i), (uint32_t)p, sid, 0u}, k0, k1);
   double z[2];
-  normal_pair(w, z[0], z[1]);
+  bm_normal_pair(w, z[0], z[1]);
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int64_t j = 2 * p + e - col0;
@@ -56,7 +150,7 @@ __global__ void __launch_bounds__(256) gaussian_transposed(uint32_t k0, uint32_t
   const int64_t p = pair0 + pl;
   const U4 w = philox10(U4{(uint32_t)(row0 + i), (uint32_t)p, sid, 0u}, k0, k1);
   double z[2];
-  normal_pair(w, z[0], z[1]);
+  bm_normal_pair(w, z[0], z[1]);
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int64_t j = 2 * p + e - col0;
@@ -78,7 +172,7 @@ __global__ void __launch_bounds__(256) gaussian_rowmajor_b(const GaussJob* __res
     const int64_t p = t - i * npairs;
     const U4 w = philox10(U4{(uint32_t)i, (uint32_t)p, (uint32_t)J.sid, 0u}, k0, k1);
     double z[2];
-    normal_pair(w, z[0], z[1]);
+    bm_normal_pair(w, z[0], z[1]);
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int64_t j = 2 * p + e;

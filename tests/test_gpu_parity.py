@@ -84,6 +84,19 @@ def test_gaussian_f64_matches_oracle(G, layout):
     assert np.max(d) <= 8
 
 
+def test_gaussian_f64_large_block_within_ulps(G):
+    """4M FP64 sketch values (both Box-Muller outputs, u1 down to its smallest
+    values and angles in every quadrant) against the oracle's NumPy log, cos and
+    sin: the device's Box-Muller steps stay within a few ulp of the library
+    functions everywhere, not only on a small block."""
+    rows, cols = 4096, 1024
+    got = host(G.gn_generate_gaussian(23, 2, rows, cols, torch.float64))
+    ref = OP.gaussian(23, 2, rows, cols, workers=8)
+    d = ulp_diff(got, ref)
+    print(f"FP64 Gaussian, 4M values: max {int(np.max(d))} ulp, {float(np.mean(d > 0)):.3f} not bit-equal")
+    assert np.max(d) <= 8
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_gaussian_rounded_equal_except_ties(G, dtype):
     rows, cols = 1000, 333
