@@ -46,19 +46,6 @@ __device__ __forceinline__ U4 philox10(U4 ctr, uint32_t k0, uint32_t k1) {
   return ctr;
 }
 
-// Two standard normals from one Philox block: 53-bit uniforms u1 in (0,1],
-// u2 in [0,1) and the Box-Muller map, all in double precision.
-__device__ __forceinline__ void normal_pair(U4 w, double& z0, double& z1) {
-  const uint64_t ka = ((uint64_t)(w.a >> 5) << 26) | (uint64_t)(w.b >> 6);
-  const uint64_t kb = ((uint64_t)(w.c >> 5) << 26) | (uint64_t)(w.d >> 6);
-  const double u1 = 1.0 - (double)ka * 0x1.0p-53;
-  const double u2 = (double)kb * 0x1.0p-53;
-  const double rad = sqrt(-2.0 * log(u1));
-  const double theta = 6.283185307179586 * u2;
-  z0 = rad * cos(theta);
-  z1 = rad * sin(theta);
-}
-
 // ---------------------------------------------------------------------------- bfloat16
 // Round a double to bfloat16 (8 significant bits) to nearest, ties to even,
 // straight from the FP64 bit pattern.  Valid for zero and for magnitudes in the

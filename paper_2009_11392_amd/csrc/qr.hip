@@ -758,8 +758,9 @@ __global__ void __launch_bounds__(256) qr_oupd_w(const double* __restrict__ Vb, 
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = qr_f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int kb = 0; kb < QO_CH; kb += 16) {
-    double a[4][2], b[4][2];
+  // 16 rows of V and D per step; the next step's loads are issued before this
+  // step's products, so every step after the first finds its operands loaded
+  auto load = [&](int kb, double (&a)[4][2], double (&b)[4][2]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t row = r0 + kb + 4 * u + lk;
@@ -772,12 +773,19 @@ __global__ void __launch_bounds__(256) qr_oupd_w(const double* __restrict__ Vb, 
         b[u][y] = (rin && col < ncols) ? D[row * ldd + col] : 0.0;
       }
     }
+  };
+  double a[2][4][2], b[2][4][2];
+  load(0, a[0], b[0]);
+#pragma unroll
+  for (int st = 0; st < QO_CH / 16; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < QO_CH / 16) load(16 * (st + 1), a[cur ^ 1], b[cur ^ 1]);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = qr_mfma(a[u][x], b[u][y], acc[x][y]);
+        for (int y = 0; y < 2; ++y) acc[x][y] = qr_mfma(a[cur][u][x], b[cur][u][y], acc[x][y]);
   }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
