@@ -688,35 +688,28 @@ __global__ void __launch_bounds__(256) build_z_b(const TruncJob* __restrict__ jo
 constexpr int QR_OB = 64;
 
 // Vb ((M - J0) x QR_OB, row-major) and Vt (its transpose, ld M - J0): the block's
-// unit lower trapezoidal reflectors, zero past the block width w.  A workgroup
-// takes QR_OB rows: C is read row-contiguously (consecutive lanes, consecutive
-// columns), and the tile goes through LDS so that Vt is written along its rows
-// as well.
-constexpr int QB_ROWS = 64;  // rows of V per workgroup
+// unit lower trapezoidal reflectors, zero past the block width w.
 __global__ void __launch_bounds__(256) qr_build_v(const double* __restrict__ C, int64_t ldc,
                                                   int64_t M, int64_t J0, int w,
                                                   double* __restrict__ Vb, double* __restrict__ Vt,
                                                   const int32_t* gate, int64_t gate_n) {
   if (gate && *gate >= gate_n) return;
-  static_assert(QR_OB == 64 && QB_ROWS == 64, "one 64 x 64 tile per workgroup");
-  __shared__ double tile[QB_ROWS][QR_OB + 1];
-  const int tid = threadIdx.x;
-  const int64_t Mp = M - J0, i0 = (int64_t)blockIdx.x * QB_ROWS;
-#pragma unroll
-  for (int q = 0; q < QB_ROWS * QR_OB / 256; ++q) {
-    const int e = tid + 256 * q, ii = e / QR_OB, c = e % QR_OB;
-    const int64_t i = i0 + ii;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t Mp = M - J0;
+  if (e >= Mp * QR_OB) return;
+  {  // Vb: Mp x QR_OB, row-major
+    const int64_t i = e / QR_OB;
+    const int c = (int)(e - i * QR_OB);
     double v = 0.0;
-    if (i < Mp && c < w) v = (i < c) ? 0.0 : (i == c ? 1.0 : C[(J0 + i) * ldc + J0 + c]);
-    if (i < Mp) Vb[i * QR_OB + c] = v;
-    tile[ii][c] = v;
+    if (c < w) v = (i < c) ? 0.0 : (i == c ? 1.0 : C[(J0 + i) * ldc + J0 + c]);
+    Vb[e] = v;
   }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < QB_ROWS * QR_OB / 256; ++q) {
-    const int e = tid + 256 * q, c = e / QB_ROWS, ii = e % QB_ROWS;
-    const int64_t i = i0 + ii;
-    if (i < Mp) Vt[(int64_t)c * Mp + i] = tile[ii][c];
+  {  // Vt: QR_OB x Mp, row-major (V by columns)
+    const int c = (int)(e / Mp);
+    const int64_t i = e - (int64_t)c * Mp;
+    double v = 0.0;
+    if (c < w) v = (i < c) ? 0.0 : (i == c ? 1.0 : C[(J0 + i) * ldc + J0 + c]);
+    Vt[e] = v;
   }
 }
 
@@ -1149,7 +1142,7 @@ gn_status launch_qr_factor(int64_t M, int64_t N, double* C, int64_t ldc, double*
       j0 += nbw;
     }
     const int64_t Mp = M - J0;
-    qr_build_v<<<dim3((unsigned)cdiv(Mp, QB_ROWS)), dim3(256), 0, s>>>(C, ldc, M, J0, nbo, w.Vb,
+    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, nbo, w.Vb,
                                                                          w.Vt, gate_k, gate_n);
     GN_LAUNCH_CHECK();
     const unsigned nchg = (unsigned)cdiv(Mp, QO_CH);  // G = V^T V
@@ -1184,7 +1177,7 @@ gn_status launch_qr_form_q(int64_t M, int64_t N, const double* C, int64_t ldc, d
     const int64_t J0 = ob * QR_OB, J1 = (J0 + QR_OB < N) ? J0 + QR_OB : N;
     const int nbo = (int)(J1 - J0);
     const int64_t Mp = M - J0, nq = N - J0;
-    qr_build_v<<<dim3((unsigned)cdiv(Mp, QB_ROWS)), dim3(256), 0, s>>>(C, ldc, M, J0, nbo, w.Vb,
+    qr_build_v<<<dim3((unsigned)cdiv(Mp * QR_OB, 256)), dim3(256), 0, s>>>(C, ldc, M, J0, nbo, w.Vb,
                                                                          w.Vt, gate_k, gate_n);
     GN_LAUNCH_CHECK();
     GN_TRY(qr_apply_block(w, Mp, Q + J0 * ldq + J0, ldq, nq, w.Tout + (size_t)ob * QR_OB * QR_OB, 0,
