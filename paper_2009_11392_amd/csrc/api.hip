@@ -868,6 +868,16 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
   if (hipStreamWaitEvent(s, ss->join, 0) != hipSuccess) return GN_ERR_HIP;
   const MatRef Mr{M, F64, rl, 1}, Mt{M, F64, 1, rl};
   const MatRef Hr{H, F64, rl, 1}, Ht{H, F64, 1, rl};
+  // U's first term G1 M^T (columns [0, r) of lcat) and V = M^T G2 (rows [r, r + rl)
+  // of rcat) need only M, G1 and G2: the side stream forms them while this stream
+  // runs the chain of small products below (neither touches lcat, rcat or DS).
+  if (hipEventRecord(ss->fork, s) != hipSuccess || hipStreamWaitEvent(s2, ss->fork, 0) != hipSuccess)
+    return GN_ERR_HIP;
+  GN_TRY(launch_dgemm_to(m, r, rl, 1.0, MatRef{G1, adt, rl, 1}, Mt, 0.0, lcat, sdt, K2, 1, nullptr,
+                         false, s2));
+  GN_TRY(launch_dgemm_to(rl, n, r, 1.0, Mt, MatRef{G2, adt, n, 1}, 0.0, rcat + (size_t)r * n * sd,
+                         sdt, n, 1, nullptr, false, s2));
+  if (hipEventRecord(ss->join, s2) != hipSuccess) return GN_ERR_HIP;
   // Bbar = -M^T H M^T
   GN_TRY(launch_dgemm(r, r, rl, 1.0, Hr, Mt, 0.0, T1, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
   GN_TRY(launch_dgemm(rl, r, r, -1.0, Mt, sq(T1), 0.0, Bb, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
@@ -892,14 +902,10 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
   GN_TRY(launch_dgemm(r, r, rl, -1.0, Q1t, sq(Y5), 1.0, T4, r, 1, kd, true, s, nullptr, 0, true, DS, DSB));
   GN_TRY(launch_dgemm(rl, r, r, 1.0, Q1r, sq(T4), 1.0, Y5, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
 
-  // U = G1 M^T + Y Cbar into columns [0, r) of lcat; V = M^T G2 into rows
-  // [r, r + rl) of rcat
-  GN_TRY(launch_dgemm_to(m, r, rl, 1.0, MatRef{G1, adt, rl, 1}, Mt, 0.0, lcat, sdt, K2, 1, nullptr,
-                         false, s, nullptr, 0, true, DS, DSB));
+  // U = G1 M^T + Y Cbar: the second term after the side stream's first
+  if (hipStreamWaitEvent(s, ss->join, 0) != hipSuccess) return GN_ERR_HIP;
   GN_TRY(launch_dgemm_to(m, r, rl, 1.0, MatRef{lcat + r * sd, sdt, K2, 1}, sq(Y5), 1.0, lcat,
                          sdt, K2, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
-  GN_TRY(launch_dgemm_to(rl, n, r, 1.0, Mt, MatRef{G2, adt, n, 1}, 0.0, rcat + (size_t)r * n * sd,
-                         sdt, n, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
   // dA = [U | Y] [X^T ; V]
   if (f32)
     return launch_gemm_f32(m, n, K2, (const float*)lcat, K2, true, (const float*)rcat, n, false,
