@@ -283,8 +283,10 @@ size_t core_product_ws_bytes(int64_t m, int64_t rl, int64_t r) {
   return align_up((size_t)core_slices(m, rl, r) * rl * r * sizeof(float));
 }
 
-// K slices of the BF16 core product: about 512 workgroups over the two terms, slices
-// at least 1024 long and a multiple of 128, at most 16.
+// K slices of the BF16 core product: the 2 x tiles x slices workgroups (one
+// 1024-thread workgroup per CU) run in rounds of 256, each of time ~ K / slices,
+// so the count that minimizes rounds / slices (the fewest such slices), with
+// slices at least 1024 long and a multiple of 128, at most 16.
 struct Bf16CoreLayout {
   int64_t kslice, nslice, nsb;
   size_t hi, lo, ones, partial, cmax, total;
@@ -292,10 +294,16 @@ struct Bf16CoreLayout {
 static Bf16CoreLayout bf16_core_layout(int64_t m, int64_t rl, int64_t r) {
   Bf16CoreLayout L{};
   const int64_t tiles = cdiv(rl, BF16Pass::BM) * cdiv(r, BF16Pass::BN);
-  int64_t sl = cdiv(512, 2 * tiles);
-  if (sl > cdiv(m, 1024)) sl = cdiv(m, 1024);
-  if (sl > 16) sl = 16;
-  if (sl < 1) sl = 1;
+  const int64_t max_sl = std::max<int64_t>(1, std::min<int64_t>(16, cdiv(m, 1024)));
+  int64_t sl = 1;
+  double best = 0.0;
+  for (int64_t c = 1; c <= max_sl; ++c) {
+    const double t = (double)cdiv(2 * tiles * c, 256) / (double)c;
+    if (c == 1 || t < best - 1e-9) {
+      best = t;
+      sl = c;
+    }
+  }
   L.kslice = cdiv(cdiv(m, sl), 128) * 128;
   L.nslice = cdiv(m, L.kslice);
   L.nsb = L.kslice / 128;
