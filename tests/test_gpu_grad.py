@@ -100,6 +100,34 @@ def test_backward_f64_truncated_core(G):
     assert relerr(host(dA), ref) <= 1e-9
 
 
+# gn_backward forks the core-only part of the adjoint, and later U's first term
+# and V, onto the per-device side stream and joins it back twice.  Two backward
+# calls enqueued at once on two streams (one with a truncated core), each with its
+# own workspace, give bit for bit the results of the same calls one at a time.
+def test_backward_on_two_streams(G):
+    m, n, r, l = 300, 200, 20, 10
+    cases = [_case(G, m, n, r, l, np.arange(1, 201, dtype=float) ** -1.5, seed=300),
+             _case(G, m, n, r, l, np.r_[np.linspace(1.0, 0.2, 14), 1e-9 * np.ones(186)], seed=41,
+                   eps=1e-6)]
+    solved = []
+    for A, Gb, p in cases:
+        AX, YtA, core = G.solve(p, dev(A))
+        solved.append((p, dev(Gb), AX, YtA, core))
+    torch.cuda.synchronize()
+    assert [c[4].rank() for c in solved] == [r, 14]
+    serial = [G.gn_backward(p, Gbd, YtA, core, AX=AX) for p, Gbd, AX, YtA, core in solved]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    both = []
+    for (p, Gbd, AX, YtA, core), st in zip(solved, streams):
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            both.append(G.gn_backward(p, Gbd, YtA, core, AX=AX))
+    torch.cuda.synchronize()
+    for a, b in zip(serial, both):
+        assert torch.equal(a, b)
+
+
 def test_autograd_function_f64(G):
     m, n, r, l = 256, 160, 16, 8
     sig = np.arange(1, 161, dtype=float) ** -1.5
