@@ -60,7 +60,7 @@ typedef enum {
   GN_ERR_WORKSPACE = 5,  /* ws too small (query gn_workspace_size)               */
   GN_ERR_HIP = 6,        /* a HIP launch or runtime call failed                  */
   GN_ERR_NUMERIC = 7,    /* (status word only) non-finite or rank-0 core         */
-  GN_ERR_UNSUPPORTED = 8 /* size beyond what this build handles                  */
+  GN_ERR_UNSUPPORTED = 8 /* size or mode beyond what the library handles       */
 } gn_status;
 
 typedef enum { GN_SKETCH_GAUSSIAN = 0, GN_SKETCH_SRHT = 1, GN_SKETCH_USER = 2 } gn_sketch_kind;

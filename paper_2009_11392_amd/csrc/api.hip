@@ -341,7 +341,7 @@ const char* gn_status_string(int32_t s) {
     case GN_ERR_WORKSPACE: return "GN_ERR_WORKSPACE: workspace too small";
     case GN_ERR_HIP: return "GN_ERR_HIP: HIP launch or runtime failure";
     case GN_ERR_NUMERIC: return "GN_ERR_NUMERIC: non-finite or rank-0 core";
-    case GN_ERR_UNSUPPORTED: return "GN_ERR_UNSUPPORTED: size beyond this build's limits";
+    case GN_ERR_UNSUPPORTED: return "GN_ERR_UNSUPPORTED: size or mode beyond the library's limits";
     default: return "unknown gn_status";
   }
 }
