@@ -225,7 +225,9 @@ def grad_bench(gn, W, steps=5, warmup=2, host_factors=False):
     t_bc = timeit_cold(lambda: bwd(False))
     del flush
     m, n, r, rl = wl.m, wl.n, wl.r, p.rl
-    fl_b = 4.0 * m * n * (r + rl) + 2.0 * m * r * rl + 4.0 * m * r * rl + 2.0 * rl * n * r
+    # pass over Gbar and final product 2mn(r + rl) each; H and U = G1 M^T 2m r rl each;
+    # V = M^T G2 + Cbar X^T 4 rl n r
+    fl_b = 4.0 * m * n * (r + rl) + 2.0 * m * r * rl + 2.0 * m * r * rl + 4.0 * rl * n * r
     fl_f = 2.0 * m * n * (r + rl) + 2.0 * m * r * n
     out = {"workload": wl.name, "m": m, "n": n, "r": r, "l": wl.l, "mode": "f32",
            "kept_rank": core.rank(), "forward_ms": t_f, "backward_ms": t_b,

@@ -868,7 +868,7 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
   if (hipStreamWaitEvent(s, ss->join, 0) != hipSuccess) return GN_ERR_HIP;
   const MatRef Mr{M, F64, rl, 1}, Mt{M, F64, 1, rl};
   const MatRef Hr{H, F64, rl, 1}, Ht{H, F64, 1, rl};
-  // U's first term G1 M^T (columns [0, r) of lcat) and V = M^T G2 (rows [r, r + rl)
+  // U = G1 M^T (columns [0, r) of lcat) and V's first term M^T G2 (rows [r, r + rl)
   // of rcat) need only M, G1 and G2: the side stream forms them while this stream
   // runs the chain of small products below (neither touches lcat, rcat or DS).
   if (hipEventRecord(ss->fork, s) != hipSuccess || hipStreamWaitEvent(s2, ss->fork, 0) != hipSuccess)
@@ -902,11 +902,13 @@ gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const voi
   GN_TRY(launch_dgemm(r, r, rl, -1.0, Q1t, sq(Y5), 1.0, T4, r, 1, kd, true, s, nullptr, 0, true, DS, DSB));
   GN_TRY(launch_dgemm(rl, r, r, 1.0, Q1r, sq(T4), 1.0, Y5, r, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
 
-  // U = G1 M^T + Y Cbar: the second term after the side stream's first
+  // dA = G1 M^T X^T + Y (Cbar X^T + M^T G2): with U = G1 M^T and V = M^T G2 from the
+  // side stream, Cbar X^T is added to V (an (r + l) x n product, against m x r for
+  // adding Y Cbar to U), and dA = [U | Y] [X^T ; V]
   if (hipStreamWaitEvent(s, ss->join, 0) != hipSuccess) return GN_ERR_HIP;
-  GN_TRY(launch_dgemm_to(m, r, rl, 1.0, MatRef{lcat + r * sd, sdt, K2, 1}, sq(Y5), 1.0, lcat,
-                         sdt, K2, 1, nullptr, false, s, nullptr, 0, true, DS, DSB));
-  // dA = [U | Y] [X^T ; V]
+  GN_TRY(launch_dgemm_to(rl, n, r, 1.0, sq(Y5), MatRef{rcat, sdt, n, 1}, 1.0,
+                         rcat + (size_t)r * n * sd, sdt, n, 1, nullptr, false, s, nullptr, 0, true,
+                         DS, DSB));
   if (f32)
     return launch_gemm_f32(m, n, K2, (const float*)lcat, K2, true, (const float*)rcat, n, false,
                            (float*)dA, ldda, s);
