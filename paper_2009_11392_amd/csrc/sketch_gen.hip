@@ -11,9 +11,9 @@ namespace {
 // sin t) with t the double nearest 2 pi u2, evaluated for exactly this domain
 // (u1 in [2^-53, 1], t in [0, 2 pi)) with a few FMAs: the generic library log, sin
 // and cos spent most of the generator's time on their range checks and on
-// reductions for arguments that never occur here.  Each result is within about one
-// ulp of the correctly rounded value (a CPU model of these steps measured at most
-// 1 ulp for the log, sine and cosine and 3 ulp for z against the C library).
+// reductions for arguments that never occur here.  The log, sine and cosine are
+// each within about one ulp of the correctly rounded value; z is within 3 ulp of
+// NumPy's log, cos and sin over a block of 4M values (measured).
 
 // ln x for x in [2^-53, 1]: x = 2^e m with m in (sqrt(2)/2, sqrt(2)], f = m - 1
 // (exact), s = f / (2 + f), ln m = 2 atanh(s) = f - (f^2/2 - s (f^2/2 + R)) with
