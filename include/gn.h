@@ -25,8 +25,9 @@
  *     (non-blocking, default priority) and two events per device, created at the
  *     first gn_core / gn_apply / gn_backward call on that device and kept until the
  *     process ends: those calls run independent parts of their work (the kept-rank
- *     scan and second QR; the solve's block inverses; the reverse mode's products
- *     and solves that need only the forward's core) on it, joined back to `stream`
+ *     scan and second QR; the solve's block inverses; the reverse mode's solves and
+ *     products that need only the forward's core, then its U and V products) on
+ *     it, joined back to `stream`
  *     by an event before returning, so work enqueued later on `stream` sees every
  *     result (the fork and join are also recorded under stream capture).
  *   * Arguments are validated synchronously; on an error the call returns
