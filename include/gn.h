@@ -301,14 +301,16 @@ gn_status gn_apply(const gn_problem* p, int32_t side, const void* AX, int64_t ld
  * kept rank k held at the value the forward gn_core chose:
  *   G1 = Gbar (Y^T A)^T, G2 = (AX)^T Gbar  (one fused pass over Gbar),
  *   H = (AX)^T G1,  Cbar = the adjoint of M at H through the core (FP64),
- *   dA = [G1 M^T + Y Cbar] X^T + Y [M^T G2]   (one rank-(r + l) product).
+ *   dA = [G1 M^T + Y Cbar] X^T + Y [M^T G2], formed as
+ *   dA = [G1 M^T | Y] [X^T ; M^T G2 + Cbar X^T]   (one product of inner size 2r + l).
  * Modes GN_MODE_F64 (A, Gbar, AX, YtA, dA double) and GN_MODE_F32 (float; the
  * core adjoint is FP64 in both).  X and Y must be GN_SKETCH_GAUSSIAN (they are
  * regenerated from p->seed); other kinds return GN_ERR_UNSUPPORTED.  AX (ld
  * ldax) and YtA (ld ldya) are the forward pass's outputs; AX may be NULL, in
  * which case it is recomputed from A (ld lda) -- A is read only then.  `core`
  * is the forward gn_core output (read only).  Workspace:
- * gn_workspace_size(GN_OP_BACKWARD) bytes, 256-byte aligned. */
+ * gn_workspace_size(GN_OP_BACKWARD) bytes, 256-byte aligned; calls that run
+ * concurrently need separate workspaces. */
 gn_status gn_backward(const gn_problem* p, const void* A, int64_t lda, const void* Gbar,
                       int64_t ldg, const void* AX, int64_t ldax, const void* YtA, int64_t ldya,
                       const gn_core_out* core, void* dA, int64_t ldda, void* ws,
